@@ -1,0 +1,198 @@
+"""Python access to the reference oracle (plain serial FP64 C, ``oracle/*.c``).
+
+TEST INFRASTRUCTURE ONLY: the test suite, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may use this module; the product path never
+does.  It is a thin ctypes wrapper: every piece of arithmetic lives in the C
+files, which follow arXiv 2211.14318 (Section 2 for W and P, Algorithm 1 for
+the 1D hull, eq. 3.3 for lamination, eq. 5.2 / Algorithm 3 for stresses).
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liboracle.so")
+SOURCES = ["energy.c", "hull.c", "lamination.c", "mlp.c"]
+
+MODEL_NH_DAMAGE = 0
+MODEL_DOUBLEWELL = 1
+TREE_NODES = 3
+
+
+def build(force=True):
+    """Compile the oracle with plain -O2 (no fast-math) against glibc libm."""
+    if not force and os.path.exists(LIB):
+        return LIB
+    srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
+    cmd = ["gcc", "-O2", "-fno-fast-math", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC",
+           "-o", LIB + ".tmp"] + srcs + ["-lm"]
+    subprocess.check_call(cmd)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+class Material(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("model", ctypes.c_int), ("mu", ctypes.c_double),
+                ("lam", ctypes.c_double), ("D_inf", ctypes.c_double), ("D0", ctypes.c_double)]
+
+
+class Level(ctypes.Structure):
+    _fields_ = [("n_dir", ctypes.c_int), ("a", ctypes.POINTER(ctypes.c_double)),
+                ("b", ctypes.POINTER(ctypes.c_double)), ("n_t", ctypes.c_int),
+                ("tau", ctypes.c_double)]
+
+
+class Lamination(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_int), ("level", Level * 2)]
+
+
+class Laminate(ctypes.Structure):
+    _fields_ = [("dir", ctypes.c_int), ("i_minus", ctypes.c_int), ("i_plus", ctypes.c_int),
+                ("xi", ctypes.c_double), ("value", ctypes.c_double),
+                ("dir_gap", ctypes.c_double), ("bridge_gap", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = ctypes.CDLL(LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.orc_psi0.restype = ctypes.c_double
+        L.orc_psi0.argtypes = [ctypes.POINTER(Material), dp]
+        L.orc_damage.restype = ctypes.c_double
+        L.orc_damage.argtypes = [ctypes.POINTER(Material), ctypes.c_double]
+        L.orc_energy.restype = ctypes.c_double
+        L.orc_energy.argtypes = [ctypes.POINTER(Material), dp, ctypes.c_double]
+        L.orc_stress0.restype = ctypes.c_int
+        L.orc_stress0.argtypes = [ctypes.POINTER(Material), dp, ctypes.c_double, dp]
+        L.orc_convexify.restype = ctypes.c_int
+        L.orc_convexify.argtypes = [ctypes.c_int, dp, dp, ip]
+        L.orc_hull_at_centre.restype = ctypes.c_double
+        L.orc_hull_at_centre.argtypes = [ctypes.c_int, dp, ctypes.c_int, ip, ip, dp]
+        L.orc_envelope.restype = ctypes.c_double
+        L.orc_envelope.argtypes = [ctypes.POINTER(Material), ctypes.POINTER(Lamination), dp,
+                                   ctypes.c_double, dp, ctypes.POINTER(Laminate)]
+        L.orc_eval_tree.restype = ctypes.c_double
+        L.orc_eval_tree.argtypes = [ctypes.POINTER(Material), ctypes.POINTER(Lamination), dp,
+                                    ctypes.c_double, ctypes.POINTER(Laminate), dp]
+        L.orc_envelope_batch.restype = None
+        L.orc_envelope_batch.argtypes = [ctypes.POINTER(Material), ctypes.POINTER(Lamination),
+                                         ctypes.c_long, dp, dp, dp, dp, ctypes.POINTER(Laminate)]
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def material(dim=2, model=MODEL_NH_DAMAGE, mu=1.0, lam=2.0, D_inf=0.99, D0=0.1):
+    return Material(dim, model, mu, lam, D_inf, D0)
+
+
+class LaminationSpec:
+    """Keeps the direction arrays alive while the C struct points at them.
+
+    levels: list of (a, b, n_t, tau), outermost first; a, b are (n_dir, dim)."""
+
+    def __init__(self, levels):
+        self._keep = []
+        self.c = Lamination()
+        self.c.depth = len(levels)
+        for k, (a, b, n_t, tau) in enumerate(levels):
+            a = np.ascontiguousarray(a, dtype=np.float64)
+            b = np.ascontiguousarray(b, dtype=np.float64)
+            assert a.shape == b.shape and n_t % 2 == 1
+            self._keep += [a, b]
+            self.c.level[k] = Level(a.shape[0], _dp(a), _dp(b), int(n_t), float(tau))
+        self.levels = levels
+
+
+def psi0(mat, G):
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    return lib().orc_psi0(ctypes.byref(mat), _dp(G))
+
+
+def damage(mat, beta):
+    return lib().orc_damage(ctypes.byref(mat), float(beta))
+
+
+def energy(mat, G, beta_n):
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    return lib().orc_energy(ctypes.byref(mat), _dp(G), float(beta_n))
+
+
+def stress0(mat, G, beta_n):
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    P = np.empty_like(G)
+    lib().orc_stress0(ctypes.byref(mat), _dp(G), float(beta_n), _dp(P))
+    return P
+
+
+def convexify(x, w):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    vert = np.empty(len(x), dtype=np.int32)
+    n = lib().orc_convexify(len(x), _dp(x), _dp(w), vert.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    return vert[:n].copy()
+
+
+def hull_at_centre(w, c=None):
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    if c is None:
+        c = (len(w) - 1) // 2
+    im, ip, gap = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    v = lib().orc_hull_at_centre(len(w), _dp(w), int(c), ctypes.byref(im), ctypes.byref(ip),
+                                 ctypes.byref(gap))
+    return v, im.value, ip.value, gap.value
+
+
+def envelope(mat, spec, F, beta_n, want_tree=False):
+    """Returns (W^k, P^k (d x d), tree or None) for one point."""
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    P = np.empty_like(F)
+    tree = (Laminate * TREE_NODES)() if want_tree else None
+    W = lib().orc_envelope(ctypes.byref(mat), ctypes.byref(spec.c), _dp(F), float(beta_n), _dp(P),
+                           tree)
+    return W, P, (tree_to_list(tree) if want_tree else None)
+
+
+def tree_to_list(tree):
+    return [dict(dir=t.dir, i_minus=t.i_minus, i_plus=t.i_plus, xi=t.xi, value=t.value,
+                 dir_gap=t.dir_gap, bridge_gap=t.bridge_gap) for t in tree]
+
+
+def eval_tree(mat, spec, F, beta_n, nodes):
+    """Energy and stress of a given tree: nodes = list of (dir, i_minus, i_plus)."""
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    P = np.empty_like(F)
+    tree = (Laminate * TREE_NODES)()
+    for k, (m, im, ip) in enumerate(nodes[:TREE_NODES]):
+        tree[k].dir, tree[k].i_minus, tree[k].i_plus = int(m), int(im), int(ip)
+    W = lib().orc_eval_tree(ctypes.byref(mat), ctypes.byref(spec.c), _dp(F), float(beta_n), tree,
+                            _dp(P))
+    return W, P
+
+
+def envelope_batch(mat, spec, F_soa, beta_n, want_stress=True, want_tree=False):
+    """SoA batch: F_soa (d*d, n), beta_n (n,) -> W (n,), P (d*d, n), trees."""
+    F_soa = np.ascontiguousarray(F_soa, dtype=np.float64)
+    beta_n = np.ascontiguousarray(beta_n, dtype=np.float64)
+    n = F_soa.shape[1]
+    W = np.empty(n)
+    P = np.empty_like(F_soa) if want_stress else None
+    trees = (Laminate * (TREE_NODES * n))() if want_tree else None
+    lib().orc_envelope_batch(ctypes.byref(mat), ctypes.byref(spec.c), n, _dp(F_soa), _dp(beta_n),
+                             _dp(W), _dp(P) if want_stress else None, trees)
+    if want_tree:
+        t = tree_to_list(trees)
+        trees = [t[p * TREE_NODES:(p + 1) * TREE_NODES] for p in range(n)]
+    return W, P, trees

@@ -1,0 +1,109 @@
+/*
+ * r1_oracle.h -- reference oracle for the rank-one lamination method of
+ * Balzani, Koehler, Neumeier, Peter, Peterseim, "Multidimensional rank-one
+ * convexification of incremental damage models at finite strains",
+ * arXiv 2211.14318.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, serial, double-precision CPU
+ * implementation written to be checked against the paper by eye.  Only the
+ * test suite, the smoke check and the CPU-baseline leg of the benchmark may
+ * load it.  It shares no code, header, table or helper with the GPU library.
+ *
+ * Conventions
+ *   - Matrices are d x d, row-major, d in {2, 3}.  In 2D the deformation is
+ *     plane strain: the 3x3 gradient is embedded with F33 = 1.
+ *   - A "level" is one lamination step (eq. 3.3): n_dir rank-one directions
+ *     R_m = a_m (x) b_m and an equispaced line grid t_i = tau*(2i-(n_t-1))/(n_t-1),
+ *     i = 0..n_t-1, n_t odd, so the centre index c = (n_t-1)/2 has t_c = 0.
+ *   - depth k: level[0] is the outermost lamination, level[k-1] the innermost,
+ *     whose line samples are values of the unrelaxed potential W.
+ *   - W = +inf where det G <= 0.
+ */
+#ifndef R1_ORACLE_H
+#define R1_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_MODEL_NH_DAMAGE 0   /* neo-Hooke psi0 (eq. 2.3) with (1-D) damage, W of eq. 2.9 */
+#define ORC_MODEL_DOUBLEWELL 1  /* test energy (G11^2-1)^2 + sum_{(i,j)!=(1,1)} (G_ij-delta_ij)^2 */
+
+#define ORC_MAX_DEPTH 2
+#define ORC_TREE_NODES 3        /* 2^ORC_MAX_DEPTH - 1 */
+
+typedef struct {
+    int dim;       /* 2 or 3 */
+    int model;     /* ORC_MODEL_* */
+    double mu, lambda, D_inf, D0;
+} orc_material;
+
+typedef struct {
+    int n_dir;
+    const double* a;   /* n_dir x dim, row-major */
+    const double* b;   /* n_dir x dim */
+    int n_t;           /* odd, >= 3 */
+    double tau;
+} orc_level;
+
+typedef struct {
+    int depth;         /* 0, 1 or 2 */
+    orc_level level[ORC_MAX_DEPTH];
+} orc_lamination;
+
+/* One node of the lamination tree (Algorithm 2 restricted to a binary tree).
+ * Nodes are numbered heap-wise: node 0 is the laminate at F, node 2k+1 is the
+ * laminate at F^- of node k and node 2k+2 the one at F^+.  A node without
+ * lamination (the centre sample is a hull vertex) has i_minus = i_plus = c,
+ * xi = 1, and both its children sit at the same point. */
+typedef struct {
+    int dir;            /* minimising direction index m* */
+    int i_minus;        /* hull vertex left of (or at) the centre */
+    int i_plus;         /* hull vertex right of (or at) the centre */
+    double xi;          /* volume fraction of F^+ : (c - i_minus)/(i_plus - i_minus) */
+    double value;       /* W^l at this node */
+    double dir_gap;     /* runner-up direction value minus the minimum (+inf if one direction) */
+    double bridge_gap;  /* distance of the nearest other sample to the chosen hull segment */
+} orc_laminate;
+
+/* Section 2 */
+double orc_psi0(const orc_material* mat, const double* G);
+double orc_damage(const orc_material* mat, double beta);
+double orc_energy(const orc_material* mat, const double* G, double beta_n);
+int orc_stress0(const orc_material* mat, const double* G, double beta_n, double* P);
+
+/* Algorithm 1 (convexify): lower hull of (x_i, w_i), x strictly increasing.
+ * Writes the indices (into x/w) of the hull vertices to vert and returns their count. */
+int orc_convexify(int L, const double* x, const double* w, int* vert);
+
+/* Value at the centre index c of the lower convex hull of the finite samples of
+ * w[0..n-1] (the finite samples form one index range containing c).  Returns the
+ * hull value and the bracketing vertices; bridge_gap as in orc_laminate (nullable). */
+double orc_hull_at_centre(int n, const double* w, int c, int* i_minus, int* i_plus,
+                          double* bridge_gap);
+
+/* Grid point t_i of a level. */
+double orc_tgrid(const orc_level* lv, int i);
+
+/* W^k(F) by successive lamination (eq. 3.3 restricted to the level's lines).
+ * P (d*d, nullable) receives the laminate stress (eq. 5.2, Algorithm 3); tree
+ * (ORC_TREE_NODES entries, nullable) receives the lamination tree. */
+double orc_envelope(const orc_material* mat, const orc_lamination* lam,
+                    const double* F, double beta_n, double* P, orc_laminate* tree);
+
+/* Energy and stress of a given lamination tree (Algorithm 3 on the tree whose
+ * dir/i_minus/i_plus entries are given; value/xi/gaps are ignored).  Returns the
+ * tree's energy; P (nullable) its stress.  Used to check a result that differs
+ * from the oracle's own at a tie. */
+double orc_eval_tree(const orc_material* mat, const orc_lamination* lam,
+                     const double* F, double beta_n, const orc_laminate* tree, double* P);
+
+/* Batched drivers over structure-of-arrays inputs F[(i*d+j)*n + p]. */
+void orc_envelope_batch(const orc_material* mat, const orc_lamination* lam, long n,
+                        const double* F, const double* beta_n, double* W, double* P,
+                        orc_laminate* trees);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
