@@ -1,0 +1,176 @@
+/*
+ * r1.h -- C-ABI of libr1, an MI355X (gfx950) library that approximates the
+ * rank-one convex envelope of the condensed incremental stress potential of a
+ * finite-strain (1-D) damage model by successive lamination, one quadrature
+ * point at a time.
+ *
+ * Method: Balzani, Koehler, Neumeier, Peter, Peterseim, "Multidimensional
+ * rank-one convexification of incremental damage models at finite strains",
+ * arXiv 2211.14318.
+ *   - W(F): the condensed incremental potential of eq. 2.9 (Section 2) with the
+ *     neo-Hooke psi0 of eq. 2.3 (plane strain in 2D), damage D(beta) =
+ *     D_inf (1 - exp(-beta/D0)) and beta = max(beta_n, psi0(F)); the constant
+ *     -psi(F_k, D_k) of eq. 2.9 is dropped.  W = +inf where det F <= 0.
+ *   - W^k(F): successive lamination (eq. 3.3) evaluated along the discrete
+ *     rank-one lines of Section 4.1 through F: for each direction R = a (x) b the
+ *     line samples W^{k-1}(F + t_i R) are convexified (Algorithm 1) and the hull
+ *     is read at t = 0; W^k(F) is the minimum over the directions.
+ *   - P^k(F): the laminate-endpoint derivative of eq. 5.2 (first case),
+ *     evaluated over the binary lamination tree (Algorithms 2 and 3).
+ *
+ * Conventions shared by every entry point
+ *   - d = material->dim in {2, 3}.  Deformation gradients and stresses are
+ *     structure-of-arrays, component-major: F[(i*d + j)*n + p] for point p.
+ *   - Every data pointer (F, beta_n, W, P, tree, flags, lam_idx, X, Y) is caller-
+ *     owned DEVICE memory on the handle's device; the library never frees it.
+ *     r1_material / r1_lamination structs and the direction arrays they point
+ *     to are HOST memory read during the call.
+ *   - dtype selects the element type of F, beta_n, W and P (float or double) and
+ *     the precision of the arithmetic.
+ *   - Calls are stream-ordered and asynchronous on `stream` (a hipStream_t; NULL
+ *     is the null stream).  A handle is not thread-safe: use one per host thread.
+ *   - Grid of a level: t_i = tau*(2i - (n_t-1))/(n_t-1), i = 0..n_t-1, n_t odd,
+ *     3 <= n_t <= 2049; the centre index c = (n_t-1)/2 has t_c = 0.
+ *   - Errors: a negative r1_status for invalid arguments or device failures
+ *     (nothing is launched on R1_EINVAL).  Conditions of single points do not
+ *     fail the call; they are reported in the optional per-point flags.
+ */
+#ifndef R1_H
+#define R1_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t r1_status;
+#define R1_OK 0
+#define R1_EINVAL (-1)        /* null pointer, bad size, even or out-of-range n_t, depth > 2, ... */
+#define R1_ENOMEM (-2)        /* device workspace could not be allocated */
+#define R1_EDEVICE (-3)       /* a HIP call failed (message via r1_last_error) */
+#define R1_ENOTTRAINED (-4)   /* surrogate used before training or loading */
+#define R1_EUNSUPPORTED (-5)  /* valid request that this build does not implement */
+#define R1_EIO (-6)           /* surrogate file could not be read or written */
+
+typedef int32_t r1_dtype;
+#define R1_F32 0
+#define R1_F64 1
+
+/* Material models */
+#define R1_NEOHOOKE_DAMAGE 0  /* W of eq. 2.9 with psi0 of eq. 2.3 */
+#define R1_TEST_DOUBLEWELL 1  /* test energy (F11^2-1)^2 + sum_{(i,j)!=(1,1)} (F_ij - delta_ij)^2 */
+
+/* Per-point flags (bit set) */
+#define R1_PT_DETLE0 1        /* det F <= 0: W = +inf, P = NaN */
+#define R1_PT_NONFINITE 2     /* F or beta_n not finite: outputs NaN */
+#define R1_PT_FALLBACK 4      /* surrogate inference answered by plain lamination */
+#define R1_PT_ITERCAP 8       /* a hull bridge search hit its iteration cap (result still a valid upper bound) */
+
+#define R1_MAX_DEPTH 2
+#define R1_TREE_NODES 3       /* nodes of a depth-2 binary lamination tree */
+#define R1_MAX_NT 2049
+#define R1_MAX_DIRS 4096
+
+typedef struct r1_handle_s* r1_handle;
+
+typedef struct {
+    int32_t dim;      /* 2 (plane strain) or 3 */
+    int32_t model;    /* R1_NEOHOOKE_DAMAGE or R1_TEST_DOUBLEWELL */
+    double mu;        /* Lame parameters */
+    double lambda;
+    double D_inf;     /* asymptotic damage, in [0, 1) */
+    double D0;        /* damage saturation, > 0 */
+} r1_material;
+
+/* One lamination level: n_dir rank-one directions a_m (x) b_m (host arrays,
+ * n_dir x dim row-major doubles) and the line grid (n_t, tau). */
+typedef struct {
+    int32_t n_dir;
+    const double* a;
+    const double* b;
+    int32_t n_t;
+    double tau;
+} r1_level;
+
+/* depth k in {1, 2}; level[0] is the outermost lamination, level[k-1] the
+ * innermost (its line samples are values of W). */
+typedef struct {
+    int32_t depth;
+    r1_level level[R1_MAX_DEPTH];
+} r1_lamination;
+
+/* One node of the lamination tree, heap-numbered: node 0 is the laminate at F,
+ * node 2k+1 the one at F^- of node k, node 2k+2 the one at F^+.  F^-/+ =
+ * G + t_{i_minus/i_plus} (a_dir (x) b_dir) for the node's point G, with volume
+ * fraction xi of F^+.  A node whose centre sample is a hull vertex has
+ * i_minus = i_plus = c and xi = 1 (no lamination; both children sit at G).
+ * Depth-1 results fill node 0 only. */
+typedef struct {
+    int32_t dir;
+    int32_t i_minus;
+    int32_t i_plus;
+    float xi;
+} r1_laminate;
+
+/* ---- handle ---------------------------------------------------------------- */
+
+/* Creates a handle bound to HIP device `device` (which becomes current). */
+r1_status r1_create(r1_handle* handle, int32_t device);
+r1_status r1_destroy(r1_handle handle);
+const char* r1_status_string(r1_status status);
+/* Text of the last device error seen by this handle ("" if none). */
+const char* r1_last_error(r1_handle handle);
+
+/* ---- plain lamination --------------------------------------------------------- */
+
+/* W[p] = W^k(F_p) (eq. 3.3 on the given levels; Section 4).  flags: nullable
+ * int32[n]. */
+r1_status r1_envelope(r1_handle handle, const r1_material* material,
+                      const r1_lamination* lamination, int64_t n, r1_dtype dtype,
+                      const void* F, const void* beta_n, void* W, int32_t* flags,
+                      void* stream);
+
+/* As r1_envelope, plus the laminate-endpoint stress P (d*d x n SoA, eq. 5.2)
+ * and, if tree != NULL, the lamination tree: R1_TREE_NODES r1_laminate per
+ * point, tree[p*R1_TREE_NODES + node]. */
+r1_status r1_envelope_stress(r1_handle handle, const r1_material* material,
+                             const r1_lamination* lamination, int64_t n, r1_dtype dtype,
+                             const void* F, const void* beta_n, void* W, void* P,
+                             r1_laminate* tree, int32_t* flags, void* stream);
+
+/* Uneven batch in one persistent launch: point p uses table[lam_idx[p]]
+ * (lam_idx: device int32[n], each in [0, n_table)).  P and tree are nullable
+ * (no stress when P == NULL).  The launch sequence is captured once into a
+ * HIP graph per (table, n, dtype, buffers) and replayed; the work split and the
+ * segment width are chosen by the built-in autotuner on first use.  lam_idx is
+ * read by the host planner on the first call for a given buffer (one
+ * device-to-host copy); later calls with the same buffers reuse the plan, so
+ * its contents must not change between calls that share lam_idx. */
+r1_status r1_envelope_batched(r1_handle handle, const r1_material* material,
+                              const r1_lamination* table, int32_t n_table, int64_t n,
+                              const int32_t* lam_idx, r1_dtype dtype, const void* F,
+                              const void* beta_n, void* W, void* P, r1_laminate* tree,
+                              int32_t* flags, void* stream);
+
+/* Segment width (lanes per line, 8..64) the library uses for lines of n_t
+ * points; 0 lets the autotuner decide (default).  Exposed for tests and tuning. */
+r1_status r1_set_segment_width(r1_handle handle, int32_t n_t, int32_t lanes);
+r1_status r1_get_segment_width(r1_handle handle, int32_t n_t, r1_dtype dtype, int32_t dim,
+                               int32_t* lanes);
+
+/* ---- measurement ---------------------------------------------------------------- */
+
+/* When enabled, every kernel launch of the handle is bracketed by HIP events
+ * recorded on its launch stream.  Kernel names: "depth1" (one-level envelope),
+ * "depth2_centre", "outer", "finalize" (two-level envelope), "batched".
+ * r1_timing_query waits for the recorded events and returns the summed elapsed
+ * milliseconds and the launch count of `kernel` since the last reset. */
+r1_status r1_timing_enable(r1_handle handle, int32_t on);
+r1_status r1_timing_reset(r1_handle handle);
+r1_status r1_timing_query(r1_handle handle, const char* kernel, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -46,6 +46,7 @@ static double level_value(const orc_material* mat, const orc_lamination* lam, in
     double* w = (double*)malloc(sizeof(double) * (size_t)n);
     double Gi[9];
     double best = INFINITY, second = INFINITY, best_gap = INFINITY;
+    double vertex_gap = INFINITY;   /* how close any direction is to laminating */
     int best_m = 0, best_im = c, best_ip = c;
     /* the centre sample is G itself for every direction */
     double wc = level_value(mat, lam, ell + 1, G, beta_n, NULL, NULL, 0);
@@ -60,6 +61,8 @@ static double level_value(const orc_material* mat, const orc_lamination* lam, in
         int im, ip;
         double gap;
         double h = orc_hull_at_centre(n, w, c, &im, &ip, tree ? &gap : NULL);
+        if (tree && im == ip && gap < vertex_gap)
+            vertex_gap = gap;
         if (h < best) {
             second = best;
             best = h; best_m = m; best_im = im; best_ip = ip;
@@ -83,7 +86,17 @@ static double level_value(const orc_material* mat, const orc_lamination* lam, in
     if (tree) {
         orc_laminate* t = &tree[node];
         t->dir = best_m; t->i_minus = best_im; t->i_plus = best_ip; t->xi = xi;
-        t->value = best; t->dir_gap = second - best; t->bridge_gap = best_gap;
+        t->value = best;
+        if (best_im == best_ip) {
+            /* no lamination: every direction reads W(G) at its centre, so equal
+             * runner-up values change nothing; the result is fragile only if some
+             * direction's centre is close to losing its vertex status */
+            t->dir_gap = INFINITY;
+            t->bridge_gap = vertex_gap;
+        } else {
+            t->dir_gap = second - best;
+            t->bridge_gap = best_gap;
+        }
     }
     if (P || tree) {
         const double* a = lv->a + best_m * d;

@@ -62,8 +62,11 @@ typedef struct {
     int i_plus;         /* hull vertex right of (or at) the centre */
     double xi;          /* volume fraction of F^+ : (c - i_minus)/(i_plus - i_minus) */
     double value;       /* W^l at this node */
-    double dir_gap;     /* runner-up direction value minus the minimum (+inf if one direction) */
-    double bridge_gap;  /* distance of the nearest other sample to the chosen hull segment */
+    double dir_gap;     /* runner-up direction value minus the minimum (+inf if one direction,
+                           or if the node does not laminate) */
+    double bridge_gap;  /* laminating node: distance of the nearest other sample above the
+                           chosen hull segment; non-laminating node: the smallest margin, over
+                           all directions, by which the centre sample stays a hull vertex */
 } orc_laminate;
 
 /* Section 2 */

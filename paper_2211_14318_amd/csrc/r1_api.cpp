@@ -1,0 +1,286 @@
+// Host side of the C-ABI declared in include/r1.h: argument checks, the
+// per-handle caches (direction tables on the device, scratch workspace,
+// segment widths), and the launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "r1.h"
+#include "r1_handle.hpp"
+#include "r1_launch.hpp"
+
+namespace {
+
+uint64_t fnv1a(const void* p, size_t n, uint64_t h) {
+  const unsigned char* b = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+}  // namespace
+
+r1_status r1h::fail(r1_handle h, hipError_t e, const char* what) {
+  if (h) {
+    h->err = std::string(what) + ": " + hipGetErrorString(e);
+  }
+  return R1_EDEVICE;
+}
+
+r1_status r1h::check_material(const r1_material* m) {
+  if (!m) return R1_EINVAL;
+  if (m->dim != 2 && m->dim != 3) return R1_EINVAL;
+  if (m->model != R1_NEOHOOKE_DAMAGE && m->model != R1_TEST_DOUBLEWELL) return R1_EINVAL;
+  if (!std::isfinite(m->mu) || !std::isfinite(m->lambda) || !std::isfinite(m->D_inf) ||
+      !std::isfinite(m->D0))
+    return R1_EINVAL;
+  if (m->model == R1_NEOHOOKE_DAMAGE && (!(m->D0 > 0.0) || m->D_inf < 0.0 || m->D_inf >= 1.0))
+    return R1_EINVAL;
+  return R1_OK;
+}
+
+r1_status r1h::check_level(const r1_level& lv) {
+  if (lv.n_dir < 1 || lv.n_dir > R1_MAX_DIRS || !lv.a || !lv.b) return R1_EINVAL;
+  if (lv.n_t < 3 || lv.n_t > R1_MAX_NT || (lv.n_t % 2) == 0) return R1_EINVAL;
+  if (!std::isfinite(lv.tau) || !(lv.tau > 0.0)) return R1_EINVAL;
+  return R1_OK;
+}
+
+r1_status r1h::check_lamination(const r1_lamination* lam) {
+  if (!lam || lam->depth < 1 || lam->depth > R1_MAX_DEPTH) return R1_EINVAL;
+  for (int k = 0; k < lam->depth; ++k) {
+    r1_status s = check_level(lam->level[k]);
+    if (s) return s;
+  }
+  return R1_OK;
+}
+
+// Device copy of a level's directions, cached by content.
+r1_status r1h::device_level(r1_handle h, const r1_level& lv, int dim, r1d::Level* out) {
+  size_t bytes = sizeof(double) * size_t(lv.n_dir) * size_t(dim);
+  uint64_t key = 1469598103934665603ull;
+  int32_t hdr[2] = {lv.n_dir, dim};
+  key = fnv1a(hdr, sizeof(hdr), key);
+  key = fnv1a(lv.a, bytes, key);
+  key = fnv1a(lv.b, bytes, key);
+  auto it = h->dirs.find(key);
+  if (it == h->dirs.end()) {
+    if (h->dirs.size() >= 512) {
+      hipError_t e = hipDeviceSynchronize();
+      if (e != hipSuccess) return fail(h, e, "hipDeviceSynchronize");
+      for (auto& kv : h->dirs) (void)hipFree(kv.second);
+      h->dirs.clear();
+    }
+    void* d = nullptr;
+    hipError_t e = hipMalloc(&d, 2 * bytes);
+    if (e != hipSuccess) return R1_ENOMEM;
+    std::vector<double> host(2 * size_t(lv.n_dir) * size_t(dim));
+    std::memcpy(host.data(), lv.a, bytes);
+    std::memcpy(host.data() + size_t(lv.n_dir) * dim, lv.b, bytes);
+    e = hipMemcpy(d, host.data(), 2 * bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(d);
+      return fail(h, e, "hipMemcpy(directions)");
+    }
+    it = h->dirs.emplace(key, d).first;
+  }
+  const double* base = static_cast<const double*>(it->second);
+  out->a = base;
+  out->b = base + size_t(lv.n_dir) * dim;
+  out->n_dir = lv.n_dir;
+  out->n_t = lv.n_t;
+  out->tau = lv.tau;
+  return R1_OK;
+}
+
+r1_status r1h::scratch(r1_handle h, size_t bytes, void** p) {
+  if (bytes > h->scratch_bytes) {
+    if (h->scratch) {
+      hipError_t e = hipDeviceSynchronize();
+      if (e != hipSuccess) return fail(h, e, "hipDeviceSynchronize");
+      (void)hipFree(h->scratch);
+      h->scratch = nullptr;
+      h->scratch_bytes = 0;
+    }
+    size_t sz = bytes + bytes / 4;
+    if (hipMalloc(&h->scratch, sz) != hipSuccess) {
+      h->scratch = nullptr;
+      return R1_ENOMEM;
+    }
+    h->scratch_bytes = sz;
+  }
+  *p = h->scratch;
+  return R1_OK;
+}
+
+// Samples per lane K for a segment of S lanes: the smallest power of two with
+// S*K/2 >= c (one sample pair per offset on each side of the centre).
+int r1h::samples_per_lane(int S, int n_t) {
+  int c = (n_t - 1) / 2;
+  for (int K = 2; K <= 32; K *= 2)
+    if (S * K / 2 >= c) return K;
+  return 0;
+}
+
+int r1h::segment_width(r1_handle h, int n_t, int dtype, int dim) {
+  auto it = h->seg_override.find(n_t);
+  if (it != h->seg_override.end()) return it->second;
+  auto jt = h->seg_tuned.find(r1h::tune_key(n_t, dtype, dim));
+  if (jt != h->seg_tuned.end()) return jt->second;
+  // default: about 16 samples per lane
+  int c = (n_t - 1) / 2;
+  int S = 8;
+  while (S < 64 && S * 8 < c) S *= 2;
+  return S;
+}
+
+extern "C" {
+
+r1_status r1_create(r1_handle* handle, int32_t device) {
+  if (!handle) return R1_EINVAL;
+  *handle = nullptr;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess) return R1_EDEVICE;
+  if (device < 0 || device >= count) return R1_EINVAL;
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return R1_EDEVICE;
+  r1_handle h = new (std::nothrow) r1_handle_s();
+  if (!h) return R1_ENOMEM;
+  h->device = device;
+  *handle = h;
+  return R1_OK;
+}
+
+r1_status r1_destroy(r1_handle h) {
+  if (!h) return R1_EINVAL;
+  (void)hipSetDevice(h->device);
+  (void)hipDeviceSynchronize();
+  (void)h->timer.collect();
+  for (auto& kv : h->dirs) (void)hipFree(kv.second);
+  if (h->scratch) (void)hipFree(h->scratch);
+  r1h::release_batched(h);
+  delete h;
+  return R1_OK;
+}
+
+const char* r1_status_string(r1_status s) {
+  switch (s) {
+    case R1_OK: return "ok";
+    case R1_EINVAL: return "invalid argument";
+    case R1_ENOMEM: return "out of device memory";
+    case R1_EDEVICE: return "device error";
+    case R1_ENOTTRAINED: return "surrogate not trained";
+    case R1_EUNSUPPORTED: return "unsupported";
+    case R1_EIO: return "i/o error";
+    default: return "unknown status";
+  }
+}
+
+const char* r1_last_error(r1_handle h) { return h ? h->err.c_str() : ""; }
+
+r1_status r1_set_segment_width(r1_handle h, int32_t n_t, int32_t lanes) {
+  if (!h || n_t < 3 || n_t > R1_MAX_NT || (n_t % 2) == 0) return R1_EINVAL;
+  if (lanes == 0) {
+    h->seg_override.erase(n_t);
+    return R1_OK;
+  }
+  if (lanes != 8 && lanes != 16 && lanes != 32 && lanes != 64) return R1_EINVAL;
+  if (r1h::samples_per_lane(lanes, n_t) == 0) return R1_EINVAL;
+  h->seg_override[n_t] = lanes;
+  return R1_OK;
+}
+
+r1_status r1_get_segment_width(r1_handle h, int32_t n_t, r1_dtype dtype, int32_t dim, int32_t* lanes) {
+  if (!h || !lanes || n_t < 3 || n_t > R1_MAX_NT || (n_t % 2) == 0) return R1_EINVAL;
+  *lanes = r1h::segment_width(h, n_t, dtype, dim);
+  return R1_OK;
+}
+
+r1_status r1_envelope_stress(r1_handle h, const r1_material* mat, const r1_lamination* lam,
+                             int64_t n, r1_dtype dtype, const void* F, const void* beta_n,
+                             void* W, void* P, r1_laminate* tree, int32_t* flags, void* stream) {
+  if (!h) return R1_EINVAL;
+  r1_status s = r1h::check_material(mat);
+  if (s) return s;
+  s = r1h::check_lamination(lam);
+  if (s) return s;
+  if (dtype != R1_F32 && dtype != R1_F64) return R1_EINVAL;
+  if (n < 0 || n > (int64_t(1) << 31)) return R1_EINVAL;
+  if (n == 0) return R1_OK;
+  if (!F || !beta_n || !W) return R1_EINVAL;
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return r1h::fail(h, e, "hipSetDevice");
+  KArgs a{};
+  a.n = n;
+  a.F = F;
+  a.beta_n = beta_n;
+  a.W = W;
+  a.P = P;
+  a.tree = tree;
+  a.flags = flags;
+  a.mat = r1d::Material{mat->dim, mat->model, mat->mu, mat->lambda, mat->D_inf, mat->D0};
+  a.want_stress = P != nullptr;
+  s = r1h::device_level(h, lam->level[0], mat->dim, &a.lv0);
+  if (s) return s;
+  const r1_level& inner = lam->level[lam->depth - 1];
+  if (lam->depth == 2) {
+    s = r1h::device_level(h, lam->level[1], mat->dim, &a.lv1);
+    if (s) return s;
+    if (int64_t(n) * lam->level[0].n_dir > int64_t(0x7fffffff)) return R1_EINVAL;
+    size_t tsz = dtype == R1_F32 ? 4 : 8;
+    size_t w1 = (tsz * size_t(n) + 255) & ~size_t(255);
+    size_t bytes = w1 + r1_outer_res_bytes(dtype) * size_t(n) * size_t(lam->level[0].n_dir);
+    void* base = nullptr;
+    s = r1h::scratch(h, bytes, &base);
+    if (s) return s;
+    a.scratch_w1f = base;
+    a.scratch_outer = static_cast<char*>(base) + w1;
+  }
+  int S = r1h::segment_width(h, inner.n_t, dtype, mat->dim);
+  int K = r1h::samples_per_lane(S, inner.n_t);
+  if (K == 0) return R1_EINVAL;
+  e = r1_launch_envelope(a, lam->depth, dtype, S, K, static_cast<hipStream_t>(stream),
+                         h->timer.on ? &h->timer : nullptr);
+  if (e != hipSuccess) return r1h::fail(h, e, "kernel launch");
+  return R1_OK;
+}
+
+r1_status r1_timing_enable(r1_handle h, int32_t on) {
+  if (!h) return R1_EINVAL;
+  h->timer.on = on != 0;
+  return R1_OK;
+}
+
+r1_status r1_timing_reset(r1_handle h) {
+  if (!h) return R1_EINVAL;
+  hipError_t e = h->timer.collect();
+  h->timer.acc.clear();
+  return e == hipSuccess ? R1_OK : r1h::fail(h, e, "timing");
+}
+
+r1_status r1_timing_query(r1_handle h, const char* kernel, double* total_ms, int64_t* launches) {
+  if (!h || !kernel || !total_ms || !launches) return R1_EINVAL;
+  hipError_t e = h->timer.collect();
+  if (e != hipSuccess) return r1h::fail(h, e, "timing");
+  auto it = h->timer.acc.find(kernel);
+  *total_ms = it == h->timer.acc.end() ? 0.0 : it->second.first;
+  *launches = it == h->timer.acc.end() ? 0 : it->second.second;
+  return R1_OK;
+}
+
+r1_status r1_envelope(r1_handle h, const r1_material* mat, const r1_lamination* lam, int64_t n,
+                      r1_dtype dtype, const void* F, const void* beta_n, void* W, int32_t* flags,
+                      void* stream) {
+  return r1_envelope_stress(h, mat, lam, n, dtype, F, beta_n, W, nullptr, nullptr, flags, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,38 @@
+// Handle state and host helpers shared by the C-ABI translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+
+#include "r1.h"
+#include "r1_device.hpp"
+#include "r1_launch.hpp"
+
+struct BatchedPlan;
+
+struct r1_handle_s {
+  int device = 0;
+  std::string err;
+  std::map<uint64_t, void*> dirs;          // content hash -> device copy of a level's a, b
+  void* scratch = nullptr;                 // grow-only workspace (depth-2 partial results)
+  size_t scratch_bytes = 0;
+  std::map<int, int> seg_override;         // n_t -> lanes per line (user setting)
+  std::map<int64_t, int> seg_tuned;        // (n_t, dtype, dim) -> lanes per line (autotuner)
+  std::map<uint64_t, BatchedPlan*> plans;  // batched launches: plan + captured graph
+  KTimer timer;                            // optional per-kernel event timing
+};
+
+namespace r1h {
+r1_status fail(r1_handle h, hipError_t e, const char* what);
+r1_status check_material(const r1_material* m);
+r1_status check_level(const r1_level& lv);
+r1_status check_lamination(const r1_lamination* lam);
+r1_status device_level(r1_handle h, const r1_level& lv, int dim, r1d::Level* out);
+r1_status scratch(r1_handle h, size_t bytes, void** p);
+int samples_per_lane(int S, int n_t);
+int segment_width(r1_handle h, int n_t, int dtype, int dim);
+inline int64_t tune_key(int n_t, int dtype, int dim) { return (int64_t(n_t) << 8) | (dtype << 4) | dim; }
+void release_batched(r1_handle h);
+}  // namespace r1h

@@ -1,0 +1,344 @@
+// Kernels of the rank-one lamination path (gfx950), as templates; the
+// r1_kernels_<dtype>_<dim>d.hip units instantiate them.
+//
+//   k_depth1    one wavefront per point: W^1 (and its laminate stress) -- the
+//               min over directions of the line hulls at the centre.
+//   k_outer     depth 2, one workgroup per (point, outer direction): the outer
+//               line's samples are inner envelopes W^1(F + t_i R), computed by
+//               the block's waves into LDS; wave 0 then takes the outer hull.
+//   k_finalize  depth 2, one wavefront per point: min over outer directions,
+//               then the stress through the two-level lamination tree.
+//
+// Lamination is eq. 3.3 of arXiv 2211.14318 on the lines of Section 4.1; the
+// stress is eq. 5.2 (first case) evaluated as Algorithm 3 on a binary tree.
+#pragma once
+#include "r1_device.hpp"
+#include "r1_launch.hpp"
+
+namespace r1k {
+using namespace r1d;
+
+template <typename T>
+struct OuterRes {       // hull of one outer line at the centre
+  T h;
+  int mp, mq, capped;
+};
+static_assert(sizeof(OuterRes<float>) == 16 && sizeof(OuterRes<double>) == 24,
+              "r1_outer_res_bytes() must match OuterRes");
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+template <typename T, int D>
+__device__ __forceinline__ bool load_point(const KArgs& a, int64_t p, double* G, double& bn) {
+  const T* F = static_cast<const T*>(a.F);
+  bool fin = true;
+#pragma unroll
+  for (int k = 0; k < D * D; ++k) {
+    G[k] = double(F[int64_t(k) * a.n + p]);
+    fin = fin && isfinite(G[k]);
+  }
+  bn = double(static_cast<const T*>(a.beta_n)[p]);
+  return fin && isfinite(bn);
+}
+
+template <int D>
+__device__ __forceinline__ void line_point(const double* G, const Level& lv, int dir, double t, double* out) {
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) out[i * D + j] = G[i * D + j] + t * lv.a[dir * D + i] * lv.b[dir * D + j];
+}
+
+__device__ __forceinline__ double t_of(const Level& lv, int m) {   // t at offset m from the centre
+  return lv.tau * double(2 * m) / double(lv.n_t - 1);
+}
+
+// Inner envelope at G and its laminate stress (P^1 = xi P0(G+) + (1-xi) P0(G-)).
+template <typename T, int D, int S, int K>
+__device__ Env<T> envelope_with_stress(const KArgs& a, const Level& lv, const Layout<T, S, K>& lay,
+                                       double bn, const double* G, double* P) {
+  Point<T> q = make_point<T>(a.mat, bn);
+  double cof[D * D];
+  cofactor<D>(G, cof);
+  T wc = w_point<T, D>(q, G, cof);
+  Env<T> e = {wc, 0, 0, 0, 0};
+  if (wc < inf_v<T>()) e = envelope_at<T, D, S, K>(q, G, wc, lv, lay);
+  double Gm[D * D], Gp[D * D], Pm[D * D], Pp[D * D];
+  line_point<D>(G, lv, e.dir, -t_of(lv, e.mp), Gm);
+  line_point<D>(G, lv, e.dir, t_of(lv, e.mq), Gp);
+  stress0<D>(a.mat, bn, Gm, Pm);
+  stress0<D>(a.mat, bn, Gp, Pp);
+  double xi = (e.mp + e.mq) ? double(e.mp) / double(e.mp + e.mq) : 1.0;
+#pragma unroll
+  for (int k = 0; k < D * D; ++k) P[k] = xi * Pp[k] + (1.0 - xi) * Pm[k];
+  return e;
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void write_bad_point(const KArgs& a, int64_t p, bool nonfinite, bool want_p) {
+  T val = nonfinite ? T(__builtin_nan("")) : inf_v<T>();
+  static_cast<T*>(a.W)[p] = val;
+  if (want_p && a.P)
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) static_cast<T*>(a.P)[int64_t(k) * a.n + p] = T(__builtin_nan(""));
+  if (a.flags) a.flags[p] = nonfinite ? R1_PT_NONFINITE : R1_PT_DETLE0;
+  if (a.tree)
+    for (int k = 0; k < R1_TREE_NODES; ++k)
+      a.tree[p * R1_TREE_NODES + k] = r1_laminate{0, 0, 0, 1.0f};
+}
+
+template <typename T, int D, int S, int K>
+__global__ __launch_bounds__(256) void k_depth1(KArgs a) {
+  const int64_t p = int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (p >= a.n) return;                       // wave-uniform
+  const Level& lv = a.lv0;
+  double G[D * D], bn;
+  bool fin = load_point<T, D>(a, p, G, bn);
+  Layout<T, S, K> lay = make_layout<T, S, K>(lv.n_t, lv.tau);
+  Point<T> q = make_point<T>(a.mat, bn);
+  double cof[D * D];
+  cofactor<D>(G, cof);
+  T wc = w_point<T, D>(q, G, cof);
+  if (!fin || !(wc < inf_v<T>())) {
+    if (lane_id() == 0) write_bad_point<T, D>(a, p, !fin, a.want_stress);
+    return;
+  }
+  Env<T> e = envelope_at<T, D, S, K>(q, G, wc, lv, lay);
+  if (lane_id() == 0) {
+    static_cast<T*>(a.W)[p] = e.h;
+    const int c = (lv.n_t - 1) / 2;
+    if (a.want_stress && a.P) {
+      double Gm[D * D], Gp[D * D], Pm[D * D], Pp[D * D];
+      line_point<D>(G, lv, e.dir, -t_of(lv, e.mp), Gm);
+      line_point<D>(G, lv, e.dir, t_of(lv, e.mq), Gp);
+      stress0<D>(a.mat, bn, Gm, Pm);
+      stress0<D>(a.mat, bn, Gp, Pp);
+      double xi = (e.mp + e.mq) ? double(e.mp) / double(e.mp + e.mq) : 1.0;
+#pragma unroll
+      for (int k = 0; k < D * D; ++k)
+        static_cast<T*>(a.P)[int64_t(k) * a.n + p] = T(xi * Pp[k] + (1.0 - xi) * Pm[k]);
+    }
+    if (a.tree) {
+      float xi = (e.mp + e.mq) ? float(double(e.mp) / double(e.mp + e.mq)) : 1.0f;
+      a.tree[p * R1_TREE_NODES] = r1_laminate{e.dir, c - e.mp, c + e.mq, xi};
+      for (int k = 1; k < R1_TREE_NODES; ++k) a.tree[p * R1_TREE_NODES + k] = r1_laminate{0, 0, 0, 1.0f};
+    }
+    if (a.flags) a.flags[p] = e.capped ? R1_PT_ITERCAP : 0;
+  }
+}
+
+// Outer hull of an LDS-resident line (wave-wide, S = 64): wl[m-1] / wr[m-1] are
+// the samples at offsets -m / +m, m = 1..c.  Same search as hull_centre.
+template <typename T>
+__device__ LineHull<T> hull_centre_lds(const T* wl, const T* wr, int c, T wc) {
+  const int lane = lane_id();
+  Cand<T> p = {-inf_v<T>(), 0, T(0)};
+  T minR = inf_v<T>();
+  for (int m = 1 + lane; m <= c; m += kWave) {
+    T inv = T(1.0 / double(m));
+    Cand<T> cd = {(wc - wl[m - 1]) * inv, m, wl[m - 1]};
+    if (beats_max(cd, p)) p = cd;
+    minR = fmin(minR, (wr[m - 1] - wc) * inv);
+  }
+  p = seg_reduce<kWave, true>(p);
+  minR = seg_min<kWave>(minR);
+  LineHull<T> r = {wc, 0, 0, 0};
+  if (!(p.key >= minR)) return r;     // wave-uniform
+  Cand<T> q = {inf_v<T>(), 0, T(0)};
+  for (int it = 0; it < kBridgeCap; ++it) {
+    T nb = inf_v<T>(), db = T(1), wb = T(0);
+    int mb = 0;
+    for (int m = 1 + lane; m <= c; m += kWave) {
+      T num = wr[m - 1] - p.w, den = T(m + p.m);
+      bool take = num * db < nb * den || (num * db == nb * den && m > mb);
+      nb = take ? num : nb; db = take ? den : db; mb = take ? m : mb; wb = take ? wr[m - 1] : wb;
+    }
+    Cand<T> qc = {nb / db, mb, wb};
+    q = seg_reduce<kWave, false>(qc);
+    nb = -inf_v<T>(); db = T(1); wb = T(0); mb = 0;
+    for (int m = 1 + lane; m <= c; m += kWave) {
+      T num = q.w - wl[m - 1], den = T(q.m + m);
+      bool take = num * db > nb * den || (num * db == nb * den && m > mb);
+      nb = take ? num : nb; db = take ? den : db; mb = take ? m : mb; wb = take ? wl[m - 1] : wb;
+    }
+    Cand<T> pc = {nb / db, mb, wb};
+    pc = seg_reduce<kWave, true>(pc);
+    if (pc.m == p.m) {
+      r.h = (T(q.m) * p.w + T(p.m) * q.w) / T(q.m + p.m);
+      r.mp = p.m; r.mq = q.m;
+      return r;
+    }
+    p = pc;
+  }
+  r.h = (T(q.m) * p.w + T(p.m) * q.w) / T(q.m + p.m);
+  r.mp = p.m; r.mq = q.m; r.capped = 1;
+  return r;
+}
+
+template <typename T, int D, int S, int K>
+__global__ __launch_bounds__(256) void k_outer(KArgs a) {
+  extern __shared__ char smem_raw[];
+  T* wl = reinterpret_cast<T*>(smem_raw);
+  const int n_dir_o = a.lv0.n_dir;
+  const int64_t p = int64_t(blockIdx.x) / n_dir_o;
+  const int mo = int(int64_t(blockIdx.x) % n_dir_o);
+  const Level& lo = a.lv0;
+  const Level& li = a.lv1;
+  const int co = (lo.n_t - 1) / 2;
+  T* wr = wl + co;
+  __shared__ int capped_any;
+  OuterRes<T>* out = static_cast<OuterRes<T>*>(a.scratch_outer) + p * n_dir_o + mo;
+  T w1f = static_cast<const T*>(a.scratch_w1f)[p];
+  if (!(w1f < inf_v<T>())) {                  // det F <= 0 or non-finite input: block-uniform
+    if (threadIdx.x == 0) *out = OuterRes<T>{w1f, 0, 0, 0};
+    return;
+  }
+  double F[D * D], bn;
+  load_point<T, D>(a, p, F, bn);
+  if (threadIdx.x == 0) capped_any = 0;
+  __syncthreads();
+  Layout<T, S, K> lay = make_layout<T, S, K>(li.n_t, li.tau);
+  Point<T> q = make_point<T>(a.mat, bn);
+  const int wave = threadIdx.x / kWave, nwave = blockDim.x / kWave;
+  int capped = 0;
+  // outer samples, interleaved left/right so the waves share both sides
+  for (int s = wave; s < 2 * co; s += nwave) {
+    int m = 1 + (s >> 1);
+    double t = (s & 1) ? t_of(lo, m) : -t_of(lo, m);
+    double G[D * D], cof[D * D];
+    line_point<D>(F, lo, mo, t, G);
+    cofactor<D>(G, cof);
+    T wc = w_point<T, D>(q, G, cof);
+    T v = wc;
+    if (wc < inf_v<T>()) {
+      Env<T> e = envelope_at<T, D, S, K>(q, G, wc, li, lay);
+      v = e.h;
+      capped |= e.capped;
+    }
+    if (lane_id() == 0) ((s & 1) ? wr : wl)[m - 1] = v;
+  }
+  if (capped && lane_id() == 0) atomicOr(&capped_any, 1);
+  __syncthreads();
+  if (wave == 0) {
+    LineHull<T> r = hull_centre_lds<T>(wl, wr, co, w1f);
+    if (lane_id() == 0) *out = OuterRes<T>{r.h, r.mp, r.mq, r.capped | capped_any};
+  }
+}
+
+template <typename T, int D, int S, int K>
+__global__ __launch_bounds__(256) void k_finalize(KArgs a) {
+  const int64_t p = int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (p >= a.n) return;
+  const Level& lo = a.lv0;
+  const Level& li = a.lv1;
+  const int n_dir_o = lo.n_dir;
+  double F[D * D], bn;
+  bool fin = load_point<T, D>(a, p, F, bn);
+  T w1f = static_cast<const T*>(a.scratch_w1f)[p];
+  if (!fin || !(w1f < inf_v<T>())) {
+    if (lane_id() == 0) write_bad_point<T, D>(a, p, !fin, a.want_stress);
+    return;
+  }
+  const OuterRes<T>* res = static_cast<const OuterRes<T>*>(a.scratch_outer) + p * n_dir_o;
+  T bh = inf_v<T>();
+  int bd = 0x7fffffff, bp = 0, bq = 0, cap = 0;
+  for (int m = lane_id(); m < n_dir_o; m += kWave) {
+    OuterRes<T> r = res[m];
+    cap |= r.capped;
+    if (r.h < bh) { bh = r.h; bd = m; bp = r.mp; bq = r.mq; }
+  }
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    T oh = __shfl_xor(bh, off);
+    int od = __shfl_xor(bd, off), op = __shfl_xor(bp, off), oq = __shfl_xor(bq, off);
+    cap |= __shfl_xor(cap, off);
+    bool take = oh < bh || (oh == bh && od < bd);
+    bh = take ? oh : bh; bd = take ? od : bd; bp = take ? op : bp; bq = take ? oq : bq;
+  }
+  const int c = (lo.n_t - 1) / 2, ci = (li.n_t - 1) / 2;
+  r1_laminate node[3];
+  double Pout[D * D];
+  if (a.want_stress || a.tree) {
+    Layout<T, S, K> lay = make_layout<T, S, K>(li.n_t, li.tau);
+    double Gm[D * D], Gp[D * D], Pm[D * D], Pp[D * D];
+    line_point<D>(F, lo, bd, -t_of(lo, bp), Gm);
+    line_point<D>(F, lo, bd, t_of(lo, bq), Gp);
+    Env<T> em = envelope_with_stress<T, D, S, K>(a, li, lay, bn, Gm, Pm);
+    cap |= em.capped;
+    Env<T> ep = em;
+    if (bp + bq) {
+      ep = envelope_with_stress<T, D, S, K>(a, li, lay, bn, Gp, Pp);
+      cap |= ep.capped;
+    } else {
+#pragma unroll
+      for (int k = 0; k < D * D; ++k) Pp[k] = Pm[k];
+    }
+    double xi = (bp + bq) ? double(bp) / double(bp + bq) : 1.0;
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) Pout[k] = xi * Pp[k] + (1.0 - xi) * Pm[k];
+    node[0] = r1_laminate{bd, c - bp, c + bq, float(xi)};
+    node[1] = r1_laminate{em.dir, ci - em.mp, ci + em.mq,
+                          (em.mp + em.mq) ? float(double(em.mp) / double(em.mp + em.mq)) : 1.0f};
+    node[2] = r1_laminate{ep.dir, ci - ep.mp, ci + ep.mq,
+                          (ep.mp + ep.mq) ? float(double(ep.mp) / double(ep.mp + ep.mq)) : 1.0f};
+  }
+  if (lane_id() == 0) {
+    static_cast<T*>(a.W)[p] = bh;
+    if (a.want_stress && a.P)
+#pragma unroll
+      for (int k = 0; k < D * D; ++k) static_cast<T*>(a.P)[int64_t(k) * a.n + p] = T(Pout[k]);
+    if (a.tree)
+      for (int k = 0; k < R1_TREE_NODES; ++k) a.tree[p * R1_TREE_NODES + k] = node[k];
+    if (a.flags) a.flags[p] = cap ? R1_PT_ITERCAP : 0;
+  }
+}
+
+// ---- dispatch ------------------------------------------------------------------
+
+template <typename T, int D, int S, int K>
+hipError_t launch_T(const KArgs& a, int depth, hipStream_t st, KTimer* tm) {
+  dim3 blk(256);
+  unsigned per = 256 / kWave;
+  if (depth == 1) {
+    dim3 grd(unsigned((a.n + per - 1) / per));
+    if (tm) tm->begin("depth1", st);
+    hipLaunchKernelGGL((k_depth1<T, D, S, K>), grd, blk, 0, st, a);
+    if (tm) tm->end(st);
+    return hipGetLastError();
+  }
+  // depth 2: W^1 at every point (the outer lines' centre), outer lines, finalize
+  KArgs pre = a;
+  pre.lv0 = a.lv1;
+  pre.W = a.scratch_w1f;
+  pre.P = nullptr;
+  pre.tree = nullptr;
+  pre.flags = nullptr;
+  pre.want_stress = 0;
+  dim3 grd(unsigned((a.n + per - 1) / per));
+  if (tm) tm->begin("depth2_centre", st);
+  hipLaunchKernelGGL((k_depth1<T, D, S, K>), grd, blk, 0, st, pre);
+  if (tm) tm->end(st);
+  size_t lds = sizeof(T) * size_t(a.lv0.n_t - 1);
+  dim3 grd_o(unsigned(a.n * a.lv0.n_dir));
+  if (tm) tm->begin("outer", st);
+  hipLaunchKernelGGL((k_outer<T, D, S, K>), grd_o, blk, lds, st, a);
+  if (tm) tm->end(st);
+  if (tm) tm->begin("finalize", st);
+  hipLaunchKernelGGL((k_finalize<T, D, S, K>), grd, blk, 0, st, a);
+  if (tm) tm->end(st);
+  return hipGetLastError();
+}
+
+template <typename T, int D>
+hipError_t launch_TD(const KArgs& a, int depth, int S, int K, hipStream_t st, KTimer* tm) {
+#define R1_CASE(SS, KK) \
+  if (S == SS && K == KK) return launch_T<T, D, SS, KK>(a, depth, st, tm);
+  R1_CASE(8, 2) R1_CASE(8, 4) R1_CASE(8, 8) R1_CASE(8, 16) R1_CASE(8, 32)
+  R1_CASE(16, 2) R1_CASE(16, 4) R1_CASE(16, 8) R1_CASE(16, 16) R1_CASE(16, 32)
+  R1_CASE(32, 2) R1_CASE(32, 4) R1_CASE(32, 8) R1_CASE(32, 16) R1_CASE(32, 32)
+  R1_CASE(64, 2) R1_CASE(64, 4) R1_CASE(64, 8) R1_CASE(64, 16) R1_CASE(64, 32)
+#undef R1_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace r1k

@@ -1,0 +1,6 @@
+// Instantiation of the lamination kernels for double, 3x3 gradients.
+#include "r1_kernels.hpp"
+
+hipError_t r1_launch_f64_3d(const KArgs& a, int depth, int S, int K, hipStream_t st, KTimer* tm) {
+  return r1k::launch_TD<double, 3>(a, depth, S, K, st, tm);
+}

@@ -1,0 +1,70 @@
+// Launch interface between the host C-ABI (r1_api.cpp) and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "r1.h"
+#include "r1_device.hpp"
+
+struct KArgs {
+  int64_t n;
+  const void* F;          // T[(d*d) * n], SoA
+  const void* beta_n;     // T[n]
+  void* W;                // T[n]
+  void* P;                // T[(d*d) * n] or null
+  r1_laminate* tree;      // [n * R1_TREE_NODES] or null
+  int32_t* flags;         // [n] or null
+  r1d::Material mat;
+  r1d::Level lv0;         // outermost (or only) level
+  r1d::Level lv1;         // inner level (depth 2)
+  int want_stress;
+  void* scratch_w1f;      // depth 2: T[n], W^1 at each point
+  void* scratch_outer;    // depth 2: per (point, outer direction) hull result
+};
+
+// Per-kernel timing with HIP events recorded on the launch stream (off by default).
+struct KTimer {
+  bool on = false;
+  struct Rec {
+    const char* name;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> pending;
+  std::map<std::string, std::pair<double, int64_t>> acc;   // name -> (total ms, launches)
+  void begin(const char* name, hipStream_t st) {
+    if (!on) return;
+    Rec r{name, nullptr, nullptr};
+    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
+    (void)hipEventRecord(r.a, st);
+    pending.push_back(r);
+  }
+  void end(hipStream_t st) {
+    if (!on || pending.empty()) return;
+    (void)hipEventRecord(pending.back().b, st);
+  }
+  hipError_t collect() {
+    hipError_t err = hipSuccess;
+    for (auto& r : pending) {
+      hipError_t e = hipEventSynchronize(r.b);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+      if (e != hipSuccess) err = e;
+      auto& x = acc[r.name];
+      x.first += ms;
+      x.second += 1;
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    pending.clear();
+    return err;
+  }
+};
+
+// depth 1 or 2; S = lanes per line of the innermost level, K = samples per lane.
+hipError_t r1_launch_envelope(const KArgs& a, int depth, int dtype, int S, int K, hipStream_t st,
+                              KTimer* tm);
+size_t r1_outer_res_bytes(int dtype);

@@ -1,0 +1,232 @@
+"""Thin ctypes binding of libr1.so (C-ABI in include/r1.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library.  Tensors are PyTorch device tensors (PyTorch is used
+for device memory and streams); outputs are allocated here with torch and
+filled by the library.  Importing this module fails loudly when the library
+has not been built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libr1.so")
+
+R1_OK = 0
+R1_F32, R1_F64 = 0, 1
+R1_NEOHOOKE_DAMAGE, R1_TEST_DOUBLEWELL = 0, 1
+PT_DETLE0, PT_NONFINITE, PT_FALLBACK, PT_ITERCAP = 1, 2, 4, 8
+TREE_NODES = 3
+
+
+class R1Error(RuntimeError):
+    def __init__(self, status, what, detail=""):
+        super().__init__("%s failed: %s (%d)%s" % (what, _status_string(status), status,
+                                                   (": " + detail) if detail else ""))
+        self.status = status
+
+
+class Material(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("model", ctypes.c_int32), ("mu", ctypes.c_double),
+                ("lam", ctypes.c_double), ("D_inf", ctypes.c_double), ("D0", ctypes.c_double)]
+
+
+class Level(ctypes.Structure):
+    _fields_ = [("n_dir", ctypes.c_int32), ("a", ctypes.POINTER(ctypes.c_double)),
+                ("b", ctypes.POINTER(ctypes.c_double)), ("n_t", ctypes.c_int32),
+                ("tau", ctypes.c_double)]
+
+
+class Lamination(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_int32), ("level", Level * 2)]
+
+
+class Laminate(ctypes.Structure):
+    _fields_ = [("dir", ctypes.c_int32), ("i_minus", ctypes.c_int32), ("i_plus", ctypes.c_int32),
+                ("xi", ctypes.c_float)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libr1.so is not built (%s); run __graft_entry__.build() or "
+                          "python -m paper_2211_14318_amd.build" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.r1_create.argtypes = [ctypes.POINTER(vp), i32]
+    L.r1_destroy.argtypes = [vp]
+    L.r1_status_string.restype = ctypes.c_char_p
+    L.r1_status_string.argtypes = [i32]
+    L.r1_last_error.restype = ctypes.c_char_p
+    L.r1_last_error.argtypes = [vp]
+    L.r1_envelope.argtypes = [vp, ctypes.POINTER(Material), ctypes.POINTER(Lamination), i64, i32,
+                              vp, vp, vp, vp, vp]
+    L.r1_envelope_stress.argtypes = [vp, ctypes.POINTER(Material), ctypes.POINTER(Lamination), i64,
+                                     i32, vp, vp, vp, vp, vp, vp, vp]
+    L.r1_envelope_batched.argtypes = [vp, ctypes.POINTER(Material), ctypes.POINTER(Lamination), i32,
+                                      i64, vp, i32, vp, vp, vp, vp, vp, vp, vp]
+    L.r1_set_segment_width.argtypes = [vp, i32, i32]
+    L.r1_get_segment_width.argtypes = [vp, i32, i32, i32, ctypes.POINTER(i32)]
+    L.r1_timing_enable.argtypes = [vp, i32]
+    L.r1_timing_reset.argtypes = [vp]
+    L.r1_timing_query.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(i64)]
+    for name in ("r1_timing_enable", "r1_timing_reset", "r1_timing_query", "r1_create", "r1_destroy", "r1_envelope", "r1_envelope_stress",
+                 "r1_envelope_batched", "r1_set_segment_width", "r1_get_segment_width"):
+        getattr(L, name).restype = i32
+    return L
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _status_string(s):
+    return _lib.r1_status_string(int(s)).decode()
+
+
+def material(dim=2, model=R1_NEOHOOKE_DAMAGE, mu=1.0, lam=2.0, D_inf=0.99, D0=0.1):
+    return Material(dim, model, mu, lam, D_inf, D0)
+
+
+def material_from(d, dim, model=R1_NEOHOOKE_DAMAGE):
+    return Material(dim, model, d["mu"], d["lam"], d["D_inf"], d["D0"])
+
+
+class LaminationSpec:
+    """levels: list of dicts {a, b, n_t, tau} (outermost first); keeps arrays alive."""
+
+    def __init__(self, levels):
+        self._keep = []
+        self.c = Lamination()
+        self.c.depth = len(levels)
+        for k, lv in enumerate(levels):
+            a = np.ascontiguousarray(lv["a"], dtype=np.float64)
+            b = np.ascontiguousarray(lv["b"], dtype=np.float64)
+            self._keep += [a, b]
+            self.c.level[k] = Level(a.shape[0], a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    int(lv["n_t"]), float(lv["tau"]))
+        self.levels = levels
+        self.depth = len(levels)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Handle:
+    """One library handle bound to a device (not thread-safe)."""
+
+    def __init__(self, device=0):
+        import torch
+        self.torch = torch
+        self.device = device
+        h = ctypes.c_void_p()
+        self._check(_lib.r1_create(ctypes.byref(h), int(device)), "r1_create", use_err=False)
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.r1_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, s, what, use_err=True):
+        if s != R1_OK:
+            detail = _lib.r1_last_error(self.h).decode() if use_err and getattr(self, "h", None) else ""
+            raise R1Error(s, what, detail)
+
+    def _stream(self, stream):
+        if stream is None:
+            stream = self.torch.cuda.current_stream(self.device)
+        return ctypes.c_void_p(stream.cuda_stream)
+
+    def set_segment_width(self, n_t, lanes):
+        self._check(_lib.r1_set_segment_width(self.h, int(n_t), int(lanes)), "r1_set_segment_width")
+
+    def segment_width(self, n_t, dtype, dim):
+        out = ctypes.c_int32()
+        self._check(_lib.r1_get_segment_width(self.h, int(n_t), int(dtype), int(dim),
+                                              ctypes.byref(out)), "r1_get_segment_width")
+        return out.value
+
+    def timing(self, on=True):
+        self._check(_lib.r1_timing_enable(self.h, int(bool(on))), "r1_timing_enable")
+
+    def timing_reset(self):
+        self._check(_lib.r1_timing_reset(self.h), "r1_timing_reset")
+
+    def timing_query(self, kernel):
+        ms, cnt = ctypes.c_double(), ctypes.c_int64()
+        self._check(_lib.r1_timing_query(self.h, kernel.encode(), ctypes.byref(ms), ctypes.byref(cnt)),
+                    "r1_timing_query")
+        return ms.value, cnt.value
+
+    def _dtype_code(self, t):
+        if t.dtype == self.torch.float32:
+            return R1_F32
+        if t.dtype == self.torch.float64:
+            return R1_F64
+        raise TypeError("F must be float32 or float64")
+
+    def envelope(self, mat, spec, F, beta_n, stress=True, tree=False, flags=True, stream=None):
+        """F: (d*d, n) device tensor (SoA), beta_n: (n,).  Returns dict of device tensors."""
+        torch = self.torch
+        n = F.shape[1]
+        d = mat.dim
+        assert F.shape[0] == d * d and F.is_contiguous() and beta_n.is_contiguous()
+        assert beta_n.shape == (n,) and beta_n.dtype == F.dtype
+        dt = self._dtype_code(F)
+        dev = F.device
+        W = torch.empty(n, dtype=F.dtype, device=dev)
+        P = torch.empty((d * d, n), dtype=F.dtype, device=dev) if stress else None
+        T = torch.empty((n, TREE_NODES, 4), dtype=torch.int32, device=dev) if tree else None
+        fl = torch.empty(n, dtype=torch.int32, device=dev) if flags else None
+        self._check(_lib.r1_envelope_stress(self.h, ctypes.byref(mat), ctypes.byref(spec.c), n, dt,
+                                            _ptr(F), _ptr(beta_n), _ptr(W), _ptr(P), _ptr(T),
+                                            _ptr(fl), self._stream(stream)),
+                    "r1_envelope_stress")
+        return dict(W=W, P=P, tree=T, flags=fl)
+
+    def envelope_into(self, mat, spec, F, beta_n, W, P=None, tree=None, flags=None, stream=None):
+        """Same, writing into caller-provided tensors (no allocation)."""
+        dt = self._dtype_code(F)
+        self._check(_lib.r1_envelope_stress(self.h, ctypes.byref(mat), ctypes.byref(spec.c),
+                                            F.shape[1], dt, _ptr(F), _ptr(beta_n), _ptr(W),
+                                            _ptr(P), _ptr(tree), _ptr(flags),
+                                            self._stream(stream)),
+                    "r1_envelope_stress")
+
+    def envelope_batched(self, mat, table_specs, lam_idx, F, beta_n, stress=False, tree=False,
+                         flags=True, stream=None):
+        torch = self.torch
+        n = F.shape[1]
+        d = mat.dim
+        dt = self._dtype_code(F)
+        arr = (Lamination * len(table_specs))(*[s.c for s in table_specs])
+        dev = F.device
+        W = torch.empty(n, dtype=F.dtype, device=dev)
+        P = torch.empty((d * d, n), dtype=F.dtype, device=dev) if stress else None
+        T = torch.empty((n, TREE_NODES, 4), dtype=torch.int32, device=dev) if tree else None
+        fl = torch.empty(n, dtype=torch.int32, device=dev) if flags else None
+        self._check(_lib.r1_envelope_batched(self.h, ctypes.byref(mat), arr, len(table_specs), n,
+                                             _ptr(lam_idx), dt, _ptr(F), _ptr(beta_n), _ptr(W),
+                                             _ptr(P), _ptr(T), _ptr(fl), self._stream(stream)),
+                    "r1_envelope_batched")
+        return dict(W=W, P=P, tree=T, flags=fl)
+
+
+def tree_view(T):
+    """(n, 3, 4) int32 tree tensor -> numpy arrays dir, i_minus, i_plus (int) and xi (float32)."""
+    a = T.cpu().numpy()
+    return a[..., 0], a[..., 1], a[..., 2], a[..., 3].view(np.float32)

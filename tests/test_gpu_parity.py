@@ -1,0 +1,186 @@
+"""GPU path (libr1 through its C-ABI) against the FP64 oracle, element by element."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2211_14318_amd import workloads as WL
+from tests import parity as PA
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_14318_amd import r1
+    h = r1.Handle(0)
+    yield r1, h, torch
+    h.close()
+
+
+def run_gpu(lib, cfg, kind, stress=True, tree=True, model=0, lanes=None):
+    r1, h, torch = lib
+    dt = torch.float64 if kind == "f64" else torch.float32
+    mat = r1.material_from(cfg["material"], cfg["dim"], model)
+    spec = r1.LaminationSpec(cfg["levels"])
+    if lanes is not None:
+        h.set_segment_width(cfg["levels"][-1]["n_t"], lanes)
+    F = torch.tensor(cfg["F"], dtype=dt, device="cuda").contiguous()
+    bn = torch.tensor(cfg["beta_n"], dtype=dt, device="cuda").contiguous()
+    out = h.envelope(mat, spec, F, bn, stress=stress, tree=tree)
+    torch.cuda.synchronize()
+    if lanes is not None:
+        h.set_segment_width(cfg["levels"][-1]["n_t"], 0)
+    res = {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+    # the oracle sees exactly the values the GPU was given
+    res["F_in"] = F.double().cpu().numpy()
+    res["bn_in"] = bn.double().cpu().numpy()
+    return res
+
+
+def run_oracle(cfg, F, bn, model=0, want_tree=True):
+    mat = PA.orc_material(cfg["material"], cfg["dim"], model)
+    spec = PA.orc_spec(cfg["levels"])
+    W, P, trees = O.envelope_batch(mat, spec, F, bn, want_stress=True, want_tree=want_tree)
+    return mat, spec, W, P, trees
+
+
+def check_case(lib, cfg, kind, model=0, lanes=None, min_exact=1):
+    g = run_gpu(lib, cfg, kind, model=model, lanes=lanes)
+    mat, spec, W, P, trees = run_oracle(cfg, g["F_in"], g["bn_in"], model)
+    err = PA.energy_errors(g["W"], W, kind)
+    fin = np.isfinite(W)
+    print("%s %s lanes=%s: max rel err %.3e (p99 %.3e), max abs err %.3e, paper E_rel max %.3e, "
+          "min |W| %.2e" % (cfg["name"], kind, lanes, err.max(), np.percentile(err, 99),
+                           np.max(np.abs(g["W"][fin] - W[fin])), PA.paper_erel(g["W"], W).max(),
+                           np.min(np.abs(W[fin]))))
+    assert err.max() <= PA.RTOL[kind], err.max()
+    depth = len(cfg["levels"])
+    ne, nt = PA.check_stress(mat, spec, depth, g["F_in"], g["bn_in"], W, P, trees, g["P"], g["tree"], kind)
+    print("   stress: %d exact, %d tie-checked" % (ne, nt))
+    assert ne >= min_exact
+    fl = g["flags"]
+    assert np.all((fl & 1) == (~np.isfinite(W)).astype(np.int32) * 1)
+    return g, W
+
+
+# ---------------------------------------------------------------- depth 1
+
+def test_config1_fp64_full(lib):
+    """64 points, 16 directions x 201 points, tau 1, depth 1, FP64 (the small workload in full)."""
+    check_case(lib, WL.config1(), "f64", min_exact=40)
+
+
+def test_config1_fp32_full(lib):
+    cfg = WL.config1()
+    check_case(lib, cfg, "f32", min_exact=40)
+
+
+@pytest.mark.parametrize("lanes", [8, 16, 32, 64])
+@pytest.mark.parametrize("n_t", [41, 201, 257])
+def test_depth1_segment_widths_and_ragged_grids(lib, lanes, n_t):
+    r1 = lib[0]
+    if n_t == 257 and lanes == 8:
+        pass
+    K_needed = (n_t - 1) / 2 / lanes
+    if K_needed > 16:
+        pytest.skip("more than 32 samples per lane")
+    cfg = WL.small_random(2, 37, (4, 4), n_t, tau=1.2, seed_tag=200 + n_t)
+    check_case(lib, cfg, "f64", lanes=lanes, min_exact=15)
+
+
+@pytest.mark.parametrize("kind", ["f64", "f32"])
+def test_depth1_3d(lib, kind):
+    cfg = WL.small_random(3, 19, (4, 4), 65, tau=1.0, seed_tag=300, sigma=0.2, det_min=0.2)
+    check_case(lib, cfg, kind, min_exact=8)
+
+
+def test_depth1_many_directions_ragged_count(lib):
+    """n_dir not a multiple of the lines per wavefront; large n_t (2049) at 64 lanes."""
+    cfg = WL.small_random(2, 9, (5, 3), 2049, tau=1.0, seed_tag=301)
+    check_case(lib, cfg, "f64", min_exact=4)
+
+
+def test_double_well_closed_form_on_gpu(lib):
+    """GPU envelope of the double-well test energy equals phi**(F11) + the convex rest."""
+    r1, h, torch = lib
+    rng = np.random.default_rng(5)
+    n = 50
+    F = np.zeros((4, n))
+    F[0] = np.round(rng.uniform(-0.9, 0.9, n), 1)
+    F[1] = rng.normal(0, 0.3, n)
+    F[2] = rng.normal(0, 0.3, n)
+    F[3] = 1 + rng.normal(0, 0.3, n)
+    a, b = WL.angle_directions(4, 4)
+    cfg = dict(name="doublewell", dim=2, material=WL.MATERIAL, F=F, beta_n=np.zeros(n),
+               levels=[WL.level(a, b, 41, 2.0)])
+    g = run_gpu(lib, cfg, "f64", model=1)
+    rest = F[1] ** 2 + F[2] ** 2 + (F[3] - 1) ** 2
+    assert np.max(np.abs(g["W"] - rest)) < 1e-13
+    assert np.max(np.abs(g["P"][0])) < 1e-12
+
+
+# ---------------------------------------------------------------- depth 2
+
+@pytest.mark.parametrize("kind", ["f64", "f32"])
+def test_depth2_small(lib, kind):
+    cfg = WL.small_random(2, 24, (4, 4), 65, tau=1.5, depth=2, inner=(4, 2, 33), seed_tag=400)
+    check_case(lib, cfg, kind, min_exact=10)
+
+
+def test_depth2_3d_small(lib):
+    cfg = WL.small_random(3, 6, (2, 2), 17, tau=1.0, depth=2, inner=(2, 2, 9), seed_tag=401,
+                          sigma=0.2, det_min=0.2)
+    check_case(lib, cfg, "f64", min_exact=2)
+
+
+# ---------------------------------------------------------------- edge cases
+
+def test_edge_points_and_minimum_grid(lib):
+    """det F <= 0 -> +inf and flag; NaN input -> NaN and flag; n_t = 3; one direction."""
+    r1, h, torch = lib
+    F = np.array([[1.0, 0.0, 0.0, -0.5], [1.1, 0.1, 0.0, 0.9], [np.nan, 0, 0, 1], [0.7, 0, 0, 0.7]]).T.copy()
+    a, b = WL.angle_directions(1, 1)
+    cfg = dict(name="edge", dim=2, material=WL.MATERIAL, F=F, beta_n=np.array([0.0, 0.1, 0.0, 0.2]),
+               levels=[WL.level(a, b, 3, 0.5)])
+    g = run_gpu(lib, cfg, "f64")
+    assert g["W"][0] == math.inf and g["flags"][0] == r1.PT_DETLE0 and np.all(np.isnan(g["P"][:, 0]))
+    assert np.isnan(g["W"][2]) and g["flags"][2] == r1.PT_NONFINITE
+    mat, spec, W, P, _ = run_oracle(cfg, np.nan_to_num(F, nan=1.0), cfg["beta_n"])
+    for p in (1, 3):
+        assert abs(g["W"][p] - W[p]) <= 1e-12 * max(abs(W[p]), 1e-3)
+
+
+def test_empty_batch_and_invalid_arguments(lib):
+    r1, h, torch = lib
+    mat = r1.material()
+    a, b = WL.angle_directions(2, 2)
+    spec = r1.LaminationSpec([WL.level(a, b, 9, 1.0)])
+    F = torch.zeros((4, 0), dtype=torch.float64, device="cuda")
+    bn = torch.zeros(0, dtype=torch.float64, device="cuda")
+    out = h.envelope(mat, spec, F, bn)
+    assert out["W"].numel() == 0
+    bad = r1.LaminationSpec([WL.level(a, b, 9, 1.0)])
+    bad.c.level[0].n_t = 10          # even grid
+    F1 = torch.eye(2, dtype=torch.float64, device="cuda").reshape(4, 1).contiguous()
+    bn1 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    with pytest.raises(r1.R1Error) as e:
+        h.envelope(mat, bad, F1, bn1)
+    assert e.value.status == -1
+    bad.c.level[0].n_t = 9
+    bad.c.depth = 3
+    with pytest.raises(r1.R1Error):
+        h.envelope(mat, bad, F1, bn1)
+    with pytest.raises(r1.R1Error):
+        h.set_segment_width(9, 12)
+
+
+def test_deterministic_across_runs(lib):
+    cfg = WL.small_random(2, 64, (4, 4), 129, tau=1.0, seed_tag=500)
+    g1 = run_gpu(lib, cfg, "f32")
+    g2 = run_gpu(lib, cfg, "f32")
+    assert np.array_equal(g1["W"], g2["W"]) and np.array_equal(g1["P"], g2["P"])
