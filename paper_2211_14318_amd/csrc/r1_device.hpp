@@ -32,9 +32,10 @@ template <typename T> __device__ __forceinline__ T inf_v();
 template <> __device__ __forceinline__ float inf_v<float>() { return __builtin_inff(); }
 template <> __device__ __forceinline__ double inf_v<double>() { return __builtin_inf(); }
 
-// Natural logarithm: hardware log2 for FP32 (v_log_f32), the device library for FP64.
-__device__ __forceinline__ float ln_t(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945309f; }
-__device__ __forceinline__ double ln_t(double x) { return log(x); }
+// Logarithm used by W: FP32 takes the hardware log2 (v_log_f32) and carries
+// ln 2 in the coefficients; FP64 takes the device library's natural log.
+__device__ __forceinline__ float lg_t(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ double lg_t(double x) { return log(x); }
 // Exponential of an argument pre-scaled by the per-point constant kexp:
 // FP32 uses the hardware exp2 (kexp carries log2 e), FP64 the device library.
 __device__ __forceinline__ float expk(float x) { return __builtin_amdgcn_exp2f(x); }
@@ -52,32 +53,37 @@ struct Level {           // one lamination level on the device
   double tau;
 };
 
-// Per-point constants of W (eq. 2.9 written as a function of psi0):
+// Per-point constants of W (eq. 2.9 written as a function of psi0).  With
+// D_n = D(beta_n):
 //   psi0 <= beta_n :  W = (1 - D_n) psi0
 //   psi0 >  beta_n :  W = psi0 - D_n beta_n - D_inf[(psi0 - beta_n) + D0 (e^{-psi0/D0} - e^{-beta_n/D0})]
-//                       = A psi0 + B - C e^{-psi0/D0}
-// with A = 1 - D_inf, C = D_inf D0, B = D_inf e^{-beta_n/D0} (beta_n + D0).
+// Both branches are  W = E1 psi0 + h(max(psi0, beta_n))  with E1 = 1 - D_n and
+//   h(m) = (D_n - D_inf) m + B - C e^{-m/D0},  B = D_inf e^{-beta_n/D0}(beta_n + D0),  C = D_inf D0,
+// because h(beta_n) = 0: one formula, no branch.  psi0 = mu/2 s - mu L + lambda/2 L^2 with
+// L = ln J; in FP32 the log is log2 and kmu = mu ln2, klam = lambda/2 ln2^2.
 template <typename T>
 struct Point {
-  T mu2, mu, lam2;
-  T bn, E1, A, B, C, kexp;
+  T mu2, kmu, klam;
+  T bn, E1, Aq, B, negC, kexp;
   int model;
 };
 
 template <typename T>
 __device__ __forceinline__ Point<T> make_point(const Material& m, double bn) {
   Point<T> q;
+  const bool f32 = sizeof(T) == 4;
+  const double ln2 = 0.6931471805599453094;
   double e = exp(-bn / m.D0);
   double Dn = m.D_inf * (1.0 - e);
   q.mu2 = T(0.5 * m.mu);
-  q.mu = T(m.mu);
-  q.lam2 = T(0.5 * m.lambda);
+  q.kmu = T(f32 ? m.mu * ln2 : m.mu);
+  q.klam = T(f32 ? 0.5 * m.lambda * ln2 * ln2 : 0.5 * m.lambda);
   q.bn = T(bn);
   q.E1 = T(1.0 - Dn);
-  q.A = T(1.0 - m.D_inf);
-  q.C = T(m.D_inf * m.D0);
+  q.Aq = T(Dn - m.D_inf);
+  q.negC = T(-m.D_inf * m.D0);
   q.B = T(m.D_inf * e * (bn + m.D0));
-  q.kexp = (sizeof(T) == 4) ? T(-1.4426950408889634 / m.D0) : T(-1.0 / m.D0);
+  q.kexp = f32 ? T(-1.4426950408889634 / m.D0) : T(-1.0 / m.D0);
   q.model = m.model;
   return q;
 }
@@ -150,16 +156,18 @@ __device__ __forceinline__ Line<T> line_setup(int model, const double* G, const 
   return L;
 }
 
-// One sample of W on a line (the hot loop: 1 log + 1 exp + ~12 VALU).
+// One sample of W on a line (the hot loop: 12 VALU + 2 transcendental).
+// det <= 0 gives NaN (J < 0) or NaN/+inf (J = 0): such samples lie outside the
+// admissible interval and every hull comparison below treats NaN as absent.
 template <typename T>
 __device__ __forceinline__ T w_sample(T t, const Line<T>& L, const Point<T>& q) {
   T J = fma(t, L.J1, L.J0);
   T s = fma(t, fma(t, L.c2, L.c1), L.c0);
-  T lnJ = ln_t(J);
-  T psi = fma(q.mu2, s, lnJ * fma(q.lam2, lnJ, -q.mu));
-  T wd = fma(q.A, psi, q.B) - q.C * expk(psi * q.kexp);
-  T w = psi <= q.bn ? q.E1 * psi : wd;
-  return J > T(0) ? w : inf_v<T>();
+  T lj = lg_t(J);
+  T psi = fma(q.mu2, s, lj * fma(q.klam, lj, -q.kmu));
+  T m = fmax(psi, q.bn);
+  T h = fma(q.negC, expk(m * q.kexp), fma(q.Aq, m, q.B));
+  return fma(q.E1, psi, h);
 }
 
 template <typename T>
@@ -178,46 +186,70 @@ __device__ __forceinline__ T w_point(const Point<T>& q, const double* G, const d
 }
 
 // ---- segment reductions ------------------------------------------------------
+//
+// Reductions over a segment of S lanes run as butterflies.  Steps 1 and 2 use
+// DPP quad permutations, steps 4 and 8 the DPP half-row / row mirrors (valid for
+// idempotent reductions once the previous steps have made each quad / half-row
+// uniform), steps 16 and 32 a lane shuffle.
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
+template <int STEP>
+__device__ __forceinline__ int partner_i(int v) {
+  if constexpr (STEP == 1) return dpp_i<0xB1>(v);          // quad_perm [1,0,3,2]
+  else if constexpr (STEP == 2) return dpp_i<0x4E>(v);     // quad_perm [2,3,0,1]
+  else if constexpr (STEP == 4) return dpp_i<0x141>(v);    // row_half_mirror
+  else if constexpr (STEP == 8) return dpp_i<0x140>(v);    // row_mirror
+  else return __shfl_xor(v, STEP, kWave);
+}
+
+template <int STEP>
+__device__ __forceinline__ float partner(float v) { return __int_as_float(partner_i<STEP>(__float_as_int(v))); }
+template <int STEP>
+__device__ __forceinline__ int partner(int v) { return partner_i<STEP>(v); }
+template <int STEP>
+__device__ __forceinline__ double partner(double v) {
+  long long b = __double_as_longlong(v);
+  int lo = partner_i<STEP>(int(b & 0xffffffffll));
+  int hi = partner_i<STEP>(int(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+template <int S, int STEP = 1, typename T>
+__device__ __forceinline__ T seg_max(T v) {
+  if constexpr (STEP < S) return seg_max<S, 2 * STEP>(fmax(v, partner<STEP>(v)));
+  else return v;
+}
+template <int S, int STEP = 1, typename T>
+__device__ __forceinline__ T seg_min(T v) {
+  if constexpr (STEP < S) return seg_min<S, 2 * STEP>(fmin(v, partner<STEP>(v)));
+  else return v;
+}
 
 template <typename T>
-struct Cand {      // a hull candidate: key (a slope or value), offset magnitude m, sample value w
+struct Cand {      // a hull candidate: key (a slope), offset magnitude m, sample value w
   T key;
   int m;
   T w;
 };
 
-// argmax of key, ties -> larger m (the outermost sample)
-template <typename T>
-__device__ __forceinline__ bool beats_max(const Cand<T>& x, const Cand<T>& y) {
-  return x.key > y.key || (x.key == y.key && x.m > y.m);
-}
-// argmin of key, ties -> larger m
-template <typename T>
-__device__ __forceinline__ bool beats_min(const Cand<T>& x, const Cand<T>& y) {
-  return x.key < y.key || (x.key == y.key && x.m > y.m);
-}
-
-template <int S, bool MAX, typename T>
-__device__ __forceinline__ Cand<T> seg_reduce(Cand<T> c) {
-#pragma unroll
-  for (int off = S / 2; off >= 1; off >>= 1) {
-    Cand<T> o;
-    o.key = __shfl_xor(c.key, off, S);
-    o.m = __shfl_xor(c.m, off, S);
-    o.w = __shfl_xor(c.w, off, S);
-    bool take = MAX ? beats_max(o, c) : beats_min(o, c);
+// argmax (MAX) or argmin of key over the segment; ties -> larger m (outermost sample)
+template <int S, bool MAX, int STEP = 1, typename T>
+__device__ __forceinline__ Cand<T> seg_arg(Cand<T> c) {
+  if constexpr (STEP < S) {
+    Cand<T> o = {partner<STEP>(c.key), partner<STEP>(c.m), partner<STEP>(c.w)};
+    bool better = MAX ? (o.key > c.key) : (o.key < c.key);
+    bool take = better || (o.key == c.key && o.m > c.m);
     c.key = take ? o.key : c.key;
     c.m = take ? o.m : c.m;
     c.w = take ? o.w : c.w;
+    return seg_arg<S, MAX, 2 * STEP>(c);
+  } else {
+    return c;
   }
-  return c;
-}
-
-template <int S, typename T>
-__device__ __forceinline__ T seg_min(T v) {
-#pragma unroll
-  for (int off = S / 2; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off, S));
-  return v;
 }
 
 // Result of one line: hull value at the centre and the bracketing vertices as
@@ -229,65 +261,96 @@ struct LineHull {
   int capped;
 };
 
-// Hull of the segment's line at its centre.  w: this lane's samples (layout
-// above); wc: centre sample; inv_m[h] = 1/m_h; mf[h] = m_h as T.  Every lane
-// of the wave must call this together (it uses cross-lane shuffles).
+// Per-lane constants of a line layout: offsets m_h = 1 + sl + S*h and t_h = tau*2m/(n_t-1)
+// of the lane's sample pairs, 1/m_h and m_h as T.
 template <typename T, int S, int K>
-__device__ __forceinline__ LineHull<T> hull_centre(const T (&w)[K], T wc, const T (&inv_m)[K / 2],
-                                                   const int (&mi)[K / 2]) {
+struct Layout {
+  T t[K / 2];
+  T inv_m[K / 2];
+  T mf[K / 2];
+  int c;
+};
+
+template <typename T, int S, int K>
+__device__ __forceinline__ Layout<T, S, K> make_layout(int n_t, double tau) {
+  Layout<T, S, K> lay;
+  int sl = threadIdx.x & (S - 1);
+  lay.c = (n_t - 1) / 2;
+#pragma unroll
+  for (int h = 0; h < K / 2; ++h) {
+    int m = 1 + sl + S * h;
+    lay.mf[h] = T(m);
+    lay.inv_m[h] = T(1.0 / double(m));
+    lay.t[h] = T(tau * double(2 * m) / double(n_t - 1));
+  }
+  return lay;
+}
+
+// Hull of the segment's line at its centre.  w: this lane's samples (layout
+// above; +inf or NaN = absent); wc: centre sample; wci[h] = wc / m_h.  Within a
+// lane m grows with h, so in-lane ties resolve to the later sample with >= / <=.
+// Every lane of the wave must call this together (cross-lane operations).
+template <typename T, int S, int K>
+__device__ __forceinline__ LineHull<T> hull_centre(const T (&w)[K], T wc, const T (&wci)[K / 2],
+                                                   const Layout<T, S, K>& lay) {
   constexpr int H = K / 2;
-  // pass 1: vertex test, and the tangent point on the left seen from the centre
-  Cand<T> p = {-inf_v<T>(), 0, T(0)};
-  T minR = inf_v<T>();
+  // pass 1 (values only): steepest slope from a left sample up to the centre, and
+  // shallowest slope from the centre to a right sample
+  T maxL = -inf_v<T>(), minR = inf_v<T>();
 #pragma unroll
   for (int h = 0; h < H; ++h) {
-    Cand<T> c = {(wc - w[h]) * inv_m[h], mi[h], w[h]};
-    if (beats_max(c, p)) p = c;
-    minR = fmin(minR, (w[H + h] - wc) * inv_m[h]);
+    maxL = fmax(maxL, fma(-w[h], lay.inv_m[h], wci[h]));
+    minR = fmin(minR, fma(w[H + h], lay.inv_m[h], -wci[h]));
   }
-  p = seg_reduce<S, true>(p);
+  maxL = seg_max<S>(maxL);
   minR = seg_min<S>(minR);
   LineHull<T> r;
   r.h = wc; r.mp = 0; r.mq = 0; r.capped = 0;
-  bool todo = p.key >= minR;          // not a strict vertex (NaN -> vertex)
-  const bool bridged = todo;          // segment-uniform
+  bool todo = maxL >= minR;           // the centre is not a strict vertex (segment-uniform)
+  if (!__any(todo)) return r;
+  const bool bridged = todo;
+  // p: tangent point on the left seen from the centre
+  Cand<T> p = {-inf_v<T>(), 0, T(0)};
+#pragma unroll
+  for (int h = 0; h < H; ++h) {
+    T key = fma(-w[h], lay.inv_m[h], wci[h]);
+    bool take = key >= p.key;
+    p.key = take ? key : p.key;
+    p.m = take ? int(lay.mf[h]) : p.m;
+    p.w = take ? w[h] : p.w;
+  }
+  p = seg_arg<S, true>(p);
   Cand<T> q = {inf_v<T>(), 0, T(0)};
   int it = 0;
   while (__any(todo)) {
-    // q: argmin over right samples of (w_j - w_p)/(m_j + m_p)
-    T nb = inf_v<T>(), db = T(1);
-    int mb = 0;
-    T wb = T(0);
-    T mpf = T(p.m);
+    // q: argmin over right samples of (w_j - w_p)/(m_j + m_p)  (cross-multiplied)
+    T nb = inf_v<T>(), db = T(1), wb = T(0), mb = T(0);
+    const T mpf = T(p.m);
 #pragma unroll
     for (int h = 0; h < H; ++h) {
       T num = w[H + h] - p.w;
-      T den = T(mi[h]) + mpf;
-      bool take = num * db < nb * den || (num * db == nb * den && mi[h] > mb);
-      nb = take ? num : nb; db = take ? den : db; mb = take ? mi[h] : mb; wb = take ? w[H + h] : wb;
+      T den = lay.mf[h] + mpf;
+      bool take = num * db <= nb * den;
+      nb = take ? num : nb; db = take ? den : db; mb = take ? lay.mf[h] : mb; wb = take ? w[H + h] : wb;
     }
-    Cand<T> qc = {nb / db, mb, wb};
-    qc = seg_reduce<S, false>(qc);
+    Cand<T> qc = {nb / db, int(mb), wb};
+    qc = seg_arg<S, false>(qc);
     // p': argmax over left samples of (w_q - w_i)/(m_q + m_i)
-    T qmf = T(qc.m);
-    nb = -inf_v<T>(); db = T(1); mb = 0; wb = T(0);
+    const T qmf = T(qc.m);
+    nb = -inf_v<T>(); db = T(1); mb = T(0); wb = T(0);
 #pragma unroll
     for (int h = 0; h < H; ++h) {
       T num = qc.w - w[h];
-      T den = qmf + T(mi[h]);
-      bool take = num * db > nb * den || (num * db == nb * den && mi[h] > mb);
-      nb = take ? num : nb; db = take ? den : db; mb = take ? mi[h] : mb; wb = take ? w[h] : wb;
+      T den = qmf + lay.mf[h];
+      bool take = num * db >= nb * den;
+      nb = take ? num : nb; db = take ? den : db; mb = take ? lay.mf[h] : mb; wb = take ? w[h] : wb;
     }
-    Cand<T> pc = {nb / db, mb, wb};
-    pc = seg_reduce<S, true>(pc);
-    bool conv = pc.m == p.m;
+    Cand<T> pc = {nb / db, int(mb), wb};
+    pc = seg_arg<S, true>(pc);
     if (todo) {
       q = qc;
-      if (conv) {
-        todo = false;
-      } else {
-        p = pc;
-      }
+      if (pc.m == p.m) todo = false;
+      else p = pc;
     }
     if (++it >= kBridgeCap) {
       if (todo) r.capped = 1;
@@ -303,28 +366,53 @@ __device__ __forceinline__ LineHull<T> hull_centre(const T (&w)[K], T wc, const 
   return r;
 }
 
-// Per-lane constants of a line layout: offsets m_h = 1 + sl + S*h, t_h = tau*2m/(n_t-1).
-template <typename T, int S, int K>
-struct Layout {
-  T t[K / 2];
-  T inv_m[K / 2];
-  int mi[K / 2];
-  int c;
+// Geometry of a point shared by all lines through it.
+template <int D>
+struct PointGeom {
+  double G[D * D];
+  double cof[D * D];
+  double det, n2;
 };
 
-template <typename T, int S, int K>
-__device__ __forceinline__ Layout<T, S, K> make_layout(int n_t, double tau) {
-  Layout<T, S, K> lay;
-  int sl = threadIdx.x & (S - 1);
-  lay.c = (n_t - 1) / 2;
+template <int D>
+__device__ __forceinline__ PointGeom<D> make_geom(const double* G) {
+  PointGeom<D> g;
 #pragma unroll
-  for (int h = 0; h < K / 2; ++h) {
-    int m = 1 + sl + S * h;
-    lay.mi[h] = m;
-    lay.inv_m[h] = T(1.0 / double(m));
-    lay.t[h] = T(tau * double(2 * m) / double(n_t - 1));
+  for (int k = 0; k < D * D; ++k) g.G[k] = G[k];
+  cofactor<D>(G, g.cof);
+  g.det = det_of<D>(G, g.cof);
+  double n2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < D * D; ++k) n2 += G[k] * G[k];
+  g.n2 = n2;
+  return g;
+}
+
+template <typename T, int D>
+__device__ __forceinline__ Line<T> line_of(int model, const PointGeom<D>& g, const double* a,
+                                           const double* b) {
+  if (model != 0) return line_setup<T, D>(model, g.G, g.cof, a, b);
+  Line<T> L;
+  double J1 = 0.0, gab = 0.0, aa = 0.0, bb = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    aa += a[i] * a[i];
+    bb += b[i] * b[i];
+    double ca = 0.0, ga = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      ca += g.cof[i * D + j] * b[j];
+      ga += g.G[i * D + j] * b[j];
+    }
+    J1 += a[i] * ca;
+    gab += a[i] * ga;
   }
-  return lay;
+  L.J0 = T(g.det);
+  L.J1 = T(J1);
+  L.c0 = T(g.n2 - double(D));
+  L.c1 = T(2.0 * gab);
+  L.c2 = T(aa * bb);
+  return L;
 }
 
 template <typename T>
@@ -340,10 +428,13 @@ template <typename T, int D, int S, int K>
 __device__ Env<T> envelope_at(const Point<T>& q, const double* G, T wc, const Level& lv,
                               const Layout<T, S, K>& lay) {
   constexpr int NSEG = kWave / S;
+  constexpr int H = K / 2;
   const int lane = threadIdx.x & (kWave - 1);
   const int seg = lane / S;
-  double cof[D * D];
-  cofactor<D>(G, cof);
+  PointGeom<D> g = make_geom<D>(G);
+  T wci[H];
+#pragma unroll
+  for (int h = 0; h < H; ++h) wci[h] = wc * lay.inv_m[h];
   Env<T> best = {inf_v<T>(), 0, 0, 0, 0};
   for (int m0 = 0; m0 < lv.n_dir; m0 += NSEG) {
     int dir = m0 + seg;
@@ -352,28 +443,28 @@ __device__ Env<T> envelope_at(const Point<T>& q, const double* G, T wc, const Le
     double a[D], b[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) { a[i] = lv.a[dd * D + i]; b[i] = lv.b[dd * D + i]; }
-    Line<T> L = line_setup<T, D>(q.model, G, cof, a, b);
+    Line<T> L = line_of<T, D>(q.model, g, a, b);
     T w[K];
     if (q.model == 0) {
 #pragma unroll
-      for (int h = 0; h < K / 2; ++h) {
-        bool valid = lay.mi[h] <= lay.c;
+      for (int h = 0; h < H; ++h) {
+        bool valid = int(lay.mf[h]) <= lay.c;
         T wl = w_sample<T>(-lay.t[h], L, q);
         T wr = w_sample<T>(lay.t[h], L, q);
         w[h] = valid ? wl : inf_v<T>();
-        w[K / 2 + h] = valid ? wr : inf_v<T>();
+        w[H + h] = valid ? wr : inf_v<T>();
       }
     } else {
 #pragma unroll
-      for (int h = 0; h < K / 2; ++h) {
-        bool valid = lay.mi[h] <= lay.c;
+      for (int h = 0; h < H; ++h) {
+        bool valid = int(lay.mf[h]) <= lay.c;
         T wl = w_sample_doublewell<T>(-lay.t[h], L);
         T wr = w_sample_doublewell<T>(lay.t[h], L);
         w[h] = valid ? wl : inf_v<T>();
-        w[K / 2 + h] = valid ? wr : inf_v<T>();
+        w[H + h] = valid ? wr : inf_v<T>();
       }
     }
-    LineHull<T> lh = hull_centre<T, S, K>(w, wc, lay.inv_m, lay.mi);
+    LineHull<T> lh = hull_centre<T, S, K>(w, wc, wci, lay);
     if (act && lh.h < best.h) {
       best.h = lh.h; best.dir = dir; best.mp = lh.mp; best.mq = lh.mq;
     }

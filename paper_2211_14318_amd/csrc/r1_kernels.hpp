@@ -128,41 +128,47 @@ __global__ __launch_bounds__(256) void k_depth1(KArgs a) {
 }
 
 // Outer hull of an LDS-resident line (wave-wide, S = 64): wl[m-1] / wr[m-1] are
-// the samples at offsets -m / +m, m = 1..c.  Same search as hull_centre.
+// the samples at offsets -m / +m, m = 1..c (NaN or +inf = absent).  Same search
+// as hull_centre: a values-only vertex test, then alternating tangent queries.
 template <typename T>
 __device__ LineHull<T> hull_centre_lds(const T* wl, const T* wr, int c, T wc) {
   const int lane = lane_id();
-  Cand<T> p = {-inf_v<T>(), 0, T(0)};
-  T minR = inf_v<T>();
+  T maxL = -inf_v<T>(), minR = inf_v<T>();
   for (int m = 1 + lane; m <= c; m += kWave) {
     T inv = T(1.0 / double(m));
-    Cand<T> cd = {(wc - wl[m - 1]) * inv, m, wl[m - 1]};
-    if (beats_max(cd, p)) p = cd;
+    maxL = fmax(maxL, (wc - wl[m - 1]) * inv);
     minR = fmin(minR, (wr[m - 1] - wc) * inv);
   }
-  p = seg_reduce<kWave, true>(p);
+  maxL = seg_max<kWave>(maxL);
   minR = seg_min<kWave>(minR);
   LineHull<T> r = {wc, 0, 0, 0};
-  if (!(p.key >= minR)) return r;     // wave-uniform
+  if (!(maxL >= minR)) return r;      // wave-uniform
+  Cand<T> p = {-inf_v<T>(), 0, T(0)};
+  for (int m = 1 + lane; m <= c; m += kWave) {
+    T key = (wc - wl[m - 1]) * T(1.0 / double(m));
+    bool take = key >= p.key;
+    p.key = take ? key : p.key; p.m = take ? m : p.m; p.w = take ? wl[m - 1] : p.w;
+  }
+  p = seg_arg<kWave, true>(p);
   Cand<T> q = {inf_v<T>(), 0, T(0)};
   for (int it = 0; it < kBridgeCap; ++it) {
     T nb = inf_v<T>(), db = T(1), wb = T(0);
     int mb = 0;
     for (int m = 1 + lane; m <= c; m += kWave) {
       T num = wr[m - 1] - p.w, den = T(m + p.m);
-      bool take = num * db < nb * den || (num * db == nb * den && m > mb);
+      bool take = num * db <= nb * den;
       nb = take ? num : nb; db = take ? den : db; mb = take ? m : mb; wb = take ? wr[m - 1] : wb;
     }
     Cand<T> qc = {nb / db, mb, wb};
-    q = seg_reduce<kWave, false>(qc);
+    q = seg_arg<kWave, false>(qc);
     nb = -inf_v<T>(); db = T(1); wb = T(0); mb = 0;
     for (int m = 1 + lane; m <= c; m += kWave) {
       T num = q.w - wl[m - 1], den = T(q.m + m);
-      bool take = num * db > nb * den || (num * db == nb * den && m > mb);
+      bool take = num * db >= nb * den;
       nb = take ? num : nb; db = take ? den : db; mb = take ? m : mb; wb = take ? wl[m - 1] : wb;
     }
     Cand<T> pc = {nb / db, mb, wb};
-    pc = seg_reduce<kWave, true>(pc);
+    pc = seg_arg<kWave, true>(pc);
     if (pc.m == p.m) {
       r.h = (T(q.m) * p.w + T(p.m) * q.w) / T(q.m + p.m);
       r.mp = p.m; r.mq = q.m;
