@@ -229,6 +229,10 @@ __device__ __forceinline__ T seg_min(T v) {
   else return v;
 }
 
+// Slope keys only order candidates across lanes: FP32 uses the hardware reciprocal.
+__device__ __forceinline__ float key_div(float n, float d) { return n * __builtin_amdgcn_rcpf(d); }
+__device__ __forceinline__ double key_div(double n, double d) { return n / d; }
+
 template <typename T>
 struct Cand {      // a hull candidate: key (a slope), offset magnitude m, sample value w
   T key;
@@ -281,7 +285,9 @@ __device__ __forceinline__ Layout<T, S, K> make_layout(int n_t, double tau) {
     int m = 1 + sl + S * h;
     lay.mf[h] = T(m);
     lay.inv_m[h] = T(1.0 / double(m));
-    lay.t[h] = T(tau * double(2 * m) / double(n_t - 1));
+    // offsets beyond the grid are padding: a NaN abscissa makes the sample NaN,
+    // which every hull comparison treats as absent (no per-sample select)
+    lay.t[h] = m <= lay.c ? T(tau * double(2 * m) / double(n_t - 1)) : T(__builtin_nan(""));
   }
   return lay;
 }
@@ -333,7 +339,7 @@ __device__ __forceinline__ LineHull<T> hull_centre(const T (&w)[K], T wc, const 
       bool take = num * db <= nb * den;
       nb = take ? num : nb; db = take ? den : db; mb = take ? lay.mf[h] : mb; wb = take ? w[H + h] : wb;
     }
-    Cand<T> qc = {nb / db, int(mb), wb};
+    Cand<T> qc = {key_div(nb, db), int(mb), wb};
     qc = seg_arg<S, false>(qc);
     // p': argmax over left samples of (w_q - w_i)/(m_q + m_i)
     const T qmf = T(qc.m);
@@ -345,7 +351,7 @@ __device__ __forceinline__ LineHull<T> hull_centre(const T (&w)[K], T wc, const 
       bool take = num * db >= nb * den;
       nb = take ? num : nb; db = take ? den : db; mb = take ? lay.mf[h] : mb; wb = take ? w[h] : wb;
     }
-    Cand<T> pc = {nb / db, int(mb), wb};
+    Cand<T> pc = {key_div(nb, db), int(mb), wb};
     pc = seg_arg<S, true>(pc);
     if (todo) {
       q = qc;
@@ -422,46 +428,37 @@ struct Env {            // W^1 at a point: value, direction, bracketing offsets
   int capped;
 };
 
-// One lamination level at point G (wave-uniform): min over directions of the
-// line hulls at the centre.  wc = W(G).  Every lane of the wave must call it.
-template <typename T, int D, int S, int K>
-__device__ Env<T> envelope_at(const Point<T>& q, const double* G, T wc, const Level& lv,
-                              const Layout<T, S, K>& lay) {
+// One lamination level at a point (wave-uniform): min over the level's n_dir
+// directions of the line hulls at the centre.  wc = W at the point;
+// line_fn(dir) returns the coefficients of W along direction dir.  Every lane of
+// the wave must call it.
+template <typename T, int S, int K, typename LineFn>
+__device__ Env<T> envelope_lines(const Point<T>& q, T wc, int n_dir, const Layout<T, S, K>& lay,
+                                 LineFn line_fn) {
   constexpr int NSEG = kWave / S;
   constexpr int H = K / 2;
   const int lane = threadIdx.x & (kWave - 1);
   const int seg = lane / S;
-  PointGeom<D> g = make_geom<D>(G);
   T wci[H];
 #pragma unroll
   for (int h = 0; h < H; ++h) wci[h] = wc * lay.inv_m[h];
   Env<T> best = {inf_v<T>(), 0, 0, 0, 0};
-  for (int m0 = 0; m0 < lv.n_dir; m0 += NSEG) {
+  for (int m0 = 0; m0 < n_dir; m0 += NSEG) {
     int dir = m0 + seg;
-    bool act = dir < lv.n_dir;
-    int dd = act ? dir : lv.n_dir - 1;
-    double a[D], b[D];
-#pragma unroll
-    for (int i = 0; i < D; ++i) { a[i] = lv.a[dd * D + i]; b[i] = lv.b[dd * D + i]; }
-    Line<T> L = line_of<T, D>(q.model, g, a, b);
+    bool act = dir < n_dir;
+    Line<T> L = line_fn(act ? dir : n_dir - 1);
     T w[K];
     if (q.model == 0) {
 #pragma unroll
       for (int h = 0; h < H; ++h) {
-        bool valid = int(lay.mf[h]) <= lay.c;
-        T wl = w_sample<T>(-lay.t[h], L, q);
-        T wr = w_sample<T>(lay.t[h], L, q);
-        w[h] = valid ? wl : inf_v<T>();
-        w[H + h] = valid ? wr : inf_v<T>();
+        w[h] = w_sample<T>(-lay.t[h], L, q);
+        w[H + h] = w_sample<T>(lay.t[h], L, q);
       }
     } else {
 #pragma unroll
       for (int h = 0; h < H; ++h) {
-        bool valid = int(lay.mf[h]) <= lay.c;
-        T wl = w_sample_doublewell<T>(-lay.t[h], L);
-        T wr = w_sample_doublewell<T>(lay.t[h], L);
-        w[h] = valid ? wl : inf_v<T>();
-        w[H + h] = valid ? wr : inf_v<T>();
+        w[h] = w_sample_doublewell<T>(-lay.t[h], L);
+        w[H + h] = w_sample_doublewell<T>(lay.t[h], L);
       }
     }
     LineHull<T> lh = hull_centre<T, S, K>(w, wc, wci, lay);
@@ -486,6 +483,76 @@ __device__ Env<T> envelope_at(const Point<T>& q, const double* G, T wc, const Le
     best.capped |= oc;
   }
   return best;
+}
+
+// One lamination level at point G with the lines set up from G's geometry.
+template <typename T, int D, int S, int K>
+__device__ Env<T> envelope_at(const Point<T>& q, const double* G, T wc, const Level& lv,
+                              const Layout<T, S, K>& lay) {
+  PointGeom<D> g = make_geom<D>(G);
+  return envelope_lines<T, S, K>(q, wc, lv.n_dir, lay, [&](int dd) {
+    double a[D], b[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) { a[i] = lv.a[dd * D + i]; b[i] = lv.b[dd * D + i]; }
+    return line_of<T, D>(q.model, g, a, b);
+  });
+}
+
+// Lines of an inner level along an outer line G(t_o) = F + t_o R_o, R_o rank one.
+// det and |.|^2 are affine / quadratic in t_o, and cof(F + t_o R_o) = cof F + t_o C1
+// because cof(R_o) = 0, so every inner coefficient is affine in t_o:
+//   J1_i = al_i + t_o be_i,  c1_i = ga_i + t_o de_i,  c2_i = |a_i|^2 |b_i|^2.
+// coef[5*i .. 5*i+4] = (al, be, ga, de, c2) of inner direction i.
+template <int D>
+__device__ __forceinline__ void cof_derivative(const double* F, const double* R, double* C1) {
+  if (D == 2) {
+    C1[0] = R[3]; C1[1] = -R[2]; C1[2] = -R[1]; C1[3] = R[0];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+        C1[i * 3 + j] = R[i1 * 3 + j1] * F[i2 * 3 + j2] + F[i1 * 3 + j1] * R[i2 * 3 + j2]
+                      - R[i1 * 3 + j2] * F[i2 * 3 + j1] - F[i1 * 3 + j2] * R[i2 * 3 + j1];
+      }
+  }
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void inner_line_coef(int model, const double* F, const double* cofF,
+                                                const double* R, const double* C1, const double* a,
+                                                const double* b, T* coef) {
+  double al = 0, be = 0, ga = 0, de = 0, aa = 0, bb = 0;
+  if (model == 0) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      aa += a[i] * a[i];
+      bb += b[i] * b[i];
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        al += a[i] * cofF[i * D + j] * b[j];
+        be += a[i] * C1[i * D + j] * b[j];
+        ga += 2.0 * a[i] * F[i * D + j] * b[j];
+        de += 2.0 * a[i] * R[i * D + j] * b[j];
+      }
+    }
+    coef[0] = T(al); coef[1] = T(be); coef[2] = T(ga); coef[3] = T(de); coef[4] = T(aa * bb);
+  } else {
+    // double-well test energy: g = G11 + t a1 b1, rest = sum_{(i,j)!=(1,1)} (G_ij - delta_ij + t a_i b_j)^2
+    double r2 = 0, e1 = 0, e1r = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        if (i == 0 && j == 0) continue;
+        double r = a[i] * b[j];
+        r2 += r * r;
+        e1 += 2.0 * (F[i * D + j] - (i == j ? 1.0 : 0.0)) * r;
+        e1r += 2.0 * R[i * D + j] * r;
+      }
+    coef[0] = T(a[0] * b[0]); coef[1] = T(0); coef[2] = T(e1); coef[3] = T(e1r); coef[4] = T(r2);
+  }
 }
 
 // P0 = dW/dF = (1 - D(max(beta_n, psi0))) (mu G + (lambda ln J - mu) G^{-T}) in double

@@ -181,17 +181,22 @@ __device__ LineHull<T> hull_centre_lds(const T* wl, const T* wr, int c, T wc) {
   return r;
 }
 
+// Inner directions whose line coefficients are tabulated in LDS per outer line.
+constexpr int kMaxTabDirs = 512;
+
 template <typename T, int D, int S, int K>
 __global__ __launch_bounds__(256) void k_outer(KArgs a) {
   extern __shared__ char smem_raw[];
-  T* wl = reinterpret_cast<T*>(smem_raw);
   const int n_dir_o = a.lv0.n_dir;
   const int64_t p = int64_t(blockIdx.x) / n_dir_o;
   const int mo = int(int64_t(blockIdx.x) % n_dir_o);
   const Level& lo = a.lv0;
   const Level& li = a.lv1;
   const int co = (lo.n_t - 1) / 2;
-  T* wr = wl + co;
+  const bool tab = li.n_dir <= kMaxTabDirs;
+  T* coef = reinterpret_cast<T*>(smem_raw);                 // 5 * n_dir_i (when tabulated)
+  T* wl = coef + (tab ? 5 * li.n_dir : 0);                  // outer samples at -m
+  T* wr = wl + co;                                          // outer samples at +m
   __shared__ int capped_any;
   OuterRes<T>* out = static_cast<OuterRes<T>*>(a.scratch_outer) + p * n_dir_o + mo;
   T w1f = static_cast<const T*>(a.scratch_w1f)[p];
@@ -201,7 +206,19 @@ __global__ __launch_bounds__(256) void k_outer(KArgs a) {
   }
   double F[D * D], bn;
   load_point<T, D>(a, p, F, bn);
+  double R[D * D];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) R[i * D + j] = lo.a[mo * D + i] * lo.b[mo * D + j];
   if (threadIdx.x == 0) capped_any = 0;
+  if (tab) {
+    double cofF[D * D], C1[D * D];
+    cofactor<D>(F, cofF);
+    cof_derivative<D>(F, R, C1);
+    for (int i = threadIdx.x; i < li.n_dir; i += blockDim.x)
+      inner_line_coef<T, D>(a.mat.model, F, cofF, R, C1, li.a + i * D, li.b + i * D, coef + 5 * i);
+  }
   __syncthreads();
   Layout<T, S, K> lay = make_layout<T, S, K>(li.n_t, li.tau);
   Point<T> q = make_point<T>(a.mat, bn);
@@ -211,15 +228,51 @@ __global__ __launch_bounds__(256) void k_outer(KArgs a) {
   for (int s = wave; s < 2 * co; s += nwave) {
     int m = 1 + (s >> 1);
     double t = (s & 1) ? t_of(lo, m) : -t_of(lo, m);
-    double G[D * D], cof[D * D];
-    line_point<D>(F, lo, mo, t, G);
-    cofactor<D>(G, cof);
-    T wc = w_point<T, D>(q, G, cof);
-    T v = wc;
-    if (wc < inf_v<T>()) {
-      Env<T> e = envelope_at<T, D, S, K>(q, G, wc, li, lay);
-      v = e.h;
-      capped |= e.capped;
+    double G[D * D];
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) G[k] = F[k] + t * R[k];
+    T v;
+    if (tab) {
+      // W(G) and the per-sample parts of every inner line: J0 = det G, c0 = |G|^2 - d
+      // (neo-Hooke) or G11 and the quadratic rest (double well)
+      double cof[D * D];
+      cofactor<D>(G, cof);
+      double J0, c0 = 0.0;
+      if (a.mat.model == 0) {
+        J0 = det_of<D>(G, cof);
+#pragma unroll
+        for (int k = 0; k < D * D; ++k) c0 += G[k] * G[k];
+        c0 -= double(D);
+      } else {
+        J0 = G[0];
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+          for (int j = 0; j < D; ++j)
+            if (i || j) c0 += (G[i * D + j] - (i == j ? 1.0 : 0.0)) * (G[i * D + j] - (i == j ? 1.0 : 0.0));
+      }
+      Line<T> L0 = {T(J0), T(0), T(c0), T(0), T(0)};
+      T wc = q.model == 0 ? w_sample<T>(T(0), L0, q) : w_sample_doublewell<T>(T(0), L0);
+      v = wc;
+      if (wc < inf_v<T>()) {
+        const T tt = T(t);
+        Env<T> e = envelope_lines<T, S, K>(q, wc, li.n_dir, lay, [&](int dd) {
+          const T* cf = coef + 5 * dd;
+          return Line<T>{L0.J0, T(fma(tt, cf[1], cf[0])), L0.c0, T(fma(tt, cf[3], cf[2])), cf[4]};
+        });
+        v = e.h;
+        capped |= e.capped;
+      }
+    } else {
+      double cof[D * D];
+      cofactor<D>(G, cof);
+      T wc = w_point<T, D>(q, G, cof);
+      v = wc;
+      if (wc < inf_v<T>()) {
+        Env<T> e = envelope_at<T, D, S, K>(q, G, wc, li, lay);
+        v = e.h;
+        capped |= e.capped;
+      }
     }
     if (lane_id() == 0) ((s & 1) ? wr : wl)[m - 1] = v;
   }
@@ -324,7 +377,7 @@ hipError_t launch_T(const KArgs& a, int depth, hipStream_t st, KTimer* tm) {
   if (tm) tm->begin("depth2_centre", st);
   hipLaunchKernelGGL((k_depth1<T, D, S, K>), grd, blk, 0, st, pre);
   if (tm) tm->end(st);
-  size_t lds = sizeof(T) * size_t(a.lv0.n_t - 1);
+  size_t lds = sizeof(T) * (size_t(a.lv0.n_t - 1) + (a.lv1.n_dir <= kMaxTabDirs ? 5 * size_t(a.lv1.n_dir) : 0));
   dim3 grd_o(unsigned(a.n * a.lv0.n_dir));
   if (tm) tm->begin("outer", st);
   hipLaunchKernelGGL((k_outer<T, D, S, K>), grd_o, blk, lds, st, a);
