@@ -159,6 +159,15 @@ r1_status r1_set_segment_width(r1_handle handle, int32_t n_t, int32_t lanes);
 r1_status r1_get_segment_width(r1_handle handle, int32_t n_t, r1_dtype dtype, int32_t dim,
                                int32_t* lanes);
 
+/* Autotuner: times every admissible segment width for lines of n_t points on a
+ * synthetic one-level batch of 2048 points (32 directions) with the given
+ * material and dtype on `stream` (synchronizes it), records the fastest for
+ * (n_t, dtype, material->dim) in the handle and returns it in *lanes
+ * (nullable).  r1_envelope_batched runs it on first use of each innermost grid
+ * size that has neither a user setting nor a tuned value. */
+r1_status r1_autotune(r1_handle handle, const r1_material* material, int32_t n_t, r1_dtype dtype,
+                      void* stream, int32_t* lanes);
+
 /* ---- measurement ---------------------------------------------------------------- */
 
 /* When enabled, every kernel launch of the handle is bracketed by HIP events

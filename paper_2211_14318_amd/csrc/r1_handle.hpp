@@ -22,6 +22,8 @@ struct r1_handle_s {
   std::map<int64_t, int> seg_tuned;        // (n_t, dtype, dim) -> lanes per line (autotuner)
   std::map<uint64_t, BatchedPlan*> plans;  // batched launches: plan + captured graph
   KTimer timer;                            // optional per-kernel event timing
+  hipStream_t capture_stream = nullptr;    // private stream for graph capture
+  uint64_t plan_serial = 0;
 };
 
 namespace r1h {
@@ -32,7 +34,10 @@ r1_status check_lamination(const r1_lamination* lam);
 r1_status device_level(r1_handle h, const r1_level& lv, int dim, r1d::Level* out);
 r1_status scratch(r1_handle h, size_t bytes, void** p);
 int samples_per_lane(int S, int n_t);
+int batch_samples_per_lane(int S, int n_t);
 int segment_width(r1_handle h, int n_t, int dtype, int dim);
 inline int64_t tune_key(int n_t, int dtype, int dim) { return (int64_t(n_t) << 8) | (dtype << 4) | dim; }
 void release_batched(r1_handle h);
+r1_status autotune(r1_handle h, const r1_material* mat, int n_t, int dtype, int dim, hipStream_t st,
+                   int* lanes);
 }  // namespace r1h

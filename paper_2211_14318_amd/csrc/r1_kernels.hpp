@@ -87,11 +87,10 @@ __device__ __forceinline__ void write_bad_point(const KArgs& a, int64_t p, bool 
       a.tree[p * R1_TREE_NODES + k] = r1_laminate{0, 0, 0, 1.0f};
 }
 
+// One-level envelope of point p on level lv, with stress, tree and flags as
+// requested by a (wave-level: every lane of the wave calls it).
 template <typename T, int D, int S, int K>
-__global__ __launch_bounds__(256) void k_depth1(KArgs a) {
-  const int64_t p = int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (p >= a.n) return;                       // wave-uniform
-  const Level& lv = a.lv0;
+__device__ void point_depth1(const KArgs& a, int64_t p, const Level& lv) {
   double G[D * D], bn;
   bool fin = load_point<T, D>(a, p, G, bn);
   Layout<T, S, K> lay = make_layout<T, S, K>(lv.n_t, lv.tau);
@@ -125,6 +124,13 @@ __global__ __launch_bounds__(256) void k_depth1(KArgs a) {
     }
     if (a.flags) a.flags[p] = e.capped ? R1_PT_ITERCAP : 0;
   }
+}
+
+template <typename T, int D, int S, int K>
+__global__ __launch_bounds__(256) void k_depth1(KArgs a) {
+  const int64_t p = int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (p >= a.n) return;                       // wave-uniform
+  point_depth1<T, D, S, K>(a, p, a.lv0);
 }
 
 // Outer hull of an LDS-resident line (wave-wide, S = 64): wl[m-1] / wr[m-1] are
@@ -184,26 +190,28 @@ __device__ LineHull<T> hull_centre_lds(const T* wl, const T* wr, int c, T wc) {
 // Inner directions whose line coefficients are tabulated in LDS per outer line.
 constexpr int kMaxTabDirs = 512;
 
+// Bytes of dynamic LDS an outer line needs: inner-line coefficient table and
+// the outer line's samples.
+template <typename T>
+__host__ __device__ inline size_t outer_lds_bytes(const Level& lo, const Level& li) {
+  return sizeof(T) * (size_t(lo.n_t - 1) + (li.n_dir <= kMaxTabDirs ? 5 * size_t(li.n_dir) : 0));
+}
+
+// One outer line (block-level, every thread calls it): the samples W^1(F + t_i R_mo)
+// are inner envelopes computed by the block's waves into LDS; wave 0 takes the
+// outer hull at the centre.  w1f = W^1(F) is the centre sample; when
+// compute_centre is set it is computed here (by wave 0) instead.  Thread 0
+// writes the result to *out.  Returns the centre value used.
 template <typename T, int D, int S, int K>
-__global__ __launch_bounds__(256) void k_outer(KArgs a) {
-  extern __shared__ char smem_raw[];
-  const int n_dir_o = a.lv0.n_dir;
-  const int64_t p = int64_t(blockIdx.x) / n_dir_o;
-  const int mo = int(int64_t(blockIdx.x) % n_dir_o);
-  const Level& lo = a.lv0;
-  const Level& li = a.lv1;
+__device__ T outer_line(const KArgs& a, int64_t p, int mo, const Level& lo, const Level& li, T w1f,
+                        bool compute_centre, OuterRes<T>* out, char* smem_raw) {
   const int co = (lo.n_t - 1) / 2;
   const bool tab = li.n_dir <= kMaxTabDirs;
   T* coef = reinterpret_cast<T*>(smem_raw);                 // 5 * n_dir_i (when tabulated)
   T* wl = coef + (tab ? 5 * li.n_dir : 0);                  // outer samples at -m
   T* wr = wl + co;                                          // outer samples at +m
   __shared__ int capped_any;
-  OuterRes<T>* out = static_cast<OuterRes<T>*>(a.scratch_outer) + p * n_dir_o + mo;
-  T w1f = static_cast<const T*>(a.scratch_w1f)[p];
-  if (!(w1f < inf_v<T>())) {                  // det F <= 0 or non-finite input: block-uniform
-    if (threadIdx.x == 0) *out = OuterRes<T>{w1f, 0, 0, 0};
-    return;
-  }
+  __shared__ T centre;
   double F[D * D], bn;
   load_point<T, D>(a, p, F, bn);
   double R[D * D];
@@ -211,7 +219,7 @@ __global__ __launch_bounds__(256) void k_outer(KArgs a) {
   for (int i = 0; i < D; ++i)
 #pragma unroll
     for (int j = 0; j < D; ++j) R[i * D + j] = lo.a[mo * D + i] * lo.b[mo * D + j];
-  if (threadIdx.x == 0) capped_any = 0;
+  if (threadIdx.x == 0) { capped_any = 0; centre = w1f; }
   if (tab) {
     double cofF[D * D], C1[D * D];
     cofactor<D>(F, cofF);
@@ -224,6 +232,18 @@ __global__ __launch_bounds__(256) void k_outer(KArgs a) {
   Point<T> q = make_point<T>(a.mat, bn);
   const int wave = threadIdx.x / kWave, nwave = blockDim.x / kWave;
   int capped = 0;
+  if (compute_centre && wave == 0) {
+    double cof[D * D];
+    cofactor<D>(F, cof);
+    T wc = w_point<T, D>(q, F, cof);
+    T v = wc;
+    if (wc < inf_v<T>()) {
+      Env<T> e = envelope_at<T, D, S, K>(q, F, wc, li, lay);
+      v = e.h;
+      capped |= e.capped;
+    }
+    if (lane_id() == 0) centre = v;
+  }
   // outer samples, interleaved left/right so the waves share both sides
   for (int s = wave; s < 2 * co; s += nwave) {
     int m = 1 + (s >> 1);
@@ -278,27 +298,46 @@ __global__ __launch_bounds__(256) void k_outer(KArgs a) {
   }
   if (capped && lane_id() == 0) atomicOr(&capped_any, 1);
   __syncthreads();
+  T cv = centre;
   if (wave == 0) {
-    LineHull<T> r = hull_centre_lds<T>(wl, wr, co, w1f);
-    if (lane_id() == 0) *out = OuterRes<T>{r.h, r.mp, r.mq, r.capped | capped_any};
+    LineHull<T> r = hull_centre_lds<T>(wl, wr, co, cv);
+    if (threadIdx.x == 0) *out = OuterRes<T>{r.h, r.mp, r.mq, r.capped | capped_any};
   }
+  __syncthreads();                            // LDS reused by the caller's next item
+  return cv;
 }
 
 template <typename T, int D, int S, int K>
-__global__ __launch_bounds__(256) void k_finalize(KArgs a) {
-  const int64_t p = int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (p >= a.n) return;
-  const Level& lo = a.lv0;
-  const Level& li = a.lv1;
+__global__ __launch_bounds__(256) void k_outer(KArgs a) {
+  extern __shared__ char smem_raw[];
+  const int n_dir_o = a.lv0.n_dir;
+  const int64_t p = int64_t(blockIdx.x) / n_dir_o;
+  const int mo = int(int64_t(blockIdx.x) % n_dir_o);
+  OuterRes<T>* out = static_cast<OuterRes<T>*>(a.scratch_outer) + p * n_dir_o + mo;
+  T w1f = static_cast<const T*>(a.scratch_w1f)[p];
+  if (!(w1f < inf_v<T>())) {                  // det F <= 0 or non-finite input: block-uniform
+    if (threadIdx.x == 0) *out = OuterRes<T>{w1f, 0, 0, 0};
+    return;
+  }
+  outer_line<T, D, S, K>(a, p, mo, a.lv0, a.lv1, w1f, false, out, smem_raw);
+}
+
+// Two-level result of point p from its outer-line results res[0 .. n_dir_o):
+// min over outer directions, then stress and tree through Algorithm 3 on the
+// binary tree (wave-level).
+template <typename T, int D, int S, int K>
+__device__ void finalize_point(const KArgs& a, int64_t p, const Level& lo, const Level& li,
+                               const OuterRes<T>* res) {
   const int n_dir_o = lo.n_dir;
   double F[D * D], bn;
   bool fin = load_point<T, D>(a, p, F, bn);
-  T w1f = static_cast<const T*>(a.scratch_w1f)[p];
-  if (!fin || !(w1f < inf_v<T>())) {
+  Point<T> q0 = make_point<T>(a.mat, bn);
+  double cof0[D * D];
+  cofactor<D>(F, cof0);
+  if (!fin || !(w_point<T, D>(q0, F, cof0) < inf_v<T>())) {
     if (lane_id() == 0) write_bad_point<T, D>(a, p, !fin, a.want_stress);
     return;
   }
-  const OuterRes<T>* res = static_cast<const OuterRes<T>*>(a.scratch_outer) + p * n_dir_o;
   T bh = inf_v<T>();
   int bd = 0x7fffffff, bp = 0, bq = 0, cap = 0;
   for (int m = lane_id(); m < n_dir_o; m += kWave) {
@@ -352,6 +391,14 @@ __global__ __launch_bounds__(256) void k_finalize(KArgs a) {
   }
 }
 
+template <typename T, int D, int S, int K>
+__global__ __launch_bounds__(256) void k_finalize(KArgs a) {
+  const int64_t p = int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (p >= a.n) return;
+  finalize_point<T, D, S, K>(a, p, a.lv0, a.lv1,
+                             static_cast<const OuterRes<T>*>(a.scratch_outer) + p * a.lv0.n_dir);
+}
+
 // ---- dispatch ------------------------------------------------------------------
 
 template <typename T, int D, int S, int K>
@@ -377,7 +424,7 @@ hipError_t launch_T(const KArgs& a, int depth, hipStream_t st, KTimer* tm) {
   if (tm) tm->begin("depth2_centre", st);
   hipLaunchKernelGGL((k_depth1<T, D, S, K>), grd, blk, 0, st, pre);
   if (tm) tm->end(st);
-  size_t lds = sizeof(T) * (size_t(a.lv0.n_t - 1) + (a.lv1.n_dir <= kMaxTabDirs ? 5 * size_t(a.lv1.n_dir) : 0));
+  size_t lds = outer_lds_bytes<T>(a.lv0, a.lv1);
   dim3 grd_o(unsigned(a.n * a.lv0.n_dir));
   if (tm) tm->begin("outer", st);
   hipLaunchKernelGGL((k_outer<T, D, S, K>), grd_o, blk, lds, st, a);

@@ -1,6 +1,14 @@
 // Instantiation of the lamination kernels for float, 2x2 gradients.
-#include "r1_kernels.hpp"
+#include "r1_batched_kernels.hpp"
 
 hipError_t r1_launch_f32_2d(const KArgs& a, int depth, int S, int K, hipStream_t st, KTimer* tm) {
   return r1k::launch_TD<float, 2>(a, depth, S, K, st, tm);
+}
+
+hipError_t r1_launch_batched_f32_2d(const BArgs& b, int grid, size_t lds, int zero_n, hipStream_t st) {
+  return r1k::launch_batched_TD<float, 2>(b, grid, lds, zero_n, st);
+}
+
+hipError_t r1_occupancy_batched_f32_2d(size_t lds, int* blocks_per_cu) {
+  return r1k::occupancy_batched_TD<float, 2>(lds, blocks_per_cu);
 }

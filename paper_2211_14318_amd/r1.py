@@ -68,11 +68,12 @@ def _load():
                                       i64, vp, i32, vp, vp, vp, vp, vp, vp, vp]
     L.r1_set_segment_width.argtypes = [vp, i32, i32]
     L.r1_get_segment_width.argtypes = [vp, i32, i32, i32, ctypes.POINTER(i32)]
+    L.r1_autotune.argtypes = [vp, ctypes.POINTER(Material), i32, i32, vp, ctypes.POINTER(i32)]
     L.r1_timing_enable.argtypes = [vp, i32]
     L.r1_timing_reset.argtypes = [vp]
     L.r1_timing_query.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(i64)]
-    for name in ("r1_timing_enable", "r1_timing_reset", "r1_timing_query", "r1_create", "r1_destroy", "r1_envelope", "r1_envelope_stress",
+    for name in ("r1_autotune", "r1_timing_enable", "r1_timing_reset", "r1_timing_query", "r1_create", "r1_destroy", "r1_envelope", "r1_envelope_stress",
                  "r1_envelope_batched", "r1_set_segment_width", "r1_get_segment_width"):
         getattr(L, name).restype = i32
     return L
@@ -158,6 +159,12 @@ class Handle:
         out = ctypes.c_int32()
         self._check(_lib.r1_get_segment_width(self.h, int(n_t), int(dtype), int(dim),
                                               ctypes.byref(out)), "r1_get_segment_width")
+        return out.value
+
+    def autotune(self, mat, n_t, dtype, stream=None):
+        out = ctypes.c_int32()
+        self._check(_lib.r1_autotune(self.h, ctypes.byref(mat), int(n_t), int(dtype),
+                                     self._stream(stream), ctypes.byref(out)), "r1_autotune")
         return out.value
 
     def timing(self, on=True):
