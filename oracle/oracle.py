@@ -86,6 +86,12 @@ def lib():
         L.orc_envelope_batch.restype = None
         L.orc_envelope_batch.argtypes = [ctypes.POINTER(Material), ctypes.POINTER(Lamination),
                                          ctypes.c_long, dp, dp, dp, dp, ctypes.POINTER(Laminate)]
+        L.orc_mlp_param_count.restype = ctypes.c_long
+        L.orc_mlp_param_count.argtypes = [ctypes.c_int] * 4
+        L.orc_mlp_forward.restype = ctypes.c_double
+        L.orc_mlp_forward.argtypes = [ctypes.c_int] * 4 + [dp, ctypes.c_long, dp, dp, dp]
+        L.orc_mlp_loss_grad.restype = ctypes.c_double
+        L.orc_mlp_loss_grad.argtypes = [ctypes.c_int] * 4 + [dp, ctypes.c_long, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -196,3 +202,32 @@ def envelope_batch(mat, spec, F_soa, beta_n, want_stress=True, want_tree=False):
         t = tree_to_list(trees)
         trees = [t[p * TREE_NODES:(p + 1) * TREE_NODES] for p in range(n)]
     return W, P, trees
+
+
+# ---- surrogate network oracle (mlp.c)
+
+def mlp_param_count(d_in, width, n_hidden, d_out):
+    return lib().orc_mlp_param_count(d_in, width, n_hidden, d_out)
+
+
+def mlp_forward(shape, params, x, y=None):
+    """shape = (d_in, width, n_hidden, d_out); x (B, d_in) -> (out (B, d_out), loss or None)."""
+    d_in, width, n_hidden, d_out = shape
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.empty((x.shape[0], d_out))
+    yy = np.ascontiguousarray(y, dtype=np.float64) if y is not None else None
+    loss = lib().orc_mlp_forward(d_in, width, n_hidden, d_out, _dp(params), x.shape[0], _dp(x),
+                                 _dp(yy) if yy is not None else None, _dp(out))
+    return out, (loss if y is not None else None)
+
+
+def mlp_loss_grad(shape, params, x, y):
+    d_in, width, n_hidden, d_out = shape
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    g = np.empty_like(params)
+    loss = lib().orc_mlp_loss_grad(d_in, width, n_hidden, d_out, _dp(params), x.shape[0], _dp(x),
+                                   _dp(y), _dp(g))
+    return loss, g

@@ -106,6 +106,14 @@ void orc_envelope_batch(const orc_material* mat, const orc_lamination* lam, long
                         const double* F, const double* beta_n, double* W, double* P,
                         orc_laminate* trees);
 
+/* Surrogate network oracle (mlp.c): FP64 MLP with SiLU hidden layers, flat
+ * parameter layout W_0, b_0, ..., W_out, b_out (row-major, out x in). */
+long orc_mlp_param_count(int d_in, int width, int n_hidden, int d_out);
+double orc_mlp_forward(int d_in, int width, int n_hidden, int d_out, const double* params,
+                       long B, const double* x, const double* y, double* out);
+double orc_mlp_loss_grad(int d_in, int width, int n_hidden, int d_out, const double* params,
+                         long B, const double* x, const double* y, double* grad);
+
 #ifdef __cplusplus
 }
 #endif

@@ -419,3 +419,36 @@ def test_direction_ties_take_the_smallest_index():
         assert W == min(vals)
         assert tree[0]["dir"] == vals.index(min(vals))
         assert vals.count(min(vals)) >= 2       # the case really is a tie
+
+
+# ---------------------------------------------------------------- surrogate network oracle
+
+def test_mlp_oracle_gradient_matches_finite_differences():
+    """Backpropagation of the FP64 network oracle against central differences of its loss."""
+    shape = (5, 12, 3, 5)
+    rng = np.random.default_rng(21)
+    npar = O.mlp_param_count(*shape)
+    assert npar == 12 * 5 + 12 + 2 * (12 * 12 + 12) + 5 * 12 + 5
+    params = rng.normal(0, 0.4, npar)
+    x = rng.normal(size=(7, 5))
+    y = rng.normal(size=(7, 5))
+    loss, g = O.mlp_loss_grad(shape, params, x, y)
+    _, loss2 = O.mlp_forward(shape, params, x, y)
+    assert abs(loss - loss2) < 1e-14
+    h = 1e-6
+    fd = np.empty(npar)
+    for k in range(npar):
+        e = np.zeros(npar)
+        e[k] = h
+        fd[k] = (O.mlp_forward(shape, params + e, x, y)[1] - O.mlp_forward(shape, params - e, x, y)[1]) / (2 * h)
+    assert np.max(np.abs(fd - g)) < 1e-8 * max(1.0, np.max(np.abs(g)))
+
+
+def test_mlp_oracle_forward_small_closed_form():
+    """One hidden unit, identity-like weights: out = w2 * silu(w1 x + b1) + b2."""
+    shape = (1, 1, 1, 1)
+    params = np.array([0.7, -0.2, 1.5, 0.3])
+    x = np.array([[0.4]])
+    out, _ = O.mlp_forward(shape, params, x)
+    z = 0.7 * 0.4 - 0.2
+    assert abs(out[0, 0] - (1.5 * z / (1 + math.exp(-z)) + 0.3)) < 1e-15
