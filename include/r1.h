@@ -168,6 +168,110 @@ r1_status r1_get_segment_width(r1_handle handle, int32_t n_t, r1_dtype dtype, in
 r1_status r1_autotune(r1_handle handle, const r1_material* material, int32_t n_t, r1_dtype dtype,
                       void* stream, int32_t* lanes);
 
+/* ---- learned surrogate ---------------------------------------------------------
+ *
+ * A multilayer perceptron (F, beta_n) -> (W^k, P^k) trained on lamination
+ * results, with plain lamination as fallback and judge.  Inputs x = (F_11 ..
+ * F_dd, beta_n) (d_in = d*d + 1), standardized with training statistics.  The
+ * network predicts the relaxation gap g = W(F) - W^k(F) >= 0 and dP = P0(F) -
+ * P^k(F); inference returns W(F) - max(g, 0) and P0(F) - dP with W(F) and
+ * P0(F) computed exactly, so W^k <= W holds by construction.  Hidden layers:
+ * n_hidden layers of `width` SiLU units; the width x width layers run as BF16
+ * MFMA with FP32 accumulation, the first layer (FP32 inputs) and the output
+ * layer in FP32.  Training: mean squared error on standardized targets, Adam,
+ * FP32 master weights, all on the device.
+ *
+ * A non-positive predicted gap means "no lamination": inference then returns
+ * W(F) and P0(F) exactly; training uses a one-sided (hinge) loss for rows that
+ * did not laminate and trains the stress outputs on laminating rows only.
+ *
+ * Routing at inference: a point goes to the fallback lamination when it lies
+ * outside the training box (per-input min/max of the training rows, det F above
+ * the smallest training det) or in a gate cell ((|F - I|, beta_n) bin x
+ * predicted class) that calibration did not accept.  Uncalibrated surrogates
+ * route on the box only.
+ *
+ * Packed rows (device, FP32, row-major): X[p] = (F_11, .., F_dd, beta_n),
+ * Y[p] = (W^k, P_11, .., P_dd).
+ */
+typedef struct r1_surrogate_s* r1_surrogate;
+
+typedef struct {
+    int32_t epochs;       /* passes over the training rows */
+    int32_t batch;        /* rows per Adam step, a multiple of 64 */
+    float lr;             /* Adam step size */
+    float beta1, beta2;   /* Adam moment decay */
+    float eps;            /* Adam denominator guard */
+    float val_fraction;   /* trailing fraction of the rows held out for the report */
+    float energy_weight;  /* weight of the energy output's squared error (stress outputs: 1) */
+    uint64_t seed;        /* shuffling */
+} r1_train_cfg;
+
+typedef struct {
+    int64_t steps;        /* Adam steps taken */
+    float train_loss;     /* mean loss over the last epoch */
+    float val_loss;       /* loss on the held-out rows */
+    double ms;            /* device time of the training loop, milliseconds */
+} r1_train_report;
+
+/* New network for d = dim (2 or 3): n_hidden in [2, 8] hidden layers of width in
+ * {32, 64, 128, 256}; weights drawn from a seeded uniform(-1/sqrt(fan_in), ..). */
+r1_status r1_surrogate_create(r1_handle handle, r1_surrogate* surrogate, int32_t dim,
+                              int32_t n_hidden, int32_t width, uint64_t seed);
+r1_status r1_surrogate_destroy(r1_surrogate surrogate);
+
+/* Packs lamination inputs/outputs (SoA, dtype) into rows X (n x (d*d+1)) and
+ * Y (n x (d*d+1)). */
+r1_status r1_surrogate_pack(r1_handle handle, int32_t dim, int64_t n, r1_dtype dtype,
+                            const void* F, const void* beta_n, const void* W, const void* P,
+                            float* X, float* Y, void* stream);
+
+/* Trains on n packed rows (the last cfg->val_fraction held out): computes the
+ * input and target statistics and the training box, then runs the epochs with
+ * a cosine decay of the step size from cfg->lr to 0.02 cfg->lr.
+ * Synchronizes `stream`; report (nullable) is host memory. */
+r1_status r1_surrogate_train(r1_handle handle, r1_surrogate surrogate, const r1_material* material,
+                             const float* X, const float* Y, int64_t n, const r1_train_cfg* cfg,
+                             r1_train_report* report, void* stream);
+
+/* Error gate: predicts n packed validation rows (X, Y from plain lamination)
+ * and, per cell = (|F - I|, beta_n) bin x predicted class (no lamination /
+ * lamination), counts the rows with |W_pred - W^k| / max(|W^k|, 1e-2) > tol.
+ * A cell is used at inference when it saw at least 16 rows and a fraction of at
+ * least `quantile` of them was within tol; other cells fall back.
+ * cells_allowed (nullable, host) receives the number of usable cells (of
+ * 2 x 16 x 8).  Synchronizes `stream`. */
+r1_status r1_surrogate_calibrate(r1_handle handle, r1_surrogate surrogate,
+                                 const r1_material* material, const float* X, const float* Y,
+                                 int64_t n, float tol, float quantile, int32_t* cells_allowed,
+                                 void* stream);
+
+/* W and P (SoA, dtype) for n points: the network where the gates accept, plain
+ * lamination with `fallback` elsewhere (flag R1_PT_FALLBACK).  n_fallback
+ * (nullable, host) receives the number of fallback points.  Synchronizes
+ * `stream` once to size the fallback launch. */
+r1_status r1_surrogate_infer(r1_handle handle, r1_surrogate surrogate, const r1_material* material,
+                             const r1_lamination* fallback, int64_t n, r1_dtype dtype,
+                             const void* F, const void* beta_n, void* W, void* P,
+                             int32_t* flags, int64_t* n_fallback, void* stream);
+
+/* Checks and persistence.  Parameters are the flat FP32 master weights in the
+ * order W_0, b_0, .., W_{n_hidden-1}, b_{n_hidden-1}, W_out, b_out (row-major,
+ * out x in), host memory.  loss_grad runs one forward and backward pass on n
+ * already standardized rows (Xn: n x d_in, Yn: n x d_out, device) without
+ * updating, writing the loss (host) and the gradient (device, same layout). */
+r1_status r1_surrogate_param_count(r1_surrogate surrogate, int64_t* count);
+r1_status r1_surrogate_get_params(r1_surrogate surrogate, float* params, int64_t count);
+r1_status r1_surrogate_set_params(r1_surrogate surrogate, const float* params, int64_t count);
+/* Standardization: x_mean, x_std (d_in), y_mean, y_std (d_out), host arrays. */
+r1_status r1_surrogate_get_norm(r1_surrogate surrogate, float* x_mean, float* x_std,
+                                float* y_mean, float* y_std);
+r1_status r1_surrogate_loss_grad(r1_handle handle, r1_surrogate surrogate, const float* Xn,
+                                 const float* Yn, int64_t n, float* grad, float* loss,
+                                 void* stream);
+r1_status r1_surrogate_save(r1_surrogate surrogate, const char* path);
+r1_status r1_surrogate_load(r1_handle handle, r1_surrogate* surrogate, const char* path);
+
 /* ---- measurement ---------------------------------------------------------------- */
 
 /* When enabled, every kernel launch of the handle is bracketed by HIP events

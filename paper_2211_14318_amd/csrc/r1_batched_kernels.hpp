@@ -66,10 +66,12 @@ __device__ void b_finalize(int var, const KArgs& a, int64_t p, const Level& lo, 
   }
 }
 
-static __global__ void k_zero_ints(int* p, int64_t n) {
+namespace {
+__global__ void k_zero_ints(int* p, int64_t n) {
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
     p[i] = 0;
 }
+}  // namespace
 
 template <typename T, int D>
 __global__ __launch_bounds__(256) void k_batched(BArgs b) {

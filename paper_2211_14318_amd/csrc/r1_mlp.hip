@@ -1,0 +1,668 @@
+// Kernels of the learned surrogate (gfx950): BF16 MFMA (v_mfma_f32_32x32x16_bf16,
+// FP32 accumulation) for the width x width layers, FP32 for the small first and
+// last layers, fused epilogues, Adam, and the fused inference kernel with the
+// routing gates.
+//
+// MFMA 32x32x16 lane layout (64 lanes): A fragment = row (lane % 32), k =
+// 8*(lane/32) .. +7; B fragment = column (lane % 32), same k; accumulator j of
+// lane l holds row 8*(j/4) + 4*(l/32) + (j%4), column l % 32.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "r1_device.hpp"
+#include "r1_mlp.hpp"
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+namespace r1m {
+
+__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu(float z) { return z * sigm(z); }
+__device__ __forceinline__ float silu_d(float z) {
+  float s = sigm(z);
+  return s * (1.0f + z * (1.0f - s));
+}
+__device__ __forceinline__ float bfr(float x) { return float(__bf16(x)); }   // BF16 rounding
+
+template <typename TB>
+__device__ __forceinline__ __bf16 to_bf(TB v) { return __bf16(v); }
+
+// C(m, n) = sum_k A(m, k) B(n, k) with A(m, k) = A[m*sam + k*sak] (FP32, rounded
+// to BF16 on load) and B(n, k) = B[n*sbn + k*sbk].  Block 4 waves = 64 x 64
+// tile, wave 32 x 32; blockIdx.z splits K in chunks of kchunk.
+// M, N multiples of 32, K and kchunk multiples of 16 (checked by the host).
+template <typename TB, int EPI>
+__global__ __launch_bounds__(256) void k_gemm_nt(int M, int N, int K, const float* A, int64_t sam,
+                                                 int64_t sak, const TB* B, int64_t sbn, int64_t sbk,
+                                                 float* C, int64_t ldc, const float* bias,
+                                                 const float* zaux, float* H, int kchunk) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int m0 = blockIdx.y * 64 + (wave >> 1) * 32;
+  const int n0 = blockIdx.x * 64 + (wave & 1) * 32;
+  if (m0 >= M || n0 >= N) return;
+  const int kb = blockIdx.z * kchunk;
+  const int ke = min(K, kb + kchunk);
+  const int r = lane & 31, kq = 8 * (lane >> 5);
+  f32x16 acc = {};
+  const float* Ar = A + int64_t(m0 + r) * sam;
+  const TB* Br = B + int64_t(n0 + r) * sbn;
+  for (int k0 = kb; k0 < ke; k0 += 16) {
+    bf16x8 a, b;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      a[i] = __bf16(Ar[int64_t(k0 + kq + i) * sak]);
+      b[i] = to_bf(Br[int64_t(k0 + kq + i) * sbk]);
+    }
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int row = m0 + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
+    const int col = n0 + r;
+    const int64_t o = int64_t(row) * ldc + col;
+    float v = acc[j];
+    if (EPI == kEpiBiasSilu) {
+      v += bias[col];
+      C[o] = v;
+      H[o] = silu(v);
+    } else if (EPI == kEpiDsilu) {
+      C[o] = v * silu_d(zaux[o]);
+    } else {
+      atomicAdd(&C[o], v);
+    }
+  }
+}
+
+// First layer (FP32): Z = X W0^T + b0, H = SiLU(Z).  X: B x d_in, W0: w x d_in.
+__global__ void k_first_fwd(int B, int d_in, int w, const float* X, const float* W, const float* b,
+                            float* Z, float* H) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= int64_t(B) * w) return;
+  const int64_t row = i / w;
+  const int o = int(i % w);
+  float z = b[o];
+  for (int k = 0; k < d_in; ++k) z = fmaf(W[o * d_in + k], X[row * d_in + k], z);
+  Z[i] = z;
+  H[i] = silu(z);
+}
+
+// Output layer (FP32 weights, BF16-rounded activations as at inference), loss and
+// dL/dout.  G is B x 32 (columns >= d_out are zero) for the padded gradient GEMMs.
+// Rows whose standardized gap target is <= z_thr did not laminate: their gap
+// output only has to stay below z_thr - margin (one-sided squared hinge) and
+// their stress outputs are not trained (inference then returns W(F), P0(F)).
+// The energy output's squared error is weighted by ew.
+__global__ void k_out_fwd_loss(int B, int w, int d_out, const float* H, const float* Wo,
+                               const float* bo, const float* Y, float z_thr, float margin,
+                               float ew, float* G, float* loss_acc) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  float e2 = 0.0f;
+  if (i < int64_t(B) * 32) {
+    const int64_t row = i / 32;
+    const int j = int(i % 32);
+    float g = 0.0f;
+    if (j < d_out) {
+      float o = bo[j];
+      for (int k = 0; k < w; ++k) o = fmaf(Wo[j * w + k], bfr(H[row * w + k]), o);
+      const bool convex = Y[row * d_out] <= z_thr;
+      float e;
+      if (!convex) e = o - Y[row * d_out + j];
+      else if (j == 0) e = fmaxf(0.0f, o - (z_thr - margin));
+      else e = 0.0f;
+      const float wj = j == 0 ? ew : 1.0f;
+      e2 = wj * e * e;
+      g = 2.0f * wj * e / float(int64_t(B) * d_out);
+    }
+    G[i] = g;
+  }
+  // block sum of the squared errors
+  __shared__ float red[256];
+  red[threadIdx.x] = e2;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(loss_acc, red[0] / float(int64_t(B) * d_out));
+}
+
+// Column sums of a B x ncol matrix into out (accumulated with atomics).
+__global__ void k_colsum(int B, int ncol, int ld, const float* A, float* out) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= ncol) return;
+  const int rows_per = (B + gridDim.y - 1) / gridDim.y;
+  const int r0 = blockIdx.y * rows_per, r1 = min(B, r0 + rows_per);
+  float s = 0.0f;
+  for (int r = r0; r < r1; ++r) s += A[int64_t(r) * ld + col];
+  atomicAdd(&out[col], s);
+}
+
+// out[o][i] += sum_b D[b*ldd + o] X[b*ldx + i] for small o, i ranges (first- and
+// output-layer weight gradients); round_x rounds X to BF16 as the forward pass did.
+__global__ void k_outer_small(int B, int no, int ni, const float* D, int ldd, const float* X, int ldx,
+                              int round_x, float* out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= no * ni) return;
+  const int o = t / ni, i = t % ni;
+  const int rows_per = (B + gridDim.y - 1) / gridDim.y;
+  const int r0 = blockIdx.y * rows_per, r1 = min(B, r0 + rows_per);
+  float s = 0.0f;
+  for (int r = r0; r < r1; ++r) {
+    float x = X[int64_t(r) * ldx + i];
+    s = fmaf(D[int64_t(r) * ldd + o], round_x ? bfr(x) : x, s);
+  }
+  atomicAdd(&out[t], s);
+}
+
+// delta of the last hidden layer: (G Wout) * SiLU'(Z), G: B x 32 (d_out used).
+__global__ void k_out_bwd_dh(int B, int w, int d_out, const float* G, const float* Wo, const float* Z,
+                             float* Dl) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= int64_t(B) * w) return;
+  const int64_t row = i / w;
+  const int k = int(i % w);
+  float s = 0.0f;
+  for (int j = 0; j < d_out; ++j) s = fmaf(G[row * 32 + j], Wo[j * w + k], s);
+  Dl[i] = s * silu_d(Z[i]);
+}
+
+// Packed rows -> SoA F (float) and beta_n.
+__global__ void k_unpack(int dd, int64_t n, const float* X, float* F, float* bn) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  for (int k = 0; k < dd; ++k) F[int64_t(k) * n + p] = X[p * (dd + 1) + k];
+  bn[p] = X[p * (dd + 1) + dd];
+}
+
+__global__ void k_adam(int64_t n, float* p, const float* g, float* m, float* v, float lr, float b1,
+                       float b2, float eps, float c1, float c2) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float gi = g[i];
+  float mi = b1 * m[i] + (1.0f - b1) * gi;
+  float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void k_to_bf16(int64_t n, const float* src, __bf16* dst) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = __bf16(src[i]);
+}
+
+__global__ void k_fill(int64_t n, float* p, float v) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Minibatch rows: row i of the batch is training row (a*(s*B + i) + c) mod n_train
+// (a permutation when gcd(a, n_train) = 1), standardized.
+__global__ void k_gather(int B, int64_t n_train, uint64_t a, uint64_t c, int64_t step, int d_in,
+                         int d_out, const float* X, const float* T, const float* xm,
+                         const float* xs, const float* ym, const float* ys, float* Xb, float* Yb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B) return;
+  const uint64_t q = (uint64_t(step) * uint64_t(B) + uint64_t(i)) % uint64_t(n_train);
+  const int64_t row = int64_t((a % uint64_t(n_train)) * q % uint64_t(n_train) + c % uint64_t(n_train)) % n_train;
+  for (int k = 0; k < d_in; ++k) Xb[int64_t(i) * d_in + k] = (X[row * d_in + k] - xm[k]) / xs[k];
+  for (int k = 0; k < d_out; ++k) Yb[int64_t(i) * d_out + k] = (T[row * d_out + k] - ym[k]) / ys[k];
+}
+
+// Rows [r0, r1) standardized (validation set).
+__global__ void k_standardize(int64_t r0, int64_t r1, int d_in, int d_out, const float* X,
+                              const float* T, const float* xm, const float* xs, const float* ym,
+                              const float* ys, float* Xb, float* Yb) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r0 + i >= r1) return;
+  const int64_t row = r0 + i;
+  for (int k = 0; k < d_in; ++k) Xb[i * d_in + k] = (X[row * d_in + k] - xm[k]) / xs[k];
+  for (int k = 0; k < d_out; ++k) Yb[i * d_out + k] = (T[row * d_out + k] - ym[k]) / ys[k];
+}
+
+// Gap-form targets from packed rows: T = (W(F) - W^k, P0(F) - P^k), W and P0 of
+// the unrelaxed potential (eq. 2.9, 2.12) in double.
+template <int D>
+__global__ void k_targets(int64_t n, r1d::Material mat, const float* X, const float* Y, float* T) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  constexpr int DI = D * D + 1;
+  double G[D * D], cof[D * D], P0[D * D];
+  for (int k = 0; k < D * D; ++k) G[k] = X[p * DI + k];
+  const double bn = X[p * DI + D * D];
+  r1d::Point<double> q = r1d::make_point<double>(mat, bn);
+  r1d::cofactor<D>(G, cof);
+  const double w = r1d::w_point<double, D>(q, G, cof);
+  r1d::stress0<D>(mat, bn, G, P0);
+  T[p * DI] = float(w - double(Y[p * DI]));
+  for (int k = 0; k < D * D; ++k) T[p * DI + 1 + k] = float(P0[k] - double(Y[p * DI + 1 + k]));
+}
+
+__device__ __forceinline__ void atomic_min_f(float* a, float v) {
+  int* ai = reinterpret_cast<int*>(a);
+  int old = *ai;
+  while (v < __int_as_float(old)) {
+    int assumed = old;
+    old = atomicCAS(ai, assumed, __float_as_int(v));
+    if (old == assumed) break;
+  }
+}
+__device__ __forceinline__ void atomic_max_f(float* a, float v) {
+  int* ai = reinterpret_cast<int*>(a);
+  int old = *ai;
+  while (v > __int_as_float(old)) {
+    int assumed = old;
+    old = atomicCAS(ai, assumed, __float_as_int(v));
+    if (old == assumed) break;
+  }
+}
+
+// Per-column sum, sum of squares, minimum and maximum over rows [0, n) of a
+// row-major n x ncol matrix (ncol <= kMaxCols), and (when dF > 0) the smallest
+// det of the dF x dF matrices in the first dF*dF columns.  Block-reduced, one
+// atomic per block and column.  stats layout: sum[c], sum2[c] (double);
+// mn[c], mx[c], det_min (float).
+__global__ __launch_bounds__(256) void k_colstats(int64_t n, int ncol, int dF, const float* A,
+                                                  double* sum, double* sum2, float* mn, float* mx,
+                                                  float* det_min) {
+  double s[kMaxCols], s2[kMaxCols];
+  float lo[kMaxCols], hi[kMaxCols];
+  float dmin = __builtin_inff();
+  for (int c = 0; c < kMaxCols; ++c) { s[c] = 0; s2[c] = 0; lo[c] = __builtin_inff(); hi[c] = -__builtin_inff(); }
+  for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < n; p += int64_t(gridDim.x) * blockDim.x) {
+    const float* row = A + p * ncol;
+    for (int c = 0; c < kMaxCols; ++c) {
+      if (c >= ncol) break;
+      float v = row[c];
+      s[c] += v; s2[c] += double(v) * v;
+      lo[c] = fminf(lo[c], v); hi[c] = fmaxf(hi[c], v);
+    }
+    if (dF == 2) dmin = fminf(dmin, row[0] * row[3] - row[1] * row[2]);
+    if (dF == 3)
+      dmin = fminf(dmin, row[0] * (row[4] * row[8] - row[5] * row[7]) - row[1] * (row[3] * row[8] - row[5] * row[6]) +
+                             row[2] * (row[3] * row[7] - row[4] * row[6]));
+  }
+  __shared__ double rs[256];
+  __shared__ float rf[256];
+  for (int c = 0; c < ncol; ++c) {
+    rs[threadIdx.x] = s[c];
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) { if (threadIdx.x < k) rs[threadIdx.x] += rs[threadIdx.x + k]; __syncthreads(); }
+    if (threadIdx.x == 0) atomicAdd(&sum[c], rs[0]);
+    __syncthreads();
+    rs[threadIdx.x] = s2[c];
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) { if (threadIdx.x < k) rs[threadIdx.x] += rs[threadIdx.x + k]; __syncthreads(); }
+    if (threadIdx.x == 0) atomicAdd(&sum2[c], rs[0]);
+    __syncthreads();
+    rf[threadIdx.x] = lo[c];
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) { if (threadIdx.x < k) rf[threadIdx.x] = fminf(rf[threadIdx.x], rf[threadIdx.x + k]); __syncthreads(); }
+    if (threadIdx.x == 0) atomic_min_f(&mn[c], rf[0]);
+    __syncthreads();
+    rf[threadIdx.x] = hi[c];
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) { if (threadIdx.x < k) rf[threadIdx.x] = fmaxf(rf[threadIdx.x], rf[threadIdx.x + k]); __syncthreads(); }
+    if (threadIdx.x == 0) atomic_max_f(&mx[c], rf[0]);
+    __syncthreads();
+  }
+  if (dF > 0) {
+    rf[threadIdx.x] = dmin;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) { if (threadIdx.x < k) rf[threadIdx.x] = fminf(rf[threadIdx.x], rf[threadIdx.x + k]); __syncthreads(); }
+    if (threadIdx.x == 0) atomic_min_f(det_min, rf[0]);
+  }
+}
+
+// Packs SoA lamination data into rows: X = (F, beta_n), Y = (W, P).
+template <typename T, int D>
+__global__ void k_pack(int64_t n, const T* F, const T* bn, const T* W, const T* P, float* X, float* Y) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  constexpr int DI = D * D + 1;
+  for (int k = 0; k < D * D; ++k) X[p * DI + k] = float(F[int64_t(k) * n + p]);
+  X[p * DI + D * D] = float(bn[p]);
+  Y[p * DI] = float(W[p]);
+  for (int k = 0; k < D * D; ++k) Y[p * DI + 1 + k] = float(P[int64_t(k) * n + p]);
+}
+
+// Bin of a point for the error gate: radius |F - I|_F over [0, r_max) and beta_n
+// over [b_lo, b_hi), clamped.
+template <int D>
+__device__ __forceinline__ int gate_bin(const InferParams& ip, const double* F, double bn) {
+  double r2 = 0.0;
+  for (int i = 0; i < D; ++i)
+    for (int j = 0; j < D; ++j) {
+      double e = F[i * D + j] - (i == j ? 1.0 : 0.0);
+      r2 += e * e;
+    }
+  int br = int(sqrt(r2) / ip.r_max * kBinsR);
+  int bb = int((bn - ip.b_lo) / (ip.b_hi - ip.b_lo) * kBinsB);
+  br = br < 0 ? 0 : (br >= kBinsR ? kBinsR - 1 : br);
+  bb = bb < 0 ? 0 : (bb >= kBinsB ? kBinsB - 1 : bb);
+  return br * kBinsB + bb;
+}
+
+// Fused inference: 4 waves x 32 points per block.  Per point: load F, beta_n;
+// gates; first layer (FP32) into the wave's LDS activations (BF16); each hidden
+// width x width layer as 32 x 16-deep MFMA tiles with B fragments read from the
+// BF16 weights in global memory (L2-resident), bias + SiLU, back to LDS; output
+// layer in FP32; exact W(F), P0(F); W = W(F) - max(g, 0), P = P0 - dP.
+// MODE 0: gates on, rejected points appended to the fallback list.
+// MODE 1 (calibration): box gate only; the bin index and predicted W go to
+// cal_bin / cal_w, rejected points get bin -1.
+template <typename T, int D, int WID, int MODE>
+__global__ __launch_bounds__(256) void k_infer(InferParams ip, const T* F, const T* bn, T* W,
+                                               T* P, int32_t* flags, int* fb_count,
+                                               int32_t* fb_list, int* cal_bin, float* cal_w) {
+  constexpr int DI = D * D + 1, DO = D * D + 1;
+  constexpr int LD = WID + 8;                      // padded BF16 row stride (bank spread)
+  extern __shared__ char smem[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __bf16* act = reinterpret_cast<__bf16*>(smem) + wave * 32 * LD;
+  const int r = lane & 31, half = lane >> 5;
+  const int64_t pt = int64_t(blockIdx.x) * 128 + wave * 32 + r;
+  const bool valid = pt < ip.n;
+  const int64_t pc = valid ? pt : ip.n - 1;        // clamp for loads
+  double G[D * D];
+  for (int k = 0; k < D * D; ++k) G[k] = double(F[int64_t(k) * ip.n + pc]);
+  const double b = double(bn[pc]);
+  float x[DI];
+  bool ok = true;
+  for (int k = 0; k < DI; ++k) {
+    float raw = k < D * D ? float(G[k]) : float(b);
+    ok = ok && raw >= ip.x_lo[k] && raw <= ip.x_hi[k];
+    x[k] = (raw - ip.x_mean[k]) / ip.x_std[k];
+  }
+  double cof[D * D];
+  r1d::cofactor<D>(G, cof);
+  const double det = r1d::det_of<D>(G, cof);
+  ok = ok && det >= double(ip.det_lo);
+  const int bin = gate_bin<D>(ip, G, b);
+  // first layer: this lane computes features [half*WID/2, (half+1)*WID/2)
+  for (int f = half * (WID / 2); f < (half + 1) * (WID / 2); ++f) {
+    float z = ip.b[0][f];
+    for (int k = 0; k < DI; ++k) z = fmaf(ip.w0[f * DI + k], x[k], z);
+    act[r * LD + f] = __bf16(silu(z));
+  }
+  __syncthreads();
+  // hidden width x width layers on the matrix cores
+  for (int l = 1; l < ip.n_hidden; ++l) {
+    const __bf16* Wl = static_cast<const __bf16*>(ip.wbf[l]);
+    f32x16 acc[WID / 32];
+#pragma unroll
+    for (int t = 0; t < WID / 32; ++t) acc[t] = f32x16{};
+    for (int k0 = 0; k0 < WID; k0 += 16) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(act + r * LD + k0 + 8 * half);
+#pragma unroll
+      for (int t = 0; t < WID / 32; ++t) {
+        const bf16x8 bw = *reinterpret_cast<const bf16x8*>(Wl + (t * 32 + r) * WID + k0 + 8 * half);
+        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bw, acc[t], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < WID / 32; ++t)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int row = 8 * (j >> 2) + 4 * half + (j & 3);
+        const int col = t * 32 + r;
+        act[row * LD + col] = __bf16(silu(acc[t][j] + ip.b[l][col]));
+      }
+    __syncthreads();
+  }
+  // output layer: each lane sums half the features of its point, partner completes
+  float out[DO];
+  for (int j = 0; j < DO; ++j) {
+    float s = 0.0f;
+    for (int k = half * (WID / 2); k < (half + 1) * (WID / 2); ++k)
+      s = fmaf(ip.wout[j * WID + k], float(act[r * LD + k]), s);
+    s += __shfl_xor(s, 32);
+    out[j] = s + ip.bout[j];
+  }
+  if (half != 0 || !valid) return;
+  // de-standardize; a non-positive gap means no lamination: W(F), P0(F) exactly
+  const double raw = double(out[0] * ip.y_std[0] + ip.y_mean[0]);
+  const bool convex = raw <= 0.0;
+  const int cls = convex ? 0 : 1;
+  r1d::Point<double> q = r1d::make_point<double>(ip.mat, b);
+  const double w_un = r1d::w_point<double, D>(q, G, cof);
+  const double wpred = convex ? w_un : w_un - raw;
+  if (MODE == 1) {
+    cal_bin[pt] = ok ? 2 * bin + cls : -1;
+    cal_w[pt] = float(wpred);
+    return;
+  }
+  if (ip.bins_on) ok = ok && ip.bin_ok[2 * bin + cls];
+  if (!ok || !(det > 0.0)) {
+    const int slot = atomicAdd(fb_count, 1);
+    fb_list[slot] = int32_t(pt);
+    return;
+  }
+  double P0[D * D];
+  r1d::stress0<D>(ip.mat, b, G, P0);
+  W[pt] = T(wpred);
+  for (int k = 0; k < D * D; ++k)
+    P[int64_t(k) * ip.n + pt] =
+        T(convex ? P0[k] : P0[k] - double(out[1 + k] * ip.y_std[1 + k] + ip.y_mean[1 + k]));
+  if (flags) flags[pt] = 0;
+}
+
+// Per (bin, predicted class) count of calibration points and of points whose
+// relative energy error exceeds tol.
+__global__ void k_bin_error(int64_t n, int DI, const float* Y, const int* cal_bin, const float* cal_w,
+                            float tol, int* bin_bad, int* bin_cnt) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int b = cal_bin[p];
+  if (b < 0) return;
+  const float ref = Y[p * DI];
+  const float e = fabsf(cal_w[p] - ref) / fmaxf(fabsf(ref), 1e-2f);
+  atomicAdd(&bin_cnt[b], 1);
+  if (!(e <= tol)) atomicAdd(&bin_bad[b], 1);
+}
+
+// Gather fallback points into compact SoA arrays, and scatter their results back.
+template <typename T, int D>
+__global__ void k_fb_gather(int64_t n, int nfb, const int32_t* list, const T* F, const T* bn, T* Fc,
+                            T* bc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nfb) return;
+  const int64_t p = list[i];
+  for (int k = 0; k < D * D; ++k) Fc[int64_t(k) * nfb + i] = F[int64_t(k) * n + p];
+  bc[i] = bn[p];
+}
+
+template <typename T, int D>
+__global__ void k_fb_scatter(int64_t n, int nfb, const int32_t* list, const T* Wc, const T* Pc,
+                             const int32_t* fc, T* W, T* P, int32_t* flags) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nfb) return;
+  const int64_t p = list[i];
+  W[p] = Wc[i];
+  for (int k = 0; k < D * D; ++k) P[int64_t(k) * n + p] = Pc[int64_t(k) * nfb + i];
+  if (flags) flags[p] = fc[i] | R1_PT_FALLBACK;
+}
+
+}  // namespace r1m
+
+// ---- launchers -----------------------------------------------------------------
+
+using namespace r1m;
+
+static inline unsigned nblk(int64_t n, int b = 256) { return unsigned((n + b - 1) / b); }
+
+hipError_t r1m_gemm(int epi, bool b_bf16, int M, int N, int K, const float* A, int64_t sam,
+                    int64_t sak, const void* B, int64_t sbn, int64_t sbk, float* C, int64_t ldc,
+                    const float* bias, const float* zaux, float* H, int ksplit, hipStream_t st) {
+  int kchunk = ((K / ksplit + 15) / 16) * 16;
+  if (kchunk < 16) kchunk = 16;
+  dim3 grid(unsigned((N + 63) / 64), unsigned((M + 63) / 64), unsigned((K + kchunk - 1) / kchunk));
+#define R1G(TB, E) hipLaunchKernelGGL((k_gemm_nt<TB, E>), grid, dim3(256), 0, st, M, N, K, A, sam, sak, \
+                                      static_cast<const TB*>(B), sbn, sbk, C, ldc, bias, zaux, H, kchunk)
+  if (b_bf16) {
+    if (epi == kEpiBiasSilu) R1G(__bf16, kEpiBiasSilu);
+    else if (epi == kEpiDsilu) R1G(__bf16, kEpiDsilu);
+    else R1G(__bf16, kEpiAtomic);
+  } else {
+    if (epi == kEpiBiasSilu) R1G(float, kEpiBiasSilu);
+    else if (epi == kEpiDsilu) R1G(float, kEpiDsilu);
+    else R1G(float, kEpiAtomic);
+  }
+#undef R1G
+  return hipGetLastError();
+}
+
+hipError_t r1m_first_fwd(int B, int d_in, int w, const float* X, const float* W, const float* b,
+                         float* Z, float* H, hipStream_t st) {
+  hipLaunchKernelGGL(k_first_fwd, dim3(nblk(int64_t(B) * w)), dim3(256), 0, st, B, d_in, w, X, W, b, Z, H);
+  return hipGetLastError();
+}
+
+hipError_t r1m_out_fwd_loss(int B, int w, int d_out, const float* H, const float* Wo, const float* bo,
+                            const float* Y, float z_thr, float margin, float ew, float* G, float* loss,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_out_fwd_loss, dim3(nblk(int64_t(B) * 32)), dim3(256), 0, st, B, w, d_out, H, Wo,
+                     bo, Y, z_thr, margin, ew, G, loss);
+  return hipGetLastError();
+}
+
+hipError_t r1m_colsum(int B, int ncol, int ld, const float* A, float* out, hipStream_t st) {
+  dim3 grid(nblk(ncol, 64), unsigned(B >= 4096 ? 32 : (B + 127) / 128));
+  hipLaunchKernelGGL(k_colsum, grid, dim3(64), 0, st, B, ncol, ld, A, out);
+  return hipGetLastError();
+}
+
+hipError_t r1m_outer_small(int B, int no, int ni, const float* D, int ldd, const float* X, int ldx,
+                           int round_x, float* out, hipStream_t st) {
+  dim3 grid(nblk(int64_t(no) * ni), unsigned(B >= 4096 ? 32 : (B + 127) / 128));
+  hipLaunchKernelGGL(k_outer_small, grid, dim3(256), 0, st, B, no, ni, D, ldd, X, ldx, round_x, out);
+  return hipGetLastError();
+}
+
+hipError_t r1m_out_bwd_dh(int B, int w, int d_out, const float* G, const float* Wo, const float* Z,
+                          float* Dl, hipStream_t st) {
+  hipLaunchKernelGGL(k_out_bwd_dh, dim3(nblk(int64_t(B) * w)), dim3(256), 0, st, B, w, d_out, G, Wo, Z, Dl);
+  return hipGetLastError();
+}
+
+hipError_t r1m_unpack(int dim, int64_t n, const float* X, float* F, float* bn, hipStream_t st) {
+  hipLaunchKernelGGL(k_unpack, dim3(nblk(n)), dim3(256), 0, st, dim * dim, n, X, F, bn);
+  return hipGetLastError();
+}
+
+hipError_t r1m_adam(int64_t n, float* p, const float* g, float* m, float* v, float lr, float b1,
+                    float b2, float eps, int64_t t, hipStream_t st) {
+  float c1 = 1.0f - powf(b1, float(t)), c2 = 1.0f - powf(b2, float(t));
+  hipLaunchKernelGGL(k_adam, dim3(nblk(n)), dim3(256), 0, st, n, p, g, m, v, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t r1m_to_bf16(int64_t n, const float* src, void* dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_to_bf16, dim3(nblk(n)), dim3(256), 0, st, n, src, static_cast<__bf16*>(dst));
+  return hipGetLastError();
+}
+
+hipError_t r1m_fill(int64_t n, float* p, float v, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill, dim3(nblk(n)), dim3(256), 0, st, n, p, v);
+  return hipGetLastError();
+}
+
+hipError_t r1m_gather(int B, int64_t n_train, uint64_t a, uint64_t c, int64_t step, int d_in, int d_out,
+                      const float* X, const float* T, const float* norm, float* Xb, float* Yb,
+                      hipStream_t st) {
+  // norm = x_mean (d_in), x_std (d_in), y_mean (d_out), y_std (d_out)
+  hipLaunchKernelGGL(k_gather, dim3(nblk(B)), dim3(256), 0, st, B, n_train, a, c, step, d_in, d_out, X, T,
+                     norm, norm + d_in, norm + 2 * d_in, norm + 2 * d_in + d_out, Xb, Yb);
+  return hipGetLastError();
+}
+
+hipError_t r1m_standardize(int64_t r0, int64_t r1, int d_in, int d_out, const float* X, const float* T,
+                           const float* norm, float* Xb, float* Yb, hipStream_t st) {
+  hipLaunchKernelGGL(k_standardize, dim3(nblk(r1 - r0)), dim3(256), 0, st, r0, r1, d_in, d_out, X, T, norm,
+                     norm + d_in, norm + 2 * d_in, norm + 2 * d_in + d_out, Xb, Yb);
+  return hipGetLastError();
+}
+
+hipError_t r1m_targets(int dim, int64_t n, const r1d::Material& mat, const float* X, const float* Y,
+                       float* T, hipStream_t st) {
+  if (dim == 2) hipLaunchKernelGGL(k_targets<2>, dim3(nblk(n)), dim3(256), 0, st, n, mat, X, Y, T);
+  else hipLaunchKernelGGL(k_targets<3>, dim3(nblk(n)), dim3(256), 0, st, n, mat, X, Y, T);
+  return hipGetLastError();
+}
+
+hipError_t r1m_colstats(int64_t n, int ncol, int dF, const float* A, double* sum, double* sum2, float* mn,
+                        float* mx, float* det_min, hipStream_t st) {
+  unsigned g = nblk(n);
+  if (g > 1024) g = 1024;
+  hipLaunchKernelGGL(k_colstats, dim3(g), dim3(256), 0, st, n, ncol, dF, A, sum, sum2, mn, mx, det_min);
+  return hipGetLastError();
+}
+
+hipError_t r1m_pack(int dtype, int dim, int64_t n, const void* F, const void* bn, const void* W,
+                    const void* P, float* X, float* Y, hipStream_t st) {
+#define R1P(T, D) hipLaunchKernelGGL((k_pack<T, D>), dim3(nblk(n)), dim3(256), 0, st, n, static_cast<const T*>(F), \
+                                     static_cast<const T*>(bn), static_cast<const T*>(W), static_cast<const T*>(P), X, Y)
+  if (dtype == R1_F32) { if (dim == 2) R1P(float, 2); else R1P(float, 3); }
+  else { if (dim == 2) R1P(double, 2); else R1P(double, 3); }
+#undef R1P
+  return hipGetLastError();
+}
+
+size_t r1m_infer_lds(int width) { return size_t(4) * 32 * (width + 8) * 2; }
+
+template <typename T, int D>
+static hipError_t infer_TD(const InferParams& ip, int mode, const void* F, const void* bn, void* W, void* P,
+                           int32_t* flags, int* fb_count, int32_t* fb_list, int* cal_bin, float* cal_w,
+                           hipStream_t st) {
+  dim3 grid(unsigned((ip.n + 127) / 128));
+  size_t lds = r1m_infer_lds(ip.width);
+#define R1I(WID, MODE) (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_infer<T, D, WID, MODE>), \
+      hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)); \
+  hipLaunchKernelGGL((k_infer<T, D, WID, MODE>), grid, dim3(256), lds, st, ip, \
+      static_cast<const T*>(F), static_cast<const T*>(bn), static_cast<T*>(W), static_cast<T*>(P), flags, \
+      fb_count, fb_list, cal_bin, cal_w)
+#define R1W(WID) if (ip.width == WID) { if (mode == 0) { R1I(WID, 0); } else { R1I(WID, 1); } return hipGetLastError(); }
+  R1W(32) R1W(64) R1W(128) R1W(256)
+#undef R1W
+#undef R1I
+  return hipErrorInvalidValue;
+}
+
+hipError_t r1m_infer(int dtype, int dim, const InferParams& ip, int mode, const void* F, const void* bn,
+                     void* W, void* P, int32_t* flags, int* fb_count, int32_t* fb_list, int* cal_bin,
+                     float* cal_w, hipStream_t st) {
+  if (dtype == R1_F32)
+    return dim == 2 ? infer_TD<float, 2>(ip, mode, F, bn, W, P, flags, fb_count, fb_list, cal_bin, cal_w, st)
+                    : infer_TD<float, 3>(ip, mode, F, bn, W, P, flags, fb_count, fb_list, cal_bin, cal_w, st);
+  return dim == 2 ? infer_TD<double, 2>(ip, mode, F, bn, W, P, flags, fb_count, fb_list, cal_bin, cal_w, st)
+                  : infer_TD<double, 3>(ip, mode, F, bn, W, P, flags, fb_count, fb_list, cal_bin, cal_w, st);
+}
+
+hipError_t r1m_bin_error(int64_t n, int DI, const float* Y, const int* cal_bin, const float* cal_w,
+                         float tol, int* bin_bad, int* bin_cnt, hipStream_t st) {
+  hipLaunchKernelGGL(k_bin_error, dim3(nblk(n)), dim3(256), 0, st, n, DI, Y, cal_bin, cal_w, tol, bin_bad, bin_cnt);
+  return hipGetLastError();
+}
+
+hipError_t r1m_fb_gather(int dtype, int dim, int64_t n, int nfb, const int32_t* list, const void* F,
+                         const void* bn, void* Fc, void* bc, hipStream_t st) {
+#define R1FG(T, D) hipLaunchKernelGGL((k_fb_gather<T, D>), dim3(nblk(nfb)), dim3(256), 0, st, n, nfb, list, \
+    static_cast<const T*>(F), static_cast<const T*>(bn), static_cast<T*>(Fc), static_cast<T*>(bc))
+  if (dtype == R1_F32) { if (dim == 2) R1FG(float, 2); else R1FG(float, 3); }
+  else { if (dim == 2) R1FG(double, 2); else R1FG(double, 3); }
+#undef R1FG
+  return hipGetLastError();
+}
+
+hipError_t r1m_fb_scatter(int dtype, int dim, int64_t n, int nfb, const int32_t* list, const void* Wc,
+                          const void* Pc, const int32_t* fc, void* W, void* P, int32_t* flags,
+                          hipStream_t st) {
+#define R1FS(T, D) hipLaunchKernelGGL((k_fb_scatter<T, D>), dim3(nblk(nfb)), dim3(256), 0, st, n, nfb, list, \
+    static_cast<const T*>(Wc), static_cast<const T*>(Pc), fc, static_cast<T*>(W), static_cast<T*>(P), flags)
+  if (dtype == R1_F32) { if (dim == 2) R1FS(float, 2); else R1FS(float, 3); }
+  else { if (dim == 2) R1FS(double, 2); else R1FS(double, 3); }
+#undef R1FS
+  return hipGetLastError();
+}

@@ -48,6 +48,18 @@ class Laminate(ctypes.Structure):
                 ("xi", ctypes.c_float)]
 
 
+class TrainCfg(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("val_fraction", ctypes.c_float), ("energy_weight", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
+
+
+class TrainReport(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("train_loss", ctypes.c_float),
+                ("val_loss", ctypes.c_float), ("ms", ctypes.c_double)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libr1.so is not built (%s); run __graft_entry__.build() or "
@@ -73,6 +85,28 @@ def _load():
     L.r1_timing_reset.argtypes = [vp]
     L.r1_timing_query.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(i64)]
+    fp = ctypes.POINTER(ctypes.c_float)
+    L.r1_surrogate_create.argtypes = [vp, ctypes.POINTER(vp), i32, i32, i32, ctypes.c_uint64]
+    L.r1_surrogate_destroy.argtypes = [vp]
+    L.r1_surrogate_pack.argtypes = [vp, i32, i64, i32, vp, vp, vp, vp, vp, vp, vp]
+    L.r1_surrogate_train.argtypes = [vp, vp, ctypes.POINTER(Material), vp, vp, i64,
+                                     ctypes.POINTER(TrainCfg), ctypes.POINTER(TrainReport), vp]
+    L.r1_surrogate_calibrate.argtypes = [vp, vp, ctypes.POINTER(Material), vp, vp, i64, ctypes.c_float,
+                                         ctypes.c_float, ctypes.POINTER(i32), vp]
+    L.r1_surrogate_infer.argtypes = [vp, vp, ctypes.POINTER(Material), ctypes.POINTER(Lamination), i64,
+                                     i32, vp, vp, vp, vp, vp, ctypes.POINTER(i64), vp]
+    L.r1_surrogate_param_count.argtypes = [vp, ctypes.POINTER(i64)]
+    L.r1_surrogate_get_params.argtypes = [vp, fp, i64]
+    L.r1_surrogate_set_params.argtypes = [vp, fp, i64]
+    L.r1_surrogate_get_norm.argtypes = [vp, fp, fp, fp, fp]
+    L.r1_surrogate_loss_grad.argtypes = [vp, vp, vp, vp, i64, vp, fp, vp]
+    L.r1_surrogate_save.argtypes = [vp, ctypes.c_char_p]
+    L.r1_surrogate_load.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_char_p]
+    for name in ("r1_surrogate_create", "r1_surrogate_destroy", "r1_surrogate_pack", "r1_surrogate_train",
+                 "r1_surrogate_calibrate", "r1_surrogate_infer", "r1_surrogate_param_count",
+                 "r1_surrogate_get_params", "r1_surrogate_set_params", "r1_surrogate_get_norm",
+                 "r1_surrogate_loss_grad", "r1_surrogate_save", "r1_surrogate_load"):
+        getattr(L, name).restype = i32
     for name in ("r1_autotune", "r1_timing_enable", "r1_timing_reset", "r1_timing_query", "r1_create", "r1_destroy", "r1_envelope", "r1_envelope_stress",
                  "r1_envelope_batched", "r1_set_segment_width", "r1_get_segment_width"):
         getattr(L, name).restype = i32
@@ -237,3 +271,116 @@ def tree_view(T):
     """(n, 3, 4) int32 tree tensor -> numpy arrays dir, i_minus, i_plus (int) and xi (float32)."""
     a = T.cpu().numpy()
     return a[..., 0], a[..., 1], a[..., 2], a[..., 3].view(np.float32)
+
+
+class Surrogate:
+    """Learned surrogate owned by a Handle (C-ABI r1_surrogate_*)."""
+
+    def __init__(self, handle, dim=2, n_hidden=4, width=128, seed=0, _ptr=None):
+        self.hd = handle
+        self.dim = dim
+        self.d_in = self.d_out = dim * dim + 1
+        self.n_hidden, self.width = n_hidden, width
+        if _ptr is None:
+            p = ctypes.c_void_p()
+            handle._check(_lib.r1_surrogate_create(handle.h, ctypes.byref(p), dim, n_hidden, width,
+                                                   ctypes.c_uint64(seed)), "r1_surrogate_create")
+            self.s = p
+        else:
+            self.s = _ptr
+
+    def close(self):
+        if getattr(self, "s", None):
+            _lib.r1_surrogate_destroy(self.s)
+            self.s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def pack(self, F, beta_n, W, P, stream=None):
+        torch = self.hd.torch
+        n = F.shape[1]
+        X = torch.empty((n, self.d_in), dtype=torch.float32, device=F.device)
+        Y = torch.empty((n, self.d_out), dtype=torch.float32, device=F.device)
+        self.hd._check(_lib.r1_surrogate_pack(self.hd.h, self.dim, n, self.hd._dtype_code(F), _ptr(F),
+                                              _ptr(beta_n), _ptr(W), _ptr(P), _ptr(X), _ptr(Y),
+                                              self.hd._stream(stream)), "r1_surrogate_pack")
+        return X, Y
+
+    def train(self, mat, X, Y, epochs=10, batch=4096, lr=1e-3, betas=(0.9, 0.999), eps=1e-8,
+              val_fraction=0.05, energy_weight=4.0, seed=0, stream=None):
+        cfg = TrainCfg(epochs, batch, lr, betas[0], betas[1], eps, val_fraction, energy_weight, seed)
+        rep = TrainReport()
+        self.hd._check(_lib.r1_surrogate_train(self.hd.h, self.s, ctypes.byref(mat), _ptr(X), _ptr(Y),
+                                               X.shape[0], ctypes.byref(cfg), ctypes.byref(rep),
+                                               self.hd._stream(stream)), "r1_surrogate_train")
+        return dict(steps=rep.steps, train_loss=rep.train_loss, val_loss=rep.val_loss, ms=rep.ms)
+
+    def calibrate(self, mat, X, Y, tol=1e-3, quantile=0.99, stream=None):
+        out = ctypes.c_int32()
+        self.hd._check(_lib.r1_surrogate_calibrate(self.hd.h, self.s, ctypes.byref(mat), _ptr(X), _ptr(Y),
+                                                   X.shape[0], tol, quantile, ctypes.byref(out),
+                                                   self.hd._stream(stream)), "r1_surrogate_calibrate")
+        return out.value
+
+    def infer(self, mat, fallback_spec, F, beta_n, stream=None, out=None):
+        torch = self.hd.torch
+        n = F.shape[1]
+        d = self.dim
+        if out is None:
+            out = dict(W=torch.empty(n, dtype=F.dtype, device=F.device),
+                       P=torch.empty((d * d, n), dtype=F.dtype, device=F.device),
+                       flags=torch.empty(n, dtype=torch.int32, device=F.device))
+        nfb = ctypes.c_int64()
+        self.hd._check(_lib.r1_surrogate_infer(self.hd.h, self.s, ctypes.byref(mat),
+                                               ctypes.byref(fallback_spec.c), n, self.hd._dtype_code(F),
+                                               _ptr(F), _ptr(beta_n), _ptr(out["W"]), _ptr(out["P"]),
+                                               _ptr(out["flags"]), ctypes.byref(nfb),
+                                               self.hd._stream(stream)), "r1_surrogate_infer")
+        out["n_fallback"] = nfb.value
+        return out
+
+    def param_count(self):
+        c = ctypes.c_int64()
+        _lib.r1_surrogate_param_count(self.s, ctypes.byref(c))
+        return c.value
+
+    def get_params(self):
+        n = self.param_count()
+        a = np.empty(n, dtype=np.float32)
+        self.hd._check(_lib.r1_surrogate_get_params(self.s, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n),
+                       "r1_surrogate_get_params")
+        return a
+
+    def set_params(self, a):
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        self.hd._check(_lib.r1_surrogate_set_params(self.s, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                                    a.size), "r1_surrogate_set_params")
+
+    def norm(self):
+        fp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        xm, xs = np.empty(self.d_in, np.float32), np.empty(self.d_in, np.float32)
+        ym, ys = np.empty(self.d_out, np.float32), np.empty(self.d_out, np.float32)
+        _lib.r1_surrogate_get_norm(self.s, fp(xm), fp(xs), fp(ym), fp(ys))
+        return dict(x_mean=xm, x_std=xs, y_mean=ym, y_std=ys)
+
+    def loss_grad(self, Xn, Yn, stream=None):
+        torch = self.hd.torch
+        g = torch.empty(self.param_count(), dtype=torch.float32, device=Xn.device)
+        loss = ctypes.c_float()
+        self.hd._check(_lib.r1_surrogate_loss_grad(self.hd.h, self.s, _ptr(Xn), _ptr(Yn), Xn.shape[0], _ptr(g),
+                                                   ctypes.byref(loss), self.hd._stream(stream)),
+                       "r1_surrogate_loss_grad")
+        return loss.value, g
+
+    def save(self, path):
+        self.hd._check(_lib.r1_surrogate_save(self.s, path.encode()), "r1_surrogate_save")
+
+    @classmethod
+    def load(cls, handle, path, dim=2, n_hidden=4, width=128):
+        p = ctypes.c_void_p()
+        handle._check(_lib.r1_surrogate_load(handle.h, ctypes.byref(p), path.encode()), "r1_surrogate_load")
+        return cls(handle, dim, n_hidden, width, _ptr=p)
