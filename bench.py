@@ -1,16 +1,21 @@
 """Benchmark: quadrature-point envelope evaluations per second on one MI355X.
 
-Workload (one step): rank-one lamination of 4,096 2D quadrature points to
-depth 2 -- outer level 64 directions x 1,025 points (tau 1.5), inner level 32
-directions x 257 points -- energy, laminate stress and lamination tree, in
-FP32 (or FP64 with --dtype f64).  Inputs are seeded synthetic gradients
+Headline workload (one step): rank-one lamination of 4,096 2D quadrature
+points to depth 2 -- outer level 64 directions x 1,025 points (tau 1.5), inner
+level 32 directions x 257 points -- energy, laminate stress and lamination
+tree, in FP32 (FP64 with --dtype f64).  Inputs are seeded synthetic gradients
 F = I + 0.3 N(0,1) (det F > 0.1) and beta_n ~ U[0, 0.5], resident in HBM.
 
 Prints one JSON line.  `roofline` prices the dominant kernel (the outer-line
 kernel, which evaluates every inner envelope) by its algorithmic flops
 (18 per W sample) against the FP32 (FP64) vector peak, timed with HIP events
 on its launch stream.  `cpu_baseline` times the FP64 oracle on a bounded
-sample of the same workload on the host's cores.
+sample of the same workload on the host's cores; the same oracle results give
+`error`, the GPU's error on those points.  Secondary legs (skip with --quick):
+`surrogate` (train the MLP on 2M lamination rows, then 1M-point inference
+with routing against plain lamination of the same configuration), `batched`
+(65,536 points with uneven grids/directions/depths in one graph replay) and
+`plain_3d` (262,144 3D points, 256 directions x 513 points).
 """
 import argparse
 import json
@@ -25,6 +30,7 @@ if ROOT not in sys.path:
 
 FLOPS_PER_W = 18           # algorithmic flops per W sample (FMA = 2), transcendentals not counted
 PEAK = {"f32": 157.3, "f64": 78.6}   # MI355X vector peak, TFLOP/s
+GAMMA = 1e-8               # relative error E_rel = |a - b| / (gamma + |b|)
 
 
 def w_samples_outer_kernel(cfg):
@@ -35,8 +41,21 @@ def w_samples_outer_kernel(cfg):
     return cfg["n"] * len(lo["a"]) * (lo["n_t"] - 1) * inner
 
 
-def _oracle_worker(args):
-    idx, dtype = args
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def erel_stats(a, b, floor=0.0):
+    import numpy as np
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    e = np.abs(a - b) / (GAMMA + np.maximum(np.abs(b), floor))
+    return dict(max=float(e.max()), p99=float(np.percentile(e, 99)), n=int(e.size))
+
+
+# ---------------------------------------------------------------- CPU baseline (oracle)
+
+def _oracle_worker(idx):
     from oracle import oracle as O
     from paper_2211_14318_amd import workloads as WL
     cfg = WL.config2()
@@ -45,8 +64,8 @@ def _oracle_worker(args):
     spec = O.LaminationSpec([(l["a"], l["b"], l["n_t"], l["tau"]) for l in cfg["levels"]])
     F = cfg["F"][:, idx].reshape(2, 2)
     t0 = time.time()
-    O.envelope(mat, spec, F, cfg["beta_n"][idx], want_tree=True)
-    return time.time() - t0
+    W, P, _ = O.envelope(mat, spec, F, cfg["beta_n"][idx], want_tree=True)
+    return idx, time.time() - t0, W, P.ravel().tolist()
 
 
 def cpu_baseline(workers):
@@ -54,13 +73,140 @@ def cpu_baseline(workers):
     O.build(force=False)
     t0 = time.time()
     with mp.get_context("spawn").Pool(workers) as pool:
-        per = pool.map(_oracle_worker, [(i, "f64") for i in range(workers)])
+        res = pool.map(_oracle_worker, list(range(workers)))
     wall = time.time() - t0
-    return dict(value=workers / wall, unit="QP/s", cores=workers, kind="oracle",
+    per = [r[1] for r in res]
+    base = dict(value=workers / wall, unit="QP/s", cores=workers, kind="oracle",
                 sample="first %d points of the workload, one point per process (energy, stress and "
                        "tree, FP64 serial oracle), %.1f s wall, %.1f s per point" %
                        (workers, wall, sum(per) / len(per)))
+    return base, {r[0]: (r[2], r[3]) for r in res}
 
+
+# ---------------------------------------------------------------- secondary legs
+
+def timed(fn, reps, torch):
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def leg_surrogate(h, r1, WL, torch, np, n_train=2_000_000, n_cal=262_144, n_inf=1_000_000, epochs=20):
+    """Config 4: MLP 5 -> 4x128 SiLU -> 5 trained on config-1-style lamination rows."""
+    mat = r1.material()
+    tr = WL.config4_training(n=n_train)
+    spec = r1.LaminationSpec(tr["levels"])
+    F = torch.tensor(tr["F"], dtype=torch.float32, device="cuda")
+    bn = torch.tensor(tr["beta_n"], dtype=torch.float32, device="cuda")
+    t0 = time.perf_counter()
+    out = h.envelope(mat, spec, F, bn, stress=True, flags=False)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    s = r1.Surrogate(h, dim=2, n_hidden=4, width=128, seed=2211)
+    X, Y = s.pack(F, bn, out["W"], out["P"])
+    del F, bn, out
+    rep = s.train(mat, X, Y, epochs=epochs, batch=4096, lr=2e-3, seed=1)
+    del X, Y
+    cal = WL.config4_training(n=n_cal, seed_tag=42)
+    Fc = torch.tensor(cal["F"], dtype=torch.float32, device="cuda")
+    bc = torch.tensor(cal["beta_n"], dtype=torch.float32, device="cuda")
+    oc = h.envelope(mat, spec, Fc, bc, stress=True, flags=False)
+    Xc, Yc = s.pack(Fc, bc, oc["W"], oc["P"])
+    cells = s.calibrate(mat, Xc, Yc, tol=1e-3, quantile=0.99)
+    del Fc, bc, oc, Xc, Yc
+    inf = WL.config4_inference(n=n_inf)
+    Fi = torch.tensor(inf["F"], dtype=torch.float32, device="cuda")
+    bi = torch.tensor(inf["beta_n"], dtype=torch.float32, device="cuda")
+    W = torch.empty(n_inf, device="cuda")
+    P = torch.empty((4, n_inf), device="cuda")
+    t_plain = timed(lambda: h.envelope_into(mat, spec, Fi, bi, W, P), 5, torch)
+    so = s.infer(mat, spec, Fi, bi)
+    t_sur = timed(lambda: s.infer(mat, spec, Fi, bi, out=so), 5, torch)
+    # errors of the accepted points against plain lamination (FP32) and against
+    # the FP64 plain lamination of the same points (the oracle-checked FP64 path)
+    fb = (so["flags"].cpu().numpy() & r1.PT_FALLBACK) != 0
+    acc = ~fb
+    Wp = W.cpu().numpy()
+    Ws = so["W"].cpu().numpy()
+    o64 = h.envelope(mat, spec, Fi.double(), bi.double(), stress=False, flags=False)
+    W64 = o64["W"].cpu().numpy()
+    e32 = np.abs(Ws[acc] - Wp[acc]) / np.maximum(np.abs(Wp[acc]), 1e-2)
+    e64 = np.abs(Ws[acc] - W64[acc]) / np.maximum(np.abs(W64[acc]), 1e-2)
+    e_all = np.abs(Ws - W64) / np.maximum(np.abs(W64), 1e-2)
+    s.close()
+    return {
+        "workload": "surrogate-2d: train 2M rows (16 dirs x 201 pts, k=1), infer 1M points",
+        "plain_qps": round(n_inf / t_plain, 1), "surrogate_qps": round(n_inf / t_sur, 1),
+        "speedup": round(t_plain / t_sur, 3), "fallback_frac": round(float(fb.mean()), 4),
+        "gate_cells_allowed": cells, "erel_floor": 1e-2,
+        "accepted_erel_vs_fp32_plain": {"max": float(e32.max()), "p99": float(np.percentile(e32, 99)),
+                                        "frac_gt_1e-3": float(np.mean(e32 > 1e-3))},
+        "accepted_erel_vs_fp64_plain": {"max": float(e64.max()), "p99": float(np.percentile(e64, 99)),
+                                        "frac_gt_1e-3": float(np.mean(e64 > 1e-3))},
+        "all_points_erel_vs_fp64_plain": {"max": float(e_all.max()), "p99": float(np.percentile(e_all, 99))},
+        "train": {"rows": n_train, "epochs": epochs, "steps": rep["steps"], "ms": round(rep["ms"], 1),
+                  "val_loss": rep["val_loss"], "data_gen_ms": round(1e3 * t_data, 1)},
+        "mlp": "5 -> 4 x 128 SiLU -> 5, BF16 MFMA / FP32 accumulate",
+    }
+
+
+def leg_batched(h, r1, WL, torch, np):
+    """Config 3: 65,536 points, per point n_t in {257..2049}, 32/64/128 directions, depth 1 or 2."""
+    cfg = WL.config3()
+    mat = r1.material()
+    specs = [r1.LaminationSpec(t) for t in cfg["table"]]
+    F = torch.tensor(cfg["F"], dtype=torch.float32, device="cuda")
+    bn = torch.tensor(cfg["beta_n"], dtype=torch.float32, device="cuda")
+    idx = torch.tensor(cfg["lam_idx"], dtype=torch.int32, device="cuda")
+    t0 = time.perf_counter()
+    out = h.envelope_batched(mat, specs, idx, F, bn, stress=True)      # plan, autotune, capture
+    torch.cuda.synchronize()
+    t_first = time.perf_counter() - t0
+    t = timed(lambda: h.envelope_batched(mat, specs, idx, F, bn, stress=True), 1, torch)
+    table, li = cfg["table"], cfg["lam_idx"]
+    wsum = 0
+    for k, lv in enumerate(table):
+        cnt = int(np.sum(li == k))
+        if len(lv) == 1:
+            wsum += cnt * len(lv[0]["a"]) * (lv[0]["n_t"] - 1)
+        else:
+            wsum += cnt * len(lv[0]["a"]) * (lv[0]["n_t"] - 1) * (len(lv[1]["a"]) * (lv[1]["n_t"] - 1) + 1)
+    W = out["W"].cpu().numpy()
+    return {"workload": cfg["name"] + " (uneven n_t/n_dir/depth, one persistent graph launch)",
+            "qps": round(cfg["n"] / t, 1), "ms": round(1e3 * t, 1), "w_samples": int(wsum),
+            "w_samples_per_s": float(wsum / t), "first_call_ms": round(1e3 * t_first, 1),
+            "all_finite": bool(np.isfinite(W).all())}
+
+
+def leg_3d(h, r1, WL, torch, np, n_check=64):
+    """Config 5: 262,144 3D points, 256 directions (Fibonacci x Fibonacci), 513 points."""
+    from oracle import oracle as O
+    cfg = WL.config5()
+    mat = r1.material(dim=3)
+    spec = r1.LaminationSpec(cfg["levels"])
+    F = torch.tensor(cfg["F"], dtype=torch.float32, device="cuda")
+    bn = torch.tensor(cfg["beta_n"], dtype=torch.float32, device="cuda")
+    n = cfg["n"]
+    W = torch.empty(n, device="cuda")
+    P = torch.empty((9, n), device="cuda")
+    t = timed(lambda: h.envelope_into(mat, spec, F, bn, W, P), 3, torch)
+    lv = cfg["levels"][0]
+    om = O.material(dim=3)
+    ospec = O.LaminationSpec([(lv["a"], lv["b"], lv["n_t"], lv["tau"])])
+    sel = np.linspace(0, n - 1, n_check).astype(int)
+    Fin = F.double().cpu().numpy()
+    bin_ = bn.double().cpu().numpy()
+    Wo, _, _ = O.envelope_batch(om, ospec, Fin[:, sel], bin_[sel], want_stress=False)
+    return {"workload": cfg["name"], "qps": round(n / t, 1), "ms": round(1e3 * t, 2),
+            "w_samples_per_s": float(n * len(lv["a"]) * (lv["n_t"] - 1) / t),
+            "erel_vs_oracle": erel_stats(W.cpu().numpy()[sel], Wo, floor=1e-2)}
+
+
+# ---------------------------------------------------------------- main
 
 def main():
     ap = argparse.ArgumentParser()
@@ -69,6 +215,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--dtype", choices=["f32", "f64"], default="f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="headline workload only")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this benchmark runs on one GPU only (quadrature points are independent; "
@@ -76,8 +225,18 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
     from paper_2211_14318_amd import r1, workloads as WL
+
+    if args.copy_probe:
+        x = torch.empty(args.copy_probe * (1 << 18), dtype=torch.float32, device="cuda").fill_(1.0)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": x.numel() * 4}))
+        return
 
     cfg = WL.config2()
     dt = torch.float32 if args.dtype == "f32" else torch.float64
@@ -109,7 +268,9 @@ def main():
     outer_ms, outer_n = h.timing_query("outer")
     h.timing(False)
     ms_per_step = 1e3 * elapsed / args.steps
-    assert torch.isfinite(W).all().item(), "non-finite envelope values"
+    Wn = W.double().cpu().numpy()
+    Pn = P.double().cpu().numpy()
+    assert np.isfinite(Wn).all(), "non-finite envelope values"
     value = n / (elapsed / args.steps)
 
     flops = FLOPS_PER_W * w_samples_outer_kernel(cfg)
@@ -138,10 +299,26 @@ def main():
                    "w_evals_per_step": w_samples_outer_kernel(cfg)},
         "roofline": roof,
     }
+    log("headline: %.1f QP/s, k_outer %.3f ms (%.1f%% of peak)" % (value, roof["avg_ms"], 100 * roof["frac"]))
+    if not args.quick:
+        out["surrogate"] = leg_surrogate(h, r1, WL, torch, np)
+        log("surrogate leg: speedup %.3f, fallback %.3f" % (out["surrogate"]["speedup"],
+                                                         out["surrogate"]["fallback_frac"]))
+        out["batched"] = leg_batched(h, r1, WL, torch, np)
+        log("batched leg: %.1f QP/s" % out["batched"]["qps"])
+        out["plain_3d"] = leg_3d(h, r1, WL, torch, np)
+        log("3d leg: %.1f QP/s" % out["plain_3d"]["qps"])
     h.close()
     if not args.no_cpu_baseline:
         workers = min(16, os.cpu_count() or 1)
-        out["cpu_baseline"] = cpu_baseline(workers)
+        log("cpu baseline: %d oracle processes" % workers)
+        base, ref = cpu_baseline(workers)
+        out["cpu_baseline"] = base
+        idx = sorted(ref)
+        out["error"] = {"vs": "FP64 oracle on the cpu_baseline points",
+                        "energy_erel": erel_stats(Wn[idx], [ref[i][0] for i in idx]),
+                        "energy_erel_floor_1e-2": erel_stats(Wn[idx], [ref[i][0] for i in idx], 1e-2),
+                        "stress_max_abs": float(np.max(np.abs(Pn[:, idx].T - np.array([ref[i][1] for i in idx]))))}
     print(json.dumps(out), flush=True)
 
 
