@@ -258,8 +258,7 @@ extern "C" r1_status r1_envelope_batched(r1_handle h, const r1_material* mat,
       }
       if (b.var < 0) return R1_EUNSUPPORTED;
       if (L.depth == 2) {
-        size_t need = ts * (size_t(L.level[0].n_t - 1) +
-                            (L.level[1].n_dir <= r1k::kMaxTabDirs ? 5 * size_t(L.level[1].n_dir) : 0));
+        size_t need = ts * r1k::outer_lds_elems(L.level[0].n_t, L.level[1].n_dir);
         lds = std::max(lds, need);
       }
     }

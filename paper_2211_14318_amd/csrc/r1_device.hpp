@@ -10,15 +10,16 @@
 // offsets m = 1 + sl + S*h (h < K/2) on both sides of the centre: w[h] is the
 // sample at t = -m*h_t (left), w[K/2+h] the one at t = +m*h_t (right).  The
 // centre sample is the same for every direction and is passed in.  Offsets
-// m > c are padding and hold +inf.  64/S lines are processed side by side.
+// m > c are padding: their abscissa is NaN, so their samples are NaN, which
+// every hull comparison treats as absent.  64/S lines are processed side by side.
 //
 // Hull at the centre: the centre is a hull vertex iff every left sample's slope
 // towards it is strictly smaller than every right sample's slope from it (one
 // pass, fused with sampling).  Otherwise the hull segment over the centre is
 // the lower common tangent ("bridge") of the left and right sample sets, found
-// by alternating tangent queries: q = tangent point on the right seen from p,
-// p = tangent point on the left seen from q, until p repeats.  Ties prefer the
-// outermost sample, matching the strict-vertex reading of Algorithm 1.
+// by slope iteration (hull_centre), with the alternating tangent search as a
+// fallback.  Ties prefer the outermost sample, matching the strict-vertex
+// reading of Algorithm 1.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -59,31 +60,45 @@ struct Level {           // one lamination level on the device
 //   psi0 >  beta_n :  W = psi0 - D_n beta_n - D_inf[(psi0 - beta_n) + D0 (e^{-psi0/D0} - e^{-beta_n/D0})]
 // Both branches are  W = E1 psi0 + h(max(psi0, beta_n))  with E1 = 1 - D_n and
 //   h(m) = (D_n - D_inf) m + B - C e^{-m/D0},  B = D_inf e^{-beta_n/D0}(beta_n + D0),  C = D_inf D0,
-// because h(beta_n) = 0: one formula, no branch.  psi0 = mu/2 s - mu L + lambda/2 L^2 with
-// L = ln J; in FP32 the log is log2 and kmu = mu ln2, klam = lambda/2 ln2^2.
+// because h(beta_n) = 0: one formula, no branch.
+//
+// Samples are evaluated in the scaled variable u = k psi0 with k = -1/D0 (FP64)
+// or -log2(e)/D0 (FP32, whose exponential is exp2), so that e^{-m/D0} is
+// exp_k(min(u, k beta_n)) with no extra multiply:
+//   W = (E1/k) u + ((D_n - D_inf)/k) v + B - C exp_k(v),   v = min(u, k beta_n).
+// psi0 = mu/2 (|G|^2 - d) - mu L + lambda/2 L^2 (L = ln J; FP32 takes log2, so
+// its L coefficients carry ln2 factors); the polynomial part k mu/2 (|G|^2 - d)
+// comes pre-scaled in the line coefficients (line_scale).
 template <typename T>
 struct Point {
-  T mu2, kmu, klam;
-  T bn, E1, Aq, B, negC, kexp;
+  T klk, kmk;            // k lambda/2 (ln2^2), k mu (ln2)
+  T ub, E1k, Aqk, B, negC;
+  double kq;             // k mu/2, applied to the line polynomial in double
   int model;
 };
+
+// k mu/2: the factor of the neo-Hooke line polynomial in the sampling form.
+template <typename T>
+__device__ __forceinline__ double line_scale(const Material& m) {
+  return (sizeof(T) == 4 ? -1.4426950408889634 : -1.0) / m.D0 * 0.5 * m.mu;
+}
 
 template <typename T>
 __device__ __forceinline__ Point<T> make_point(const Material& m, double bn) {
   Point<T> q;
   const bool f32 = sizeof(T) == 4;
   const double ln2 = 0.6931471805599453094;
+  const double k = (f32 ? -1.4426950408889634 : -1.0) / m.D0;
   double e = exp(-bn / m.D0);
   double Dn = m.D_inf * (1.0 - e);
-  q.mu2 = T(0.5 * m.mu);
-  q.kmu = T(f32 ? m.mu * ln2 : m.mu);
-  q.klam = T(f32 ? 0.5 * m.lambda * ln2 * ln2 : 0.5 * m.lambda);
-  q.bn = T(bn);
-  q.E1 = T(1.0 - Dn);
-  q.Aq = T(Dn - m.D_inf);
+  q.kmk = T(k * (f32 ? m.mu * ln2 : m.mu));
+  q.klk = T(k * (f32 ? 0.5 * m.lambda * ln2 * ln2 : 0.5 * m.lambda));
+  q.ub = T(k * bn);
+  q.E1k = T((1.0 - Dn) / k);
+  q.Aqk = T((Dn - m.D_inf) / k);
   q.negC = T(-m.D_inf * m.D0);
   q.B = T(m.D_inf * e * (bn + m.D0));
-  q.kexp = f32 ? T(-1.4426950408889634 / m.D0) : T(-1.0 / m.D0);
+  q.kq = line_scale<T>(m);
   q.model = m.model;
   return q;
 }
@@ -118,7 +133,7 @@ __device__ __forceinline__ double det_of(const double* G, const double* cof) {
 }
 
 template <typename T, int D>
-__device__ __forceinline__ Line<T> line_setup(int model, const double* G, const double* cof,
+__device__ __forceinline__ Line<T> line_setup(int model, double kq, const double* G, const double* cof,
                                               const double* a, const double* b) {
   Line<T> L;
   if (model == 0) {
@@ -136,9 +151,9 @@ __device__ __forceinline__ Line<T> line_setup(int model, const double* G, const 
     }
     L.J0 = T(det_of<D>(G, cof));
     L.J1 = T(J1);
-    L.c0 = T(n2 - double(D));
-    L.c1 = T(2.0 * gab);
-    L.c2 = T(aa * bb);
+    L.c0 = T(kq * (n2 - double(D)));
+    L.c1 = T(kq * 2.0 * gab);
+    L.c2 = T(kq * aa * bb);
   } else {
     double r0 = 0.0, r1 = 0.0, r2 = 0.0;
 #pragma unroll
@@ -156,18 +171,18 @@ __device__ __forceinline__ Line<T> line_setup(int model, const double* G, const 
   return L;
 }
 
-// One sample of W on a line (the hot loop: 12 VALU + 2 transcendental).
+// One sample of W on a line (the hot loop: 9 VALU + 2 transcendental).  The
+// line's c0, c1, c2 are the scaled polynomial k mu/2 |G(t)|^2 - d (see Point).
 // det <= 0 gives NaN (J < 0) or NaN/+inf (J = 0): such samples lie outside the
 // admissible interval and every hull comparison below treats NaN as absent.
 template <typename T>
 __device__ __forceinline__ T w_sample(T t, const Line<T>& L, const Point<T>& q) {
   T J = fma(t, L.J1, L.J0);
-  T s = fma(t, fma(t, L.c2, L.c1), L.c0);
+  T u = fma(t, fma(t, L.c2, L.c1), L.c0);
   T lj = lg_t(J);
-  T psi = fma(q.mu2, s, lj * fma(q.klam, lj, -q.kmu));
-  T m = fmax(psi, q.bn);
-  T h = fma(q.negC, expk(m * q.kexp), fma(q.Aq, m, q.B));
-  return fma(q.E1, psi, h);
+  u = fma(lj, fma(q.klk, lj, -q.kmk), u);
+  T v = fmin(u, q.ub);
+  return fma(q.negC, expk(v), fma(q.E1k, u, fma(q.Aqk, v, q.B)));
 }
 
 template <typename T>
@@ -181,7 +196,7 @@ __device__ __forceinline__ T w_sample_doublewell(T t, const Line<T>& L) {
 template <typename T, int D>
 __device__ __forceinline__ T w_point(const Point<T>& q, const double* G, const double* cof) {
   double a0[3] = {0, 0, 0};
-  Line<T> L = line_setup<T, D>(q.model, G, cof, a0, a0);
+  Line<T> L = line_setup<T, D>(q.model, q.kq, G, cof, a0, a0);
   return q.model == 0 ? w_sample<T>(T(0), L, q) : w_sample_doublewell<T>(T(0), L);
 }
 
@@ -194,7 +209,7 @@ __device__ __forceinline__ T w_point(const Point<T>& q, const double* G, const d
 
 template <int CTRL>
 __device__ __forceinline__ int dpp_i(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
 }
 
 template <int STEP>
@@ -228,6 +243,28 @@ __device__ __forceinline__ T seg_min(T v) {
   if constexpr (STEP < S) return seg_min<S, 2 * STEP>(fmin(v, partner<STEP>(v)));
   else return v;
 }
+
+// Integer reductions: the DPP move fuses into v_min_i32 / v_max_i32 (one
+// instruction per butterfly step).
+template <int S, int STEP = 1>
+__device__ __forceinline__ int seg_min_i(int v) {
+  if constexpr (STEP < S) return seg_min_i<S, 2 * STEP>(min(v, partner_i<STEP>(v)));
+  else return v;
+}
+template <int S, int STEP = 1>
+__device__ __forceinline__ int seg_max_i(int v) {
+  if constexpr (STEP < S) return seg_max_i<S, 2 * STEP>(max(v, partner_i<STEP>(v)));
+  else return v;
+}
+
+// Order-preserving map of non-NaN floats to int (an involution): float min/max
+// across lanes run as integer min/max of the keys, which fuse with DPP, while a
+// float min/max of a DPP result needs extra canonicalizing instructions.
+__device__ __forceinline__ int ord_key(float x) {
+  int i = __float_as_int(x);
+  return i ^ ((i >> 31) & 0x7fffffff);
+}
+__device__ __forceinline__ float ord_val(int k) { return __int_as_float(k ^ ((k >> 31) & 0x7fffffff)); }
 
 // Slope keys only order candidates across lanes: FP32 uses the hardware reciprocal.
 __device__ __forceinline__ float key_div(float n, float d) { return n * __builtin_amdgcn_rcpf(d); }
@@ -292,41 +329,43 @@ __device__ __forceinline__ Layout<T, S, K> make_layout(int n_t, double tau) {
   return lay;
 }
 
-// Hull of the segment's line at its centre.  w: this lane's samples (layout
-// above; +inf or NaN = absent); wc: centre sample; wci[h] = wc / m_h.  Within a
-// lane m grows with h, so in-lane ties resolve to the later sample with >= / <=.
-// Every lane of the wave must call this together (cross-lane operations).
+// Segment argmin of the lanes' candidates (key e, offset m, value w), ties to
+// the larger m (the outermost sample); returns the winner's m and w.  A lane
+// without a candidate passes e = +inf and m <= 0.
+template <int S>
+__device__ __forceinline__ void seg_argmin_outer(float e, int m, float w, int& m_out, float& w_out) {
+  const int k = ord_key(e);
+  const int kmin = seg_min_i<S>(k);
+  const int ms = seg_max_i<S>(k == kmin ? m : -1);
+  // the winner's lane is the one whose own candidate is ms
+  const int lane = threadIdx.x & (kWave - 1);
+  const int src = (lane & ~(S - 1)) | ((ms - 1) & (S - 1));
+  w_out = __shfl(w, src, kWave);
+  m_out = ms;
+}
+template <int S>
+__device__ __forceinline__ void seg_argmin_outer(double e, int m, double w, int& m_out, double& w_out) {
+  Cand<double> c = {e, m, w};
+  c = seg_arg<S, false>(c);
+  m_out = c.m;
+  w_out = c.w;
+}
+
+// Slope pass budget of the bridge search before it hands over to the
+// alternating tangent search (which always terminates).
+constexpr int kSlopePasses = 12;
+
+// Alternating tangent search for the bridge over the centre, from the left
+// point (p_m, p_w): q = tangent point on the right seen from p, p = tangent
+// point on the left seen from q, until p repeats.  Segments with todo unset
+// keep their inputs.  Every lane of the wave must call it.
 template <typename T, int S, int K>
-__device__ __forceinline__ LineHull<T> hull_centre(const T (&w)[K], T wc, const T (&wci)[K / 2],
-                                                   const Layout<T, S, K>& lay) {
+__device__ __forceinline__ void bridge_alternating(const T (&w)[K], const Layout<T, S, K>& lay,
+                                                   bool todo, int& p_m, T& p_w, int& q_m, T& q_w,
+                                                   int& capped) {
   constexpr int H = K / 2;
-  // pass 1 (values only): steepest slope from a left sample up to the centre, and
-  // shallowest slope from the centre to a right sample
-  T maxL = -inf_v<T>(), minR = inf_v<T>();
-#pragma unroll
-  for (int h = 0; h < H; ++h) {
-    maxL = fmax(maxL, fma(-w[h], lay.inv_m[h], wci[h]));
-    minR = fmin(minR, fma(w[H + h], lay.inv_m[h], -wci[h]));
-  }
-  maxL = seg_max<S>(maxL);
-  minR = seg_min<S>(minR);
-  LineHull<T> r;
-  r.h = wc; r.mp = 0; r.mq = 0; r.capped = 0;
-  bool todo = maxL >= minR;           // the centre is not a strict vertex (segment-uniform)
-  if (!__any(todo)) return r;
-  const bool bridged = todo;
-  // p: tangent point on the left seen from the centre
-  Cand<T> p = {-inf_v<T>(), 0, T(0)};
-#pragma unroll
-  for (int h = 0; h < H; ++h) {
-    T key = fma(-w[h], lay.inv_m[h], wci[h]);
-    bool take = key >= p.key;
-    p.key = take ? key : p.key;
-    p.m = take ? int(lay.mf[h]) : p.m;
-    p.w = take ? w[h] : p.w;
-  }
-  p = seg_arg<S, true>(p);
-  Cand<T> q = {inf_v<T>(), 0, T(0)};
+  Cand<T> p = {T(0), p_m, p_w};
+  Cand<T> q = {inf_v<T>(), q_m, q_w};
   int it = 0;
   while (__any(todo)) {
     // q: argmin over right samples of (w_j - w_p)/(m_j + m_p)  (cross-multiplied)
@@ -359,15 +398,97 @@ __device__ __forceinline__ LineHull<T> hull_centre(const T (&w)[K], T wc, const 
       else p = pc;
     }
     if (++it >= kBridgeCap) {
-      if (todo) r.capped = 1;
+      if (todo) capped = 1;
       break;
     }
   }
+  p_m = p.m; p_w = p.w; q_m = q.m; q_w = q.w;
+}
+
+// Hull of the segment's line at its centre.  w: this lane's samples (layout
+// above; NaN = absent); wc: centre sample; wci[h] = wc / m_h.  sig: on entry a
+// slope to start the bridge search from (NaN: none), on exit the bridge slope
+// (NaN when the centre is a vertex).  Every lane of the wave must call this
+// together (cross-lane operations).
+//
+// Vertex test: the centre is a strict hull vertex iff the steepest slope from
+// a left sample up to the centre is below the shallowest slope from the centre
+// to a right sample.  Otherwise the hull over the centre is the bridge (lower
+// common tangent) of the two sides, found by slope iteration: at slope s the
+// lowest left and right samples under the tilt, p = argmin w + s m and
+// q = argmin w - s m (ties to the outermost sample), are the points where lines
+// of slope s support the two sides; s <- slope(p, q) until (p, q) repeats, when
+// every sample lies on or above the line through p and q.  The bridge slope is
+// bracketed by the two vertex-test slopes, which give the cold start; a warm
+// start (the previous point's slope on a nearby line) usually needs two passes.
+template <typename T, int S, int K>
+__device__ __forceinline__ LineHull<T> hull_centre(const T (&w)[K], T wc, const T (&wci)[K / 2],
+                                                   const Layout<T, S, K>& lay, T& sig) {
+  constexpr int H = K / 2;
+  T maxL = -inf_v<T>(), minR = inf_v<T>();
+#pragma unroll
+  for (int h = 0; h < H; ++h) {
+    maxL = fmax(maxL, fma(-w[h], lay.inv_m[h], wci[h]));
+    minR = fmin(minR, fma(w[H + h], lay.inv_m[h], -wci[h]));
+  }
+  bool todo;
+  if constexpr (sizeof(T) == 4) {
+    const int kl = seg_max_i<S>(ord_key(maxL));
+    const int kr = seg_min_i<S>(ord_key(minR));
+    todo = kl >= kr;
+    maxL = ord_val(kl);
+    minR = ord_val(kr);
+  } else {
+    maxL = seg_max<S>(maxL);
+    minR = seg_min<S>(minR);
+    todo = maxL >= minR;
+  }
+  LineHull<T> r;
+  r.h = wc; r.mp = 0; r.mq = 0; r.capped = 0;
+  const T nan = T(__builtin_nan(""));
+  if (!__any(todo)) {
+    sig = nan;
+    return r;
+  }
+  const bool bridged = todo;
+  T s = sig == sig ? fmin(fmax(sig, minR), maxL) : T(0.5) * (maxL + minR);
+  const int sl = threadIdx.x & (S - 1);
+  int mp = 0, mq = 0;
+  T wp = T(0), wq = T(0);
+  for (int pass = 0; pass < kSlopePasses && __any(todo); ++pass) {
+    T eL = inf_v<T>(), eR = inf_v<T>(), wL = T(0), wR = T(0);
+    int hL = -1, hR = -1;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      const T e = fma(s, lay.mf[h], w[h]);           // left sample at -m
+      const bool tl = e <= eL;
+      eL = tl ? e : eL; hL = tl ? h : hL; wL = tl ? w[h] : wL;
+      const T f = fma(-s, lay.mf[h], w[H + h]);      // right sample at +m
+      const bool tr = f <= eR;
+      eR = tr ? f : eR; hR = tr ? h : hR; wR = tr ? w[H + h] : wR;
+    }
+    int mpn, mqn;
+    T wpn, wqn;
+    seg_argmin_outer<S>(eL, 1 + sl + S * hL, wL, mpn, wpn);
+    seg_argmin_outer<S>(eR, 1 + sl + S * hR, wR, mqn, wqn);
+    if (todo) {
+      if (pass > 0 && mpn == mp && mqn == mq) {
+        todo = false;
+      } else {
+        mp = mpn; mq = mqn; wp = wpn; wq = wqn;
+        s = key_div(wq - wp, T(mq + mp));
+      }
+    }
+  }
+  if (__any(todo)) bridge_alternating<T, S, K>(w, lay, todo, mp, wp, mq, wq, r.capped);
   if (bridged) {
-    T mpf = T(p.m), mqf = T(q.m);
-    r.h = (mqf * p.w + mpf * q.w) / (mqf + mpf);
-    r.mp = p.m;
-    r.mq = q.m;
+    T mpf = T(mp), mqf = T(mq);
+    r.h = (mqf * wp + mpf * wq) / (mqf + mpf);
+    r.mp = mp;
+    r.mq = mq;
+    sig = key_div(wq - wp, mqf + mpf);
+  } else {
+    sig = nan;
   }
   return r;
 }
@@ -395,9 +516,9 @@ __device__ __forceinline__ PointGeom<D> make_geom(const double* G) {
 }
 
 template <typename T, int D>
-__device__ __forceinline__ Line<T> line_of(int model, const PointGeom<D>& g, const double* a,
-                                           const double* b) {
-  if (model != 0) return line_setup<T, D>(model, g.G, g.cof, a, b);
+__device__ __forceinline__ Line<T> line_of(int model, double kq, const PointGeom<D>& g,
+                                           const double* a, const double* b) {
+  if (model != 0) return line_setup<T, D>(model, kq, g.G, g.cof, a, b);
   Line<T> L;
   double J1 = 0.0, gab = 0.0, aa = 0.0, bb = 0.0;
 #pragma unroll
@@ -415,9 +536,9 @@ __device__ __forceinline__ Line<T> line_of(int model, const PointGeom<D>& g, con
   }
   L.J0 = T(g.det);
   L.J1 = T(J1);
-  L.c0 = T(g.n2 - double(D));
-  L.c1 = T(2.0 * gab);
-  L.c2 = T(aa * bb);
+  L.c0 = T(kq * (g.n2 - double(D)));
+  L.c1 = T(kq * 2.0 * gab);
+  L.c2 = T(kq * aa * bb);
   return L;
 }
 
@@ -430,11 +551,14 @@ struct Env {            // W^1 at a point: value, direction, bracketing offsets
 
 // One lamination level at a point (wave-uniform): min over the level's n_dir
 // directions of the line hulls at the centre.  wc = W at the point;
-// line_fn(dir) returns the coefficients of W along direction dir.  Every lane of
-// the wave must call it.
+// line_fn(dir) returns the coefficients of W along direction dir.  warm
+// (optional, n_dir entries owned by this wave) carries each direction's bridge
+// slope from one call to the next as the start of the bridge search: NaN for
+// none; callers whose successive points are close pass it.  Every lane of the
+// wave must call it.
 template <typename T, int S, int K, typename LineFn>
 __device__ Env<T> envelope_lines(const Point<T>& q, T wc, int n_dir, const Layout<T, S, K>& lay,
-                                 LineFn line_fn) {
+                                 LineFn line_fn, T* warm = nullptr) {
   constexpr int NSEG = kWave / S;
   constexpr int H = K / 2;
   const int lane = threadIdx.x & (kWave - 1);
@@ -461,7 +585,9 @@ __device__ Env<T> envelope_lines(const Point<T>& q, T wc, int n_dir, const Layou
         w[H + h] = w_sample_doublewell<T>(lay.t[h], L);
       }
     }
-    LineHull<T> lh = hull_centre<T, S, K>(w, wc, wci, lay);
+    T sg = (warm && act) ? warm[dir] : T(__builtin_nan(""));
+    LineHull<T> lh = hull_centre<T, S, K>(w, wc, wci, lay, sg);
+    if (warm && act && (lane & (S - 1)) == 0) warm[dir] = sg;
     if (act && lh.h < best.h) {
       best.h = lh.h; best.dir = dir; best.mp = lh.mp; best.mq = lh.mq;
     }
@@ -494,7 +620,7 @@ __device__ Env<T> envelope_at(const Point<T>& q, const double* G, T wc, const Le
     double a[D], b[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) { a[i] = lv.a[dd * D + i]; b[i] = lv.b[dd * D + i]; }
-    return line_of<T, D>(q.model, g, a, b);
+    return line_of<T, D>(q.model, q.kq, g, a, b);
   });
 }
 
@@ -502,7 +628,8 @@ __device__ Env<T> envelope_at(const Point<T>& q, const double* G, T wc, const Le
 // det and |.|^2 are affine / quadratic in t_o, and cof(F + t_o R_o) = cof F + t_o C1
 // because cof(R_o) = 0, so every inner coefficient is affine in t_o:
 //   J1_i = al_i + t_o be_i,  c1_i = ga_i + t_o de_i,  c2_i = |a_i|^2 |b_i|^2.
-// coef[5*i .. 5*i+4] = (al, be, ga, de, c2) of inner direction i.
+// coef[5*i .. 5*i+4] = (al, be, ga, de, c2) of inner direction i, the last three
+// times kq (the sampling form of the neo-Hooke polynomial, see Point).
 template <int D>
 __device__ __forceinline__ void cof_derivative(const double* F, const double* R, double* C1) {
   if (D == 2) {
@@ -520,7 +647,7 @@ __device__ __forceinline__ void cof_derivative(const double* F, const double* R,
 }
 
 template <typename T, int D>
-__device__ __forceinline__ void inner_line_coef(int model, const double* F, const double* cofF,
+__device__ __forceinline__ void inner_line_coef(int model, double kq, const double* F, const double* cofF,
                                                 const double* R, const double* C1, const double* a,
                                                 const double* b, T* coef) {
   double al = 0, be = 0, ga = 0, de = 0, aa = 0, bb = 0;
@@ -537,7 +664,7 @@ __device__ __forceinline__ void inner_line_coef(int model, const double* F, cons
         de += 2.0 * a[i] * R[i * D + j] * b[j];
       }
     }
-    coef[0] = T(al); coef[1] = T(be); coef[2] = T(ga); coef[3] = T(de); coef[4] = T(aa * bb);
+    coef[0] = T(al); coef[1] = T(be); coef[2] = T(kq * ga); coef[3] = T(kq * de); coef[4] = T(kq * aa * bb);
   } else {
     // double-well test energy: g = G11 + t a1 b1, rest = sum_{(i,j)!=(1,1)} (G_ij - delta_ij + t a_i b_j)^2
     double r2 = 0, e1 = 0, e1r = 0;

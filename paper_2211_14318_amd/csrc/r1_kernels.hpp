@@ -190,11 +190,20 @@ __device__ LineHull<T> hull_centre_lds(const T* wl, const T* wr, int c, T wc) {
 // Inner directions whose line coefficients are tabulated in LDS per outer line.
 constexpr int kMaxTabDirs = 512;
 
-// Bytes of dynamic LDS an outer line needs: inner-line coefficient table and
-// the outer line's samples.
+// Waves of an outer-line block (blocks are 256 threads).
+constexpr int kOuterWaves = 4;
+
+// Elements of T of dynamic LDS an outer line needs: the outer line's samples
+// and, when the inner level is tabulated, its coefficient table and each
+// wave's warm-start bridge slopes.
+__host__ __device__ inline size_t outer_lds_elems(int n_t_outer, int n_dir_inner) {
+  return size_t(n_t_outer - 1) +
+         (n_dir_inner <= kMaxTabDirs ? size_t(5 + kOuterWaves) * size_t(n_dir_inner) : 0);
+}
+
 template <typename T>
 __host__ __device__ inline size_t outer_lds_bytes(const Level& lo, const Level& li) {
-  return sizeof(T) * (size_t(lo.n_t - 1) + (li.n_dir <= kMaxTabDirs ? 5 * size_t(li.n_dir) : 0));
+  return sizeof(T) * outer_lds_elems(lo.n_t, li.n_dir);
 }
 
 // One outer line (block-level, every thread calls it): the samples W^1(F + t_i R_mo)
@@ -208,7 +217,8 @@ __device__ T outer_line(const KArgs& a, int64_t p, int mo, const Level& lo, cons
   const int co = (lo.n_t - 1) / 2;
   const bool tab = li.n_dir <= kMaxTabDirs;
   T* coef = reinterpret_cast<T*>(smem_raw);                 // 5 * n_dir_i (when tabulated)
-  T* wl = coef + (tab ? 5 * li.n_dir : 0);                  // outer samples at -m
+  T* warm = coef + (tab ? 5 * li.n_dir : 0);                // kOuterWaves * n_dir_i (when tabulated)
+  T* wl = warm + (tab ? kOuterWaves * li.n_dir : 0);        // outer samples at -m
   T* wr = wl + co;                                          // outer samples at +m
   __shared__ int capped_any;
   __shared__ T centre;
@@ -225,7 +235,9 @@ __device__ T outer_line(const KArgs& a, int64_t p, int mo, const Level& lo, cons
     cofactor<D>(F, cofF);
     cof_derivative<D>(F, R, C1);
     for (int i = threadIdx.x; i < li.n_dir; i += blockDim.x)
-      inner_line_coef<T, D>(a.mat.model, F, cofF, R, C1, li.a + i * D, li.b + i * D, coef + 5 * i);
+      inner_line_coef<T, D>(a.mat.model, line_scale<T>(a.mat), F, cofF, R, C1, li.a + i * D, li.b + i * D,
+                            coef + 5 * i);
+    for (int i = threadIdx.x; i < kOuterWaves * li.n_dir; i += blockDim.x) warm[i] = T(__builtin_nan(""));
   }
   __syncthreads();
   Layout<T, S, K> lay = make_layout<T, S, K>(li.n_t, li.tau);
@@ -244,7 +256,10 @@ __device__ T outer_line(const KArgs& a, int64_t p, int mo, const Level& lo, cons
     }
     if (lane_id() == 0) centre = v;
   }
-  // outer samples, interleaved left/right so the waves share both sides
+  // outer samples, interleaved left/right so the waves share both sides; a
+  // wave walks one side outwards in steps of two samples, so the previous
+  // sample's inner bridge slopes (warm, per inner direction) start the next
+  T* warm_w = warm + wave * li.n_dir;          // blocks have kOuterWaves waves
   for (int s = wave; s < 2 * co; s += nwave) {
     int m = 1 + (s >> 1);
     double t = (s & 1) ? t_of(lo, m) : -t_of(lo, m);
@@ -253,7 +268,7 @@ __device__ T outer_line(const KArgs& a, int64_t p, int mo, const Level& lo, cons
     for (int k = 0; k < D * D; ++k) G[k] = F[k] + t * R[k];
     T v;
     if (tab) {
-      // W(G) and the per-sample parts of every inner line: J0 = det G, c0 = |G|^2 - d
+      // W(G) and the per-sample parts of every inner line: J0 = det G, c0 = kq (|G|^2 - d)
       // (neo-Hooke) or G11 and the quadratic rest (double well)
       double cof[D * D];
       cofactor<D>(G, cof);
@@ -262,7 +277,7 @@ __device__ T outer_line(const KArgs& a, int64_t p, int mo, const Level& lo, cons
         J0 = det_of<D>(G, cof);
 #pragma unroll
         for (int k = 0; k < D * D; ++k) c0 += G[k] * G[k];
-        c0 -= double(D);
+        c0 = q.kq * (c0 - double(D));
       } else {
         J0 = G[0];
 #pragma unroll
@@ -279,7 +294,7 @@ __device__ T outer_line(const KArgs& a, int64_t p, int mo, const Level& lo, cons
         Env<T> e = envelope_lines<T, S, K>(q, wc, li.n_dir, lay, [&](int dd) {
           const T* cf = coef + 5 * dd;
           return Line<T>{L0.J0, T(fma(tt, cf[1], cf[0])), L0.c0, T(fma(tt, cf[3], cf[2])), cf[4]};
-        });
+        }, warm_w);
         v = e.h;
         capped |= e.capped;
       }
