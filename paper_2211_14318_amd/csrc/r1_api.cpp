@@ -3,6 +3,7 @@
 // segment widths), and the launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -98,6 +99,19 @@ r1_status r1h::device_level(r1_handle h, const r1_level& lv, int dim, r1d::Level
   out->n_dir = lv.n_dir;
   out->n_t = lv.n_t;
   out->tau = lv.tau;
+  // |a|^2 |b|^2 shared by every direction (unit directions: 1 up to rounding)
+  // lets the kernels form the common part of the line polynomial once per point
+  double ab0 = 0.0, dev = 0.0;
+  for (int32_t m = 0; m < lv.n_dir; ++m) {
+    double aa = 0.0, bb = 0.0;
+    for (int i = 0; i < dim; ++i) {
+      aa += lv.a[size_t(m) * dim + i] * lv.a[size_t(m) * dim + i];
+      bb += lv.b[size_t(m) * dim + i] * lv.b[size_t(m) * dim + i];
+    }
+    if (m == 0) ab0 = aa * bb;
+    dev = std::max(dev, std::fabs(aa * bb - ab0));
+  }
+  out->ab2 = (lv.n_dir > 0 && dev <= 8.0 * 2.220446049250313e-16 * ab0) ? ab0 : std::nan("");
   return R1_OK;
 }
 

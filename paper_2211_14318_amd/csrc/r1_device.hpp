@@ -52,6 +52,7 @@ struct Level {           // one lamination level on the device
   const double* b;
   int n_dir, n_t;
   double tau;
+  double ab2;            // |a|^2 |b|^2 when equal for every direction (to rounding), else NaN
 };
 
 // Per-point constants of W (eq. 2.9 written as a function of psi0).  With
@@ -179,6 +180,19 @@ template <typename T>
 __device__ __forceinline__ T w_sample(T t, const Line<T>& L, const Point<T>& q) {
   T J = fma(t, L.J1, L.J0);
   T u = fma(t, fma(t, L.c2, L.c1), L.c0);
+  T lj = lg_t(J);
+  u = fma(lj, fma(q.klk, lj, -q.kmk), u);
+  T v = fmin(u, q.ub);
+  return fma(q.negC, expk(v), fma(q.E1k, u, fma(q.Aqk, v, q.B)));
+}
+
+// Same, with the part of the line polynomial that is common to every line
+// through the point given per sample: base = c0 + c2 t^2 (8 VALU + 2
+// transcendental).
+template <typename T>
+__device__ __forceinline__ T w_sample_base(T t, T base, const Line<T>& L, const Point<T>& q) {
+  T J = fma(t, L.J1, L.J0);
+  T u = fma(t, L.c1, base);
   T lj = lg_t(J);
   u = fma(lj, fma(q.klk, lj, -q.kmk), u);
   T v = fmin(u, q.ub);
@@ -329,43 +343,49 @@ __device__ __forceinline__ Layout<T, S, K> make_layout(int n_t, double tau) {
   return lay;
 }
 
-// Segment argmin of the lanes' candidates (key e, offset m, value w), ties to
-// the larger m (the outermost sample); returns the winner's m and w.  A lane
-// without a candidate passes e = +inf and m <= 0.
+// Segment minimum of the lanes' candidate keys e with the offset m of the
+// minimizer, ties to the larger m (the outermost sample).  A lane without a
+// candidate passes e = +inf and m <= 0.
 template <int S>
-__device__ __forceinline__ void seg_argmin_outer(float e, int m, float w, int& m_out, float& w_out) {
+__device__ __forceinline__ void seg_argmin_outer(float e, int m, int& m_out, float& e_out) {
   const int k = ord_key(e);
   const int kmin = seg_min_i<S>(k);
-  const int ms = seg_max_i<S>(k == kmin ? m : -1);
-  // the winner's lane is the one whose own candidate is ms
-  const int lane = threadIdx.x & (kWave - 1);
-  const int src = (lane & ~(S - 1)) | ((ms - 1) & (S - 1));
-  w_out = __shfl(w, src, kWave);
-  m_out = ms;
+  m_out = seg_max_i<S>(k == kmin ? m : -1);
+  e_out = ord_val(kmin);
 }
 template <int S>
-__device__ __forceinline__ void seg_argmin_outer(double e, int m, double w, int& m_out, double& w_out) {
-  Cand<double> c = {e, m, w};
+__device__ __forceinline__ void seg_argmin_outer(double e, int m, int& m_out, double& e_out) {
+  Cand<double> c = {e, m, 0.0};
   c = seg_arg<S, false>(c);
   m_out = c.m;
-  w_out = c.w;
+  e_out = c.key;
 }
 
 // Slope pass budget of the bridge search before it hands over to the
 // alternating tangent search (which always terminates).
 constexpr int kSlopePasses = 12;
 
-// Alternating tangent search for the bridge over the centre, from the left
-// point (p_m, p_w): q = tangent point on the right seen from p, p = tangent
-// point on the left seen from q, until p repeats.  Segments with todo unset
-// keep their inputs.  Every lane of the wave must call it.
+// Alternating tangent search for the bridge over the centre: p starts as the
+// tangent point on the left seen from the centre; then q = tangent point on
+// the right seen from p, p = tangent point on the left seen from q, until p
+// repeats.  Segments with todo unset are left alone.  Every lane of the wave
+// must call it.
 template <typename T, int S, int K>
-__device__ __forceinline__ void bridge_alternating(const T (&w)[K], const Layout<T, S, K>& lay,
-                                                   bool todo, int& p_m, T& p_w, int& q_m, T& q_w,
-                                                   int& capped) {
+__device__ __forceinline__ void bridge_alternating(const T (&w)[K], const T (&wci)[K / 2],
+                                                   const Layout<T, S, K>& lay, bool todo,
+                                                   int& p_m, T& p_w, int& q_m, T& q_w, int& capped) {
   constexpr int H = K / 2;
-  Cand<T> p = {T(0), p_m, p_w};
-  Cand<T> q = {inf_v<T>(), q_m, q_w};
+  Cand<T> p = {-inf_v<T>(), 0, T(0)};
+#pragma unroll
+  for (int h = 0; h < H; ++h) {
+    T key = fma(-w[h], lay.inv_m[h], wci[h]);
+    bool take = key >= p.key;
+    p.key = take ? key : p.key;
+    p.m = take ? int(lay.mf[h]) : p.m;
+    p.w = take ? w[h] : p.w;
+  }
+  p = seg_arg<S, true>(p);
+  Cand<T> q = {inf_v<T>(), 0, T(0)};
   int it = 0;
   while (__any(todo)) {
     // q: argmin over right samples of (w_j - w_p)/(m_j + m_p)  (cross-multiplied)
@@ -394,15 +414,21 @@ __device__ __forceinline__ void bridge_alternating(const T (&w)[K], const Layout
     pc = seg_arg<S, true>(pc);
     if (todo) {
       q = qc;
-      if (pc.m == p.m) todo = false;
-      else p = pc;
+      if (pc.m == p.m) {
+        todo = false;
+        p_m = p.m; p_w = p.w; q_m = q.m; q_w = q.w;
+      } else {
+        p = pc;
+      }
     }
     if (++it >= kBridgeCap) {
-      if (todo) capped = 1;
+      if (todo) {
+        capped = 1;
+        p_m = p.m; p_w = p.w; q_m = q.m; q_w = q.w;
+      }
       break;
     }
   }
-  p_m = p.m; p_w = p.w; q_m = q.m; q_w = q.w;
 }
 
 // Hull of the segment's line at its centre.  w: this lane's samples (layout
@@ -418,9 +444,13 @@ __device__ __forceinline__ void bridge_alternating(const T (&w)[K], const Layout
 // lowest left and right samples under the tilt, p = argmin w + s m and
 // q = argmin w - s m (ties to the outermost sample), are the points where lines
 // of slope s support the two sides; s <- slope(p, q) until (p, q) repeats, when
-// every sample lies on or above the line through p and q.  The bridge slope is
-// bracketed by the two vertex-test slopes, which give the cold start; a warm
-// start (the previous point's slope on a nearby line) usually needs two passes.
+// every sample lies on or above the line through p and q.  The tilted minima
+// e_p = w_p + s m_p and e_q = w_q - s m_q give both the next slope,
+// s + (e_q - e_p)/(m_p + m_q), and the hull value at the centre,
+// (m_q e_p + m_p e_q)/(m_p + m_q), in which the rounding of s cancels.  The
+// bridge slope is bracketed by the two vertex-test slopes, which give the cold
+// start; a warm start (the previous point's slope on a nearby line) usually
+// needs two passes.
 template <typename T, int S, int K>
 __device__ __forceinline__ LineHull<T> hull_centre(const T (&w)[K], T wc, const T (&wci)[K / 2],
                                                    const Layout<T, S, K>& lay, T& sig) {
@@ -454,39 +484,49 @@ __device__ __forceinline__ LineHull<T> hull_centre(const T (&w)[K], T wc, const 
   T s = sig == sig ? fmin(fmax(sig, minR), maxL) : T(0.5) * (maxL + minR);
   const int sl = threadIdx.x & (S - 1);
   int mp = 0, mq = 0;
-  T wp = T(0), wq = T(0);
+  T ep = T(0), eq = T(0);
   for (int pass = 0; pass < kSlopePasses && __any(todo); ++pass) {
-    T eL = inf_v<T>(), eR = inf_v<T>(), wL = T(0), wR = T(0);
+    T eL = inf_v<T>(), eR = inf_v<T>();
     int hL = -1, hR = -1;
 #pragma unroll
     for (int h = 0; h < H; ++h) {
       const T e = fma(s, lay.mf[h], w[h]);           // left sample at -m
       const bool tl = e <= eL;
-      eL = tl ? e : eL; hL = tl ? h : hL; wL = tl ? w[h] : wL;
+      eL = tl ? e : eL; hL = tl ? h : hL;
       const T f = fma(-s, lay.mf[h], w[H + h]);      // right sample at +m
       const bool tr = f <= eR;
-      eR = tr ? f : eR; hR = tr ? h : hR; wR = tr ? w[H + h] : wR;
+      eR = tr ? f : eR; hR = tr ? h : hR;
     }
     int mpn, mqn;
-    T wpn, wqn;
-    seg_argmin_outer<S>(eL, 1 + sl + S * hL, wL, mpn, wpn);
-    seg_argmin_outer<S>(eR, 1 + sl + S * hR, wR, mqn, wqn);
+    T epn, eqn;
+    seg_argmin_outer<S>(eL, 1 + sl + S * hL, mpn, epn);
+    seg_argmin_outer<S>(eR, 1 + sl + S * hR, mqn, eqn);
     if (todo) {
       if (pass > 0 && mpn == mp && mqn == mq) {
         todo = false;
+        ep = epn; eq = eqn;
       } else {
-        mp = mpn; mq = mqn; wp = wpn; wq = wqn;
-        s = key_div(wq - wp, T(mq + mp));
+        mp = mpn; mq = mqn;
+        s = s + key_div(eqn - epn, T(mq + mp));
       }
     }
   }
-  if (__any(todo)) bridge_alternating<T, S, K>(w, lay, todo, mp, wp, mq, wq, r.capped);
+  if (__any(todo)) {
+    // slope budget spent (not seen in practice): finish with the alternating search
+    T wp = T(0), wq = T(0);
+    bridge_alternating<T, S, K>(w, wci, lay, todo, mp, wp, mq, wq, r.capped);
+    if (todo) {       // express its result in the tilted form used below
+      s = key_div(wq - wp, T(mq + mp));
+      ep = fma(s, T(mp), wp);
+      eq = fma(-s, T(mq), wq);
+    }
+  }
   if (bridged) {
     T mpf = T(mp), mqf = T(mq);
-    r.h = (mqf * wp + mpf * wq) / (mqf + mpf);
+    r.h = (mqf * ep + mpf * eq) / (mqf + mpf);
     r.mp = mp;
     r.mq = mq;
-    sig = key_div(wq - wp, mqf + mpf);
+    sig = s;
   } else {
     sig = nan;
   }
@@ -554,11 +594,13 @@ struct Env {            // W^1 at a point: value, direction, bracketing offsets
 // line_fn(dir) returns the coefficients of W along direction dir.  warm
 // (optional, n_dir entries owned by this wave) carries each direction's bridge
 // slope from one call to the next as the start of the bridge search: NaN for
-// none; callers whose successive points are close pass it.  Every lane of the
-// wave must call it.
+// none; callers whose successive points are close pass it.  c2u: when every
+// line has the same c2 (and, being lines through one point, the same c0), that
+// c2; the polynomial part c0 + c2 t^2 is then formed once per point (NaN: not
+// uniform).  Every lane of the wave must call it.
 template <typename T, int S, int K, typename LineFn>
 __device__ Env<T> envelope_lines(const Point<T>& q, T wc, int n_dir, const Layout<T, S, K>& lay,
-                                 LineFn line_fn, T* warm = nullptr) {
+                                 LineFn line_fn, T* warm = nullptr, T c2u = T(__builtin_nan(""))) {
   constexpr int NSEG = kWave / S;
   constexpr int H = K / 2;
   const int lane = threadIdx.x & (kWave - 1);
@@ -566,13 +608,26 @@ __device__ Env<T> envelope_lines(const Point<T>& q, T wc, int n_dir, const Layou
   T wci[H];
 #pragma unroll
   for (int h = 0; h < H; ++h) wci[h] = wc * lay.inv_m[h];
+  const bool shared = q.model == 0 && c2u == c2u;
+  T base[H];
+  if (shared) {
+    const T c0 = line_fn(0).c0;
+#pragma unroll
+    for (int h = 0; h < H; ++h) base[h] = fma(c2u, lay.t[h] * lay.t[h], c0);
+  }
   Env<T> best = {inf_v<T>(), 0, 0, 0, 0};
   for (int m0 = 0; m0 < n_dir; m0 += NSEG) {
     int dir = m0 + seg;
     bool act = dir < n_dir;
     Line<T> L = line_fn(act ? dir : n_dir - 1);
     T w[K];
-    if (q.model == 0) {
+    if (shared) {
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        w[h] = w_sample_base<T>(-lay.t[h], base[h], L, q);
+        w[H + h] = w_sample_base<T>(lay.t[h], base[h], L, q);
+      }
+    } else if (q.model == 0) {
 #pragma unroll
       for (int h = 0; h < H; ++h) {
         w[h] = w_sample<T>(-lay.t[h], L, q);
@@ -621,7 +676,7 @@ __device__ Env<T> envelope_at(const Point<T>& q, const double* G, T wc, const Le
 #pragma unroll
     for (int i = 0; i < D; ++i) { a[i] = lv.a[dd * D + i]; b[i] = lv.b[dd * D + i]; }
     return line_of<T, D>(q.model, q.kq, g, a, b);
-  });
+  }, nullptr, T(q.kq * lv.ab2));
 }
 
 // Lines of an inner level along an outer line G(t_o) = F + t_o R_o, R_o rank one.

@@ -294,7 +294,7 @@ __device__ T outer_line(const KArgs& a, int64_t p, int mo, const Level& lo, cons
         Env<T> e = envelope_lines<T, S, K>(q, wc, li.n_dir, lay, [&](int dd) {
           const T* cf = coef + 5 * dd;
           return Line<T>{L0.J0, T(fma(tt, cf[1], cf[0])), L0.c0, T(fma(tt, cf[3], cf[2])), cf[4]};
-        }, warm_w);
+        }, warm_w, T(q.kq * li.ab2));
         v = e.h;
         capped |= e.capped;
       }
