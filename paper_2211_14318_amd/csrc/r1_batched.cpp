@@ -234,7 +234,8 @@ extern "C" r1_status r1_envelope_batched(r1_handle h, const r1_material* mat,
     for (int64_t p = 0; p < n; ++p)
       if (idx[p] < 0 || idx[p] >= n_table) return R1_EINVAL;
     std::vector<BEntry> ent(static_cast<size_t>(n_table));
-    size_t lds = 0;
+    constexpr int NV = R1_N_BATCH_VARIANTS;
+    size_t lds[NV] = {};
     const size_t ts = dtype == R1_F32 ? 4 : 8;
     for (int k = 0; k < n_table; ++k) {
       const r1_lamination& L = table[k];
@@ -258,47 +259,65 @@ extern "C" r1_status r1_envelope_batched(r1_handle h, const r1_material* mat,
       }
       if (b.var < 0) return R1_EUNSUPPORTED;
       if (L.depth == 2) {
-        size_t need = ts * r1k::outer_lds_elems(L.level[0].n_t, L.level[1].n_dir);
-        lds = std::max(lds, need);
+        size_t need = r1k::outer_lds_bytes(ts, L.level[0].n_t, L.level[1].n_dir);
+        lds[b.var] = std::max(lds[b.var], need);
       }
     }
-    // work list: outer lines of depth-2 points (largest first), then groups of
-    // up to 4 depth-1 points (largest first) to fill the tail
-    std::vector<int64_t> d2, d1;
-    for (int64_t p = 0; p < n; ++p) (table[idx[p]].depth == 2 ? d2 : d1).push_back(p);
+    // work lists per layout variant, each ordered largest first: point items
+    // (groups of up to 4 depth-1 points; groups of up to 4 depth-2 points for
+    // the centre values), outer lines of depth-2 points, depth-2 points to finalize
+    std::vector<int64_t> d2[NV], d1[NV];
+    for (int64_t p = 0; p < n; ++p) {
+      const int c = ent[idx[p]].var;
+      (table[idx[p]].depth == 2 ? d2[c] : d1[c]).push_back(p);
+    }
     auto cost = [&](int64_t p) {
       const r1_lamination& L = table[idx[p]];
       if (L.depth == 1) return double(L.level[0].n_dir) * double(L.level[0].n_t - 1);
       return double(L.level[0].n_t - 1) *
              (double(L.level[1].n_dir) * double(L.level[1].n_t - 1) + 1.0);
     };
-    std::stable_sort(d2.begin(), d2.end(), [&](int64_t x, int64_t y) { return cost(x) > cost(y); });
-    std::stable_sort(d1.begin(), d1.end(), [&](int64_t x, int64_t y) { return cost(x) > cost(y); });
     std::vector<int64_t> pbase(static_cast<size_t>(n), 0);
-    int64_t n_outer = 0;
-    for (int64_t p : d2) {
-      pbase[p] = n_outer;
-      n_outer += table[idx[p]].level[0].n_dir;
-    }
-    const int64_t n_groups = (int64_t(d1.size()) + 3) / 4;
-    const int64_t n_items = n_outer + n_groups;
-    if (n_items >= (int64_t(1) << 31)) return R1_EINVAL;
     std::vector<int4> items;
-    items.reserve(size_t(n_items));
-    for (int64_t p : d2)
-      for (int mo = 0; mo < table[idx[p]].level[0].n_dir; ++mo) items.push_back(int4{1, int(p), mo, 0});
-    std::vector<int32_t> order(d1.begin(), d1.end());
-    for (int64_t g = 0; g < n_groups; ++g) {
-      int cnt = int(std::min<int64_t>(4, int64_t(d1.size()) - 4 * g));
-      items.push_back(int4{0, int(4 * g), cnt, 0});
+    std::vector<int32_t> order;
+    int64_t n_outer = 0;
+    // per variant and kind: first item (or order entry for kBFinal) and count
+    int64_t first[NV][3] = {}, count[NV][3] = {};
+    for (int c = 0; c < NV; ++c) {
+      std::stable_sort(d2[c].begin(), d2[c].end(), [&](int64_t x, int64_t y) { return cost(x) > cost(y); });
+      std::stable_sort(d1[c].begin(), d1[c].end(), [&](int64_t x, int64_t y) { return cost(x) > cost(y); });
+      first[c][kBPoint] = int64_t(items.size());
+      for (int kind = 0; kind < 2; ++kind) {
+        const std::vector<int64_t>& pts = kind == 0 ? d1[c] : d2[c];
+        const int64_t o0 = int64_t(order.size());
+        order.insert(order.end(), pts.begin(), pts.end());
+        for (int64_t g = 0; 4 * g < int64_t(pts.size()); ++g) {
+          int cnt = int(std::min<int64_t>(4, int64_t(pts.size()) - 4 * g));
+          items.push_back(int4{kind == 0 ? 0 : 2, int(o0 + 4 * g), cnt, 0});
+        }
+      }
+      count[c][kBPoint] = int64_t(items.size()) - first[c][kBPoint];
+      first[c][kBOuter] = int64_t(items.size());
+      for (int64_t p : d2[c]) {
+        pbase[p] = n_outer;
+        n_outer += table[idx[p]].level[0].n_dir;
+        for (int mo = 0; mo < table[idx[p]].level[0].n_dir; ++mo) items.push_back(int4{1, int(p), mo, 0});
+      }
+      count[c][kBOuter] = int64_t(items.size()) - first[c][kBOuter];
+      first[c][kBFinal] = int64_t(order.size());
+      order.insert(order.end(), d2[c].begin(), d2[c].end());
+      count[c][kBFinal] = int64_t(d2[c].size());
     }
+    const int64_t n_items = int64_t(items.size());
+    if (n_items >= (int64_t(1) << 31) || int64_t(order.size()) >= (int64_t(1) << 31)) return R1_EINVAL;
     const size_t res_sz = r1_outer_res_bytes(dtype);
     size_t off_tab = 0;
     size_t off_items = off_tab + align_up(sizeof(BEntry) * ent.size());
     size_t off_order = off_items + align_up(sizeof(int4) * std::max<size_t>(items.size(), 1));
     size_t off_pbase = off_order + align_up(sizeof(int32_t) * std::max<size_t>(order.size(), 1));
     size_t off_cnt = off_pbase + align_up(sizeof(int64_t) * size_t(n));
-    size_t off_outer = off_cnt + align_up(sizeof(int) * (size_t(n) + 1));
+    size_t off_w1f = off_cnt + align_up(sizeof(int) * size_t(2 * NV));
+    size_t off_outer = off_w1f + align_up(ts * size_t(n));
     size_t total = off_outer + align_up(res_sz * std::max<int64_t>(n_outer, 1));
     pl = new BatchedPlan();
     if (hipMalloc(&pl->dev, total) != hipSuccess) {
@@ -317,33 +336,56 @@ extern "C" r1_status r1_envelope_batched(r1_handle h, const r1_material* mat,
       free_plan(pl);
       return r1h::fail(h, e, "upload plan");
     }
-    BArgs ba{};
-    ba.base.n = n;
-    ba.base.F = F;
-    ba.base.beta_n = beta_n;
-    ba.base.W = W;
-    ba.base.P = P;
-    ba.base.tree = tree;
-    ba.base.flags = flags;
-    ba.base.mat = r1d::Material{mat->dim, mat->model, mat->mu, mat->lambda, mat->D_inf, mat->D0};
-    ba.base.want_stress = P != nullptr;
-    ba.table = reinterpret_cast<const BEntry*>(base + off_tab);
-    ba.lam_idx = lam_idx;
-    ba.items = reinterpret_cast<const int4*>(base + off_items);
-    ba.n_items = int(n_items);
-    ba.counter = reinterpret_cast<int*>(base + off_cnt);
-    ba.pdone = ba.counter + 1;
-    ba.pbase = reinterpret_cast<const int64_t*>(base + off_pbase);
-    ba.order = reinterpret_cast<const int32_t*>(base + off_order);
-    ba.outer = base + off_outer;
-    int per_cu = 0, n_cu = 0;
-    e = r1_occupancy_batched(dtype, dim, lds, &per_cu);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, h->device);
-    if (e != hipSuccess || per_cu < 1 || n_cu < 1) {
+    int n_cu = 0;
+    e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, h->device);
+    if (e != hipSuccess || n_cu < 1) {
       free_plan(pl);
-      return e != hipSuccess ? r1h::fail(h, e, "occupancy") : R1_EUNSUPPORTED;
+      return e != hipSuccess ? r1h::fail(h, e, "device attribute") : R1_EUNSUPPORTED;
     }
-    int64_t grid = std::min<int64_t>(int64_t(per_cu) * n_cu, n_items);
+    // launches: per variant k_bpoint, k_bouter, k_bfinal; counters [2c + kind]
+    struct Launch { BArgs b; int var, kind, grid; size_t lds; };
+    std::vector<Launch> launches;
+    for (int c = 0; c < NV; ++c) {
+      for (int kind = 0; kind < 3; ++kind) {
+        if (count[c][kind] == 0) continue;
+        Launch L{};
+        BArgs& b = L.b;
+        b.base.n = n;
+        b.base.F = F;
+        b.base.beta_n = beta_n;
+        b.base.W = W;
+        b.base.P = P;
+        b.base.tree = tree;
+        b.base.flags = flags;
+        b.base.mat = r1d::Material{mat->dim, mat->model, mat->mu, mat->lambda, mat->D_inf, mat->D0};
+        b.base.want_stress = P != nullptr;
+        b.table = reinterpret_cast<const BEntry*>(base + off_tab);
+        b.lam_idx = lam_idx;
+        b.pbase = reinterpret_cast<const int64_t*>(base + off_pbase);
+        b.outer = base + off_outer;
+        b.w1f = base + off_w1f;
+        b.n_items = int(count[c][kind]);
+        if (kind == kBFinal) {
+          b.order = reinterpret_cast<const int32_t*>(base + off_order) + first[c][kind];
+          L.grid = int((count[c][kind] + 3) / 4);
+        } else {
+          b.order = reinterpret_cast<const int32_t*>(base + off_order);
+          b.items = reinterpret_cast<const int4*>(base + off_items) + first[c][kind];
+          b.counter = reinterpret_cast<int*>(base + off_cnt) + 2 * c + kind;
+          L.lds = kind == kBOuter ? lds[c] : 0;
+          int per_cu = 0;
+          e = r1_occupancy_batched(dtype, dim, c, kind, L.lds, &per_cu);
+          if (e != hipSuccess || per_cu < 1) {
+            free_plan(pl);
+            return e != hipSuccess ? r1h::fail(h, e, "occupancy") : R1_EUNSUPPORTED;
+          }
+          L.grid = int(std::min<int64_t>(int64_t(per_cu) * n_cu, count[c][kind]));
+        }
+        L.var = c;
+        L.kind = kind;
+        launches.push_back(L);
+      }
+    }
     // capture the launch sequence once; replays run it unchanged
     if (!h->capture_stream) {
       e = hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking);
@@ -355,7 +397,14 @@ extern "C" r1_status r1_envelope_batched(r1_handle h, const r1_material* mat,
     }
     e = hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      hipError_t le = r1_launch_batched(ba, dtype, dim, int(grid), lds, int(n) + 1, h->capture_stream);
+      hipError_t le = hipSuccess;
+      int zero_n = 2 * NV;                     // every queue head, once, by a fill kernel
+      for (size_t k = 0; k < launches.size() && le == hipSuccess; ++k) {
+        const Launch& L = launches[k];
+        le = r1_launch_batched(L.b, dtype, dim, L.var, L.kind, L.grid, L.lds, reinterpret_cast<int*>(base + off_cnt),
+                               zero_n, h->capture_stream);
+        zero_n = 0;
+      }
       e = hipStreamEndCapture(h->capture_stream, &pl->graph);
       if (le != hipSuccess) e = le;
     }

@@ -1,15 +1,21 @@
-// Persistent kernel for uneven batches: every point carries its own lamination
-// (grid size, direction count, depth), all in one launch.
+// Persistent kernels for uneven batches: every point carries its own
+// lamination (grid size, direction count, depth), all in one captured graph.
 //
-// Work items (planned and ordered on the host, largest first):
-//   kind 0  up to 4 depth-1 points, one per wavefront of the block;
-//   kind 1  one outer line (point, outer direction) of a depth-2 point, taken by
-//           the whole block.  The block that finishes the last outer line of a
-//           point (per-point counter, device-scope release/acquire) runs the
-//           point's finalization: min over outer directions, stress, tree.
-// Blocks pop items from a global counter until the list is exhausted, so every
-// wave reaches the exit.  The innermost level's layout (lanes per line S,
-// samples per lane K) is a per-table-entry variant chosen by the autotuner.
+// The innermost level's layout (lanes per line S, samples per lane K) is a
+// per-table-entry variant chosen by the autotuner.  For each variant present
+// three kernels run in turn:
+//   k_bpoint  (persistent) groups of up to 4 points, one per wavefront: the
+//             full one-level result of depth-1 points, and W^1 at depth-2
+//             points (the centre of their outer lines) into scratch;
+//   k_bouter  (persistent) one outer line (point, outer direction) of a
+//             depth-2 point per block, as in the plain depth-2 path;
+//   k_bfinal  one wavefront per depth-2 point: min over outer directions,
+//             stress, tree.
+// Work lists are planned and ordered on the host (largest first).  Blocks of a
+// persistent kernel pop items from a global counter until the list is
+// exhausted, so every wave reaches the exit.  Separate kernels per variant and
+// per kind keep each one at the register budget, and occupancy, of the plain
+// kernel doing the same work.
 #pragma once
 #include "r1_kernels.hpp"
 
@@ -23,48 +29,19 @@ struct BArgs {
   KArgs base;              // n, F, beta_n, W, P, tree, flags, material, want_stress
   const BEntry* table;
   const int32_t* lam_idx;  // caller's per-point table index
-  const int4* items;       // {kind, x, y, z}
+  const int4* items;       // this launch's work list (persistent kernels)
   int n_items;
-  int* counter;            // queue head, zeroed before each launch
-  int* pdone;              // per point: finished outer lines, zeroed before each launch
+  int* counter;            // this launch's queue head, zeroed before the launches
+  const int32_t* order;    // point ids: groups of point items, depth-2 lists of k_bfinal
   const int64_t* pbase;    // per point: first outer-result slot
-  const int32_t* order;    // depth-1 points, grouped by the kind-0 items
   void* outer;             // per outer line: hull result
+  void* w1f;               // per point: W^1 at the point (depth-2 points)
 };
 
+// Batched launch kinds.
+constexpr int kBPoint = 0, kBOuter = 1, kBFinal = 2;
+
 namespace r1k {
-
-template <typename T, int D>
-__device__ void b_point_depth1(int var, const KArgs& a, int64_t p, const Level& lv) {
-  switch (var) {
-#define X(V, S, K) case V: point_depth1<T, D, S, K>(a, p, lv); break;
-    R1_BATCH_VARIANTS(X)
-#undef X
-    default: break;
-  }
-}
-
-template <typename T, int D>
-__device__ void b_outer_line(int var, const KArgs& a, int64_t p, int mo, const Level& lo,
-                             const Level& li, OuterRes<T>* out, char* smem) {
-  switch (var) {
-#define X(V, S, K) case V: outer_line<T, D, S, K>(a, p, mo, lo, li, T(0), true, out, smem); break;
-    R1_BATCH_VARIANTS(X)
-#undef X
-    default: break;
-  }
-}
-
-template <typename T, int D>
-__device__ void b_finalize(int var, const KArgs& a, int64_t p, const Level& lo, const Level& li,
-                           const OuterRes<T>* res) {
-  switch (var) {
-#define X(V, S, K) case V: finalize_point<T, D, S, K>(a, p, lo, li, res); break;
-    R1_BATCH_VARIANTS(X)
-#undef X
-    default: break;
-  }
-}
 
 namespace {
 __global__ void k_zero_ints(int* p, int64_t n) {
@@ -73,66 +50,111 @@ __global__ void k_zero_ints(int* p, int64_t n) {
 }
 }  // namespace
 
-template <typename T, int D>
-__global__ __launch_bounds__(256) void k_batched(BArgs b) {
-  extern __shared__ char smem_raw[];
-  __shared__ int s_item, s_last;
-  const KArgs& a = b.base;
+// Pops the next item of the block's persistent loop; block-uniform.
+__device__ __forceinline__ int next_item(int* counter, int* s_item) {
+  __syncthreads();                               // previous item done with s_item / LDS
+  if (threadIdx.x == 0) *s_item = atomicAdd(counter, 1);
+  __syncthreads();
+  return *s_item;
+}
+
+// items: {kind, first, count, 0} -- kind 0: depth-1 points order[first ..
+// first + count), full result; kind 2: depth-2 points, W^1 into w1f.
+template <typename T, int D, int S, int K>
+__global__ __launch_bounds__(256) void k_bpoint(BArgs b) {
+  __shared__ int s_item;
   for (;;) {
-    __syncthreads();                               // previous item done with s_item / LDS
-    if (threadIdx.x == 0) s_item = atomicAdd(b.counter, 1);
-    __syncthreads();
-    const int it = s_item;
-    if (it >= b.n_items) return;                   // block-uniform: every wave exits
+    const int it = next_item(b.counter, &s_item);
+    if (it >= b.n_items) return;                 // block-uniform: every wave exits
     const int4 w = b.items[it];
-    if (w.x == 0) {
-      const int wave = threadIdx.x / kWave;
-      if (wave < w.z) {
-        const int64_t p = b.order[w.y + wave];
-        const BEntry& e = b.table[b.lam_idx[p]];
-        b_point_depth1<T, D>(e.var, a, p, e.lv0);
-      }
-    } else {
-      const int64_t p = w.y;
-      const int mo = w.z;
+    const int wave = threadIdx.x / kWave;
+    if (wave < w.z) {
+      const int64_t p = b.order[w.y + wave];
       const BEntry& e = b.table[b.lam_idx[p]];
-      OuterRes<T>* res = static_cast<OuterRes<T>*>(b.outer) + b.pbase[p];
-      // inadmissible or non-finite points skip the outer line; finalization reports them
-      double F[D * D], bn;
-      bool fin = load_point<T, D>(a, p, F, bn);
-      Point<T> q = make_point<T>(a.mat, bn);
-      double cof[D * D];
-      cofactor<D>(F, cof);
-      bool bad = !fin || !(w_point<T, D>(q, F, cof) < inf_v<T>());
-      if (bad) {
-        if (threadIdx.x == 0) res[mo] = OuterRes<T>{inf_v<T>(), 0, 0, 0};
-      } else {
-        b_outer_line<T, D>(e.var, a, p, mo, e.lv0, e.lv1, res + mo, smem_raw);
+      const bool centre = w.x == 2;
+      KArgs x = b.base;
+      if (centre) {
+        x.W = b.w1f;
+        x.P = nullptr;
+        x.tree = nullptr;
+        x.flags = nullptr;
+        x.want_stress = 0;
       }
-      if (threadIdx.x == 0) {
-        __threadfence();                           // release this line's result
-        s_last = atomicAdd(&b.pdone[p], 1) == e.lv0.n_dir - 1;
-      }
-      __syncthreads();
-      if (s_last) {
-        __threadfence();                           // acquire the other lines' results
-        if (threadIdx.x < kWave) b_finalize<T, D>(e.var, a, p, e.lv0, e.lv1, res);
-      }
+      point_depth1<T, D, S, K>(x, p, centre ? e.lv1 : e.lv0);
     }
   }
 }
 
+// items: {1, point, outer direction, 0}.
+template <typename T, int D, int S, int K>
+__global__ __launch_bounds__(256, (sizeof(T) == 4 && D == 2 && K <= 16) ? 3 : 1) void k_bouter(BArgs b) {
+  extern __shared__ char smem_raw[];
+  __shared__ int s_item;
+  for (;;) {
+    const int it = next_item(b.counter, &s_item);
+    if (it >= b.n_items) return;                 // block-uniform: every wave exits
+    const int4 w = b.items[it];
+    const int64_t p = w.y;
+    const int mo = w.z;
+    const BEntry& e = b.table[b.lam_idx[p]];
+    OuterRes<T>* res = static_cast<OuterRes<T>*>(b.outer) + b.pbase[p] + mo;
+    const T w1f = static_cast<const T*>(b.w1f)[p];
+    if (!(w1f < inf_v<T>())) {                   // det F <= 0 or non-finite input: block-uniform
+      if (threadIdx.x == 0) *res = OuterRes<T>{w1f, 0, 0, 0};
+    } else {
+      outer_line<T, D, S, K>(b.base, p, mo, e.lv0, e.lv1, w1f, false, res, smem_raw);
+    }
+  }
+}
+
+// One wavefront per depth-2 point order[0 .. n_items).
+template <typename T, int D, int S, int K>
+__global__ __launch_bounds__(256) void k_bfinal(BArgs b) {
+  const int64_t i = int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (i >= b.n_items) return;                    // wave-uniform
+  const int64_t p = b.order[i];
+  const BEntry& e = b.table[b.lam_idx[p]];
+  finalize_point<T, D, S, K>(b.base, p, e.lv0, e.lv1, static_cast<const OuterRes<T>*>(b.outer) + b.pbase[p]);
+}
+
+// Zeroes zero_n ints at zero_p (when zero_n > 0), then launches the kernel of
+// the given kind for layout variant var on grid blocks.
 template <typename T, int D>
-hipError_t launch_batched_TD(const BArgs& b, int grid, size_t lds, int zero_n, hipStream_t st) {
-  hipLaunchKernelGGL(k_zero_ints, dim3(unsigned((zero_n + 255) / 256 < 1024 ? (zero_n + 255) / 256 : 1024)),
-                     dim3(256), 0, st, b.counter, int64_t(zero_n));
-  hipLaunchKernelGGL((k_batched<T, D>), dim3(unsigned(grid)), dim3(256), lds, st, b);
+hipError_t launch_batched_TD(const BArgs& b, int var, int kind, int grid, size_t lds, int* zero_p,
+                             int zero_n, hipStream_t st) {
+  if (zero_n > 0)
+    hipLaunchKernelGGL(k_zero_ints, dim3(unsigned((zero_n + 255) / 256 < 1024 ? (zero_n + 255) / 256 : 1024)),
+                       dim3(256), 0, st, zero_p, int64_t(zero_n));
+  switch (var) {
+#define X(V, S, K)                                                                                   \
+  case V:                                                                                            \
+    if (kind == kBPoint)                                                                             \
+      hipLaunchKernelGGL((k_bpoint<T, D, S, K>), dim3(unsigned(grid)), dim3(256), 0, st, b);          \
+    else if (kind == kBOuter)                                                                        \
+      hipLaunchKernelGGL((k_bouter<T, D, S, K>), dim3(unsigned(grid)), dim3(256), lds, st, b);        \
+    else                                                                                             \
+      hipLaunchKernelGGL((k_bfinal<T, D, S, K>), dim3(unsigned(grid)), dim3(256), 0, st, b);          \
+    break;
+    R1_BATCH_VARIANTS(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
+// Resident blocks per CU of a persistent kernel (kind kBPoint or kBOuter).
 template <typename T, int D>
-hipError_t occupancy_batched_TD(size_t lds, int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batched<T, D>, 256, lds);
+hipError_t occupancy_batched_TD(int var, int kind, size_t lds, int* blocks_per_cu) {
+  switch (var) {
+#define X(V, S, K)                                                                                    \
+  case V:                                                                                             \
+    return kind == kBOuter                                                                            \
+               ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_bouter<T, D, S, K>, 256, lds) \
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_bpoint<T, D, S, K>, 256, 0);
+    R1_BATCH_VARIANTS(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace r1k

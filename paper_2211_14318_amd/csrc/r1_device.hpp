@@ -431,60 +431,15 @@ __device__ __forceinline__ void bridge_alternating(const T (&w)[K], const T (&wc
   }
 }
 
-// Hull of the segment's line at its centre.  w: this lane's samples (layout
-// above; NaN = absent); wc: centre sample; wci[h] = wc / m_h.  sig: on entry a
-// slope to start the bridge search from (NaN: none), on exit the bridge slope
-// (NaN when the centre is a vertex).  Every lane of the wave must call this
-// together (cross-lane operations).
-//
-// Vertex test: the centre is a strict hull vertex iff the steepest slope from
-// a left sample up to the centre is below the shallowest slope from the centre
-// to a right sample.  Otherwise the hull over the centre is the bridge (lower
-// common tangent) of the two sides, found by slope iteration: at slope s the
-// lowest left and right samples under the tilt, p = argmin w + s m and
-// q = argmin w - s m (ties to the outermost sample), are the points where lines
-// of slope s support the two sides; s <- slope(p, q) until (p, q) repeats, when
-// every sample lies on or above the line through p and q.  The tilted minima
-// e_p = w_p + s m_p and e_q = w_q - s m_q give both the next slope,
-// s + (e_q - e_p)/(m_p + m_q), and the hull value at the centre,
-// (m_q e_p + m_p e_q)/(m_p + m_q), in which the rounding of s cancels.  The
-// bridge slope is bracketed by the two vertex-test slopes, which give the cold
-// start; a warm start (the previous point's slope on a nearby line) usually
-// needs two passes.
+// Slope iteration for the bridge over the centre (see hull_centre) on the
+// segments with todo set, from slope s: on return those that converged have
+// todo cleared, the pair (mp, mq), the tilted minima (ep, eq) and the slope s
+// of the last pass.  Every lane of the wave must call it.
 template <typename T, int S, int K>
-__device__ __forceinline__ LineHull<T> hull_centre(const T (&w)[K], T wc, const T (&wci)[K / 2],
-                                                   const Layout<T, S, K>& lay, T& sig) {
+__device__ __forceinline__ void slope_bridge(const T (&w)[K], const Layout<T, S, K>& lay, bool& todo,
+                                             T& s, int& mp, int& mq, T& ep, T& eq) {
   constexpr int H = K / 2;
-  T maxL = -inf_v<T>(), minR = inf_v<T>();
-#pragma unroll
-  for (int h = 0; h < H; ++h) {
-    maxL = fmax(maxL, fma(-w[h], lay.inv_m[h], wci[h]));
-    minR = fmin(minR, fma(w[H + h], lay.inv_m[h], -wci[h]));
-  }
-  bool todo;
-  if constexpr (sizeof(T) == 4) {
-    const int kl = seg_max_i<S>(ord_key(maxL));
-    const int kr = seg_min_i<S>(ord_key(minR));
-    todo = kl >= kr;
-    maxL = ord_val(kl);
-    minR = ord_val(kr);
-  } else {
-    maxL = seg_max<S>(maxL);
-    minR = seg_min<S>(minR);
-    todo = maxL >= minR;
-  }
-  LineHull<T> r;
-  r.h = wc; r.mp = 0; r.mq = 0; r.capped = 0;
-  const T nan = T(__builtin_nan(""));
-  if (!__any(todo)) {
-    sig = nan;
-    return r;
-  }
-  const bool bridged = todo;
-  T s = sig == sig ? fmin(fmax(sig, minR), maxL) : T(0.5) * (maxL + minR);
   const int sl = threadIdx.x & (S - 1);
-  int mp = 0, mq = 0;
-  T ep = T(0), eq = T(0);
   for (int pass = 0; pass < kSlopePasses && __any(todo); ++pass) {
     T eL = inf_v<T>(), eR = inf_v<T>();
     int hL = -1, hR = -1;
@@ -511,6 +466,86 @@ __device__ __forceinline__ LineHull<T> hull_centre(const T (&w)[K], T wc, const 
       }
     }
   }
+}
+
+// Hull of the segment's line at its centre.  w: this lane's samples (layout
+// above; NaN = absent); wc: centre sample; wci[h] = wc / m_h.  sig: on entry a
+// slope to start the bridge search from (NaN: none), on exit the bridge slope
+// (NaN when the centre is a vertex).  Every lane of the wave must call this
+// together (cross-lane operations).
+//
+// Vertex test: the centre is a strict hull vertex iff the steepest slope from
+// a left sample up to the centre is below the shallowest slope from the centre
+// to a right sample.  Otherwise the hull over the centre is the bridge (lower
+// common tangent) of the two sides, found by slope iteration: at slope s the
+// lowest left and right samples under the tilt, p = argmin w + s m and
+// q = argmin w - s m (ties to the outermost sample), are the points where lines
+// of slope s support the two sides; s <- slope(p, q) until (p, q) repeats, when
+// every sample lies on or above the line through p and q.  The tilted minima
+// e_p = w_p + s m_p and e_q = w_q - s m_q give both the next slope,
+// s + (e_q - e_p)/(m_p + m_q), and the hull value at the centre,
+// (m_q e_p + m_p e_q)/(m_p + m_q), in which the rounding of s cancels.  The
+// bridge slope is bracketed by the two vertex-test slopes, which give the cold
+// start; a warm start (the previous point's slope on a nearby line) usually
+// needs two passes.
+//
+// hot (wave-uniform): every line of the wave has a warm start.  The vertex
+// test is then skipped: the centre is a vertex exactly when the bridge of the
+// other samples passes above it.  If any line of the wave ends without a
+// bridge (no sample on one side, or no convergence), the wave takes the
+// standard path instead.
+template <typename T, int S, int K>
+__device__ __forceinline__ LineHull<T> hull_centre(const T (&w)[K], T wc, const T (&wci)[K / 2],
+                                                   const Layout<T, S, K>& lay, T& sig, bool hot) {
+  constexpr int H = K / 2;
+  LineHull<T> r;
+  r.h = wc; r.mp = 0; r.mq = 0; r.capped = 0;
+  const T nan = T(__builtin_nan(""));
+  if (hot) {
+    bool todo = true;
+    T s = sig;
+    int mp = 0, mq = 0;
+    T ep = T(0), eq = T(0);
+    slope_bridge<T, S, K>(w, lay, todo, s, mp, mq, ep, eq);
+    if (!__any(todo || !(mp >= 1 && mq >= 1))) {
+      const T mpf = T(mp), mqf = T(mq);
+      const T hb = (mqf * ep + mpf * eq) / (mqf + mpf);
+      if (hb <= wc) {
+        r.h = hb; r.mp = mp; r.mq = mq;
+        sig = s;
+      } else {
+        sig = nan;
+      }
+      return r;
+    }
+  }
+  T maxL = -inf_v<T>(), minR = inf_v<T>();
+#pragma unroll
+  for (int h = 0; h < H; ++h) {
+    maxL = fmax(maxL, fma(-w[h], lay.inv_m[h], wci[h]));
+    minR = fmin(minR, fma(w[H + h], lay.inv_m[h], -wci[h]));
+  }
+  bool todo;
+  if constexpr (sizeof(T) == 4) {
+    const int kl = seg_max_i<S>(ord_key(maxL));
+    const int kr = seg_min_i<S>(ord_key(minR));
+    todo = kl >= kr;
+    maxL = ord_val(kl);
+    minR = ord_val(kr);
+  } else {
+    maxL = seg_max<S>(maxL);
+    minR = seg_min<S>(minR);
+    todo = maxL >= minR;
+  }
+  if (!__any(todo)) {
+    sig = nan;
+    return r;
+  }
+  const bool bridged = todo;
+  T s = sig == sig ? fmin(fmax(sig, minR), maxL) : T(0.5) * (maxL + minR);
+  int mp = 0, mq = 0;
+  T ep = T(0), eq = T(0);
+  slope_bridge<T, S, K>(w, lay, todo, s, mp, mq, ep, eq);
   if (__any(todo)) {
     // slope budget spent (not seen in practice): finish with the alternating search
     T wp = T(0), wq = T(0);
@@ -522,7 +557,7 @@ __device__ __forceinline__ LineHull<T> hull_centre(const T (&w)[K], T wc, const 
     }
   }
   if (bridged) {
-    T mpf = T(mp), mqf = T(mq);
+    const T mpf = T(mp), mqf = T(mq);
     r.h = (mqf * ep + mpf * eq) / (mqf + mpf);
     r.mp = mp;
     r.mq = mq;
@@ -597,10 +632,15 @@ struct Env {            // W^1 at a point: value, direction, bracketing offsets
 // none; callers whose successive points are close pass it.  c2u: when every
 // line has the same c2 (and, being lines through one point, the same c0), that
 // c2; the polynomial part c0 + c2 t^2 is then formed once per point (NaN: not
-// uniform).  Every lane of the wave must call it.
+// uniform).  order (optional with warm, n_dir entries owned by this wave): the
+// directions are visited with those that had a bridge last time first, so that
+// lines needing a bridge search share wavefronts; ties in the minimum go to the
+// smaller direction index whatever the visiting order.  Every lane of the wave
+// must call it.
 template <typename T, int S, int K, typename LineFn>
 __device__ Env<T> envelope_lines(const Point<T>& q, T wc, int n_dir, const Layout<T, S, K>& lay,
-                                 LineFn line_fn, T* warm = nullptr, T c2u = T(__builtin_nan(""))) {
+                                 LineFn line_fn, T* warm = nullptr, T c2u = T(__builtin_nan("")),
+                                 int* order = nullptr) {
   constexpr int NSEG = kWave / S;
   constexpr int H = K / 2;
   const int lane = threadIdx.x & (kWave - 1);
@@ -615,11 +655,29 @@ __device__ Env<T> envelope_lines(const Point<T>& q, T wc, int n_dir, const Layou
 #pragma unroll
     for (int h = 0; h < H; ++h) base[h] = fma(c2u, lay.t[h] * lay.t[h], c0);
   }
+  if (order) {
+    // stable partition of the directions: warm (bridged last time) first
+    int n_warm = 0;
+    for (int c0 = 0; c0 < n_dir; c0 += kWave)
+      n_warm += __popcll(__ballot(c0 + lane < n_dir && warm[c0 + lane] == warm[c0 + lane]));
+    int seen_warm = 0, seen_cold = 0;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int c0 = 0; c0 < n_dir; c0 += kWave) {
+      const int i = c0 + lane;
+      const bool valid = i < n_dir;
+      const bool hot = valid && warm[i] == warm[i];
+      const unsigned long long mh = __ballot(hot), mc = __ballot(valid && !hot);
+      if (valid)
+        order[hot ? seen_warm + __popcll(mh & below) : n_warm + seen_cold + __popcll(mc & below)] = i;
+      seen_warm += __popcll(mh);
+      seen_cold += __popcll(mc);
+    }
+  }
   Env<T> best = {inf_v<T>(), 0, 0, 0, 0};
   for (int m0 = 0; m0 < n_dir; m0 += NSEG) {
-    int dir = m0 + seg;
-    bool act = dir < n_dir;
-    Line<T> L = line_fn(act ? dir : n_dir - 1);
+    const bool act = m0 + seg < n_dir;
+    const int dir = order ? order[act ? m0 + seg : n_dir - 1] : (act ? m0 + seg : n_dir - 1);
+    Line<T> L = line_fn(dir);
     T w[K];
     if (shared) {
 #pragma unroll
@@ -641,9 +699,10 @@ __device__ Env<T> envelope_lines(const Point<T>& q, T wc, int n_dir, const Layou
       }
     }
     T sg = (warm && act) ? warm[dir] : T(__builtin_nan(""));
-    LineHull<T> lh = hull_centre<T, S, K>(w, wc, wci, lay, sg);
+    const bool hot = warm && __all(act && sg == sg);
+    LineHull<T> lh = hull_centre<T, S, K>(w, wc, wci, lay, sg, hot);
     if (warm && act && (lane & (S - 1)) == 0) warm[dir] = sg;
-    if (act && lh.h < best.h) {
+    if (act && (lh.h < best.h || (lh.h == best.h && dir < best.dir))) {
       best.h = lh.h; best.dir = dir; best.mp = lh.mp; best.mq = lh.mq;
     }
     best.capped |= lh.capped;

@@ -18,25 +18,32 @@ size_t r1_outer_res_bytes(int dtype) {
 }
 
 struct BArgs;
-hipError_t r1_launch_batched_f32_2d(const BArgs& b, int grid, size_t lds, int zero_n, hipStream_t st);
-hipError_t r1_launch_batched_f32_3d(const BArgs& b, int grid, size_t lds, int zero_n, hipStream_t st);
-hipError_t r1_launch_batched_f64_2d(const BArgs& b, int grid, size_t lds, int zero_n, hipStream_t st);
-hipError_t r1_launch_batched_f64_3d(const BArgs& b, int grid, size_t lds, int zero_n, hipStream_t st);
-hipError_t r1_occupancy_batched_f32_2d(size_t lds, int* blocks_per_cu);
-hipError_t r1_occupancy_batched_f32_3d(size_t lds, int* blocks_per_cu);
-hipError_t r1_occupancy_batched_f64_2d(size_t lds, int* blocks_per_cu);
-hipError_t r1_occupancy_batched_f64_3d(size_t lds, int* blocks_per_cu);
+hipError_t r1_launch_batched_f32_2d(const BArgs& b, int var, int kind, int grid, size_t lds, int* zero_p, int zero_n,
+                                    hipStream_t st);
+hipError_t r1_launch_batched_f32_3d(const BArgs& b, int var, int kind, int grid, size_t lds, int* zero_p, int zero_n,
+                                    hipStream_t st);
+hipError_t r1_launch_batched_f64_2d(const BArgs& b, int var, int kind, int grid, size_t lds, int* zero_p, int zero_n,
+                                    hipStream_t st);
+hipError_t r1_launch_batched_f64_3d(const BArgs& b, int var, int kind, int grid, size_t lds, int* zero_p, int zero_n,
+                                    hipStream_t st);
+hipError_t r1_occupancy_batched_f32_2d(int var, int kind, size_t lds, int* blocks_per_cu);
+hipError_t r1_occupancy_batched_f32_3d(int var, int kind, size_t lds, int* blocks_per_cu);
+hipError_t r1_occupancy_batched_f64_2d(int var, int kind, size_t lds, int* blocks_per_cu);
+hipError_t r1_occupancy_batched_f64_3d(int var, int kind, size_t lds, int* blocks_per_cu);
 
-hipError_t r1_launch_batched(const BArgs& b, int dtype, int dim, int grid, size_t lds, int zero_n,
-                             hipStream_t st) {
+hipError_t r1_launch_batched(const BArgs& b, int dtype, int dim, int var, int kind, int grid, size_t lds, int* zero_p,
+                             int zero_n, hipStream_t st) {
   if (dtype == R1_F32)
-    return dim == 2 ? r1_launch_batched_f32_2d(b, grid, lds, zero_n, st) : r1_launch_batched_f32_3d(b, grid, lds, zero_n, st);
-  return dim == 2 ? r1_launch_batched_f64_2d(b, grid, lds, zero_n, st) : r1_launch_batched_f64_3d(b, grid, lds, zero_n, st);
+    return dim == 2 ? r1_launch_batched_f32_2d(b, var, kind, grid, lds, zero_p, zero_n, st)
+                    : r1_launch_batched_f32_3d(b, var, kind, grid, lds, zero_p, zero_n, st);
+  return dim == 2 ? r1_launch_batched_f64_2d(b, var, kind, grid, lds, zero_p, zero_n, st)
+                  : r1_launch_batched_f64_3d(b, var, kind, grid, lds, zero_p, zero_n, st);
 }
 
-hipError_t r1_occupancy_batched(int dtype, int dim, size_t lds, int* blocks_per_cu) {
+hipError_t r1_occupancy_batched(int dtype, int dim, int var, int kind, size_t lds, int* blocks_per_cu) {
   if (dtype == R1_F32)
-    return dim == 2 ? r1_occupancy_batched_f32_2d(lds, blocks_per_cu) : r1_occupancy_batched_f32_3d(lds, blocks_per_cu);
-  return dim == 2 ? r1_occupancy_batched_f64_2d(lds, blocks_per_cu) : r1_occupancy_batched_f64_3d(lds, blocks_per_cu);
+    return dim == 2 ? r1_occupancy_batched_f32_2d(var, kind, lds, blocks_per_cu)
+                    : r1_occupancy_batched_f32_3d(var, kind, lds, blocks_per_cu);
+  return dim == 2 ? r1_occupancy_batched_f64_2d(var, kind, lds, blocks_per_cu)
+                  : r1_occupancy_batched_f64_3d(var, kind, lds, blocks_per_cu);
 }
-

@@ -90,7 +90,7 @@ __device__ __forceinline__ void write_bad_point(const KArgs& a, int64_t p, bool 
 // One-level envelope of point p on level lv, with stress, tree and flags as
 // requested by a (wave-level: every lane of the wave calls it).
 template <typename T, int D, int S, int K>
-__device__ void point_depth1(const KArgs& a, int64_t p, const Level& lv) {
+__device__ __forceinline__ void point_depth1(const KArgs& a, int64_t p, const Level& lv) {
   double G[D * D], bn;
   bool fin = load_point<T, D>(a, p, G, bn);
   Layout<T, S, K> lay = make_layout<T, S, K>(lv.n_t, lv.tau);
@@ -193,17 +193,19 @@ constexpr int kMaxTabDirs = 512;
 // Waves of an outer-line block (blocks are 256 threads).
 constexpr int kOuterWaves = 4;
 
-// Elements of T of dynamic LDS an outer line needs: the outer line's samples
-// and, when the inner level is tabulated, its coefficient table and each
-// wave's warm-start bridge slopes.
-__host__ __device__ inline size_t outer_lds_elems(int n_t_outer, int n_dir_inner) {
-  return size_t(n_t_outer - 1) +
-         (n_dir_inner <= kMaxTabDirs ? size_t(5 + kOuterWaves) * size_t(n_dir_inner) : 0);
+// Bytes of dynamic LDS an outer line needs for samples of elem_bytes bytes:
+// the outer line's samples and, when the inner level is tabulated, its
+// coefficient table, each wave's warm-start bridge slopes and each wave's
+// direction visiting order (int).
+__host__ __device__ inline size_t outer_lds_bytes(size_t elem_bytes, int n_t_outer, int n_dir_inner) {
+  const bool tab = n_dir_inner <= kMaxTabDirs;
+  return elem_bytes * (size_t(n_t_outer - 1) + (tab ? size_t(5 + kOuterWaves) * size_t(n_dir_inner) : 0)) +
+         (tab ? sizeof(int) * size_t(kOuterWaves) * size_t(n_dir_inner) : 0);
 }
 
 template <typename T>
 __host__ __device__ inline size_t outer_lds_bytes(const Level& lo, const Level& li) {
-  return sizeof(T) * outer_lds_elems(lo.n_t, li.n_dir);
+  return outer_lds_bytes(sizeof(T), lo.n_t, li.n_dir);
 }
 
 // One outer line (block-level, every thread calls it): the samples W^1(F + t_i R_mo)
@@ -212,7 +214,7 @@ __host__ __device__ inline size_t outer_lds_bytes(const Level& lo, const Level& 
 // compute_centre is set it is computed here (by wave 0) instead.  Thread 0
 // writes the result to *out.  Returns the centre value used.
 template <typename T, int D, int S, int K>
-__device__ T outer_line(const KArgs& a, int64_t p, int mo, const Level& lo, const Level& li, T w1f,
+__device__ __forceinline__ T outer_line(const KArgs& a, int64_t p, int mo, const Level& lo, const Level& li, T w1f,
                         bool compute_centre, OuterRes<T>* out, char* smem_raw) {
   const int co = (lo.n_t - 1) / 2;
   const bool tab = li.n_dir <= kMaxTabDirs;
@@ -220,6 +222,7 @@ __device__ T outer_line(const KArgs& a, int64_t p, int mo, const Level& lo, cons
   T* warm = coef + (tab ? 5 * li.n_dir : 0);                // kOuterWaves * n_dir_i (when tabulated)
   T* wl = warm + (tab ? kOuterWaves * li.n_dir : 0);        // outer samples at -m
   T* wr = wl + co;                                          // outer samples at +m
+  int* order = reinterpret_cast<int*>(wr + co);             // kOuterWaves * n_dir_i (when tabulated)
   __shared__ int capped_any;
   __shared__ T centre;
   double F[D * D], bn;
@@ -260,6 +263,7 @@ __device__ T outer_line(const KArgs& a, int64_t p, int mo, const Level& lo, cons
   // wave walks one side outwards in steps of two samples, so the previous
   // sample's inner bridge slopes (warm, per inner direction) start the next
   T* warm_w = warm + wave * li.n_dir;          // blocks have kOuterWaves waves
+  int* order_w = order + wave * li.n_dir;
   for (int s = wave; s < 2 * co; s += nwave) {
     int m = 1 + (s >> 1);
     double t = (s & 1) ? t_of(lo, m) : -t_of(lo, m);
@@ -294,7 +298,7 @@ __device__ T outer_line(const KArgs& a, int64_t p, int mo, const Level& lo, cons
         Env<T> e = envelope_lines<T, S, K>(q, wc, li.n_dir, lay, [&](int dd) {
           const T* cf = coef + 5 * dd;
           return Line<T>{L0.J0, T(fma(tt, cf[1], cf[0])), L0.c0, T(fma(tt, cf[3], cf[2])), cf[4]};
-        }, warm_w, T(q.kq * li.ab2));
+        }, warm_w, T(q.kq * li.ab2), order_w);
         v = e.h;
         capped |= e.capped;
       }
@@ -323,7 +327,7 @@ __device__ T outer_line(const KArgs& a, int64_t p, int mo, const Level& lo, cons
 }
 
 template <typename T, int D, int S, int K>
-__global__ __launch_bounds__(256) void k_outer(KArgs a) {
+__global__ __launch_bounds__(256, (sizeof(T) == 4 && D == 2 && K <= 16) ? 3 : 1) void k_outer(KArgs a) {
   extern __shared__ char smem_raw[];
   const int n_dir_o = a.lv0.n_dir;
   const int64_t p = int64_t(blockIdx.x) / n_dir_o;
@@ -341,7 +345,7 @@ __global__ __launch_bounds__(256) void k_outer(KArgs a) {
 // min over outer directions, then stress and tree through Algorithm 3 on the
 // binary tree (wave-level).
 template <typename T, int D, int S, int K>
-__device__ void finalize_point(const KArgs& a, int64_t p, const Level& lo, const Level& li,
+__device__ __forceinline__ void finalize_point(const KArgs& a, int64_t p, const Level& lo, const Level& li,
                                const OuterRes<T>* res) {
   const int n_dir_o = lo.n_dir;
   double F[D * D], bn;

@@ -70,16 +70,24 @@ hipError_t r1_launch_envelope(const KArgs& a, int depth, int dtype, int S, int K
 size_t r1_outer_res_bytes(int dtype);
 
 struct BArgs;
-// Persistent uneven-batch launch (zeroes counter[0 .. zero_n) first, then runs
-// `grid` persistent blocks with `lds` bytes of dynamic LDS).
-hipError_t r1_launch_batched(const BArgs& b, int dtype, int dim, int grid, size_t lds, int zero_n,
-                             hipStream_t st);
-hipError_t r1_occupancy_batched(int dtype, int dim, size_t lds, int* blocks_per_cu);
+// Uneven-batch kernel of the given kind (kBPoint, kBOuter, kBFinal) for layout
+// variant var on `grid` blocks with `lds` bytes of dynamic LDS, preceded by
+// zeroing zero_n ints at zero_p when zero_n > 0.
+hipError_t r1_launch_batched(const BArgs& b, int dtype, int dim, int var, int kind, int grid, size_t lds,
+                             int* zero_p, int zero_n, hipStream_t st);
+hipError_t r1_occupancy_batched(int dtype, int dim, int var, int kind, size_t lds, int* blocks_per_cu);
 // Layout variants of the persistent kernel, (variant, S, K): lanes per line and
 // samples per lane of the innermost level.
 #define R1_BATCH_VARIANTS(X) \
   X(0, 16, 4) X(1, 16, 8) X(2, 8, 32) X(3, 16, 16) X(4, 32, 8) X(5, 64, 4) \
   X(6, 16, 32) X(7, 32, 16) X(8, 64, 8) X(9, 32, 32) X(10, 64, 16) X(11, 64, 32)
+
+// Number of layout variants.
+constexpr int R1_N_BATCH_VARIANTS = 0
+#define X(V, SS, KK) + 1
+    R1_BATCH_VARIANTS(X)
+#undef X
+    ;
 
 // Variant index of (S, K), or -1.
 inline int r1_batch_variant(int S, int K) {
