@@ -187,9 +187,9 @@ r1_status r1_autotune(r1_handle handle, const r1_material* material, int32_t n_t
  *
  * Routing at inference: a point goes to the fallback lamination when it lies
  * outside the training box (per-input min/max of the training rows, det F above
- * the smallest training det) or in a gate cell ((|F - I|, beta_n) bin x
- * predicted class) that calibration did not accept.  Uncalibrated surrogates
- * route on the box only.
+ * the smallest training det) or when its predicted gap exceeds the threshold
+ * calibration set for its gate cell ((|F - I|, beta_n) bin).  Uncalibrated
+ * surrogates route on the box only.
  *
  * Packed rows (device, FP32, row-major): X[p] = (F_11, .., F_dd, beta_n),
  * Y[p] = (W^k, P_11, .., P_dd).
@@ -235,12 +235,14 @@ r1_status r1_surrogate_train(r1_handle handle, r1_surrogate surrogate, const r1_
                              r1_train_report* report, void* stream);
 
 /* Error gate: predicts n packed validation rows (X, Y from plain lamination)
- * and, per cell = (|F - I|, beta_n) bin x predicted class (no lamination /
- * lamination), counts the rows with |W_pred - W^k| / max(|W^k|, 1e-2) > tol.
- * A cell is used at inference when it saw at least 16 rows and a fraction of at
- * least `quantile` of them was within tol; other cells fall back.
- * cells_allowed (nullable, host) receives the number of usable cells (of
- * 2 x 16 x 8).  Synchronizes `stream`. */
+ * and, per cell = (|F - I|, beta_n) bin, orders the rows by predicted gap g.
+ * The cell's threshold is the largest g such that the rows with predicted gap
+ * <= g number at least 16 and a fraction of at least `quantile` of them has
+ * |W_pred - W^k| / max(|W^k|, 1e-2) <= tol; at inference a point is served by
+ * the network when its predicted gap is at most its cell's threshold, and
+ * falls back otherwise (cells without a threshold always fall back).
+ * cells_allowed (nullable, host) receives the number of cells with a
+ * threshold (of 16 x 8).  Synchronizes `stream`. */
 r1_status r1_surrogate_calibrate(r1_handle handle, r1_surrogate surrogate,
                                  const r1_material* material, const float* X, const float* Y,
                                  int64_t n, float tol, float quantile, int32_t* cells_allowed,

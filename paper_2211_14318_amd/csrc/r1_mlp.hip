@@ -350,12 +350,13 @@ __device__ __forceinline__ int gate_bin(const InferParams& ip, const double* F, 
 // BF16 weights in global memory (L2-resident), bias + SiLU, back to LDS; output
 // layer in FP32; exact W(F), P0(F); W = W(F) - max(g, 0), P = P0 - dP.
 // MODE 0: gates on, rejected points appended to the fallback list.
-// MODE 1 (calibration): box gate only; the bin index and predicted W go to
-// cal_bin / cal_w, rejected points get bin -1.
+// MODE 1 (calibration): box gate only; the gate cell, predicted W and
+// predicted gap go to cal_bin / cal_w / cal_gap, rejected points get cell -1.
 template <typename T, int D, int WID, int MODE>
 __global__ __launch_bounds__(256) void k_infer(InferParams ip, const T* F, const T* bn, T* W,
                                                T* P, int32_t* flags, int* fb_count,
-                                               int32_t* fb_list, int* cal_bin, float* cal_w) {
+                                               int32_t* fb_list, int* cal_bin, float* cal_w,
+                                               float* cal_gap) {
   constexpr int DI = D * D + 1, DO = D * D + 1;
   constexpr int LD = WID + 8;                      // padded BF16 row stride (bank spread)
   extern __shared__ char smem[];
@@ -423,18 +424,19 @@ __global__ __launch_bounds__(256) void k_infer(InferParams ip, const T* F, const
   }
   if (half != 0 || !valid) return;
   // de-standardize; a non-positive gap means no lamination: W(F), P0(F) exactly
-  const double raw = double(out[0] * ip.y_std[0] + ip.y_mean[0]);
+  const float rawf = out[0] * ip.y_std[0] + ip.y_mean[0];
+  const double raw = double(rawf);
   const bool convex = raw <= 0.0;
-  const int cls = convex ? 0 : 1;
   r1d::Point<double> q = r1d::make_point<double>(ip.mat, b);
   const double w_un = r1d::w_point<double, D>(q, G, cof);
   const double wpred = convex ? w_un : w_un - raw;
   if (MODE == 1) {
-    cal_bin[pt] = ok ? 2 * bin + cls : -1;
+    cal_bin[pt] = ok ? bin : -1;
     cal_w[pt] = float(wpred);
+    cal_gap[pt] = rawf;
     return;
   }
-  if (ip.bins_on) ok = ok && ip.bin_ok[2 * bin + cls];
+  if (ip.bins_on) ok = ok && rawf <= ip.gate_tau[bin];
   if (!ok || !(det > 0.0)) {
     const int slot = atomicAdd(fb_count, 1);
     fb_list[slot] = int32_t(pt);
@@ -447,20 +449,6 @@ __global__ __launch_bounds__(256) void k_infer(InferParams ip, const T* F, const
     P[int64_t(k) * ip.n + pt] =
         T(convex ? P0[k] : P0[k] - double(out[1 + k] * ip.y_std[1 + k] + ip.y_mean[1 + k]));
   if (flags) flags[pt] = 0;
-}
-
-// Per (bin, predicted class) count of calibration points and of points whose
-// relative energy error exceeds tol.
-__global__ void k_bin_error(int64_t n, int DI, const float* Y, const int* cal_bin, const float* cal_w,
-                            float tol, int* bin_bad, int* bin_cnt) {
-  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  const int b = cal_bin[p];
-  if (b < 0) return;
-  const float ref = Y[p * DI];
-  const float e = fabsf(cal_w[p] - ref) / fmaxf(fabsf(ref), 1e-2f);
-  atomicAdd(&bin_cnt[b], 1);
-  if (!(e <= tol)) atomicAdd(&bin_bad[b], 1);
 }
 
 // Gather fallback points into compact SoA arrays, and scatter their results back.
@@ -615,14 +603,14 @@ size_t r1m_infer_lds(int width) { return size_t(4) * 32 * (width + 8) * 2; }
 template <typename T, int D>
 static hipError_t infer_TD(const InferParams& ip, int mode, const void* F, const void* bn, void* W, void* P,
                            int32_t* flags, int* fb_count, int32_t* fb_list, int* cal_bin, float* cal_w,
-                           hipStream_t st) {
+                           float* cal_gap, hipStream_t st) {
   dim3 grid(unsigned((ip.n + 127) / 128));
   size_t lds = r1m_infer_lds(ip.width);
 #define R1I(WID, MODE) (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_infer<T, D, WID, MODE>), \
       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)); \
   hipLaunchKernelGGL((k_infer<T, D, WID, MODE>), grid, dim3(256), lds, st, ip, \
       static_cast<const T*>(F), static_cast<const T*>(bn), static_cast<T*>(W), static_cast<T*>(P), flags, \
-      fb_count, fb_list, cal_bin, cal_w)
+      fb_count, fb_list, cal_bin, cal_w, cal_gap)
 #define R1W(WID) if (ip.width == WID) { if (mode == 0) { R1I(WID, 0); } else { R1I(WID, 1); } return hipGetLastError(); }
   R1W(32) R1W(64) R1W(128) R1W(256)
 #undef R1W
@@ -632,18 +620,12 @@ static hipError_t infer_TD(const InferParams& ip, int mode, const void* F, const
 
 hipError_t r1m_infer(int dtype, int dim, const InferParams& ip, int mode, const void* F, const void* bn,
                      void* W, void* P, int32_t* flags, int* fb_count, int32_t* fb_list, int* cal_bin,
-                     float* cal_w, hipStream_t st) {
+                     float* cal_w, float* cal_gap, hipStream_t st) {
   if (dtype == R1_F32)
-    return dim == 2 ? infer_TD<float, 2>(ip, mode, F, bn, W, P, flags, fb_count, fb_list, cal_bin, cal_w, st)
-                    : infer_TD<float, 3>(ip, mode, F, bn, W, P, flags, fb_count, fb_list, cal_bin, cal_w, st);
-  return dim == 2 ? infer_TD<double, 2>(ip, mode, F, bn, W, P, flags, fb_count, fb_list, cal_bin, cal_w, st)
-                  : infer_TD<double, 3>(ip, mode, F, bn, W, P, flags, fb_count, fb_list, cal_bin, cal_w, st);
-}
-
-hipError_t r1m_bin_error(int64_t n, int DI, const float* Y, const int* cal_bin, const float* cal_w,
-                         float tol, int* bin_bad, int* bin_cnt, hipStream_t st) {
-  hipLaunchKernelGGL(k_bin_error, dim3(nblk(n)), dim3(256), 0, st, n, DI, Y, cal_bin, cal_w, tol, bin_bad, bin_cnt);
-  return hipGetLastError();
+    return dim == 2 ? infer_TD<float, 2>(ip, mode, F, bn, W, P, flags, fb_count, fb_list, cal_bin, cal_w, cal_gap, st)
+                    : infer_TD<float, 3>(ip, mode, F, bn, W, P, flags, fb_count, fb_list, cal_bin, cal_w, cal_gap, st);
+  return dim == 2 ? infer_TD<double, 2>(ip, mode, F, bn, W, P, flags, fb_count, fb_list, cal_bin, cal_w, cal_gap, st)
+                  : infer_TD<double, 3>(ip, mode, F, bn, W, P, flags, fb_count, fb_list, cal_bin, cal_w, cal_gap, st);
 }
 
 hipError_t r1m_fb_gather(int dtype, int dim, int64_t n, int nfb, const int32_t* list, const void* F,

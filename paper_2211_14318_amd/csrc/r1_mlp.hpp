@@ -14,7 +14,7 @@ constexpr int kMaxCols = 10;      // d_in, d_out <= 10
 constexpr int kMaxHidden = 8;
 constexpr int kBinsR = 16;        // error-gate bins over |F - I|_F
 constexpr int kBinsB = 8;         // ... and over beta_n
-constexpr int kGateCells = 2 * kBinsR * kBinsB;   // bins x {predicted convex, laminating}
+constexpr int kGateCells = kBinsR * kBinsB;   // each with a threshold on the predicted gap
 constexpr float kZeroGap = 1e-6f;  // gap targets at or below this did not laminate
 constexpr float kHingeMargin = 0.25f;  // standardized margin below the no-lamination threshold
 
@@ -32,7 +32,7 @@ struct InferParams {
   float det_lo;
   double r_max, b_lo, b_hi;
   int bins_on;
-  const int* bin_ok;                // 2 * kBinsR * kBinsB: (bin, predicted convex / laminating)
+  const float* gate_tau;            // kGateCells: accept when the predicted gap is <= the cell's value
 };
 
 hipError_t r1m_gemm(int epi, bool b_bf16, int M, int N, int K, const float* A, int64_t sam,
@@ -67,9 +67,7 @@ hipError_t r1m_unpack(int dim, int64_t n, const float* X, float* F, float* bn, h
 size_t r1m_infer_lds(int width);
 hipError_t r1m_infer(int dtype, int dim, const InferParams& ip, int mode, const void* F, const void* bn,
                      void* W, void* P, int32_t* flags, int* fb_count, int32_t* fb_list, int* cal_bin,
-                     float* cal_w, hipStream_t st);
-hipError_t r1m_bin_error(int64_t n, int DI, const float* Y, const int* cal_bin, const float* cal_w,
-                         float tol, int* bin_bad, int* bin_cnt, hipStream_t st);
+                     float* cal_w, float* cal_gap, hipStream_t st);
 hipError_t r1m_fb_gather(int dtype, int dim, int64_t n, int nfb, const int32_t* list, const void* F,
                          const void* bn, void* Fc, void* bc, hipStream_t st);
 hipError_t r1m_fb_scatter(int dtype, int dim, int64_t n, int nfb, const int32_t* list, const void* Wc,

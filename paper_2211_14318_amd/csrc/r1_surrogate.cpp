@@ -30,8 +30,8 @@ struct r1_surrogate_s {
   double r_max = 1.0, b_lo = 0.0, b_hi = 1.0;
   bool trained = false;
   int bins_on = 0;
-  int bin_ok_h[kGateCells] = {};
-  int* bin_ok = nullptr;
+  float gate_tau_h[kGateCells] = {};        // per gate cell: accept predicted gaps <= this
+  float* gate_tau = nullptr;
   float* norm_dev = nullptr;                // device copy of norm
   void* ws = nullptr;                       // training / inference workspace
   size_t ws_bytes = 0;
@@ -89,18 +89,18 @@ r1_status alloc_state(r1_surrogate s) {
   if (hipMalloc(&s->params, pb) != hipSuccess || hipMalloc(&s->grad, pb) != hipSuccess ||
       hipMalloc(&s->m, pb) != hipSuccess || hipMalloc(&s->v, pb) != hipSuccess ||
       hipMalloc(&s->wbf, size_t(std::max(1, s->n_hidden - 1)) * s->width * s->width * 2) != hipSuccess ||
-      hipMalloc(&s->bin_ok, sizeof(int) * kGateCells) != hipSuccess ||
+      hipMalloc(&s->gate_tau, sizeof(float) * kGateCells) != hipSuccess ||
       hipMalloc(&s->norm_dev, sizeof(float) * 4 * kMaxCols) != hipSuccess)
     return R1_ENOMEM;
   if (hipMemset(s->m, 0, pb) != hipSuccess || hipMemset(s->v, 0, pb) != hipSuccess ||
-      hipMemset(s->bin_ok, 0, sizeof(int) * kGateCells) != hipSuccess)
+      hipMemset(s->gate_tau, 0, sizeof(float) * kGateCells) != hipSuccess)
     return R1_EDEVICE;
   return R1_OK;
 }
 
 void free_state(r1_surrogate s) {
   for (void* p : {static_cast<void*>(s->params), static_cast<void*>(s->grad), static_cast<void*>(s->m),
-                  static_cast<void*>(s->v), s->wbf, static_cast<void*>(s->bin_ok),
+                  static_cast<void*>(s->v), s->wbf, static_cast<void*>(s->gate_tau),
                   static_cast<void*>(s->norm_dev), s->ws})
     if (p) (void)hipFree(p);
 }
@@ -230,7 +230,7 @@ InferParams infer_params(r1_surrogate s, const r1_material* mat, int64_t n) {
   ip.b_lo = s->b_lo;
   ip.b_hi = s->b_hi;
   ip.bins_on = s->bins_on;
-  ip.bin_ok = s->bin_ok;
+  ip.gate_tau = s->gate_tau;
   return ip;
 }
 
@@ -531,7 +531,7 @@ r1_status r1_surrogate_calibrate(r1_handle h, r1_surrogate s, const r1_material*
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int dd = s->dim * s->dim;
   size_t bytes = al(sizeof(float) * size_t(n) * dd) + al(sizeof(float) * size_t(n)) + al(sizeof(int) * size_t(n)) +
-                 al(sizeof(float) * size_t(n)) + 2 * al(sizeof(int) * kGateCells);
+                 2 * al(sizeof(float) * size_t(n));
   rs = grow(s, bytes);
   if (rs) return rs;
   char* p = static_cast<char*>(s->ws);
@@ -539,29 +539,48 @@ r1_status r1_surrogate_calibrate(r1_handle h, r1_surrogate s, const r1_material*
   float* bs = reinterpret_cast<float*>(p); p += al(sizeof(float) * size_t(n));
   int* cbin = reinterpret_cast<int*>(p); p += al(sizeof(int) * size_t(n));
   float* cw = reinterpret_cast<float*>(p); p += al(sizeof(float) * size_t(n));
-  int* bbad = reinterpret_cast<int*>(p); p += al(sizeof(int) * kGateCells);
-  int* bcnt = reinterpret_cast<int*>(p);
+  float* cg = reinterpret_cast<float*>(p);
   InferParams ip = infer_params(s, mat, n);
   hipError_t e = r1m_unpack(s->dim, n, X, Fs, bs, st);
-  if (e == hipSuccess) e = hipMemsetAsync(bbad, 0, sizeof(int) * kGateCells, st);
-  if (e == hipSuccess) e = hipMemsetAsync(bcnt, 0, sizeof(int) * kGateCells, st);
   if (e == hipSuccess) e = r1m_infer(R1_F32, s->dim, ip, 1, Fs, bs, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                     cbin, cw, st);
-  if (e == hipSuccess) e = r1m_bin_error(n, s->d_in, Y, cbin, cw, tol, bbad, bcnt, st);
-  std::vector<int> hbad(kGateCells), hcnt(kGateCells);
-  if (e == hipSuccess) e = hipMemcpyAsync(hbad.data(), bbad, sizeof(int) * hbad.size(), hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(hcnt.data(), bcnt, sizeof(int) * hcnt.size(), hipMemcpyDeviceToHost, st);
+                                     cbin, cw, cg, st);
+  std::vector<int> hbin(static_cast<size_t>(n));
+  std::vector<float> hw(static_cast<size_t>(n)), hg(static_cast<size_t>(n)), hy(size_t(n) * s->d_out);
+  if (e == hipSuccess) e = hipMemcpyAsync(hbin.data(), cbin, sizeof(int) * hbin.size(), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(hw.data(), cw, sizeof(float) * hw.size(), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(hg.data(), cg, sizeof(float) * hg.size(), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(hy.data(), Y, sizeof(float) * hy.size(), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return r1h::fail(h, e, "calibrate");
-  // a cell is used when it saw enough calibration points and at least the
-  // requested quantile of them were within tol
-  int allowed = 0;
-  for (int b = 0; b < kGateCells; ++b) {
-    const int need = 16;
-    s->bin_ok_h[b] = (hcnt[b] >= need && double(hcnt[b] - hbad[b]) >= double(quantile) * hcnt[b]) ? 1 : 0;
-    allowed += s->bin_ok_h[b];
+  // per cell: calibration points ordered by predicted gap; the threshold is
+  // the largest predicted gap whose prefix (all points at or below it) has at
+  // least 16 points and at least the requested quantile of them within tol
+  // (relative energy error, |W| floored at 1e-2)
+  std::vector<std::vector<std::pair<float, bool>>> cell(kGateCells);
+  for (int64_t i = 0; i < n; ++i) {
+    if (hbin[i] < 0 || hbin[i] >= kGateCells) continue;
+    const float ref = hy[size_t(i) * s->d_out];
+    const float err = std::fabs(hw[i] - ref) / std::max(std::fabs(ref), 1e-2f);
+    cell[hbin[i]].push_back({hg[i], err <= tol});
   }
-  e = hipMemcpy(s->bin_ok, s->bin_ok_h, sizeof(int) * kGateCells, hipMemcpyHostToDevice);
+  int allowed = 0;
+  for (int c = 0; c < kGateCells; ++c) {
+    auto& v = cell[c];
+    std::sort(v.begin(), v.end(), [](const std::pair<float, bool>& x, const std::pair<float, bool>& y) {
+      return x.first < y.first;
+    });
+    float tau = -INFINITY;
+    int64_t good = 0;
+    for (size_t k = 0; k < v.size(); ++k) {
+      good += v[k].second ? 1 : 0;
+      const int64_t cnt = int64_t(k) + 1;
+      const bool boundary = k + 1 == v.size() || v[k + 1].first > v[k].first;
+      if (boundary && cnt >= 16 && double(good) >= double(quantile) * double(cnt)) tau = v[k].first;
+    }
+    s->gate_tau_h[c] = tau;
+    allowed += tau > -INFINITY ? 1 : 0;
+  }
+  e = hipMemcpy(s->gate_tau, s->gate_tau_h, sizeof(float) * kGateCells, hipMemcpyHostToDevice);
   if (e != hipSuccess) return r1h::fail(h, e, "calibrate upload");
   s->bins_on = 1;
   if (cells_allowed) *cells_allowed = allowed;
@@ -598,7 +617,7 @@ r1_status r1_surrogate_infer(r1_handle h, r1_surrogate s, const r1_material* mat
   InferParams ip = infer_params(s, mat, n);
   hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int), st);
   if (e == hipSuccess)
-    e = r1m_infer(dtype, s->dim, ip, 0, F, beta_n, W, P, flags, cnt, list, nullptr, nullptr, st);
+    e = r1m_infer(dtype, s->dim, ip, 0, F, beta_n, W, P, flags, cnt, list, nullptr, nullptr, nullptr, st);
   int nfb = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&nfb, cnt, sizeof(int), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -647,14 +666,14 @@ r1_status r1_surrogate_save(r1_surrogate s, const char* path) {
     return R1_EDEVICE;
   FILE* f = std::fopen(path, "wb");
   if (!f) return R1_EIO;
-  const char magic[8] = {'R', '1', 'S', 'U', 'R', 'R', '0', '1'};
+  const char magic[8] = {'R', '1', 'S', 'U', 'R', 'R', '0', '2'};
   int32_t hdr[6] = {s->dim, s->n_hidden, s->width, s->bins_on, int32_t(s->trained), 0};
   bool ok = std::fwrite(magic, 1, 8, f) == 8 && std::fwrite(hdr, sizeof(hdr), 1, f) == 1 &&
             std::fwrite(&s->t, sizeof(s->t), 1, f) == 1 && std::fwrite(s->norm, sizeof(s->norm), 1, f) == 1 &&
             std::fwrite(s->x_lo, sizeof(s->x_lo), 1, f) == 1 && std::fwrite(s->x_hi, sizeof(s->x_hi), 1, f) == 1 &&
             std::fwrite(&s->det_lo, sizeof(s->det_lo), 1, f) == 1 && std::fwrite(&s->r_max, sizeof(double), 1, f) == 1 &&
             std::fwrite(&s->b_lo, sizeof(double), 1, f) == 1 && std::fwrite(&s->b_hi, sizeof(double), 1, f) == 1 &&
-            std::fwrite(s->bin_ok_h, sizeof(s->bin_ok_h), 1, f) == 1 &&
+            std::fwrite(s->gate_tau_h, sizeof(s->gate_tau_h), 1, f) == 1 &&
             std::fwrite(p.data(), pb, 1, f) == 1 && std::fwrite(m.data(), pb, 1, f) == 1 &&
             std::fwrite(v.data(), pb, 1, f) == 1;
   ok = (std::fclose(f) == 0) && ok;
@@ -668,7 +687,7 @@ r1_status r1_surrogate_load(r1_handle h, r1_surrogate* out, const char* path) {
   if (!f) return R1_EIO;
   char magic[8];
   int32_t hdr[6];
-  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "R1SURR01", 8) == 0 &&
+  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "R1SURR02", 8) == 0 &&
             std::fread(hdr, sizeof(hdr), 1, f) == 1;
   r1_surrogate s = nullptr;
   if (ok) {
@@ -682,7 +701,7 @@ r1_status r1_surrogate_load(r1_handle h, r1_surrogate* out, const char* path) {
          std::fread(s->x_lo, sizeof(s->x_lo), 1, f) == 1 && std::fread(s->x_hi, sizeof(s->x_hi), 1, f) == 1 &&
          std::fread(&s->det_lo, sizeof(s->det_lo), 1, f) == 1 && std::fread(&s->r_max, sizeof(double), 1, f) == 1 &&
          std::fread(&s->b_lo, sizeof(double), 1, f) == 1 && std::fread(&s->b_hi, sizeof(double), 1, f) == 1 &&
-         std::fread(s->bin_ok_h, sizeof(s->bin_ok_h), 1, f) == 1 &&
+         std::fread(s->gate_tau_h, sizeof(s->gate_tau_h), 1, f) == 1 &&
          std::fread(p.data(), pb, 1, f) == 1 && std::fread(m.data(), pb, 1, f) == 1 &&
          std::fread(v.data(), pb, 1, f) == 1;
     if (ok) {
@@ -691,7 +710,7 @@ r1_status r1_surrogate_load(r1_handle h, r1_surrogate* out, const char* path) {
       ok = hipMemcpy(s->params, p.data(), pb, hipMemcpyHostToDevice) == hipSuccess &&
            hipMemcpy(s->m, m.data(), pb, hipMemcpyHostToDevice) == hipSuccess &&
            hipMemcpy(s->v, v.data(), pb, hipMemcpyHostToDevice) == hipSuccess &&
-           hipMemcpy(s->bin_ok, s->bin_ok_h, sizeof(s->bin_ok_h), hipMemcpyHostToDevice) == hipSuccess &&
+           hipMemcpy(s->gate_tau, s->gate_tau_h, sizeof(s->gate_tau_h), hipMemcpyHostToDevice) == hipSuccess &&
            hipMemcpy(s->norm_dev, s->norm, sizeof(s->norm), hipMemcpyHostToDevice) == hipSuccess &&
            refresh_bf16(s, nullptr) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
     }

@@ -104,7 +104,7 @@ def trained(lib):
     Fc, bc, oc = laminate(lib, cal["F"], cal["beta_n"], cal["levels"], torch.float32)
     Xc, Yc = s.pack(Fc, bc, oc["W"], oc["P"])
     allowed = s.calibrate(mat, Xc, Yc, tol=1e-3, quantile=0.99)
-    print("calibration: %d of %d gate cells allowed" % (allowed, 2 * 16 * 8))
+    print("calibration: %d of %d gate cells with a threshold" % (allowed, 16 * 8))
     yield s, rep1, rep, allowed, cfg["levels"]
     s.close()
 
