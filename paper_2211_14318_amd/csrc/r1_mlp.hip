@@ -15,6 +15,8 @@
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
+constexpr int kWaveM = 64;
+
 namespace r1m {
 
 __device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + __expf(-z)); }
@@ -344,7 +346,8 @@ __device__ __forceinline__ int gate_bin(const InferParams& ip, const double* F, 
   return br * kBinsB + bb;
 }
 
-// Fused inference: 4 waves x 32 points per block.  Per point: load F, beta_n;
+// Fused inference for widths whose weights do not fit in LDS (see
+// k_infer_lds): 4 waves x 32 points per block.  Per point: load F, beta_n;
 // gates; first layer (FP32) into the wave's LDS activations (BF16); each hidden
 // width x width layer as 32 x 16-deep MFMA tiles with B fragments read from the
 // BF16 weights in global memory (L2-resident), bias + SiLU, back to LDS; output
@@ -449,6 +452,185 @@ __global__ __launch_bounds__(256) void k_infer(InferParams ip, const T* F, const
     P[int64_t(k) * ip.n + pt] =
         T(convex ? P0[k] : P0[k] - double(out[1 + k] * ip.y_std[1 + k] + ip.y_mean[1 + k]));
   if (flags) flags[pt] = 0;
+}
+
+// Bytes of LDS k_infer_lds needs: the BF16 hidden layers (rows padded by 8)
+// and the FP32 first layer, biases, last layer.
+__host__ __device__ inline size_t infer_lds_bytes(int width, int n_hidden, int d_in, int d_out) {
+  return size_t(n_hidden - 1) * width * (width + 8) * 2 +
+         sizeof(float) * (size_t(width) * d_in + size_t(n_hidden) * width + size_t(d_out) * width + d_out);
+}
+
+// Fused inference with LDS-resident weights and register-resident activations.
+// A persistent block of 8 waves stages the hidden layers (BF16), the first and
+// last layers and the biases in LDS once; each wave then takes tiles of 32
+// points.  Lane (p = lane % 32, half = lane / 32) of a tile:
+//  * first layer in FP32 for the 8 features per 16-deep k step that its B
+//    fragments hold (features 16 s + 8 half + i);
+//  * each width x width layer as (width/32) x (width/16) MFMA 32x32x16 steps with
+//    the weights as A (rows = output features) and the activations as B
+//    (columns = points); bias + SiLU on the accumulators (lane holds features
+//    8 (j/4) + 4 half + j%4 of each 32-feature tile), and one exchange of four
+//    packed values with the lane 32 away forms the next layer's B fragments;
+//  * last layer: FP32 dot products over each lane's half of the features,
+//    completed by the same exchange;
+//  * gates, then W(F) (lower half) and P0(F) (upper half) in FP64.
+// MODE as in k_infer.
+template <typename T, int D, int WID, int MODE>
+__global__ __launch_bounds__(512) void k_infer_lds(InferParams ip, const T* F, const T* bn, T* W, T* P,
+                                                   int32_t* flags, int* fb_count, int32_t* fb_list,
+                                                   int* cal_bin, float* cal_w, float* cal_gap) {
+  constexpr int DI = D * D + 1, DO = D * D + 1;
+  constexpr int LDW = WID + 8;
+  constexpr int NS = WID / 16, NT = WID / 32;
+  extern __shared__ char smem[];
+  const int L = ip.n_hidden;
+  __bf16* wl = reinterpret_cast<__bf16*>(smem);                       // (L-1) x WID x LDW
+  float* w0 = reinterpret_cast<float*>(wl + size_t(L - 1) * WID * LDW);  // WID x DI
+  float* bb = w0 + WID * DI;                                          // L x WID
+  float* wo = bb + L * WID;                                           // DO x WID
+  float* bo = wo + DO * WID;                                          // DO
+  for (int i = threadIdx.x; i < (L - 1) * WID * (WID / 8); i += blockDim.x) {
+    const int l = i / (WID * (WID / 8)), rem = i % (WID * (WID / 8));
+    const int row = rem / (WID / 8), c8 = rem % (WID / 8);
+    *reinterpret_cast<bf16x8*>(wl + (size_t(l) * WID + row) * LDW + c8 * 8) =
+        *reinterpret_cast<const bf16x8*>(static_cast<const __bf16*>(ip.wbf[l + 1]) + row * WID + c8 * 8);
+  }
+  for (int i = threadIdx.x; i < WID * DI; i += blockDim.x) w0[i] = ip.w0[i];
+  for (int i = threadIdx.x; i < L * WID; i += blockDim.x) bb[i] = ip.b[i / WID][i % WID];
+  for (int i = threadIdx.x; i < DO * WID; i += blockDim.x) wo[i] = ip.wout[i];
+  if (threadIdx.x < DO) bo[threadIdx.x] = ip.bout[threadIdx.x];
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, r = lane & 31, half = lane >> 5;
+  const int64_t waves = int64_t(gridDim.x) * (blockDim.x >> 6);
+  for (int64_t tile = int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6); tile * 32 < ip.n;
+       tile += waves) {
+    const int64_t pt = tile * 32 + r;
+    const bool valid = pt < ip.n;
+    const int64_t pc = valid ? pt : ip.n - 1;        // clamp for loads
+    double G[D * D];
+    for (int k = 0; k < D * D; ++k) G[k] = double(F[int64_t(k) * ip.n + pc]);
+    const double b = double(bn[pc]);
+    float x[DI];
+    bool ok = true;
+    for (int k = 0; k < DI; ++k) {
+      const float raw = k < D * D ? float(G[k]) : float(b);
+      ok = ok && raw >= ip.x_lo[k] && raw <= ip.x_hi[k];
+      x[k] = (raw - ip.x_mean[k]) / ip.x_std[k];
+    }
+    // first layer: the features of this lane's B fragments
+    bf16x8 bf[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int f = s * 16 + 8 * half + i;
+        float z = bb[f];
+#pragma unroll
+        for (int k = 0; k < DI; ++k) z = fmaf(w0[f * DI + k], x[k], z);
+        bf[s][i] = __bf16(silu(z));
+      }
+    // hidden layers on the matrix cores
+    f32x16 acc[NT];
+    for (int l = 1; l < L; ++l) {
+      const __bf16* wlay = wl + size_t(l - 1) * WID * LDW;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t] = f32x16{};
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const bf16x8 a = *reinterpret_cast<const bf16x8*>(wlay + (t * 32 + r) * LDW + s * 16 + 8 * half);
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bf[s], acc[t], 0, 0, 0);
+        }
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+          acc[t][j] = silu(acc[t][j] + bb[l * WID + t * 32 + 8 * (j >> 2) + 4 * half + (j & 3)]);
+      if (l + 1 < L) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const int t = s >> 1, j0 = 8 * (s & 1);
+          __bf16 keep[4], send[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            keep[i] = __bf16(half ? acc[t][j0 + 4 + i] : acc[t][j0 + i]);
+            send[i] = __bf16(half ? acc[t][j0 + i] : acc[t][j0 + 4 + i]);
+          }
+          const uint32_t s01 = uint32_t(__builtin_bit_cast(uint16_t, send[0])) |
+                               (uint32_t(__builtin_bit_cast(uint16_t, send[1])) << 16);
+          const uint32_t s23 = uint32_t(__builtin_bit_cast(uint16_t, send[2])) |
+                               (uint32_t(__builtin_bit_cast(uint16_t, send[3])) << 16);
+          const uint32_t r01 = uint32_t(__shfl_xor(int(s01), 32, kWaveM));
+          const uint32_t r23 = uint32_t(__shfl_xor(int(s23), 32, kWaveM));
+          __bf16 recv[4] = {__builtin_bit_cast(__bf16, uint16_t(r01 & 0xffffu)),
+                            __builtin_bit_cast(__bf16, uint16_t(r01 >> 16)),
+                            __builtin_bit_cast(__bf16, uint16_t(r23 & 0xffffu)),
+                            __builtin_bit_cast(__bf16, uint16_t(r23 >> 16))};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            bf[s][i] = half ? recv[i] : keep[i];
+            bf[s][4 + i] = half ? keep[i] : recv[i];
+          }
+        }
+      }
+    }
+    // last layer: this lane's features, completed by the lane 32 away
+    float out[DO];
+#pragma unroll
+    for (int o = 0; o < DO; ++o) {
+      float sacc = 0.0f;
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+          sacc = fmaf(wo[o * WID + t * 32 + 8 * (j >> 2) + 4 * half + (j & 3)], acc[t][j], sacc);
+      sacc += __shfl_xor(sacc, 32, kWaveM);
+      out[o] = sacc + bo[o];
+    }
+    double cof[D * D];
+    r1d::cofactor<D>(G, cof);
+    const double det = r1d::det_of<D>(G, cof);
+    ok = ok && det >= double(ip.det_lo);
+    const int bin = gate_bin<D>(ip, G, b);
+    const float rawf = out[0] * ip.y_std[0] + ip.y_mean[0];
+    const double raw = double(rawf);
+    const bool convex = raw <= 0.0;
+    if (MODE == 1) {
+      if (valid && half == 0) {
+        r1d::Point<double> q = r1d::make_point<double>(ip.mat, b);
+        const double w_un = r1d::w_point<double, D>(q, G, cof);
+        cal_bin[pt] = ok ? bin : -1;
+        cal_w[pt] = float(convex ? w_un : w_un - raw);
+        cal_gap[pt] = rawf;
+      }
+      continue;
+    }
+    if (ip.bins_on) ok = ok && rawf <= ip.gate_tau[bin];
+    ok = ok && det > 0.0;
+    // fallback list: one atomic per wave
+    const bool rej = valid && half == 0 && !ok;
+    const unsigned long long m = __ballot(rej);
+    int base = 0;
+    if (lane == 0 && m) base = atomicAdd(fb_count, __popcll(m));
+    base = __shfl(base, 0, kWaveM);
+    if (rej) fb_list[base + __popcll(m & ((1ull << lane) - 1ull))] = int32_t(pt);
+    if (!valid || !ok) continue;
+    if (half == 0) {
+      r1d::Point<double> q = r1d::make_point<double>(ip.mat, b);
+      const double w_un = r1d::w_point<double, D>(q, G, cof);
+      W[pt] = T(convex ? w_un : w_un - raw);
+      if (flags) flags[pt] = 0;
+    } else {
+      double P0[D * D];
+      r1d::stress0<D>(ip.mat, b, G, P0);
+      for (int k = 0; k < D * D; ++k)
+        P[int64_t(k) * ip.n + pt] =
+            T(convex ? P0[k] : P0[k] - double(out[1 + k] * ip.y_std[1 + k] + ip.y_mean[1 + k]));
+    }
+  }
 }
 
 // Gather fallback points into compact SoA arrays, and scatter their results back.
@@ -604,6 +786,26 @@ template <typename T, int D>
 static hipError_t infer_TD(const InferParams& ip, int mode, const void* F, const void* bn, void* W, void* P,
                            int32_t* flags, int* fb_count, int32_t* fb_list, int* cal_bin, float* cal_w,
                            float* cal_gap, hipStream_t st) {
+  const size_t lds2 = infer_lds_bytes(ip.width, ip.n_hidden, D * D + 1, D * D + 1);
+  if (ip.width <= 128 && lds2 <= size_t(160) * 1024) {
+    // weights resident in LDS: one persistent block of 8 waves per CU
+    int dev = 0, n_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const int64_t blocks = (ip.n + 255) / 256;
+    dim3 grid(unsigned(blocks < n_cu ? blocks : n_cu));
+#define R1L(WID, MODE) (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_infer_lds<T, D, WID, MODE>), \
+      hipFuncAttributeMaxDynamicSharedMemorySize, int(lds2)); \
+  hipLaunchKernelGGL((k_infer_lds<T, D, WID, MODE>), grid, dim3(512), lds2, st, ip, \
+      static_cast<const T*>(F), static_cast<const T*>(bn), static_cast<T*>(W), static_cast<T*>(P), flags, \
+      fb_count, fb_list, cal_bin, cal_w, cal_gap)
+#define R1V(WID) if (ip.width == WID) { if (mode == 0) { R1L(WID, 0); } else { R1L(WID, 1); } return hipGetLastError(); }
+    R1V(32) R1V(64) R1V(128)
+#undef R1V
+#undef R1L
+    return hipErrorInvalidValue;
+  }
   dim3 grid(unsigned((ip.n + 127) / 128));
   size_t lds = r1m_infer_lds(ip.width);
 #define R1I(WID, MODE) (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_infer<T, D, WID, MODE>), \
@@ -612,7 +814,7 @@ static hipError_t infer_TD(const InferParams& ip, int mode, const void* F, const
       static_cast<const T*>(F), static_cast<const T*>(bn), static_cast<T*>(W), static_cast<T*>(P), flags, \
       fb_count, fb_list, cal_bin, cal_w, cal_gap)
 #define R1W(WID) if (ip.width == WID) { if (mode == 0) { R1I(WID, 0); } else { R1I(WID, 1); } return hipGetLastError(); }
-  R1W(32) R1W(64) R1W(128) R1W(256)
+  R1W(256)
 #undef R1W
 #undef R1I
   return hipErrorInvalidValue;
