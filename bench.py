@@ -14,8 +14,9 @@ sample of the same workload on the host's cores; the same oracle results give
 `error`, the GPU's error on those points.  Secondary legs (skip with --quick):
 `surrogate` (train the MLP on 2M lamination rows, then 1M-point inference
 with routing against plain lamination of the same configuration), `batched`
-(65,536 points with uneven grids/directions/depths in one graph replay) and
-`plain_3d` (262,144 3D points, 256 directions x 513 points).
+(65,536 points with uneven grids/directions/depths in one graph replay),
+`plain_3d` (262,144 3D points, 256 directions x 513 points) and
+`surrogate_3d` (a 4 x 256 network on the same 3D workload).
 """
 import argparse
 import json
@@ -151,6 +152,55 @@ def leg_surrogate(h, r1, WL, torch, np, n_train=2_000_000, n_cal=262_144, n_inf=
         "train": {"rows": n_train, "epochs": epochs, "steps": rep["steps"], "ms": round(rep["ms"], 1),
                   "val_loss": rep["val_loss"], "data_gen_ms": round(1e3 * t_data, 1)},
         "mlp": "5 -> 4 x 128 SiLU -> 5, BF16 MFMA / FP32 accumulate",
+    }
+
+
+def leg_surrogate_3d(h, r1, WL, torch, np, n_train=1_000_000, n_cal=131_072, epochs=8):
+    """3D: MLP 10 -> 4x256 SiLU -> 10 trained on 3D lamination rows (256 directions
+    x 513 points), against plain lamination of the 262,144-point 3D workload."""
+    mat = r1.material(dim=3)
+    tr = WL.config5(n=n_train, seed_tag=50)
+    spec = r1.LaminationSpec(tr["levels"])
+    F = torch.tensor(tr["F"], dtype=torch.float32, device="cuda")
+    bn = torch.tensor(tr["beta_n"], dtype=torch.float32, device="cuda")
+    out = h.envelope(mat, spec, F, bn, stress=True, flags=False)
+    s = r1.Surrogate(h, dim=3, n_hidden=4, width=256, seed=2211)
+    X, Y = s.pack(F, bn, out["W"], out["P"])
+    del F, bn, out
+    rep = s.train(mat, X, Y, epochs=epochs, batch=4096, lr=1e-3, seed=1)
+    del X, Y
+    cal = WL.config5(n=n_cal, seed_tag=51)
+    Fc = torch.tensor(cal["F"], dtype=torch.float32, device="cuda")
+    bc = torch.tensor(cal["beta_n"], dtype=torch.float32, device="cuda")
+    oc = h.envelope(mat, spec, Fc, bc, stress=True, flags=False)
+    Xc, Yc = s.pack(Fc, bc, oc["W"], oc["P"])
+    cells = s.calibrate(mat, Xc, Yc, tol=1e-3, quantile=0.99)
+    del Fc, bc, oc, Xc, Yc
+    inf = WL.config5()
+    n = inf["n"]
+    Fi = torch.tensor(inf["F"], dtype=torch.float32, device="cuda")
+    bi = torch.tensor(inf["beta_n"], dtype=torch.float32, device="cuda")
+    W = torch.empty(n, device="cuda")
+    P = torch.empty((9, n), device="cuda")
+    t_plain = timed(lambda: h.envelope_into(mat, spec, Fi, bi, W, P), 3, torch)
+    so = s.infer(mat, spec, Fi, bi)
+    t_sur = timed(lambda: s.infer(mat, spec, Fi, bi, out=so), 3, torch)
+    fb = (so["flags"].cpu().numpy() & r1.PT_FALLBACK) != 0
+    Wp, Ws = W.cpu().numpy(), so["W"].cpu().numpy()
+    e = np.abs(Ws - Wp) / np.maximum(np.abs(Wp), 1e-2)
+    acc = ~fb
+    s.close()
+    return {
+        "workload": "surrogate-3d: train 1M rows (256 dirs x 513 pts, k=1), infer " + inf["name"],
+        "plain_qps": round(n / t_plain, 1), "surrogate_qps": round(n / t_sur, 1),
+        "speedup": round(t_plain / t_sur, 3), "fallback_frac": round(float(fb.mean()), 4),
+        "gate_cells_allowed": cells, "erel_floor": 1e-2,
+        "accepted_erel_vs_fp32_plain": {"max": float(e[acc].max()) if acc.any() else None,
+                                        "p99": float(np.percentile(e[acc], 99)) if acc.any() else None,
+                                        "frac_gt_1e-3": float(np.mean(e[acc] > 1e-3)) if acc.any() else None},
+        "train": {"rows": n_train, "epochs": epochs, "steps": rep["steps"], "ms": round(rep["ms"], 1),
+                  "val_loss": rep["val_loss"]},
+        "mlp": "10 -> 4 x 256 SiLU -> 10, BF16 MFMA / FP32 accumulate",
     }
 
 
@@ -308,6 +358,9 @@ def main():
         log("batched leg: %.1f QP/s" % out["batched"]["qps"])
         out["plain_3d"] = leg_3d(h, r1, WL, torch, np)
         log("3d leg: %.1f QP/s" % out["plain_3d"]["qps"])
+        out["surrogate_3d"] = leg_surrogate_3d(h, r1, WL, torch, np)
+        log("3d surrogate leg: speedup %.3f, fallback %.3f" % (out["surrogate_3d"]["speedup"],
+                                                            out["surrogate_3d"]["fallback_frac"]))
     h.close()
     if not args.no_cpu_baseline:
         workers = min(16, os.cpu_count() or 1)

@@ -187,10 +187,10 @@ def config4_inference(n=1_000_000, seed_tag=41):
     return _cfg("surrogate-infer-2d-n%d" % n, 2, F, beta_n, [level(a, b, 201, 1.0)], "f32")
 
 
-def config5(n=262144, n_a=16, n_b=16, n_t=513):
+def config5(n=262144, n_a=16, n_b=16, n_t=513, seed_tag=5):
     """3D FP32: F = I + 0.2 N (det > 0.2), beta_n ~ U[0, 0.5], 256 directions
     (16-point Fibonacci spheres for a and b), 513 points on [-1, 1], depth 1."""
-    rng = rng_for(5)
+    rng = rng_for(seed_tag)
     F = perturbed_identity(rng, n, 3, 0.2, 0.2)
     beta_n = rng.uniform(0.0, 0.5, size=n)
     a, b = fibonacci_directions(n_a, n_b)

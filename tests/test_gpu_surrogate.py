@@ -42,11 +42,12 @@ def hidden_blocks(d_in, width, n_hidden, d_out):
     return out
 
 
-@pytest.mark.parametrize("width", [32, 128])
-def test_gradients_match_fp64_oracle(lib, width):
+@pytest.mark.parametrize("dim,width", [(2, 32), (2, 128), (3, 256)])
+def test_gradients_match_fp64_oracle(lib, dim, width):
     r1, h, torch = lib
-    s = r1.Surrogate(h, dim=2, n_hidden=4, width=width, seed=3)
-    shape = (5, width, 4, 5)
+    d = dim * dim + 1
+    s = r1.Surrogate(h, dim=dim, n_hidden=4, width=width, seed=3)
+    shape = (d, width, 4, d)
     rng = np.random.default_rng(9)
     params = s.get_params().astype(np.float64)
     # the matrix-core layers use BF16 weights: give the oracle the same weights
@@ -54,20 +55,20 @@ def test_gradients_match_fp64_oracle(lib, width):
     for a, b in hidden_blocks(*shape):
         p_bf[a:b] = bf16_round(params[a:b])
     B = 128
-    Xn = rng.normal(size=(B, 5)).astype(np.float32)
-    Yn = rng.normal(size=(B, 5)).astype(np.float32)
+    Xn = rng.normal(size=(B, d)).astype(np.float32)
+    Yn = rng.normal(size=(B, d)).astype(np.float32)
     loss_g, g_g = s.loss_grad(torch.tensor(Xn, device="cuda"), torch.tensor(Yn, device="cuda"))
     g_g = g_g.cpu().numpy().astype(np.float64)
     loss_c, g_c = O.mlp_loss_grad(shape, p_bf, Xn.astype(np.float64), Yn.astype(np.float64))
     rel = np.linalg.norm(g_g - g_c) / np.linalg.norm(g_c)
-    print("width %d: loss gpu %.6f cpu %.6f, gradient rel err %.3e" % (width, loss_g, loss_c, rel))
+    print("dim %d width %d: loss gpu %.6f cpu %.6f, gradient rel err %.3e" % (dim, width, loss_g, loss_c, rel))
     assert abs(loss_g - loss_c) <= 1e-2 * abs(loss_c)
     assert rel < 2e-2
     # every layer's gradient points the same way
     offs = [0]
     for l in range(5):
-        n_in = 5 if l == 0 else width
-        n_out = 5 if l == 4 else width
+        n_in = d if l == 0 else width
+        n_out = d if l == 4 else width
         offs.append(offs[-1] + n_out * n_in + n_out)
     for l in range(5):
         a, b = offs[l], offs[l + 1]
@@ -226,3 +227,56 @@ def test_surrogate_gain_over_plain_lamination(lib, trained):
     print("plain %.3f ms, surrogate %.3f ms (fallback %.1f%%): speedup %.2fx" % (
         1e3 * t_plain, 1e3 * t_sur, 100 * out["n_fallback"] / n, t_plain / t_sur))
     assert t_sur < t_plain
+
+
+@pytest.mark.parametrize("width", [128, 256])
+def test_3d_inference_matches_oracle_forward(lib, width):
+    """3D network (inputs: 9 F entries and beta_n): after a short training on 3D
+    lamination data, uncalibrated inference (box gate only) equals the FP64 network
+    oracle's forward mapped through W(F) and P0(F).  Width 128 runs the kernel with
+    LDS-resident weights, width 256 the one that reads them from L2."""
+    r1, h, torch = lib
+    cfg = WL.config5(n=16384)
+    lv = cfg["levels"][0]
+    lv = dict(lv, a=lv["a"][:64], b=lv["b"][:64], n_t=129)
+    mat = r1.material(dim=3)
+    spec = r1.LaminationSpec([lv])
+    Ft = torch.tensor(cfg["F"], dtype=torch.float32, device="cuda").contiguous()
+    bt = torch.tensor(cfg["beta_n"], dtype=torch.float32, device="cuda").contiguous()
+    out = h.envelope(mat, spec, Ft, bt, stress=True)
+    s = r1.Surrogate(h, dim=3, n_hidden=4, width=width, seed=5)
+    X, Y = s.pack(Ft, bt, out["W"], out["P"])
+    rep = s.train(mat, X, Y, epochs=4, batch=1024, lr=1e-3, seed=1)
+    assert np.isfinite(rep["val_loss"])
+    inf = WL.config5(n=2048)
+    Fi = torch.tensor(inf["F"], dtype=torch.float32, device="cuda").contiguous()
+    bi = torch.tensor(inf["beta_n"], dtype=torch.float32, device="cuda").contiguous()
+    res = s.infer(mat, spec, Fi, bi)
+    torch.cuda.synchronize()
+    fl = res["flags"].cpu().numpy()
+    ok = np.nonzero((fl & r1.PT_FALLBACK) == 0)[0][:256]
+    assert len(ok) > 100
+    nm = s.norm()
+    params = s.get_params().astype(np.float64)
+    Fn, bn = Fi.double().cpu().numpy(), bi.double().cpu().numpy()
+    x = np.concatenate([Fn[:, ok].T, bn[ok, None]], axis=1)
+    xn = (x.astype(np.float32) - nm["x_mean"]) / nm["x_std"]
+    y, _ = O.mlp_forward((10, width, 4, 10), params, xn.astype(np.float64))
+    y = y * nm["y_std"] + nm["y_mean"]
+    om = O.material(dim=3)
+    lam = y[:, 0] > 0
+    W_ref = np.array([O.energy(om, Fn[:, p].reshape(3, 3), bn[p]) for p in ok]) - np.where(lam, y[:, 0], 0)
+    P_ref = np.array([O.stress0(om, Fn[:, p].reshape(3, 3), bn[p]).ravel() for p in ok]) - \
+        np.where(lam[:, None], y[:, 1:], 0)
+    Wg = res["W"].cpu().numpy()[ok]
+    Pg = res["P"].cpu().numpy()[:, ok].T
+    near = np.abs(y[:, 0]) < 0.02 * nm["y_std"][0]
+    far = ~near
+    err_w = np.max(np.abs(Wg - W_ref)[far])
+    err_p = np.max(np.abs(Pg - P_ref)[far])
+    print("3d width %d: %d accepted points, max |dW| %.2e, max |dP| %.2e (y_std %.2e)" % (
+        width, far.sum(), err_w, err_p, nm["y_std"][0]))
+    assert far.sum() > 80
+    assert err_w < 0.02 * nm["y_std"][0] + 1e-6
+    assert err_p < 0.02 * np.max(nm["y_std"][1:]) + 1e-6
+    s.close()
