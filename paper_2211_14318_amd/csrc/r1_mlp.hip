@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "r1_device.hpp"
 #include "r1_mlp.hpp"
 
@@ -698,15 +700,17 @@ hipError_t r1m_out_fwd_loss(int B, int w, int d_out, const float* H, const float
   return hipGetLastError();
 }
 
+// Row chunks of 16 (column sums) and 32 (outer products) rows per thread keep the
+// serial chains short; the chunk sums meet in atomics.
 hipError_t r1m_colsum(int B, int ncol, int ld, const float* A, float* out, hipStream_t st) {
-  dim3 grid(nblk(ncol, 64), unsigned(B >= 4096 ? 32 : (B + 127) / 128));
+  dim3 grid(nblk(ncol, 64), unsigned(std::min(65535, (B + 15) / 16)));
   hipLaunchKernelGGL(k_colsum, grid, dim3(64), 0, st, B, ncol, ld, A, out);
   return hipGetLastError();
 }
 
 hipError_t r1m_outer_small(int B, int no, int ni, const float* D, int ldd, const float* X, int ldx,
                            int round_x, float* out, hipStream_t st) {
-  dim3 grid(nblk(int64_t(no) * ni), unsigned(B >= 4096 ? 32 : (B + 127) / 128));
+  dim3 grid(nblk(int64_t(no) * ni), unsigned(std::min(65535, (B + 31) / 32)));
   hipLaunchKernelGGL(k_outer_small, grid, dim3(256), 0, st, B, no, ni, D, ldd, X, ldx, round_x, out);
   return hipGetLastError();
 }
