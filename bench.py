@@ -42,6 +42,28 @@ def w_samples_outer_kernel(cfg):
     return cfg["n"] * len(lo["a"]) * (lo["n_t"] - 1) * inner
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_outer_depth2_n4096_64x1025_32x257_f32_hbm.txt")
+TRAFFIC_SOURCES = ["paper_2211_14318_amd/csrc/r1_device.hpp", "paper_2211_14318_amd/csrc/r1_kernels.hpp"]
+
+
+def measured_traffic():
+    """HBM bytes per k_outer launch from the committed counter summary, or None when the
+    kernel sources have changed since the counters were taken (or the file is absent)."""
+    import hashlib
+    try:
+        kv = {}
+        for line in open(TRAFFIC_FILE):
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+        h = hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read() for f in TRAFFIC_SOURCES))
+        if h.hexdigest()[:16] != kv.get("source_fingerprint"):
+            return None
+        return int(float(kv["bytes_per_launch"]))
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
@@ -327,7 +349,8 @@ def main():
     avg_s = outer_ms / max(outer_n, 1) / 1e3
     achieved = flops / avg_s / 1e12
     roof = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK[args.dtype], unit="TFLOP/s",
-                frac=round(achieved / PEAK[args.dtype], 4), traffic=None,
+                frac=round(achieved / PEAK[args.dtype], 4),
+                traffic=measured_traffic() if args.dtype == "f32" else None,
                 kernel="k_outer", avg_ms=round(outer_ms / max(outer_n, 1), 3),
                 w_samples_per_launch=w_samples_outer_kernel(cfg), flops_per_w=FLOPS_PER_W)
     out = {

@@ -144,10 +144,10 @@ int r1h::samples_per_lane(int S, int n_t) {
   return 0;
 }
 
-int r1h::segment_width(r1_handle h, int n_t, int dtype, int dim) {
+int r1h::segment_width(r1_handle h, int n_t, int dtype, int dim, int role) {
   auto it = h->seg_override.find(n_t);
   if (it != h->seg_override.end()) return it->second;
-  auto jt = h->seg_tuned.find(r1h::tune_key(n_t, dtype, dim));
+  auto jt = h->seg_tuned.find(r1h::tune_key(n_t, dtype, dim, role));
   if (jt != h->seg_tuned.end()) return jt->second;
   // default: about 16 samples per lane
   int c = (n_t - 1) / 2;
@@ -219,6 +219,12 @@ r1_status r1_get_segment_width(r1_handle h, int32_t n_t, r1_dtype dtype, int32_t
   return R1_OK;
 }
 
+r1_status r1_get_inner_segment_width(r1_handle h, int32_t n_t, r1_dtype dtype, int32_t dim, int32_t* lanes) {
+  if (!h || !lanes || n_t < 3 || n_t > R1_MAX_NT || (n_t % 2) == 0) return R1_EINVAL;
+  *lanes = r1h::segment_width(h, n_t, dtype, dim, r1h::kRoleInner);
+  return R1_OK;
+}
+
 r1_status r1_envelope_stress(r1_handle h, const r1_material* mat, const r1_lamination* lam,
                              int64_t n, r1_dtype dtype, const void* F, const void* beta_n,
                              void* W, void* P, r1_laminate* tree, int32_t* flags, void* stream) {
@@ -259,7 +265,7 @@ r1_status r1_envelope_stress(r1_handle h, const r1_material* mat, const r1_lamin
     a.scratch_w1f = base;
     a.scratch_outer = static_cast<char*>(base) + w1;
   }
-  int S = r1h::segment_width(h, inner.n_t, dtype, mat->dim);
+  int S = r1h::segment_width(h, inner.n_t, dtype, mat->dim, lam->depth == 2 ? r1h::kRoleInner : r1h::kRoleLevel);
   int K = r1h::samples_per_lane(S, inner.n_t);
   if (K == 0) return R1_EINVAL;
   e = r1_launch_envelope(a, lam->depth, dtype, S, K, static_cast<hipStream_t>(stream),

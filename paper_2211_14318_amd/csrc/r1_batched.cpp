@@ -75,10 +75,13 @@ void r1h::release_batched(r1_handle h) {
   }
 }
 
-// Times every admissible segment width for lines of n_t points on a synthetic
-// one-level batch (2048 points near the identity, 32 directions) and records
-// the fastest for (n_t, dtype, dim).
-r1_status r1h::autotune(r1_handle h, const r1_material* mat, int n_t, int dtype, int dim,
+// Times every admissible segment width for lines of n_t points and records
+// the fastest for (n_t, dtype, dim, role).  Role kRoleLevel: a synthetic
+// one-level batch (2048 points near the identity, 32 directions).  Role
+// kRoleInner: the same 32 directions as the inner level of a depth-2 batch
+// (128 points, outer level of 8 directions x 129 points), timed through the
+// depth-2 path, whose inner lines are sampled along outer lines.
+r1_status r1h::autotune(r1_handle h, const r1_material* mat, int n_t, int dtype, int dim, int role,
                         hipStream_t st, int* lanes) {
   const int key_dim = dim;
   std::vector<int> cands;
@@ -86,11 +89,13 @@ r1_status r1h::autotune(r1_handle h, const r1_material* mat, int n_t, int dtype,
     if (batch_samples_per_lane(S, n_t) > 0) cands.push_back(S);
   if (cands.empty()) return R1_EINVAL;
   if (cands.size() == 1) {
-    h->seg_tuned[tune_key(n_t, dtype, key_dim)] = cands[0];
+    h->seg_tuned[tune_key(n_t, dtype, key_dim, role)] = cands[0];
     if (lanes) *lanes = cands[0];
     return R1_OK;
   }
-  const int n = 2048, na = 8, nb = 4, dd = dim * dim;
+  const bool inner = role == kRoleInner;
+  const int n = inner ? 128 : 2048, na = 8, nb = 4, dd = dim * dim;
+  const int nao = 4, nbo = 2, nt_o = 129;
   const size_t ts = dtype == R1_F32 ? 4 : 8;
   std::vector<double> Fd(size_t(dd) * n), bnd(n), a(size_t(na * nb) * dim, 0.0), b(size_t(na * nb) * dim, 0.0);
   Lcg rng{0x9e3779b97f4a7c15ull ^ uint64_t(n_t)};
@@ -114,6 +119,15 @@ r1_status r1h::autotune(r1_handle h, const r1_material* mat, int n_t, int dtype,
       b[m * dim + 0] = std::cos(M_PI * j / nb);
       b[m * dim + 1] = std::sin(M_PI * j / nb);
     }
+  std::vector<double> ao(size_t(nao * nbo) * dim, 0.0), bo(size_t(nao * nbo) * dim, 0.0);
+  for (int i = 0; i < nao; ++i)
+    for (int j = 0; j < nbo; ++j) {
+      int m = i * nbo + j;
+      ao[m * dim + 0] = std::cos(M_PI * (i + 0.5) / nao);
+      ao[m * dim + 1] = std::sin(M_PI * (i + 0.5) / nao);
+      bo[m * dim + 0] = std::cos(M_PI * (j + 0.25) / nbo);
+      bo[m * dim + 1] = std::sin(M_PI * (j + 0.25) / nbo);
+    }
   std::vector<char> Fh(ts * Fd.size()), bnh(ts * n);
   for (size_t i = 0; i < Fd.size(); ++i) {
     if (ts == 4) { float v = float(Fd[i]); std::memcpy(&Fh[4 * i], &v, 4); }
@@ -124,7 +138,8 @@ r1_status r1h::autotune(r1_handle h, const r1_material* mat, int n_t, int dtype,
     else std::memcpy(&bnh[8 * i], &bnd[i], 8);
   }
   void* buf = nullptr;
-  size_t bytes = align_up(Fh.size()) + align_up(bnh.size()) + align_up(ts * n);
+  const size_t res_bytes = inner ? align_up(ts * n) + align_up(r1_outer_res_bytes(dtype) * n * nao * nbo) : 0;
+  size_t bytes = align_up(Fh.size()) + align_up(bnh.size()) + align_up(ts * n) + res_bytes;
   if (hipMalloc(&buf, bytes) != hipSuccess) return R1_ENOMEM;
   char* base = static_cast<char*>(buf);
   void* dF = base;
@@ -133,22 +148,32 @@ r1_status r1h::autotune(r1_handle h, const r1_material* mat, int n_t, int dtype,
   hipError_t e = hipMemcpy(dF, Fh.data(), Fh.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(dB, bnh.data(), bnh.size(), hipMemcpyHostToDevice);
   r1_level lv{na * nb, a.data(), b.data(), n_t, 1.0};
+  r1_level lvo{nao * nbo, ao.data(), bo.data(), nt_o, 1.0};
   KArgs ka{};
   ka.n = n;
   ka.F = dF;
   ka.beta_n = dB;
   ka.W = dW;
   ka.mat = r1d::Material{dim, mat->model, mat->mu, mat->lambda, mat->D_inf, mat->D0};
-  r1_status s = e == hipSuccess ? device_level(h, lv, dim, &ka.lv0) : fail(h, e, "hipMemcpy(tune)");
+  r1_status s = e == hipSuccess ? R1_OK : fail(h, e, "hipMemcpy(tune)");
+  if (!s && inner) {
+    ka.scratch_w1f = static_cast<char*>(dW) + align_up(ts * n);
+    ka.scratch_outer = static_cast<char*>(ka.scratch_w1f) + align_up(ts * n);
+    s = device_level(h, lvo, dim, &ka.lv0);
+    if (!s) s = device_level(h, lv, dim, &ka.lv1);
+  } else if (!s) {
+    s = device_level(h, lv, dim, &ka.lv0);
+  }
+  const int depth = inner ? 2 : 1;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (!s && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) s = R1_EDEVICE;
   int best = cands[0];
   float best_ms = 1e30f;
   for (size_t ci = 0; !s && ci < cands.size(); ++ci) {
     int S = cands[ci], K = batch_samples_per_lane(S, n_t);
-    e = r1_launch_envelope(ka, 1, dtype, S, K, st, nullptr);                 // warm-up
+    e = r1_launch_envelope(ka, depth, dtype, S, K, st, nullptr);             // warm-up
     if (e == hipSuccess) e = hipEventRecord(e0, st);
-    for (int r = 0; r < 2 && e == hipSuccess; ++r) e = r1_launch_envelope(ka, 1, dtype, S, K, st, nullptr);
+    for (int r = 0; r < 2 && e == hipSuccess; ++r) e = r1_launch_envelope(ka, depth, dtype, S, K, st, nullptr);
     if (e == hipSuccess) e = hipEventRecord(e1, st);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;
@@ -161,7 +186,7 @@ r1_status r1h::autotune(r1_handle h, const r1_material* mat, int n_t, int dtype,
   (void)hipStreamSynchronize(st);
   (void)hipFree(buf);
   if (s) return s;
-  h->seg_tuned[tune_key(n_t, dtype, key_dim)] = best;
+  h->seg_tuned[tune_key(n_t, dtype, key_dim, role)] = best;
   if (lanes) *lanes = best;
   return R1_OK;
 }
@@ -176,7 +201,22 @@ extern "C" r1_status r1_autotune(r1_handle h, const r1_material* mat, int32_t n_
   hipError_t e = hipSetDevice(h->device);
   if (e != hipSuccess) return r1h::fail(h, e, "hipSetDevice");
   int S = 0;
-  s = r1h::autotune(h, mat, n_t, dtype, mat->dim, static_cast<hipStream_t>(stream), &S);
+  s = r1h::autotune(h, mat, n_t, dtype, mat->dim, r1h::kRoleLevel, static_cast<hipStream_t>(stream), &S);
+  if (!s && lanes) *lanes = S;
+  return s;
+}
+
+extern "C" r1_status r1_autotune_inner(r1_handle h, const r1_material* mat, int32_t n_t, r1_dtype dtype,
+                                       void* stream, int32_t* lanes) {
+  if (!h) return R1_EINVAL;
+  r1_status s = r1h::check_material(mat);
+  if (s) return s;
+  if (dtype != R1_F32 && dtype != R1_F64) return R1_EINVAL;
+  if (n_t < 3 || n_t > R1_MAX_NT || (n_t % 2) == 0) return R1_EINVAL;
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return r1h::fail(h, e, "hipSetDevice");
+  int S = 0;
+  s = r1h::autotune(h, mat, n_t, dtype, mat->dim, r1h::kRoleInner, static_cast<hipStream_t>(stream), &S);
   if (!s && lanes) *lanes = S;
   return s;
 }
@@ -246,11 +286,12 @@ extern "C" r1_status r1_envelope_batched(r1_handle h, const r1_material* mat,
       if (!s && L.depth == 2) s = r1h::device_level(h, L.level[1], dim, &b.lv1);
       if (s) return s;
       const int nti = L.level[L.depth - 1].n_t;
-      if (!h->seg_override.count(nti) && !h->seg_tuned.count(r1h::tune_key(nti, dtype, dim))) {
-        s = r1h::autotune(h, mat, nti, dtype, dim, st, nullptr);
+      const int role = L.depth == 2 ? r1h::kRoleInner : r1h::kRoleLevel;
+      if (!h->seg_override.count(nti) && !h->seg_tuned.count(r1h::tune_key(nti, dtype, dim, role))) {
+        s = r1h::autotune(h, mat, nti, dtype, dim, role, st, nullptr);
         if (s) return s;
       }
-      int S = r1h::segment_width(h, nti, dtype, dim);
+      int S = r1h::segment_width(h, nti, dtype, dim, role);
       int K = r1h::batch_samples_per_lane(S, nti);
       b.var = K > 0 ? r1_batch_variant(S, K) : -1;
       for (int S2 = 16; b.var < 0 && S2 <= 64; S2 *= 2) {   // width outside the variant set

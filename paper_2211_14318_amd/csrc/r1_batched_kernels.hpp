@@ -50,28 +50,37 @@ __global__ void k_zero_ints(int* p, int64_t n) {
 }
 }  // namespace
 
+// Wave-uniform values as scalars, so the table entries and levels they index are
+// loaded into SGPRs (a value read from LDS or memory is not known to be uniform).
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni(int64_t v) {
+  const uint64_t u = uint64_t(v);
+  return int64_t(uint64_t(uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(u))))) |
+                 (uint64_t(uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(u >> 32))))) << 32));
+}
+
 // Pops the next item of the block's persistent loop; block-uniform.
 __device__ __forceinline__ int next_item(int* counter, int* s_item) {
   __syncthreads();                               // previous item done with s_item / LDS
   if (threadIdx.x == 0) *s_item = atomicAdd(counter, 1);
   __syncthreads();
-  return *s_item;
+  return uni(*s_item);
 }
 
 // items: {kind, first, count, 0} -- kind 0: depth-1 points order[first ..
 // first + count), full result; kind 2: depth-2 points, W^1 into w1f.
 template <typename T, int D, int S, int K>
-__global__ __launch_bounds__(256) void k_bpoint(BArgs b) {
+__global__ __launch_bounds__(256, (sizeof(T) == 4 && D == 2) ? 2 : 1) void k_bpoint(BArgs b) {
   __shared__ int s_item;
   for (;;) {
     const int it = next_item(b.counter, &s_item);
     if (it >= b.n_items) return;                 // block-uniform: every wave exits
     const int4 w = b.items[it];
-    const int wave = threadIdx.x / kWave;
-    if (wave < w.z) {
-      const int64_t p = b.order[w.y + wave];
-      const BEntry& e = b.table[b.lam_idx[p]];
-      const bool centre = w.x == 2;
+    const int wave = uni(int(threadIdx.x / kWave));
+    if (wave < uni(w.z)) {
+      const int64_t p = uni(int64_t(b.order[uni(w.y) + wave]));
+      const BEntry& e = b.table[uni(b.lam_idx[p])];
+      const bool centre = uni(w.x) == 2;
       KArgs x = b.base;
       if (centre) {
         x.W = b.w1f;
@@ -87,16 +96,16 @@ __global__ __launch_bounds__(256) void k_bpoint(BArgs b) {
 
 // items: {1, point, outer direction, 0}.
 template <typename T, int D, int S, int K>
-__global__ __launch_bounds__(256, (sizeof(T) == 4 && D == 2 && K <= 16) ? 3 : 1) void k_bouter(BArgs b) {
+__global__ __launch_bounds__(256, (sizeof(T) == 4 && D == 2) ? (K <= 16 ? 3 : 2) : 1) void k_bouter(BArgs b) {
   extern __shared__ char smem_raw[];
   __shared__ int s_item;
   for (;;) {
     const int it = next_item(b.counter, &s_item);
     if (it >= b.n_items) return;                 // block-uniform: every wave exits
     const int4 w = b.items[it];
-    const int64_t p = w.y;
-    const int mo = w.z;
-    const BEntry& e = b.table[b.lam_idx[p]];
+    const int64_t p = uni(w.y);
+    const int mo = uni(w.z);
+    const BEntry& e = b.table[uni(b.lam_idx[p])];
     OuterRes<T>* res = static_cast<OuterRes<T>*>(b.outer) + b.pbase[p] + mo;
     const T w1f = static_cast<const T*>(b.w1f)[p];
     if (!(w1f < inf_v<T>())) {                   // det F <= 0 or non-finite input: block-uniform
@@ -110,10 +119,10 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && D == 2 && K <= 16) ? 3 : 1)
 // One wavefront per depth-2 point order[0 .. n_items).
 template <typename T, int D, int S, int K>
 __global__ __launch_bounds__(256) void k_bfinal(BArgs b) {
-  const int64_t i = int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int64_t i = int64_t(blockIdx.x) * (blockDim.x / kWave) + uni(int(threadIdx.x / kWave));
   if (i >= b.n_items) return;                    // wave-uniform
-  const int64_t p = b.order[i];
-  const BEntry& e = b.table[b.lam_idx[p]];
+  const int64_t p = uni(int64_t(b.order[i]));
+  const BEntry& e = b.table[uni(b.lam_idx[p])];
   finalize_point<T, D, S, K>(b.base, p, e.lv0, e.lv1, static_cast<const OuterRes<T>*>(b.outer) + b.pbase[p]);
 }
 

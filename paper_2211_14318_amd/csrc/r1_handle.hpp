@@ -19,7 +19,7 @@ struct r1_handle_s {
   void* scratch = nullptr;                 // grow-only workspace (depth-2 partial results)
   size_t scratch_bytes = 0;
   std::map<int, int> seg_override;         // n_t -> lanes per line (user setting)
-  std::map<int64_t, int> seg_tuned;        // (n_t, dtype, dim) -> lanes per line (autotuner)
+  std::map<int64_t, int> seg_tuned;        // (n_t, dtype, dim, role) -> lanes per line (autotuner)
   std::map<uint64_t, BatchedPlan*> plans;  // batched launches: plan + captured graph
   KTimer timer;                            // optional per-kernel event timing
   hipStream_t capture_stream = nullptr;    // private stream for graph capture
@@ -35,9 +35,15 @@ r1_status device_level(r1_handle h, const r1_level& lv, int dim, r1d::Level* out
 r1_status scratch(r1_handle h, size_t bytes, void** p);
 int samples_per_lane(int S, int n_t);
 int batch_samples_per_lane(int S, int n_t);
-int segment_width(r1_handle h, int n_t, int dtype, int dim);
-inline int64_t tune_key(int n_t, int dtype, int dim) { return (int64_t(n_t) << 8) | (dtype << 4) | dim; }
+// Roles of a level's lines for the segment width: lines of a one-level
+// envelope (depth-1 points, and the two extra envelopes of a depth-2 point's
+// stress), or the inner level of depth-2 points (sampled along outer lines).
+constexpr int kRoleLevel = 0, kRoleInner = 1;
+int segment_width(r1_handle h, int n_t, int dtype, int dim, int role = kRoleLevel);
+inline int64_t tune_key(int n_t, int dtype, int dim, int role) {
+  return (int64_t(n_t) << 8) | (role << 6) | (dtype << 4) | dim;
+}
 void release_batched(r1_handle h);
-r1_status autotune(r1_handle h, const r1_material* mat, int n_t, int dtype, int dim, hipStream_t st,
+r1_status autotune(r1_handle h, const r1_material* mat, int n_t, int dtype, int dim, int role, hipStream_t st,
                    int* lanes);
 }  // namespace r1h

@@ -81,6 +81,8 @@ def _load():
     L.r1_set_segment_width.argtypes = [vp, i32, i32]
     L.r1_get_segment_width.argtypes = [vp, i32, i32, i32, ctypes.POINTER(i32)]
     L.r1_autotune.argtypes = [vp, ctypes.POINTER(Material), i32, i32, vp, ctypes.POINTER(i32)]
+    L.r1_autotune_inner.argtypes = [vp, ctypes.POINTER(Material), i32, i32, vp, ctypes.POINTER(i32)]
+    L.r1_get_inner_segment_width.argtypes = [vp, i32, i32, i32, ctypes.POINTER(i32)]
     L.r1_timing_enable.argtypes = [vp, i32]
     L.r1_timing_reset.argtypes = [vp]
     L.r1_timing_query.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
@@ -107,7 +109,7 @@ def _load():
                  "r1_surrogate_get_params", "r1_surrogate_set_params", "r1_surrogate_get_norm",
                  "r1_surrogate_loss_grad", "r1_surrogate_save", "r1_surrogate_load"):
         getattr(L, name).restype = i32
-    for name in ("r1_autotune", "r1_timing_enable", "r1_timing_reset", "r1_timing_query", "r1_create", "r1_destroy", "r1_envelope", "r1_envelope_stress",
+    for name in ("r1_autotune", "r1_autotune_inner", "r1_get_inner_segment_width", "r1_timing_enable", "r1_timing_reset", "r1_timing_query", "r1_create", "r1_destroy", "r1_envelope", "r1_envelope_stress",
                  "r1_envelope_batched", "r1_set_segment_width", "r1_get_segment_width"):
         getattr(L, name).restype = i32
     return L
@@ -199,6 +201,18 @@ class Handle:
         out = ctypes.c_int32()
         self._check(_lib.r1_autotune(self.h, ctypes.byref(mat), int(n_t), int(dtype),
                                      self._stream(stream), ctypes.byref(out)), "r1_autotune")
+        return out.value
+
+    def autotune_inner(self, mat, n_t, dtype, stream=None):
+        out = ctypes.c_int32()
+        self._check(_lib.r1_autotune_inner(self.h, ctypes.byref(mat), int(n_t), int(dtype),
+                                           self._stream(stream), ctypes.byref(out)), "r1_autotune_inner")
+        return out.value
+
+    def inner_segment_width(self, n_t, dtype, dim):
+        out = ctypes.c_int32()
+        self._check(_lib.r1_get_inner_segment_width(self.h, int(n_t), int(dtype), int(dim),
+                                                    ctypes.byref(out)), "r1_get_inner_segment_width")
         return out.value
 
     def timing(self, on=True):

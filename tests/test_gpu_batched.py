@@ -140,9 +140,16 @@ def test_batched_rejects_bad_table_index(lib):
 
 
 def test_autotuner_returns_admissible_width(lib):
+    """One-level lines and inner levels of depth 2 are tuned separately (the inner
+    level on the depth-2 path); each query returns its own role's choice."""
     r1, h, torch = lib
     mat = r1.material()
     for nt in (257, 1025):
         lanes = h.autotune(mat, nt, r1.R1_F32)
         assert lanes in (8, 16, 32, 64)
+        assert h.segment_width(nt, r1.R1_F32, 2) == lanes
+        inner = h.autotune_inner(mat, nt, r1.R1_F32)
+        print("n_t %d: one-level lanes %d, inner lanes %d" % (nt, lanes, inner))
+        assert inner in (8, 16, 32, 64)
+        assert h.inner_segment_width(nt, r1.R1_F32, 2) == inner
         assert h.segment_width(nt, r1.R1_F32, 2) == lanes
