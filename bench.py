@@ -31,6 +31,7 @@ if ROOT not in sys.path:
 
 FLOPS_PER_W = 18           # algorithmic flops per W sample (FMA = 2), transcendentals not counted
 PEAK = {"f32": 157.3, "f64": 78.6}   # MI355X vector peak, TFLOP/s
+PEAK_NONPACKED = {"f32": 78.6, "f64": 78.6}   # without packed FP32 (this build does not emit it)
 GAMMA = 1e-8               # relative error E_rel = |a - b| / (gamma + |b|)
 
 
@@ -99,11 +100,31 @@ def cpu_baseline(workers):
         res = pool.map(_oracle_worker, list(range(workers)))
     wall = time.time() - t0
     per = [r[1] for r in res]
+    w_per_point = w_samples_outer_kernel(_cfg2_shape()) / 4096.0
     base = dict(value=workers / wall, unit="QP/s", cores=workers, kind="oracle",
                 sample="first %d points of the workload, one point per process (energy, stress and "
                        "tree, FP64 serial oracle), %.1f s wall, %.1f s per point" %
-                       (workers, wall, sum(per) / len(per)))
+                       (workers, wall, sum(per) / len(per)),
+                single_core_qps=len(per) / sum(per),
+                w_evals_per_s=workers / wall * w_per_point,
+                single_core_w_evals_per_s=len(per) / sum(per) * w_per_point,
+                cpu_model=_cpu_model())
     return base, {r[0]: (r[2], r[3]) for r in res}
+
+
+def _cfg2_shape():
+    from paper_2211_14318_amd import workloads as WL
+    return WL.config2(n=4096)
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 # ---------------------------------------------------------------- secondary legs
@@ -160,6 +181,16 @@ def leg_surrogate(h, r1, WL, torch, np, n_train=2_000_000, n_cal=262_144, n_inf=
     e32 = np.abs(Ws[acc] - Wp[acc]) / np.maximum(np.abs(Wp[acc]), 1e-2)
     e64 = np.abs(Ws[acc] - W64[acc]) / np.maximum(np.abs(W64[acc]), 1e-2)
     e_all = np.abs(Ws - W64) / np.maximum(np.abs(W64), 1e-2)
+    # the FP64 oracle on a subset of the inference points
+    from oracle import oracle as O
+    n_o = 2000
+    lv = inf["levels"][0]
+    om = O.material(dim=2)
+    ospec = O.LaminationSpec([(lv["a"], lv["b"], lv["n_t"], lv["tau"])])
+    Wo, _, _ = O.envelope_batch(om, ospec, Fi[:, :n_o].double().cpu().numpy(), bi[:n_o].double().cpu().numpy(),
+                                want_stress=False)
+    eo = np.abs(Ws[:n_o] - Wo) / np.maximum(np.abs(Wo), 1e-2)
+    acc_o = acc[:n_o]
     s.close()
     return {
         "workload": "surrogate-2d: train 2M rows (16 dirs x 201 pts, k=1), infer 1M points",
@@ -171,6 +202,10 @@ def leg_surrogate(h, r1, WL, torch, np, n_train=2_000_000, n_cal=262_144, n_inf=
         "accepted_erel_vs_fp64_plain": {"max": float(e64.max()), "p99": float(np.percentile(e64, 99)),
                                         "frac_gt_1e-3": float(np.mean(e64 > 1e-3))},
         "all_points_erel_vs_fp64_plain": {"max": float(e_all.max()), "p99": float(np.percentile(e_all, 99))},
+        "erel_vs_oracle_first_%d" % n_o: {"served": int(acc_o.sum()), "served_max": float(eo[acc_o].max()),
+                                          "served_p99": float(np.percentile(eo[acc_o], 99)),
+                                          "served_frac_gt_1e-3": float(np.mean(eo[acc_o] > 1e-3)),
+                                          "fallback_max": float(eo[~acc_o].max())},
         "train": {"rows": n_train, "epochs": epochs, "steps": rep["steps"], "ms": round(rep["ms"], 1),
                   "val_loss": rep["val_loss"], "data_gen_ms": round(1e3 * t_data, 1)},
         "mlp": "5 -> 4 x 128 SiLU -> 5, BF16 MFMA / FP32 accumulate",
@@ -351,6 +386,8 @@ def main():
     roof = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK[args.dtype], unit="TFLOP/s",
                 frac=round(achieved / PEAK[args.dtype], 4),
                 traffic=measured_traffic() if args.dtype == "f32" else None,
+                peak_nonpacked=PEAK_NONPACKED[args.dtype],
+                frac_nonpacked=round(achieved / PEAK_NONPACKED[args.dtype], 4),
                 kernel="k_outer", avg_ms=round(outer_ms / max(outer_n, 1), 3),
                 w_samples_per_launch=w_samples_outer_kernel(cfg), flops_per_w=FLOPS_PER_W)
     out = {

@@ -66,6 +66,10 @@ typedef int32_t r1_dtype;
 #define R1_PT_NONFINITE 2     /* F or beta_n not finite: outputs NaN */
 #define R1_PT_FALLBACK 4      /* surrogate inference answered by plain lamination */
 #define R1_PT_ITERCAP 8       /* a hull bridge search hit its iteration cap (result still a valid upper bound) */
+#define R1_PT_TIE 16          /* the laminate is ambiguous: a winning direction that laminates has a
+                                 runner-up within 1e-10 (FP64) / 1e-5 (FP32) of max(|W|, 1e-3 / 1e-2),
+                                 at the top level or (depth 2) at an endpoint's inner envelope; W is
+                                 unaffected, the tree and P may be any of the tied laminates' */
 
 #define R1_MAX_DEPTH 2
 #define R1_TREE_NODES 3       /* nodes of a depth-2 binary lamination tree */

@@ -622,7 +622,18 @@ struct Env {            // W^1 at a point: value, direction, bracketing offsets
   T h;
   int dir, mp, mq;
   int capped;
+  T second;             // runner-up over directions (the smallest value of another direction)
 };
+
+// A point's laminate is ambiguous when its winning direction laminates and
+// another direction's value is within the tie margin: 1e-10 (FP64) or 1e-5
+// (FP32) of max(|W|, 1e-3 / 1e-2).
+template <typename T>
+__device__ __forceinline__ bool near_tie(const Env<T>& e) {
+  const T margin = sizeof(T) == 4 ? T(1e-5) : T(1e-10);
+  const T floor = sizeof(T) == 4 ? T(1e-2) : T(1e-3);
+  return (e.mp + e.mq) > 0 && e.second - e.h <= margin * fmax(fabs(e.h), floor);
+}
 
 // One lamination level at a point (wave-uniform): min over the level's n_dir
 // directions of the line hulls at the centre.  wc = W at the point;
@@ -673,7 +684,7 @@ __device__ Env<T> envelope_lines(const Point<T>& q, T wc, int n_dir, const Layou
       seen_cold += __popcll(mc);
     }
   }
-  Env<T> best = {inf_v<T>(), 0, 0, 0, 0};
+  Env<T> best = {inf_v<T>(), 0, 0, 0, 0, inf_v<T>()};
   for (int m0 = 0; m0 < n_dir; m0 += NSEG) {
     const bool act = m0 + seg < n_dir;
     const int dir = order ? order[act ? m0 + seg : n_dir - 1] : (act ? m0 + seg : n_dir - 1);
@@ -702,8 +713,13 @@ __device__ Env<T> envelope_lines(const Point<T>& q, T wc, int n_dir, const Layou
     const bool hot = warm && __all(act && sg == sg);
     LineHull<T> lh = hull_centre<T, S, K>(w, wc, wci, lay, sg, hot);
     if (warm && act && (lane & (S - 1)) == 0) warm[dir] = sg;
-    if (act && (lh.h < best.h || (lh.h == best.h && dir < best.dir))) {
-      best.h = lh.h; best.dir = dir; best.mp = lh.mp; best.mq = lh.mq;
+    if (act) {
+      if (lh.h < best.h || (lh.h == best.h && dir < best.dir)) {
+        best.second = best.h;
+        best.h = lh.h; best.dir = dir; best.mp = lh.mp; best.mq = lh.mq;
+      } else {
+        best.second = fmin(best.second, lh.h);
+      }
     }
     best.capped |= lh.capped;
   }
@@ -715,7 +731,9 @@ __device__ Env<T> envelope_lines(const Point<T>& q, T wc, int n_dir, const Layou
     int op = __shfl_xor(best.mp, off, kWave);
     int oq = __shfl_xor(best.mq, off, kWave);
     int oc = __shfl_xor(best.capped, off, kWave);
+    T os = __shfl_xor(best.second, off, kWave);
     bool take = oh < best.h || (oh == best.h && od < best.dir);
+    best.second = take ? fmin(os, best.h) : fmin(best.second, oh);
     best.h = take ? oh : best.h;
     best.dir = take ? od : best.dir;
     best.mp = take ? op : best.mp;

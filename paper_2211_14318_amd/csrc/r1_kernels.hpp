@@ -61,7 +61,7 @@ __device__ Env<T> envelope_with_stress(const KArgs& a, const Level& lv, const La
   double cof[D * D];
   cofactor<D>(G, cof);
   T wc = w_point<T, D>(q, G, cof);
-  Env<T> e = {wc, 0, 0, 0, 0};
+  Env<T> e = {wc, 0, 0, 0, 0, inf_v<T>()};
   if (wc < inf_v<T>()) e = envelope_at<T, D, S, K>(q, G, wc, lv, lay);
   double Gm[D * D], Gp[D * D], Pm[D * D], Pp[D * D];
   line_point<D>(G, lv, e.dir, -t_of(lv, e.mp), Gm);
@@ -122,7 +122,7 @@ __device__ __forceinline__ void point_depth1(const KArgs& a, int64_t p, const Le
       a.tree[p * R1_TREE_NODES] = r1_laminate{e.dir, c - e.mp, c + e.mq, xi};
       for (int k = 1; k < R1_TREE_NODES; ++k) a.tree[p * R1_TREE_NODES + k] = r1_laminate{0, 0, 0, 1.0f};
     }
-    if (a.flags) a.flags[p] = e.capped ? R1_PT_ITERCAP : 0;
+    if (a.flags) a.flags[p] = (e.capped ? R1_PT_ITERCAP : 0) | (near_tie(e) ? R1_PT_TIE : 0);
   }
 }
 
@@ -357,21 +357,24 @@ __device__ __forceinline__ void finalize_point(const KArgs& a, int64_t p, const 
     if (lane_id() == 0) write_bad_point<T, D>(a, p, !fin, a.want_stress);
     return;
   }
-  T bh = inf_v<T>();
+  T bh = inf_v<T>(), bs = inf_v<T>();
   int bd = 0x7fffffff, bp = 0, bq = 0, cap = 0;
   for (int m = lane_id(); m < n_dir_o; m += kWave) {
     OuterRes<T> r = res[m];
     cap |= r.capped;
-    if (r.h < bh) { bh = r.h; bd = m; bp = r.mp; bq = r.mq; }
+    if (r.h < bh) { bs = bh; bh = r.h; bd = m; bp = r.mp; bq = r.mq; }
+    else bs = fmin(bs, r.h);
   }
 #pragma unroll
   for (int off = 1; off < kWave; off <<= 1) {
-    T oh = __shfl_xor(bh, off);
+    T oh = __shfl_xor(bh, off), os = __shfl_xor(bs, off);
     int od = __shfl_xor(bd, off), op = __shfl_xor(bp, off), oq = __shfl_xor(bq, off);
     cap |= __shfl_xor(cap, off);
     bool take = oh < bh || (oh == bh && od < bd);
+    bs = take ? fmin(os, bh) : fmin(bs, oh);
     bh = take ? oh : bh; bd = take ? od : bd; bp = take ? op : bp; bq = take ? oq : bq;
   }
+  bool tie = near_tie(Env<T>{bh, bd, bp, bq, 0, bs});
   const int c = (lo.n_t - 1) / 2, ci = (li.n_t - 1) / 2;
   r1_laminate node[3];
   double Pout[D * D];
@@ -382,10 +385,12 @@ __device__ __forceinline__ void finalize_point(const KArgs& a, int64_t p, const 
     line_point<D>(F, lo, bd, t_of(lo, bq), Gp);
     Env<T> em = envelope_with_stress<T, D, S, K>(a, li, lay, bn, Gm, Pm);
     cap |= em.capped;
+    tie = tie || near_tie(em);
     Env<T> ep = em;
     if (bp + bq) {
       ep = envelope_with_stress<T, D, S, K>(a, li, lay, bn, Gp, Pp);
       cap |= ep.capped;
+      tie = tie || near_tie(ep);
     } else {
 #pragma unroll
       for (int k = 0; k < D * D; ++k) Pp[k] = Pm[k];
@@ -406,7 +411,7 @@ __device__ __forceinline__ void finalize_point(const KArgs& a, int64_t p, const 
       for (int k = 0; k < D * D; ++k) static_cast<T*>(a.P)[int64_t(k) * a.n + p] = T(Pout[k]);
     if (a.tree)
       for (int k = 0; k < R1_TREE_NODES; ++k) a.tree[p * R1_TREE_NODES + k] = node[k];
-    if (a.flags) a.flags[p] = cap ? R1_PT_ITERCAP : 0;
+    if (a.flags) a.flags[p] = (cap ? R1_PT_ITERCAP : 0) | (tie ? R1_PT_TIE : 0);
   }
 }
 

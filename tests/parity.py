@@ -58,6 +58,32 @@ def is_tie(tree, depth, W, kind):
     return False
 
 
+TIE_FLAG = {"f64": 1e-10, "f32": 1e-5}   # the library's tie margin (flag R1_PT_TIE)
+PT_TIE = 16
+
+
+def check_tie_flags(trees_orc, depth, W_orc, flags_gpu, kind):
+    """The GPU's R1_PT_TIE flag against the oracle's runner-up gaps: every node of the
+    tree whose winning direction laminates (oracle dir_gap finite) counts; a gap below a
+    tenth of the margin must be flagged, a gap above ten times the margin must not.
+    Returns (n_flagged, n_between)."""
+    n_flag = n_mid = 0
+    for p in range(len(W_orc)):
+        if not np.isfinite(W_orc[p]):
+            continue
+        nodes = trees_orc[p][:1] if depth == 1 else trees_orc[p][:3]
+        g = min(nd["dir_gap"] / (TIE_FLAG[kind] * max(abs(nd["value"]), W_FLOOR[kind])) for nd in nodes)
+        flagged = bool(flags_gpu[p] & PT_TIE)
+        if g < 0.1:
+            assert flagged, (p, g)
+        elif g > 10.0:
+            assert not flagged, (p, g)
+        else:
+            n_mid += 1
+        n_flag += flagged
+    return n_flag, n_mid
+
+
 def check_stress(mat, spec, depth, F_soa, beta_n, W_orc, P_orc, trees_orc, P_gpu, tree_gpu, kind):
     """Returns (n_checked_exact, n_ties).  tree_gpu: (n, 3, 4) int32 array."""
     d = mat.dim

@@ -65,6 +65,8 @@ def check_case(lib, cfg, kind, model=0, lanes=None, min_exact=1):
     assert ne >= min_exact
     fl = g["flags"]
     assert np.all((fl & 1) == (~np.isfinite(W)).astype(np.int32) * 1)
+    nf, nm = PA.check_tie_flags(trees, depth, W, fl, kind)
+    print("   tie flags: %d set, %d within 10x of the margin" % (nf, nm))
     return g, W
 
 
@@ -139,6 +141,34 @@ def test_depth2_3d_small(lib):
 
 
 # ---------------------------------------------------------------- edge cases
+
+@pytest.mark.parametrize("kind,depth", [("f64", 1), ("f32", 1), ("f64", 2)])
+def test_tie_flag_on_duplicated_directions(lib, kind, depth):
+    """Listing every (outer) direction twice makes the laminate of every laminating
+    point an exact tie: the energy, the tree (smallest index wins) and the stress stay
+    those of the single list, and R1_PT_TIE is set exactly where the point laminates."""
+    r1, h, torch = lib
+    if depth == 1:
+        cfg = WL.config1()
+    else:
+        cfg = WL.small_random(2, 24, (4, 4), 65, tau=1.5, depth=2, inner=(4, 2, 33), seed_tag=400)
+    lv0 = cfg["levels"][0]
+    dup = dict(cfg, levels=[dict(lv0, a=np.concatenate([lv0["a"], lv0["a"]]), b=np.concatenate([lv0["b"], lv0["b"]]))]
+               + cfg["levels"][1:])
+    g1 = run_gpu(lib, cfg, kind)
+    g2 = run_gpu(lib, dup, kind)
+    assert np.array_equal(g1["W"], g2["W"])
+    assert np.array_equal(g1["P"], g2["P"], equal_nan=True)
+    assert np.array_equal(g1["tree"], g2["tree"])
+    c = (lv0["n_t"] - 1) // 2
+    lam = g2["tree"][:, 0, 1] < c                  # top-level laminate present
+    fl2 = g2["flags"]
+    assert np.all(((fl2 & r1.PT_TIE) != 0)[lam])
+    if depth == 1:
+        assert not np.any(((fl2 & r1.PT_TIE) != 0)[~lam])
+    print("%s depth %d: %d of %d points laminate, all flagged" % (kind, depth, lam.sum(), len(lam)))
+    assert lam.sum() >= 5
+
 
 def test_edge_points_and_minimum_grid(lib):
     """det F <= 0 -> +inf and flag; NaN input -> NaN and flag; n_t = 3; one direction."""
