@@ -137,3 +137,61 @@ int orc_stress0(const orc_material* mat, const double* G, double beta_n, double*
             P[i * d + j] = g * (mat->mu * F3[i][j] + (mat->lambda * lnJ - mat->mu) * cof[i][j] / J);
     return 0;
 }
+
+/* A0 = d^2 W / dG dG, the nominal tangent moduli of Section 2 at a leaf of the
+ * lamination tree (Algorithm 3 sums them like the stresses).  With W = g(psi0),
+ * g'(psi) = 1 - D(max(beta_n, psi)) and g''(psi) = -D'(psi) while loading
+ * (psi0 > beta_n, as in orc_stress0), 0 otherwise:
+ *   A0_ijkl = g' d^2psi0/dG_ij dG_kl + g'' S_ij S_kl,
+ *   S = dpsi0/dG = mu G + (lambda ln J - mu) G^{-T},
+ *   d^2psi0/dG_ij dG_kl = mu d_ik d_jl + lambda G^{-T}_ij G^{-T}_kl
+ *                         - (lambda ln J - mu) G^{-T}_il G^{-T}_kj
+ * (d ln J / dG = G^{-T}, d G^{-T}_ij / dG_kl = -G^{-T}_il G^{-T}_kj).  In 2D the
+ * indices run over the in-plane block of the plane-strain embedding.
+ * A[(i*d+j)*d*d + k*d+l]; NaN where det G <= 0. */
+int orc_tangent0(const orc_material* mat, const double* G, double beta_n, double* A)
+{
+    int d = mat->dim, dd = d * d;
+    if (mat->model == ORC_MODEL_DOUBLEWELL) {
+        for (int a = 0; a < dd * dd; ++a)
+            A[a] = 0.0;
+        for (int a = 0; a < dd; ++a)
+            A[a * dd + a] = 2.0;
+        A[0] = 12.0 * G[0] * G[0] - 4.0;
+        return 0;
+    }
+    double F3[3][3];
+    embed3(d, G, F3);
+    double J = det3(F3);
+    if (!(J > 0.0)) {
+        for (int a = 0; a < dd * dd; ++a)
+            A[a] = NAN;
+        return -1;
+    }
+    double Finv_T[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+            Finv_T[i][j] = (F3[i1][j1] * F3[i2][j2] - F3[i1][j2] * F3[i2][j1]) / J;
+        }
+    double lnJ = log(J);
+    double p0 = orc_psi0(mat, G);
+    double beta = p0 > beta_n ? p0 : beta_n;
+    double g1 = 1.0 - orc_damage(mat, beta);
+    double g2 = p0 > beta_n ? -mat->D_inf / mat->D0 * exp(-p0 / mat->D0) : 0.0;
+    double c = mat->lambda * lnJ - mat->mu;
+    double S[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            S[i][j] = mat->mu * F3[i][j] + c * Finv_T[i][j];
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j)
+            for (int k = 0; k < d; ++k)
+                for (int l = 0; l < d; ++l) {
+                    double h = (i == k && j == l ? mat->mu : 0.0)
+                             + mat->lambda * Finv_T[i][j] * Finv_T[k][l]
+                             - c * Finv_T[i][l] * Finv_T[k][j];
+                    A[(i * d + j) * dd + k * d + l] = g1 * h + g2 * S[i][j] * S[k][l];
+                }
+    return 0;
+}

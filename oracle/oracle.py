@@ -3,8 +3,9 @@
 TEST INFRASTRUCTURE ONLY: the test suite, ``__graft_entry__.smoke()`` and the
 CPU-baseline leg of ``bench.py`` may use this module; the product path never
 does.  It is a thin ctypes wrapper: every piece of arithmetic lives in the C
-files, which follow arXiv 2211.14318 (Section 2 for W and P, Algorithm 1 for
-the 1D hull, eq. 3.3 for lamination, eq. 5.2 / Algorithm 3 for stresses).
+files, which follow arXiv 2211.14318 (Section 2 for W, P and the tangent
+moduli, Algorithm 1 for the 1D hull, eq. 3.3 for lamination, eq. 5.2 /
+Algorithm 3 for stresses and tangent moduli).
 """
 import ctypes
 import os
@@ -73,6 +74,17 @@ def lib():
         L.orc_energy.argtypes = [ctypes.POINTER(Material), dp, ctypes.c_double]
         L.orc_stress0.restype = ctypes.c_int
         L.orc_stress0.argtypes = [ctypes.POINTER(Material), dp, ctypes.c_double, dp]
+        L.orc_tangent0.restype = ctypes.c_int
+        L.orc_tangent0.argtypes = [ctypes.POINTER(Material), dp, ctypes.c_double, dp]
+        L.orc_envelope_tangent.restype = ctypes.c_double
+        L.orc_envelope_tangent.argtypes = [ctypes.POINTER(Material), ctypes.POINTER(Lamination), dp,
+                                           ctypes.c_double, dp, dp, ctypes.POINTER(Laminate)]
+        L.orc_eval_tree_tangent.restype = ctypes.c_double
+        L.orc_eval_tree_tangent.argtypes = [ctypes.POINTER(Material), ctypes.POINTER(Lamination), dp,
+                                            ctypes.c_double, ctypes.POINTER(Laminate), dp, dp]
+        L.orc_envelope_batch_tangent.restype = None
+        L.orc_envelope_batch_tangent.argtypes = [ctypes.POINTER(Material), ctypes.POINTER(Lamination),
+                                                 ctypes.c_long, dp, dp, dp, dp, dp, ctypes.POINTER(Laminate)]
         L.orc_convexify.restype = ctypes.c_int
         L.orc_convexify.argtypes = [ctypes.c_int, dp, dp, ip]
         L.orc_hull_at_centre.restype = ctypes.c_double
@@ -141,6 +153,58 @@ def stress0(mat, G, beta_n):
     P = np.empty_like(G)
     lib().orc_stress0(ctypes.byref(mat), _dp(G), float(beta_n), _dp(P))
     return P
+
+
+def tangent0(mat, G, beta_n):
+    """d^2 W / dG dG as a (d*d, d*d) array."""
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    dd = G.size
+    A = np.empty((dd, dd))
+    lib().orc_tangent0(ctypes.byref(mat), _dp(G), float(beta_n), _dp(A))
+    return A
+
+
+def envelope_tangent(mat, spec, F, beta_n, want_tree=False):
+    """Returns (W^k, P^k (d x d), A^k (d*d x d*d), tree or None) for one point."""
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    dd = F.size
+    P = np.empty_like(F)
+    A = np.empty((dd, dd))
+    tree = (Laminate * TREE_NODES)() if want_tree else None
+    W = lib().orc_envelope_tangent(ctypes.byref(mat), ctypes.byref(spec.c), _dp(F), float(beta_n), _dp(P),
+                                   _dp(A), tree)
+    return W, P, A, (tree_to_list(tree) if want_tree else None)
+
+
+def eval_tree_tangent(mat, spec, F, beta_n, nodes):
+    """Energy, stress and tangent moduli of a given tree: nodes = list of (dir, i_minus, i_plus)."""
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    dd = F.size
+    P = np.empty_like(F)
+    A = np.empty((dd, dd))
+    tree = (Laminate * TREE_NODES)()
+    for k, (m, im, ip) in enumerate(nodes[:TREE_NODES]):
+        tree[k].dir, tree[k].i_minus, tree[k].i_plus = int(m), int(im), int(ip)
+    W = lib().orc_eval_tree_tangent(ctypes.byref(mat), ctypes.byref(spec.c), _dp(F), float(beta_n), tree,
+                                    _dp(P), _dp(A))
+    return W, P, A
+
+
+def envelope_batch_tangent(mat, spec, F_soa, beta_n, want_tree=False):
+    """SoA batch: F_soa (d*d, n), beta_n (n,) -> W (n,), P (d*d, n), A (d^4, n), trees."""
+    F_soa = np.ascontiguousarray(F_soa, dtype=np.float64)
+    beta_n = np.ascontiguousarray(beta_n, dtype=np.float64)
+    dd, n = F_soa.shape
+    W = np.empty(n)
+    P = np.empty_like(F_soa)
+    A = np.empty((dd * dd, n))
+    trees = (Laminate * (TREE_NODES * n))() if want_tree else None
+    lib().orc_envelope_batch_tangent(ctypes.byref(mat), ctypes.byref(spec.c), n, _dp(F_soa), _dp(beta_n),
+                                     _dp(W), _dp(P), _dp(A), trees)
+    if want_tree:
+        t = tree_to_list(trees)
+        trees = [t[p * TREE_NODES:(p + 1) * TREE_NODES] for p in range(n)]
+    return W, P, A, trees
 
 
 def convexify(x, w):

@@ -74,6 +74,8 @@ double orc_psi0(const orc_material* mat, const double* G);
 double orc_damage(const orc_material* mat, double beta);
 double orc_energy(const orc_material* mat, const double* G, double beta_n);
 int orc_stress0(const orc_material* mat, const double* G, double beta_n, double* P);
+/* Tangent moduli d^2 W / dG dG (d^2 x d^2, A[(i*d+j)*d*d + k*d+l]); NaN where det G <= 0. */
+int orc_tangent0(const orc_material* mat, const double* G, double beta_n, double* A);
 
 /* Algorithm 1 (convexify): lower hull of (x_i, w_i), x strictly increasing.
  * Writes the indices (into x/w) of the hull vertices to vert and returns their count. */
@@ -101,10 +103,22 @@ double orc_envelope(const orc_material* mat, const orc_lamination* lam,
 double orc_eval_tree(const orc_material* mat, const orc_lamination* lam,
                      const double* F, double beta_n, const orc_laminate* tree, double* P);
 
+/* The same with the tangent moduli of the laminate (Algorithm 3's third output:
+ * the tree-weighted sum of the leaves' d^2 W / dG dG); A (d^4, nullable). */
+double orc_envelope_tangent(const orc_material* mat, const orc_lamination* lam,
+                            const double* F, double beta_n, double* P, double* A, orc_laminate* tree);
+double orc_eval_tree_tangent(const orc_material* mat, const orc_lamination* lam,
+                             const double* F, double beta_n, const orc_laminate* tree, double* P,
+                             double* A);
+
 /* Batched drivers over structure-of-arrays inputs F[(i*d+j)*n + p]. */
 void orc_envelope_batch(const orc_material* mat, const orc_lamination* lam, long n,
                         const double* F, const double* beta_n, double* W, double* P,
                         orc_laminate* trees);
+/* With the tangent moduli, SoA A[(ij*d*d + kl)*n + p] (nullable). */
+void orc_envelope_batch_tangent(const orc_material* mat, const orc_lamination* lam, long n,
+                                const double* F, const double* beta_n, double* W, double* P,
+                                double* A, orc_laminate* trees);
 
 /* Surrogate network oracle (mlp.c): FP64 MLP with SiLU hidden layers, flat
  * parameter layout W_0, b_0, ..., W_out, b_out (row-major, out x in). */

@@ -317,6 +317,87 @@ def test_laminate_stress_is_derivative_of_envelope(depth):
     assert checked >= 5
 
 
+def fd_jac(f, F, h=1e-6):
+    """Central-difference Jacobian of a matrix-valued f: (d*d, d*d), column = input entry."""
+    dd = F.size
+    J = np.zeros((dd, dd))
+    for c, idx in enumerate(np.ndindex(F.shape)):
+        E = np.zeros_like(F)
+        E[idx] = h
+        J[:, c] = (np.ravel(f(F + E)) - np.ravel(f(F - E))) / (2 * h)
+    return J
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_tangent0_small_strain_moduli_at_identity(dim):
+    """At F = I without damage the tangent moduli of Section 2 reduce to the isotropic
+    small-strain moduli  mu (d_ik d_jl + d_il d_jk) + lambda d_ij d_kl."""
+    mu, lam = 1.3, 0.7
+    mat = O.material(dim=dim, mu=mu, lam=lam, D_inf=0.0)
+    A = O.tangent0(mat, np.eye(dim), 0.0)
+    ref = np.zeros((dim, dim, dim, dim))
+    for i, j, k, l in np.ndindex(ref.shape):
+        ref[i, j, k, l] = mu * ((i == k) * (j == l) + (i == l) * (j == k)) + lam * (i == j) * (k == l)
+    assert np.allclose(A, ref.reshape(dim * dim, dim * dim), rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_tangent0_is_derivative_of_stress0(dim):
+    """A = dP/dF (Section 2) on the damage-loading and the elastic-unloading branches of
+    beta = max(beta_k, psi0), symmetric as a Hessian; the double-well test energy likewise."""
+    for model in (O.MODEL_NH_DAMAGE, O.MODEL_DOUBLEWELL):
+        mat = O.material(dim=dim, model=model)
+        rng = np.random.default_rng(4)
+        n = 0
+        for k in range(20):
+            F = np.eye(dim) + 0.3 * rng.standard_normal((dim, dim))
+            if np.linalg.det(F) < 0.2:
+                continue
+            bn = 0.0 if k % 2 else 10.0
+            A = O.tangent0(mat, F, bn)
+            J = fd_jac(lambda X: O.stress0(mat, X, bn), F)
+            assert np.allclose(A, J, rtol=1e-6, atol=1e-7), (model, k)
+            assert np.allclose(A, A.T, rtol=0, atol=1e-12 * np.abs(A).max())
+            n += 1
+        assert n >= 10
+    assert np.all(np.isnan(O.tangent0(O.material(dim=dim), -np.eye(dim) if dim == 3 else np.diag([1.0, -1.0]), 0.0)))
+
+
+@pytest.mark.parametrize("depth", [1, 2])
+def test_laminate_tangent_is_derivative_of_laminate_stress(depth):
+    """Algorithm 3 sums the leaves' tangent moduli with the tree weights.  Where the tree
+    stays the same under the finite-difference steps (the grid moves with F), that sum is
+    the exact derivative of the laminate stress; it is also what the tree evaluation gives."""
+    mat = O.material(dim=2)
+    cfg = WL.small_random(2, 10, (4, 4), 41, tau=1.5, depth=depth, inner=(4, 2, 21), seed_tag=14)
+    spec = spec_of(cfg["levels"])
+    nn = 1 if depth == 1 else 3
+    key = lambda t: [(x["dir"], x["i_minus"], x["i_plus"]) for x in t[:nn]]
+    checked = lam_checked = 0
+    h = 1e-7
+    for p in range(cfg["n"]):
+        F = cfg["F"][:, p].reshape(2, 2)
+        bn = cfg["beta_n"][p]
+        W, P, A, tree = O.envelope_tangent(mat, spec, F, bn, want_tree=True)
+        We, Pe, Ae = O.eval_tree_tangent(mat, spec, F, bn, key(tree) + [(0, 0, 0)] * (3 - nn))
+        assert abs(We - W) <= 1e-14 * max(abs(W), 1.0) and np.array_equal(Pe, P) and np.array_equal(Ae, A)
+        assert np.allclose(A, A.T, rtol=0, atol=1e-12 * np.abs(A).max())
+        same = True
+        for idx in np.ndindex(F.shape):
+            E = np.zeros_like(F)
+            E[idx] = h
+            for sgn in (1, -1):
+                if key(O.envelope(mat, spec, F + sgn * E, bn, want_tree=True)[2]) != key(tree):
+                    same = False
+        if not same:
+            continue
+        J = fd_jac(lambda X: O.envelope(mat, spec, X, bn)[1], F, h=h)
+        assert np.allclose(A, J, rtol=1e-5, atol=1e-5), (p, A, J)
+        checked += 1
+        lam_checked += tree[0]["i_minus"] != tree[0]["i_plus"]
+    assert checked >= 5 and lam_checked >= 3, (checked, lam_checked)
+
+
 def test_tree_invariants_and_eval():
     """H_M structure (Section 3.1): weights sum to 1, the barycentre is F, rank(F+ - F-) = 1;
     Algorithm 3 on the returned tree reproduces the envelope and its stress."""
