@@ -21,7 +21,7 @@
  * Conventions shared by every entry point
  *   - d = material->dim in {2, 3}.  Deformation gradients and stresses are
  *     structure-of-arrays, component-major: F[(i*d + j)*n + p] for point p.
- *   - Every data pointer (F, beta_n, W, P, tree, flags, lam_idx, X, Y) is caller-
+ *   - Every data pointer (F, beta_n, W, P, A, tree, flags, lam_idx, X, Y) is caller-
  *     owned DEVICE memory on the handle's device; the library never frees it.
  *     r1_material / r1_lamination structs and the direction arrays they point
  *     to are HOST memory read during the call.
@@ -142,6 +142,33 @@ r1_status r1_envelope_stress(r1_handle handle, const r1_material* material,
                              const r1_lamination* lamination, int64_t n, r1_dtype dtype,
                              const void* F, const void* beta_n, void* W, void* P,
                              r1_laminate* tree, int32_t* flags, void* stream);
+
+/* As r1_envelope_stress, plus the tangent moduli of the laminate (Algorithm 3,
+ * third output; the consistent tangent of the relaxed stress used in Section 5):
+ * A = dP^k/dF as the tree-weighted sum of the leaf moduli d^2W/dF dF of eq. 2.9,
+ * with the weights of P.  A (device, non-null) is d^4 x n SoA in dtype:
+ * A[((i*d + j)*d*d + k*d + l) * n + p] = dP_ij / dF_kl at point p.  P and tree
+ * are nullable (tree == NULL: the tree lives in handle workspace).  A is NaN
+ * where W is +inf or NaN (flags R1_PT_DETLE0, R1_PT_NONFINITE).  Where the
+ * laminate is ambiguous (R1_PT_TIE) A belongs to the tree written, like P. */
+r1_status r1_envelope_tangent(r1_handle handle, const r1_material* material,
+                              const r1_lamination* lamination, int64_t n, r1_dtype dtype,
+                              const void* F, const void* beta_n, void* W, void* P, void* A,
+                              r1_laminate* tree, int32_t* flags, void* stream);
+
+/* Tangent moduli A (layout of r1_envelope_tangent) of given lamination trees
+ * (Algorithm 3 on tree[p*R1_TREE_NODES ..], nodes as written by the envelope
+ * calls for the same lamination): leaves F^-/+ of each node rebuilt from its
+ * direction and sample indices, weights xi = (c - i_minus)/(i_plus - i_minus)
+ * (the stored float xi is not read).  W (device, dtype[n]) marks the points to
+ * skip: A is NaN where W is not finite.  A node whose direction or indices do
+ * not name a laminate of its level (dir outside [0, n_dir), not i_minus <= c <=
+ * i_plus, indices outside [0, n_t)) gives NaN for its point; all device
+ * buffers are read-only but A. */
+r1_status r1_laminate_tangent(r1_handle handle, const r1_material* material,
+                              const r1_lamination* lamination, int64_t n, r1_dtype dtype,
+                              const void* F, const void* beta_n, const void* W,
+                              const r1_laminate* tree, void* A, void* stream);
 
 /* Uneven batch in one persistent launch: point p uses table[lam_idx[p]]
  * (lam_idx: device int32[n], each in [0, n_table)).  P and tree are nullable
@@ -296,7 +323,7 @@ r1_status r1_surrogate_load(r1_handle handle, r1_surrogate* surrogate, const cha
 
 /* When enabled, every kernel launch of the handle is bracketed by HIP events
  * recorded on its launch stream.  Kernel names: "depth1" (one-level envelope),
- * "depth2_centre", "outer", "finalize" (two-level envelope), "batched".
+ * "depth2_centre", "outer", "finalize" (two-level envelope), "tangent" (tangent moduli), "batched".
  * r1_timing_query waits for the recorded events and returns the summed elapsed
  * milliseconds and the launch count of `kernel` since the last reset. */
 r1_status r1_timing_enable(r1_handle handle, int32_t on);

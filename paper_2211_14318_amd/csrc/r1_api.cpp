@@ -225,51 +225,113 @@ r1_status r1_get_inner_segment_width(r1_handle h, int32_t n_t, r1_dtype dtype, i
   return R1_OK;
 }
 
-r1_status r1_envelope_stress(r1_handle h, const r1_material* mat, const r1_lamination* lam,
-                             int64_t n, r1_dtype dtype, const void* F, const void* beta_n,
-                             void* W, void* P, r1_laminate* tree, int32_t* flags, void* stream) {
-  if (!h) return R1_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// Kernel arguments shared by the envelope and tangent launches.
+r1_status fill_args(r1_handle h, const r1_material* mat, const r1_lamination* lam, int64_t n, r1_dtype dtype,
+                    const void* F, const void* beta_n, KArgs* a) {
   r1_status s = r1h::check_material(mat);
   if (s) return s;
   s = r1h::check_lamination(lam);
   if (s) return s;
   if (dtype != R1_F32 && dtype != R1_F64) return R1_EINVAL;
   if (n < 0 || n > (int64_t(1) << 31)) return R1_EINVAL;
+  *a = KArgs{};
+  a->n = n;
+  a->F = F;
+  a->beta_n = beta_n;
+  a->mat = r1d::Material{mat->dim, mat->model, mat->mu, mat->lambda, mat->D_inf, mat->D0};
   if (n == 0) return R1_OK;
-  if (!F || !beta_n || !W) return R1_EINVAL;
   hipError_t e = hipSetDevice(h->device);
   if (e != hipSuccess) return r1h::fail(h, e, "hipSetDevice");
-  KArgs a{};
-  a.n = n;
-  a.F = F;
-  a.beta_n = beta_n;
+  s = r1h::device_level(h, lam->level[0], mat->dim, &a->lv0);
+  if (s) return s;
+  if (lam->depth == 2) s = r1h::device_level(h, lam->level[1], mat->dim, &a->lv1);
+  return s;
+}
+
+// Envelope with optional stress, tree, flags and tangent moduli (A != nullptr:
+// the tree goes to workspace when the caller passes none).
+r1_status envelope_impl(r1_handle h, const r1_material* mat, const r1_lamination* lam, int64_t n,
+                        r1_dtype dtype, const void* F, const void* beta_n, void* W, void* P,
+                        r1_laminate* tree, int32_t* flags, void* A, void* stream) {
+  if (!h) return R1_EINVAL;
+  KArgs a;
+  r1_status s = fill_args(h, mat, lam, n, dtype, F, beta_n, &a);
+  if (s) return s;
+  if (n == 0) return R1_OK;
+  if (!F || !beta_n || !W) return R1_EINVAL;
   a.W = W;
   a.P = P;
   a.tree = tree;
   a.flags = flags;
-  a.mat = r1d::Material{mat->dim, mat->model, mat->mu, mat->lambda, mat->D_inf, mat->D0};
   a.want_stress = P != nullptr;
-  s = r1h::device_level(h, lam->level[0], mat->dim, &a.lv0);
-  if (s) return s;
   const r1_level& inner = lam->level[lam->depth - 1];
+  size_t bytes = 0, w1 = 0;
   if (lam->depth == 2) {
-    s = r1h::device_level(h, lam->level[1], mat->dim, &a.lv1);
-    if (s) return s;
     if (int64_t(n) * lam->level[0].n_dir > int64_t(0x7fffffff)) return R1_EINVAL;
     size_t tsz = dtype == R1_F32 ? 4 : 8;
-    size_t w1 = (tsz * size_t(n) + 255) & ~size_t(255);
-    size_t bytes = w1 + r1_outer_res_bytes(dtype) * size_t(n) * size_t(lam->level[0].n_dir);
+    w1 = (tsz * size_t(n) + 255) & ~size_t(255);
+    bytes = w1 + r1_outer_res_bytes(dtype) * size_t(n) * size_t(lam->level[0].n_dir);
+  }
+  size_t tree_off = (bytes + 255) & ~size_t(255);
+  if (A && !tree) bytes = tree_off + sizeof(r1_laminate) * R1_TREE_NODES * size_t(n);
+  if (bytes) {
     void* base = nullptr;
     s = r1h::scratch(h, bytes, &base);
     if (s) return s;
-    a.scratch_w1f = base;
-    a.scratch_outer = static_cast<char*>(base) + w1;
+    if (lam->depth == 2) {
+      a.scratch_w1f = base;
+      a.scratch_outer = static_cast<char*>(base) + w1;
+    }
+    if (A && !tree) a.tree = reinterpret_cast<r1_laminate*>(static_cast<char*>(base) + tree_off);
   }
   int S = r1h::segment_width(h, inner.n_t, dtype, mat->dim, lam->depth == 2 ? r1h::kRoleInner : r1h::kRoleLevel);
   int K = r1h::samples_per_lane(S, inner.n_t);
   if (K == 0) return R1_EINVAL;
-  e = r1_launch_envelope(a, lam->depth, dtype, S, K, static_cast<hipStream_t>(stream),
-                         h->timer.on ? &h->timer : nullptr);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  KTimer* tm = h->timer.on ? &h->timer : nullptr;
+  hipError_t e = r1_launch_envelope(a, lam->depth, dtype, S, K, st, tm);
+  if (e != hipSuccess) return r1h::fail(h, e, "kernel launch");
+  if (A) {
+    e = r1_launch_tangent(a, lam->depth, dtype, a.tree, A, st, tm);
+    if (e != hipSuccess) return r1h::fail(h, e, "kernel launch");
+  }
+  return R1_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+r1_status r1_envelope_stress(r1_handle h, const r1_material* mat, const r1_lamination* lam,
+                             int64_t n, r1_dtype dtype, const void* F, const void* beta_n,
+                             void* W, void* P, r1_laminate* tree, int32_t* flags, void* stream) {
+  return envelope_impl(h, mat, lam, n, dtype, F, beta_n, W, P, tree, flags, nullptr, stream);
+}
+
+r1_status r1_envelope_tangent(r1_handle h, const r1_material* mat, const r1_lamination* lam,
+                              int64_t n, r1_dtype dtype, const void* F, const void* beta_n,
+                              void* W, void* P, void* A, r1_laminate* tree, int32_t* flags,
+                              void* stream) {
+  if (!A && n > 0) return R1_EINVAL;
+  return envelope_impl(h, mat, lam, n, dtype, F, beta_n, W, P, tree, flags, A, stream);
+}
+
+r1_status r1_laminate_tangent(r1_handle h, const r1_material* mat, const r1_lamination* lam,
+                              int64_t n, r1_dtype dtype, const void* F, const void* beta_n,
+                              const void* W, const r1_laminate* tree, void* A, void* stream) {
+  if (!h) return R1_EINVAL;
+  KArgs a;
+  r1_status s = fill_args(h, mat, lam, n, dtype, F, beta_n, &a);
+  if (s) return s;
+  if (n == 0) return R1_OK;
+  if (!F || !beta_n || !W || !tree || !A) return R1_EINVAL;
+  a.W = const_cast<void*>(W);
+  hipError_t e = r1_launch_tangent(a, lam->depth, dtype, tree, A, static_cast<hipStream_t>(stream),
+                                   h->timer.on ? &h->timer : nullptr);
   if (e != hipSuccess) return r1h::fail(h, e, "kernel launch");
   return R1_OK;
 }

@@ -68,6 +68,11 @@ struct KTimer {
 hipError_t r1_launch_envelope(const KArgs& a, int depth, int dtype, int S, int K, hipStream_t st,
                               KTimer* tm);
 size_t r1_outer_res_bytes(int dtype);
+// Tangent moduli A (d^4 x n SoA) by Algorithm 3 on tree[n * R1_TREE_NODES] for the
+// levels a.lv0 (and a.lv1 at depth 2); reads a.F, a.beta_n and a.W (A is NaN
+// where W is not finite or a tree node does not name a laminate of its level).
+hipError_t r1_launch_tangent(const KArgs& a, int depth, int dtype, const r1_laminate* tree, void* A, hipStream_t st,
+                             KTimer* tm);
 
 struct BArgs;
 // Uneven-batch kernel of the given kind (kBPoint, kBOuter, kBFinal) for layout

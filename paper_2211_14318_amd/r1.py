@@ -76,6 +76,10 @@ def _load():
                               vp, vp, vp, vp, vp]
     L.r1_envelope_stress.argtypes = [vp, ctypes.POINTER(Material), ctypes.POINTER(Lamination), i64,
                                      i32, vp, vp, vp, vp, vp, vp, vp]
+    L.r1_envelope_tangent.argtypes = [vp, ctypes.POINTER(Material), ctypes.POINTER(Lamination), i64,
+                                      i32, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.r1_laminate_tangent.argtypes = [vp, ctypes.POINTER(Material), ctypes.POINTER(Lamination), i64,
+                                      i32, vp, vp, vp, vp, vp, vp]
     L.r1_envelope_batched.argtypes = [vp, ctypes.POINTER(Material), ctypes.POINTER(Lamination), i32,
                                       i64, vp, i32, vp, vp, vp, vp, vp, vp, vp]
     L.r1_set_segment_width.argtypes = [vp, i32, i32]
@@ -110,7 +114,7 @@ def _load():
                  "r1_surrogate_loss_grad", "r1_surrogate_save", "r1_surrogate_load"):
         getattr(L, name).restype = i32
     for name in ("r1_autotune", "r1_autotune_inner", "r1_get_inner_segment_width", "r1_timing_enable", "r1_timing_reset", "r1_timing_query", "r1_create", "r1_destroy", "r1_envelope", "r1_envelope_stress",
-                 "r1_envelope_batched", "r1_set_segment_width", "r1_get_segment_width"):
+                 "r1_envelope_tangent", "r1_laminate_tangent", "r1_envelope_batched", "r1_set_segment_width", "r1_get_segment_width"):
         getattr(L, name).restype = i32
     return L
 
@@ -234,8 +238,10 @@ class Handle:
             return R1_F64
         raise TypeError("F must be float32 or float64")
 
-    def envelope(self, mat, spec, F, beta_n, stress=True, tree=False, flags=True, stream=None):
-        """F: (d*d, n) device tensor (SoA), beta_n: (n,).  Returns dict of device tensors."""
+    def envelope(self, mat, spec, F, beta_n, stress=True, tree=False, flags=True, tangent=False,
+                 stream=None):
+        """F: (d*d, n) device tensor (SoA), beta_n: (n,).  Returns dict of device tensors;
+        with tangent=True also A, the (d**4, n) tangent moduli dP_ij/dF_kl."""
         torch = self.torch
         n = F.shape[1]
         d = mat.dim
@@ -247,11 +253,32 @@ class Handle:
         P = torch.empty((d * d, n), dtype=F.dtype, device=dev) if stress else None
         T = torch.empty((n, TREE_NODES, 4), dtype=torch.int32, device=dev) if tree else None
         fl = torch.empty(n, dtype=torch.int32, device=dev) if flags else None
+        if tangent:
+            A = torch.empty((d ** 4, n), dtype=F.dtype, device=dev)
+            self._check(_lib.r1_envelope_tangent(self.h, ctypes.byref(mat), ctypes.byref(spec.c), n, dt,
+                                                 _ptr(F), _ptr(beta_n), _ptr(W), _ptr(P), _ptr(A),
+                                                 _ptr(T), _ptr(fl), self._stream(stream)),
+                        "r1_envelope_tangent")
+            return dict(W=W, P=P, A=A, tree=T, flags=fl)
         self._check(_lib.r1_envelope_stress(self.h, ctypes.byref(mat), ctypes.byref(spec.c), n, dt,
                                             _ptr(F), _ptr(beta_n), _ptr(W), _ptr(P), _ptr(T),
                                             _ptr(fl), self._stream(stream)),
                     "r1_envelope_stress")
         return dict(W=W, P=P, tree=T, flags=fl)
+
+    def laminate_tangent(self, mat, spec, F, beta_n, W, tree, stream=None):
+        """Tangent moduli (d**4, n) of the given (n, 3, 4) int32 trees (Algorithm 3)."""
+        n = F.shape[1]
+        d = mat.dim
+        assert F.shape[0] == d * d and F.is_contiguous() and beta_n.is_contiguous()
+        assert W.shape == (n,) and W.dtype == F.dtype and tree.shape == (n, TREE_NODES, 4)
+        assert tree.dtype == self.torch.int32 and tree.is_contiguous()
+        A = self.torch.empty((d ** 4, n), dtype=F.dtype, device=F.device)
+        self._check(_lib.r1_laminate_tangent(self.h, ctypes.byref(mat), ctypes.byref(spec.c), n,
+                                             self._dtype_code(F), _ptr(F), _ptr(beta_n), _ptr(W),
+                                             _ptr(tree), _ptr(A), self._stream(stream)),
+                    "r1_laminate_tangent")
+        return A
 
     def envelope_into(self, mat, spec, F, beta_n, W, P=None, tree=None, flags=None, stream=None):
         """Same, writing into caller-provided tensors (no allocation)."""

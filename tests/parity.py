@@ -110,3 +110,27 @@ def check_stress(mat, spec, depth, F_soa, beta_n, W_orc, P_orc, trees_orc, P_gpu
             assert g_nodes[:nn] == o_nodes[:nn], (p, g_nodes, o_nodes)
             assert np.max(np.abs(P_gpu[:, p] - P_orc[:, p])) <= PTOL[kind] * scale, (p, P_gpu[:, p], P_orc[:, p])
     return n_exact, n_ties
+
+
+def oracle_envelope_points(mat_dict, dim, levels, F_soa, beta_n, model=0):
+    """Process-pool worker (picklable arguments only): the oracle's envelope, stress and
+    tree at the given points."""
+    mat = orc_material(mat_dict, dim, model)
+    spec = orc_spec(levels)
+    return O.envelope_batch(mat, spec, F_soa, beta_n, want_stress=True, want_tree=True)
+
+
+def oracle_pool_map(mat_dict, dim, levels, F_soa, beta_n, workers):
+    """The oracle at each column of F_soa, one point per task on `workers` fresh
+    interpreters (spawned: the parent may hold a GPU context).  Returns W, P, trees."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    n = F_soa.shape[1]
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        futs = [ex.submit(oracle_envelope_points, mat_dict, dim, levels, F_soa[:, p:p + 1].copy(),
+                          beta_n[p:p + 1].copy()) for p in range(n)]
+        res = [f.result() for f in futs]
+    W = np.concatenate([r[0] for r in res])
+    P = np.concatenate([r[1] for r in res], axis=1)
+    trees = [r[2][0] for r in res]
+    return W, P, trees
