@@ -19,6 +19,7 @@ SOURCES = ["energy.c", "hull.c", "lamination.c", "mlp.c"]
 
 MODEL_NH_DAMAGE = 0
 MODEL_DOUBLEWELL = 1
+MODEL_STVK_DAMAGE = 2
 TREE_NODES = 3
 
 

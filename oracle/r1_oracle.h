@@ -28,6 +28,7 @@ extern "C" {
 
 #define ORC_MODEL_NH_DAMAGE 0   /* neo-Hooke psi0 (eq. 2.3) with (1-D) damage, W of eq. 2.9 */
 #define ORC_MODEL_DOUBLEWELL 1  /* test energy (G11^2-1)^2 + sum_{(i,j)!=(1,1)} (G_ij-delta_ij)^2 */
+#define ORC_MODEL_STVK_DAMAGE 2 /* St. Venant-Kirchhoff psi0 (eq. 2.2) with (1-D) damage, W of eq. 2.9 */
 
 #define ORC_MAX_DEPTH 2
 #define ORC_TREE_NODES 3        /* 2^ORC_MAX_DEPTH - 1 */

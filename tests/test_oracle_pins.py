@@ -83,6 +83,96 @@ def test_hull_reproduces_printed_relaxation_on_rank_one_path(fname, wcol, rccol,
     assert vert[0] == 0 and vert[1] == 1
 
 
+# ---------------------------------------------------------------- St. Venant-Kirchhoff (eq. 2.2)
+
+def stvk(dim, lam=0.5, mu=1.0, D_inf=0.9, D0=0.3):
+    return O.material(dim=dim, model=O.MODEL_STVK_DAMAGE, mu=mu, lam=lam, D_inf=D_inf, D0=D0)
+
+
+def test_stvk_energy_matches_printed_3d_rankd_paths():
+    """Section 6.8, STVK panel, W along diag(s,1,1), diag(s,s,1), diag(s,s,s) (eq. 6.3) with the
+    STVK material of Table 6.3.  One history value, recovered from the printed W(I), fits all
+    60 printed values.  That value is 0.0799, not the table's beta_k = 0.07: (1 - D(0.07)) 0.07
+    does not give the printed W(I), so the table's entry is read as a misprint."""
+    g = load_golden("stvk3d_rankd_paths.txt")
+    mat = stvk(3)
+    i1 = int(np.flatnonzero(g[:, 0] == 1.0)[0])
+    beta_k = recover_beta(mat, g[i1, 1])
+    assert abs(beta_k - 0.0799) < 1e-3
+    err = []
+    for row in g:
+        s = row[0]
+        for col, diag in ((1, [s, 1, 1]), (3, [s, s, 1]), (5, [s, s, s])):
+            err.append(O.energy(mat, np.diag(diag), beta_k) - (row[col] - g[i1, col]))
+    assert len(err) == 60 and np.max(np.abs(err)) < 1e-12, np.max(np.abs(err))
+
+
+def test_stvk_hull_reproduces_printed_relaxation_on_tension_side():
+    """Along the uniaxial (rank-one) path the printed STVK relaxation is the 1D lower hull
+    (Algorithm 1) of the printed W samples for s >= 0.8, through the laminating stretch
+    s = 1.2 .. 1.9.  Below s = 0.8 the printed curve comes from the paper's relaxation on its
+    9-dimensional grid near the grid's edge (at s = 0.1 it lies below the sample W itself),
+    which a hull along this one line does not reproduce; those rows are not compared."""
+    g = load_golden("stvk3d_rankd_paths.txt")
+    w = g[:, 1]
+    n_lam = 0
+    for k in np.flatnonzero(g[:, 0] >= 0.8 - 1e-12):
+        v, _, _, _ = O.hull_at_centre(w, k)
+        assert abs(v - g[k, 2]) < 1e-13, (k, v, g[k, 2])
+        n_lam += g[k, 2] < g[k, 1] - 1e-6
+    assert n_lam >= 5
+
+
+def test_stvk_plane_strain_energy_matches_printed_elastic_branch():
+    """Section 6.6, STVK panel (Table 6.2 STVK material, plane strain).  These curves were
+    drawn inside the relax-then-fix simulation: each path has its own history value, and
+    their loading branches are not eq. 2.9 for any one choice of D0, D_inf and the two
+    histories (a least-squares fit leaves 0.04), so only the elastic stretches are used,
+    where W - W(I) = (1 - D(beta_n)) psi0: the printed values divided by psi0 are one
+    constant per path on s in [0.5, 1.3] (rank-one path) and [0.7, 1.2] (rank-two path),
+    which pins the plane-strain psi0 of eq. 2.2 along both paths.  That constant fixes
+    D(beta_n); the oracle's W with that history must give every value of the stretch."""
+    g = load_golden("stvk2d_biaxial_paths.txt")
+    mat = stvk(2, D_inf=0.99, D0=0.4)
+    undamaged = stvk(2, D_inf=0.0, D0=0.4)
+    i1 = int(np.flatnonzero(g[:, 0] == 1.0)[0])
+    n = 0
+    for col, path, lo, hi in ((1, lambda s: np.diag([s, 1.0]), 0.5, 1.3), (3, lambda s: np.diag([s, s]), 0.7, 1.2)):
+        rows = [k for k in range(len(g)) if lo - 1e-9 <= g[k, 0] <= hi + 1e-9 and k != i1]
+        r = np.array([(g[k, col] - g[i1, col]) / O.energy(undamaged, path(g[k, 0]), 0.0) for k in rows])
+        assert (r.max() - r.min()) < 1e-12 * r.mean(), r
+        beta_n = -mat.D0 * math.log(1.0 - (1.0 - r.mean()) / mat.D_inf)
+        for k in rows:
+            assert O.energy(undamaged, path(g[k, 0]), 0.0) <= beta_n
+            assert abs(O.energy(mat, path(g[k, 0]), beta_n) - (g[k, col] - g[i1, col])) < 1e-13
+            n += 1
+    assert n == 13, n
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_stvk_green_lagrange_form_reflections_and_det_le_0(dim):
+    """Eq. 2.2 written in the invariants equals lambda/2 (tr E)^2 + mu |E|^2 with the
+    Green-Lagrange strain E = (F^T F - I)/2 (plane strain: E33 = 0); it depends on F only
+    through F^T F, so W(RF) = W(F) and P(RF) = R P(F) for every orthogonal R, reflections
+    included, and W is finite where det F <= 0."""
+    lam, mu = 0.7, 1.3
+    mat0 = stvk(dim, lam=lam, mu=mu, D_inf=0.0)
+    mat = stvk(dim, lam=lam, mu=mu)
+    rng = np.random.default_rng(21)
+    R = np.eye(dim)
+    R[0, 0] = -1.0
+    for _ in range(10):
+        F = np.eye(dim) + 0.4 * rng.standard_normal((dim, dim))
+        E = 0.5 * (F.T @ F - np.eye(dim))
+        assert abs(O.energy(mat0, F, 0.0) - (0.5 * lam * np.trace(E) ** 2 + mu * np.sum(E * E))) < 1e-13
+        bn = rng.uniform(0.0, 0.3)
+        assert abs(O.energy(mat, R @ F, bn) - O.energy(mat, F, bn)) < 1e-14
+        assert np.allclose(O.stress0(mat, R @ F, bn), R @ O.stress0(mat, F, bn), rtol=0, atol=1e-13)
+    Fneg = R.copy()
+    assert np.isfinite(O.energy(mat, Fneg, 0.0)) and np.all(np.isfinite(O.stress0(mat, Fneg, 0.0)))
+    assert O.energy(mat, np.zeros((dim, dim)), 0.0) > 0.0
+
+
 # ---------------------------------------------------------------- P3: brute force on tiny grids
 
 def brute_vertices(w):
@@ -221,8 +311,9 @@ def spec_of(levels):
     return O.LaminationSpec([(l["a"], l["b"], l["n_t"], l["tau"]) for l in levels])
 
 
-def test_envelope_below_W_and_monotone_in_depth_and_refinement():
-    mat = O.material(dim=2)
+@pytest.mark.parametrize("model", [O.MODEL_NH_DAMAGE, O.MODEL_STVK_DAMAGE])
+def test_envelope_below_W_and_monotone_in_depth_and_refinement(model):
+    mat = O.material(dim=2, model=model)
     cfg = WL.small_random(2, 16, (4, 4), 33, tau=1.5, depth=2, inner=(4, 2, 17), seed_tag=12)
     lv0, lv1 = cfg["levels"]
     s1 = spec_of([lv1])
@@ -281,14 +372,18 @@ def fd_grad(f, F, h=1e-6):
     return G
 
 
+@pytest.mark.parametrize("model", [O.MODEL_NH_DAMAGE, O.MODEL_STVK_DAMAGE])
 @pytest.mark.parametrize("dim", [2, 3])
-def test_stress0_is_derivative_of_W(dim):
-    """P = dW/dF (eq. 2.12), on both branches of beta = max(beta_k, psi0)."""
-    mat = O.material(dim=dim)
+def test_stress0_is_derivative_of_W(dim, model):
+    """P = dW/dF (eq. 2.12), on both branches of beta = max(beta_k, psi0); St. Venant-Kirchhoff
+    also where det F <= 0 (eq. 2.2 has no barrier)."""
+    mat = O.material(dim=dim, model=model)
     rng = np.random.default_rng(3)
     for k in range(20):
         F = np.eye(dim) + 0.3 * rng.standard_normal((dim, dim))
-        if np.linalg.det(F) < 0.2:
+        if model == O.MODEL_STVK_DAMAGE and k % 5 == 0:
+            F[0] *= -1.0
+        elif np.linalg.det(F) < 0.2:
             continue
         bn = 0.0 if k % 2 else 10.0    # damage branch / elastic-unloading branch
         P = O.stress0(mat, F, bn)
@@ -297,11 +392,12 @@ def test_stress0_is_derivative_of_W(dim):
     assert np.all(O.stress0(mat, np.eye(dim), 0.0) == 0.0)
 
 
+@pytest.mark.parametrize("model", [O.MODEL_NH_DAMAGE, O.MODEL_STVK_DAMAGE])
 @pytest.mark.parametrize("depth", [1, 2])
-def test_laminate_stress_is_derivative_of_envelope(depth):
+def test_laminate_stress_is_derivative_of_envelope(depth, model):
     """Away from switches W^k(F) = xi W^{k-1}(F+) + (1-xi) W^{k-1}(F-) with the grid moving
     with F, so the laminate stress of eq. 5.2 is the exact gradient of W^k."""
-    mat = O.material(dim=2)
+    mat = O.material(dim=2, model=model)
     cfg = WL.small_random(2, 10, (4, 4), 41, tau=1.5, depth=depth, inner=(4, 2, 21), seed_tag=14)
     spec = spec_of(cfg["levels"])
     checked = 0
@@ -328,12 +424,14 @@ def fd_jac(f, F, h=1e-6):
     return J
 
 
+@pytest.mark.parametrize("model", [O.MODEL_NH_DAMAGE, O.MODEL_STVK_DAMAGE])
 @pytest.mark.parametrize("dim", [2, 3])
-def test_tangent0_small_strain_moduli_at_identity(dim):
+def test_tangent0_small_strain_moduli_at_identity(dim, model):
     """At F = I without damage the tangent moduli of Section 2 reduce to the isotropic
-    small-strain moduli  mu (d_ik d_jl + d_il d_jk) + lambda d_ij d_kl."""
+    small-strain moduli  mu (d_ik d_jl + d_il d_jk) + lambda d_ij d_kl (both energies
+    linearise to the same Lame law)."""
     mu, lam = 1.3, 0.7
-    mat = O.material(dim=dim, mu=mu, lam=lam, D_inf=0.0)
+    mat = O.material(dim=dim, model=model, mu=mu, lam=lam, D_inf=0.0)
     A = O.tangent0(mat, np.eye(dim), 0.0)
     ref = np.zeros((dim, dim, dim, dim))
     for i, j, k, l in np.ndindex(ref.shape):
@@ -345,13 +443,15 @@ def test_tangent0_small_strain_moduli_at_identity(dim):
 def test_tangent0_is_derivative_of_stress0(dim):
     """A = dP/dF (Section 2) on the damage-loading and the elastic-unloading branches of
     beta = max(beta_k, psi0), symmetric as a Hessian; the double-well test energy likewise."""
-    for model in (O.MODEL_NH_DAMAGE, O.MODEL_DOUBLEWELL):
+    for model in (O.MODEL_NH_DAMAGE, O.MODEL_DOUBLEWELL, O.MODEL_STVK_DAMAGE):
         mat = O.material(dim=dim, model=model)
         rng = np.random.default_rng(4)
         n = 0
         for k in range(20):
             F = np.eye(dim) + 0.3 * rng.standard_normal((dim, dim))
-            if np.linalg.det(F) < 0.2:
+            if model == O.MODEL_STVK_DAMAGE and k % 5 == 0:
+                F[0] *= -1.0
+            elif np.linalg.det(F) < 0.2:
                 continue
             bn = 0.0 if k % 2 else 10.0
             A = O.tangent0(mat, F, bn)
@@ -363,12 +463,13 @@ def test_tangent0_is_derivative_of_stress0(dim):
     assert np.all(np.isnan(O.tangent0(O.material(dim=dim), -np.eye(dim) if dim == 3 else np.diag([1.0, -1.0]), 0.0)))
 
 
+@pytest.mark.parametrize("model", [O.MODEL_NH_DAMAGE, O.MODEL_STVK_DAMAGE])
 @pytest.mark.parametrize("depth", [1, 2])
-def test_laminate_tangent_is_derivative_of_laminate_stress(depth):
+def test_laminate_tangent_is_derivative_of_laminate_stress(depth, model):
     """Algorithm 3 sums the leaves' tangent moduli with the tree weights.  Where the tree
     stays the same under the finite-difference steps (the grid moves with F), that sum is
     the exact derivative of the laminate stress; it is also what the tree evaluation gives."""
-    mat = O.material(dim=2)
+    mat = O.material(dim=2, model=model)
     cfg = WL.small_random(2, 10, (4, 4), 41, tau=1.5, depth=depth, inner=(4, 2, 21), seed_tag=14)
     spec = spec_of(cfg["levels"])
     nn = 1 if depth == 1 else 3
@@ -398,10 +499,11 @@ def test_laminate_tangent_is_derivative_of_laminate_stress(depth):
     assert checked >= 5 and lam_checked >= 3, (checked, lam_checked)
 
 
-def test_tree_invariants_and_eval():
+@pytest.mark.parametrize("model", [O.MODEL_NH_DAMAGE, O.MODEL_STVK_DAMAGE])
+def test_tree_invariants_and_eval(model):
     """H_M structure (Section 3.1): weights sum to 1, the barycentre is F, rank(F+ - F-) = 1;
     Algorithm 3 on the returned tree reproduces the envelope and its stress."""
-    mat = O.material(dim=2)
+    mat = O.material(dim=2, model=model)
     cfg = WL.small_random(2, 10, (4, 4), 41, tau=1.5, depth=2, inner=(4, 2, 21), seed_tag=15)
     spec = spec_of(cfg["levels"])
     lv0 = cfg["levels"][0]
@@ -425,9 +527,10 @@ def test_tree_invariants_and_eval():
 
 # ---------------------------------------------------------------- depth 2 against brute force
 
-def test_depth2_against_independent_brute_force():
+@pytest.mark.parametrize("model", [O.MODEL_NH_DAMAGE, O.MODEL_STVK_DAMAGE])
+def test_depth2_against_independent_brute_force(model):
     """A tiny depth-2 case recomputed by O(n^2) chord minima over explicitly built lines."""
-    mat = O.material(dim=2)
+    mat = O.material(dim=2, model=model)
     cfg = WL.small_random(2, 4, (2, 2), 9, tau=1.2, depth=2, inner=(2, 2, 7), seed_tag=16)
     spec = spec_of(cfg["levels"])
 
