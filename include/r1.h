@@ -8,9 +8,10 @@
  * rank-one convexification of incremental damage models at finite strains",
  * arXiv 2211.14318.
  *   - W(F): the condensed incremental potential of eq. 2.9 (Section 2) with the
- *     neo-Hooke psi0 of eq. 2.3 (plane strain in 2D), damage D(beta) =
- *     D_inf (1 - exp(-beta/D0)) and beta = max(beta_n, psi0(F)); the constant
- *     -psi(F_k, D_k) of eq. 2.9 is dropped.  W = +inf where det F <= 0.
+ *     neo-Hooke psi0 of eq. 2.3 or the St. Venant-Kirchhoff psi0 of eq. 2.2
+ *     (plane strain in 2D), damage D(beta) = D_inf (1 - exp(-beta/D0)) and
+ *     beta = max(beta_n, psi0(F)); the constant -psi(F_k, D_k) of eq. 2.9 is
+ *     dropped.  Neo-Hooke: W = +inf where det F <= 0.
  *   - W^k(F): successive lamination (eq. 3.3) evaluated along the discrete
  *     rank-one lines of Section 4.1 through F: for each direction R = a (x) b the
  *     line samples W^{k-1}(F + t_i R) are convexified (Algorithm 1) and the hull
@@ -60,9 +61,11 @@ typedef int32_t r1_dtype;
 /* Material models */
 #define R1_NEOHOOKE_DAMAGE 0  /* W of eq. 2.9 with psi0 of eq. 2.3 */
 #define R1_TEST_DOUBLEWELL 1  /* test energy (F11^2-1)^2 + sum_{(i,j)!=(1,1)} (F_ij - delta_ij)^2 */
+#define R1_STVK_DAMAGE 2      /* W of eq. 2.9 with the St. Venant-Kirchhoff psi0 of eq. 2.2
+                                 (defined for every F: no det F constraint, flag R1_PT_DETLE0 unused) */
 
 /* Per-point flags (bit set) */
-#define R1_PT_DETLE0 1        /* det F <= 0: W = +inf, P = NaN */
+#define R1_PT_DETLE0 1        /* neo-Hooke, det F <= 0: W = +inf, P = NaN */
 #define R1_PT_NONFINITE 2     /* F or beta_n not finite: outputs NaN */
 #define R1_PT_FALLBACK 4      /* surrogate inference answered by plain lamination */
 #define R1_PT_ITERCAP 8       /* a hull bridge search hit its iteration cap (result still a valid upper bound) */
@@ -80,7 +83,7 @@ typedef struct r1_handle_s* r1_handle;
 
 typedef struct {
     int32_t dim;      /* 2 (plane strain) or 3 */
-    int32_t model;    /* R1_NEOHOOKE_DAMAGE or R1_TEST_DOUBLEWELL */
+    int32_t model;    /* R1_NEOHOOKE_DAMAGE, R1_STVK_DAMAGE or R1_TEST_DOUBLEWELL */
     double mu;        /* Lame parameters */
     double lambda;
     double D_inf;     /* asymptotic damage, in [0, 1) */

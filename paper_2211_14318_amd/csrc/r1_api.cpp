@@ -39,11 +39,12 @@ r1_status r1h::fail(r1_handle h, hipError_t e, const char* what) {
 r1_status r1h::check_material(const r1_material* m) {
   if (!m) return R1_EINVAL;
   if (m->dim != 2 && m->dim != 3) return R1_EINVAL;
-  if (m->model != R1_NEOHOOKE_DAMAGE && m->model != R1_TEST_DOUBLEWELL) return R1_EINVAL;
+  if (m->model != R1_NEOHOOKE_DAMAGE && m->model != R1_TEST_DOUBLEWELL && m->model != R1_STVK_DAMAGE)
+    return R1_EINVAL;
   if (!std::isfinite(m->mu) || !std::isfinite(m->lambda) || !std::isfinite(m->D_inf) ||
       !std::isfinite(m->D0))
     return R1_EINVAL;
-  if (m->model == R1_NEOHOOKE_DAMAGE && (!(m->D0 > 0.0) || m->D_inf < 0.0 || m->D_inf >= 1.0))
+  if (m->model != R1_TEST_DOUBLEWELL && (!(m->D0 > 0.0) || m->D_inf < 0.0 || m->D_inf >= 1.0))
     return R1_EINVAL;
   return R1_OK;
 }

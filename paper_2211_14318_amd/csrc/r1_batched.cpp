@@ -415,7 +415,7 @@ extern "C" r1_status r1_envelope_batched(r1_handle h, const r1_material* mat,
           b.counter = reinterpret_cast<int*>(base + off_cnt) + 2 * c + kind;
           L.lds = kind == kBOuter ? lds[c] : 0;
           int per_cu = 0;
-          e = r1_occupancy_batched(dtype, dim, c, kind, L.lds, &per_cu);
+          e = r1_occupancy_batched(dtype, dim, mat->model, c, kind, L.lds, &per_cu);
           if (e != hipSuccess || per_cu < 1) {
             free_plan(pl);
             return e != hipSuccess ? r1h::fail(h, e, "occupancy") : R1_EUNSUPPORTED;
@@ -442,7 +442,7 @@ extern "C" r1_status r1_envelope_batched(r1_handle h, const r1_material* mat,
       int zero_n = 2 * NV;                     // every queue head, once, by a fill kernel
       for (size_t k = 0; k < launches.size() && le == hipSuccess; ++k) {
         const Launch& L = launches[k];
-        le = r1_launch_batched(L.b, dtype, dim, L.var, L.kind, L.grid, L.lds, reinterpret_cast<int*>(base + off_cnt),
+        le = r1_launch_batched(L.b, dtype, dim, L.b.base.mat.model, L.var, L.kind, L.grid, L.lds, reinterpret_cast<int*>(base + off_cnt),
                                zero_n, h->capture_stream);
         zero_n = 0;
       }

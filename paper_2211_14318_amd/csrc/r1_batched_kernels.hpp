@@ -69,7 +69,7 @@ __device__ __forceinline__ int next_item(int* counter, int* s_item) {
 
 // items: {kind, first, count, 0} -- kind 0: depth-1 points order[first ..
 // first + count), full result; kind 2: depth-2 points, W^1 into w1f.
-template <typename T, int D, int S, int K>
+template <typename T, int D, int S, int K, int M>
 __global__ __launch_bounds__(256, (sizeof(T) == 4 && D == 2) ? 2 : 1) void k_bpoint(BArgs b) {
   __shared__ int s_item;
   for (;;) {
@@ -89,14 +89,14 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && D == 2) ? 2 : 1) void k_bpo
         x.flags = nullptr;
         x.want_stress = 0;
       }
-      point_depth1<T, D, S, K>(x, p, centre ? e.lv1 : e.lv0);
+      point_depth1<T, D, S, K, M>(x, p, centre ? e.lv1 : e.lv0);
     }
   }
 }
 
 // items: {1, point, outer direction, 0}.
-template <typename T, int D, int S, int K>
-__global__ __launch_bounds__(256, (sizeof(T) == 4 && D == 2) ? (K <= 16 ? 3 : 2) : 1) void k_bouter(BArgs b) {
+template <typename T, int D, int S, int K, int M>
+__global__ __launch_bounds__(256, (sizeof(T) == 4 && D == 2) ? (K <= 16 && M == kFamNH ? 3 : 2) : 1) void k_bouter(BArgs b) {
   extern __shared__ char smem_raw[];
   __shared__ int s_item;
   for (;;) {
@@ -111,24 +111,24 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && D == 2) ? (K <= 16 ? 3 : 2)
     if (!(w1f < inf_v<T>())) {                   // det F <= 0 or non-finite input: block-uniform
       if (threadIdx.x == 0) *res = OuterRes<T>{w1f, 0, 0, 0};
     } else {
-      outer_line<T, D, S, K>(b.base, p, mo, e.lv0, e.lv1, w1f, false, res, smem_raw);
+      outer_line<T, D, S, K, M>(b.base, p, mo, e.lv0, e.lv1, w1f, false, res, smem_raw);
     }
   }
 }
 
 // One wavefront per depth-2 point order[0 .. n_items).
-template <typename T, int D, int S, int K>
+template <typename T, int D, int S, int K, int M>
 __global__ __launch_bounds__(256) void k_bfinal(BArgs b) {
   const int64_t i = int64_t(blockIdx.x) * (blockDim.x / kWave) + uni(int(threadIdx.x / kWave));
   if (i >= b.n_items) return;                    // wave-uniform
   const int64_t p = uni(int64_t(b.order[i]));
   const BEntry& e = b.table[uni(b.lam_idx[p])];
-  finalize_point<T, D, S, K>(b.base, p, e.lv0, e.lv1, static_cast<const OuterRes<T>*>(b.outer) + b.pbase[p]);
+  finalize_point<T, D, S, K, M>(b.base, p, e.lv0, e.lv1, static_cast<const OuterRes<T>*>(b.outer) + b.pbase[p]);
 }
 
 // Zeroes zero_n ints at zero_p (when zero_n > 0), then launches the kernel of
 // the given kind for layout variant var on grid blocks.
-template <typename T, int D>
+template <typename T, int D, int M>
 hipError_t launch_batched_TD(const BArgs& b, int var, int kind, int grid, size_t lds, int* zero_p,
                              int zero_n, hipStream_t st) {
   if (zero_n > 0)
@@ -138,11 +138,11 @@ hipError_t launch_batched_TD(const BArgs& b, int var, int kind, int grid, size_t
 #define X(V, S, K)                                                                                   \
   case V:                                                                                            \
     if (kind == kBPoint)                                                                             \
-      hipLaunchKernelGGL((k_bpoint<T, D, S, K>), dim3(unsigned(grid)), dim3(256), 0, st, b);          \
+      hipLaunchKernelGGL((k_bpoint<T, D, S, K, M>), dim3(unsigned(grid)), dim3(256), 0, st, b);          \
     else if (kind == kBOuter)                                                                        \
-      hipLaunchKernelGGL((k_bouter<T, D, S, K>), dim3(unsigned(grid)), dim3(256), lds, st, b);        \
+      hipLaunchKernelGGL((k_bouter<T, D, S, K, M>), dim3(unsigned(grid)), dim3(256), lds, st, b);        \
     else                                                                                             \
-      hipLaunchKernelGGL((k_bfinal<T, D, S, K>), dim3(unsigned(grid)), dim3(256), 0, st, b);          \
+      hipLaunchKernelGGL((k_bfinal<T, D, S, K, M>), dim3(unsigned(grid)), dim3(256), 0, st, b);          \
     break;
     R1_BATCH_VARIANTS(X)
 #undef X
@@ -152,14 +152,14 @@ hipError_t launch_batched_TD(const BArgs& b, int var, int kind, int grid, size_t
 }
 
 // Resident blocks per CU of a persistent kernel (kind kBPoint or kBOuter).
-template <typename T, int D>
+template <typename T, int D, int M>
 hipError_t occupancy_batched_TD(int var, int kind, size_t lds, int* blocks_per_cu) {
   switch (var) {
 #define X(V, S, K)                                                                                    \
   case V:                                                                                             \
     return kind == kBOuter                                                                            \
-               ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_bouter<T, D, S, K>, 256, lds) \
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_bpoint<T, D, S, K>, 256, 0);
+               ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_bouter<T, D, S, K, M>, 256, lds) \
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_bpoint<T, D, S, K, M>, 256, 0);
     R1_BATCH_VARIANTS(X)
 #undef X
     default: return hipErrorInvalidValue;

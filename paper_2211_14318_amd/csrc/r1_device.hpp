@@ -43,7 +43,7 @@ __device__ __forceinline__ float expk(float x) { return __builtin_amdgcn_exp2f(x
 __device__ __forceinline__ double expk(double x) { return exp(x); }
 
 struct Material {
-  int dim, model;        // model: 0 neo-Hooke damage, 1 double-well test energy
+  int dim, model;        // model: 0 neo-Hooke damage, 1 double-well test energy, 2 St. Venant-Kirchhoff damage
   double mu, lambda, D_inf, D0;
 };
 
@@ -54,6 +54,13 @@ struct Level {           // one lamination level on the device
   double tau;
   double ab2;            // |a|^2 |b|^2 when equal for every direction (to rounding), else NaN
 };
+
+// Model families, a compile-time parameter M of the sampling code: kFamNH is the
+// neo-Hooke damage model with the double-well test energy (told apart at run
+// time by Point::model), kFamSTVK the St. Venant-Kirchhoff damage model.  Each
+// family gets its own kernels, so neither pays registers for the other's paths.
+constexpr int kFamNH = 0;
+constexpr int kFamSTVK = 2;
 
 // Per-point constants of W (eq. 2.9 written as a function of psi0).  With
 // D_n = D(beta_n):
@@ -69,22 +76,27 @@ struct Level {           // one lamination level on the device
 //   W = (E1/k) u + ((D_n - D_inf)/k) v + B - C exp_k(v),   v = min(u, k beta_n).
 // psi0 = mu/2 (|G|^2 - d) - mu L + lambda/2 L^2 (L = ln J; FP32 takes log2, so
 // its L coefficients carry ln2 factors); the polynomial part k mu/2 (|G|^2 - d)
-// comes pre-scaled in the line coefficients (line_scale).
+// comes pre-scaled in the line coefficients (line_scale).  St. Venant-Kirchhoff
+// psi0 is a quartic along a rank-one line, pre-scaled by k as a whole.
 template <typename T>
 struct Point {
   T klk, kmk;            // k lambda/2 (ln2^2), k mu (ln2)
   T ub, E1k, Aqk, B, negC;
-  double kq;             // k mu/2, applied to the line polynomial in double
+  double kq;             // scale of the line polynomial, applied in double (line_scale)
+  double lam, mu;        // Lame parameters (St. Venant-Kirchhoff line coefficients)
   int model;
 };
 
-// k mu/2: the factor of the neo-Hooke line polynomial in the sampling form.
-template <typename T>
+// Factor of the line polynomial in the sampling form: k mu/2 for the neo-Hooke
+// |G|^2 part, k for the St. Venant-Kirchhoff quartic.
+template <typename T, int M = kFamNH>
 __device__ __forceinline__ double line_scale(const Material& m) {
-  return (sizeof(T) == 4 ? -1.4426950408889634 : -1.0) / m.D0 * 0.5 * m.mu;
+  const double k = (sizeof(T) == 4 ? -1.4426950408889634 : -1.0) / m.D0;
+  if constexpr (M == kFamSTVK) return k;
+  return k * 0.5 * m.mu;
 }
 
-template <typename T>
+template <typename T, int M = kFamNH>
 __device__ __forceinline__ Point<T> make_point(const Material& m, double bn) {
   Point<T> q;
   const bool f32 = sizeof(T) == 4;
@@ -99,16 +111,25 @@ __device__ __forceinline__ Point<T> make_point(const Material& m, double bn) {
   q.Aqk = T((Dn - m.D_inf) / k);
   q.negC = T(-m.D_inf * m.D0);
   q.B = T(m.D_inf * e * (bn + m.D0));
-  q.kq = line_scale<T>(m);
+  q.kq = line_scale<T, M>(m);
+  q.lam = m.lambda;
+  q.mu = m.mu;
   q.model = m.model;
   return q;
+}
+
+// Same, for code whose model is known at run time only.
+template <typename T>
+__device__ __forceinline__ Point<T> make_point_any(const Material& m, double bn) {
+  return m.model == 2 ? make_point<T, kFamSTVK>(m, bn) : make_point<T, kFamNH>(m, bn);
 }
 
 // Coefficients of W along G + t a(x)b.  det is affine along rank-one lines:
 // det(G + t a(x)b) = det G + t a.cof(G) b; |G + t a(x)b|^2 = |G|^2 + 2t a.Gb + t^2 |a|^2|b|^2.
 // For the double-well test energy: g(t) = G11 + t a1 b1 and the quadratic rest.
+// St. Venant-Kirchhoff: k psi0(t) = c0 + c1 t + c2 t^2 + c3 t^3 + c4 t^4 (J0, J1 unused).
 template <typename T>
-struct Line { T J0, J1, c0, c1, c2; };
+struct Line { T J0, J1, c0, c1, c2, c3, c4; };
 
 template <int D>
 __device__ __forceinline__ void cofactor(const double* G, double* cof) {
@@ -133,10 +154,76 @@ __device__ __forceinline__ double det_of(const double* G, const double* cof) {
   return s;
 }
 
+// St. Venant-Kirchhoff (eq. 2.2) along G + t a(x)b, from the Green-Lagrange strain
+// E(t) = E0 + t E1 + t^2 E2 with E0 = (G^T G - I)/2, E1 = sym(G^T a (x) b) and
+// E2 = |a|^2 b (x) b / 2 (plane strain: the in-plane block, E33 = 0):
+// psi0 = lambda/2 (tr E)^2 + mu E:E.  With e1 = a.Gb and e2 = |a|^2 |b|^2 / 2
+// (= tr E1, tr E2; E1:E2 = e1 e2, E2:E2 = e2^2):
+//   p0 = lambda/2 e0^2 + mu E0:E0,               e0 = tr E0
+//   p1 = lambda e0 e1 + 2 mu a.G E0 b
+//   p2 = lambda/2 (e1^2 + 2 e0 e2) + mu (|G^T a|^2 |b|^2 / 2 + e1^2 / 2 + |a|^2 b.E0 b)
+//   p3 = (lambda + 2 mu) e1 e2,   p4 = (lambda/2 + mu) e2^2.
+// Coefficients are formed in double and scaled by k.
 template <typename T, int D>
-__device__ __forceinline__ Line<T> line_setup(int model, double kq, const double* G, const double* cof,
-                                              const double* a, const double* b) {
+__device__ __forceinline__ Line<T> stvk_line(double lam, double mu, double k, const double* G, const double* a,
+                                             const double* b) {
+  double E0[D * D], e0 = 0.0, ee = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      double c = 0.0;
+#pragma unroll
+      for (int r = 0; r < D; ++r) c += G[r * D + i] * G[r * D + j];
+      E0[i * D + j] = 0.5 * (c - (i == j ? 1.0 : 0.0));
+    }
+#pragma unroll
+  for (int i = 0; i < D; ++i) e0 += E0[i * D + i];
+#pragma unroll
+  for (int i = 0; i < D * D; ++i) ee += E0[i] * E0[i];
+  double gta[D], e0b[D], aa = 0.0, bb = 0.0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    double u = 0.0, v = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      u += G[i * D + j] * a[i];
+      v += E0[j * D + i] * b[i];
+    }
+    gta[j] = u;
+    e0b[j] = v;
+    aa += a[j] * a[j];
+    bb += b[j] * b[j];
+  }
+  double e1 = 0.0, ge0b = 0.0, beb = 0.0, gta2 = 0.0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    e1 += gta[j] * b[j];
+    ge0b += gta[j] * e0b[j];
+    beb += b[j] * e0b[j];
+    gta2 += gta[j] * gta[j];
+  }
+  const double e2 = 0.5 * aa * bb;
   Line<T> L;
+  L.J0 = T(0);
+  L.J1 = T(0);
+  L.c0 = T(k * (0.5 * lam * e0 * e0 + mu * ee));
+  L.c1 = T(k * (lam * e0 * e1 + 2.0 * mu * ge0b));
+  L.c2 = T(k * (0.5 * lam * (e1 * e1 + 2.0 * e0 * e2) + mu * (0.5 * gta2 * bb + 0.5 * e1 * e1 + aa * beb)));
+  L.c3 = T(k * ((lam + 2.0 * mu) * e1 * e2));
+  L.c4 = T(k * ((0.5 * lam + mu) * e2 * e2));
+  return L;
+}
+
+template <typename T, int D, int M = kFamNH>
+__device__ __forceinline__ Line<T> line_setup(const Point<T>& q, const double* G, const double* cof,
+                                              const double* a, const double* b) {
+  if constexpr (M == kFamSTVK) return stvk_line<T, D>(q.lam, q.mu, q.kq, G, a, b);
+  const int model = q.model;
+  const double kq = q.kq;
+  Line<T> L;
+  L.c3 = T(0);
+  L.c4 = T(0);
   if (model == 0) {
     double J1 = 0.0, gab = 0.0, n2 = 0.0, aa = 0.0, bb = 0.0;
 #pragma unroll
@@ -199,6 +286,15 @@ __device__ __forceinline__ T w_sample_base(T t, T base, const Line<T>& L, const 
   return fma(q.negC, expk(v), fma(q.E1k, u, fma(q.Aqk, v, q.B)));
 }
 
+// St. Venant-Kirchhoff sample: the quartic k psi0(t), then the damage part of
+// w_sample (7 VALU + 1 transcendental).
+template <typename T>
+__device__ __forceinline__ T w_sample_stvk(T t, const Line<T>& L, const Point<T>& q) {
+  T u = fma(t, fma(t, fma(t, fma(t, L.c4, L.c3), L.c2), L.c1), L.c0);
+  T v = fmin(u, q.ub);
+  return fma(q.negC, expk(v), fma(q.E1k, u, fma(q.Aqk, v, q.B)));
+}
+
 template <typename T>
 __device__ __forceinline__ T w_sample_doublewell(T t, const Line<T>& L) {
   T g = fma(t, L.J1, L.J0);
@@ -207,11 +303,18 @@ __device__ __forceinline__ T w_sample_doublewell(T t, const Line<T>& L) {
 }
 
 // W at a point (the centre sample of every line through it), in the path's precision.
-template <typename T, int D>
+template <typename T, int D, int M = kFamNH>
 __device__ __forceinline__ T w_point(const Point<T>& q, const double* G, const double* cof) {
   double a0[3] = {0, 0, 0};
-  Line<T> L = line_setup<T, D>(q.model, q.kq, G, cof, a0, a0);
+  Line<T> L = line_setup<T, D, M>(q, G, cof, a0, a0);
+  if constexpr (M == kFamSTVK) return w_sample_stvk<T>(T(0), L, q);
   return q.model == 0 ? w_sample<T>(T(0), L, q) : w_sample_doublewell<T>(T(0), L);
+}
+
+// Same, for code whose model is known at run time only.
+template <typename T, int D>
+__device__ __forceinline__ T w_point_any(const Point<T>& q, const double* G, const double* cof) {
+  return q.model == 2 ? w_point<T, D, kFamSTVK>(q, G, cof) : w_point<T, D, kFamNH>(q, G, cof);
 }
 
 // ---- segment reductions ------------------------------------------------------
@@ -590,11 +693,15 @@ __device__ __forceinline__ PointGeom<D> make_geom(const double* G) {
   return g;
 }
 
-template <typename T, int D>
-__device__ __forceinline__ Line<T> line_of(int model, double kq, const PointGeom<D>& g,
-                                           const double* a, const double* b) {
-  if (model != 0) return line_setup<T, D>(model, kq, g.G, g.cof, a, b);
+template <typename T, int D, int M = kFamNH>
+__device__ __forceinline__ Line<T> line_of(const Point<T>& q, const PointGeom<D>& g, const double* a,
+                                           const double* b) {
+  if constexpr (M == kFamSTVK) return line_setup<T, D, M>(q, g.G, g.cof, a, b);
+  if (q.model != 0) return line_setup<T, D, M>(q, g.G, g.cof, a, b);
+  const double kq = q.kq;
   Line<T> L;
+  L.c3 = T(0);
+  L.c4 = T(0);
   double J1 = 0.0, gab = 0.0, aa = 0.0, bb = 0.0;
 #pragma unroll
   for (int i = 0; i < D; ++i) {
@@ -648,7 +755,7 @@ __device__ __forceinline__ bool near_tie(const Env<T>& e) {
 // lines needing a bridge search share wavefronts; ties in the minimum go to the
 // smaller direction index whatever the visiting order.  Every lane of the wave
 // must call it.
-template <typename T, int S, int K, typename LineFn>
+template <typename T, int S, int K, int M = kFamNH, typename LineFn>
 __device__ Env<T> envelope_lines(const Point<T>& q, T wc, int n_dir, const Layout<T, S, K>& lay,
                                  LineFn line_fn, T* warm = nullptr, T c2u = T(__builtin_nan("")),
                                  int* order = nullptr) {
@@ -659,7 +766,7 @@ __device__ Env<T> envelope_lines(const Point<T>& q, T wc, int n_dir, const Layou
   T wci[H];
 #pragma unroll
   for (int h = 0; h < H; ++h) wci[h] = wc * lay.inv_m[h];
-  const bool shared = q.model == 0 && c2u == c2u;
+  const bool shared = M == kFamNH && q.model == 0 && c2u == c2u;
   T base[H];
   if (shared) {
     const T c0 = line_fn(0).c0;
@@ -690,7 +797,13 @@ __device__ Env<T> envelope_lines(const Point<T>& q, T wc, int n_dir, const Layou
     const int dir = order ? order[act ? m0 + seg : n_dir - 1] : (act ? m0 + seg : n_dir - 1);
     Line<T> L = line_fn(dir);
     T w[K];
-    if (shared) {
+    if constexpr (M == kFamSTVK) {
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        w[h] = w_sample_stvk<T>(-lay.t[h], L, q);
+        w[H + h] = w_sample_stvk<T>(lay.t[h], L, q);
+      }
+    } else if (shared) {
 #pragma unroll
       for (int h = 0; h < H; ++h) {
         w[h] = w_sample_base<T>(-lay.t[h], base[h], L, q);
@@ -744,15 +857,15 @@ __device__ Env<T> envelope_lines(const Point<T>& q, T wc, int n_dir, const Layou
 }
 
 // One lamination level at point G with the lines set up from G's geometry.
-template <typename T, int D, int S, int K>
+template <typename T, int D, int S, int K, int M = kFamNH>
 __device__ Env<T> envelope_at(const Point<T>& q, const double* G, T wc, const Level& lv,
                               const Layout<T, S, K>& lay) {
   PointGeom<D> g = make_geom<D>(G);
-  return envelope_lines<T, S, K>(q, wc, lv.n_dir, lay, [&](int dd) {
+  return envelope_lines<T, S, K, M>(q, wc, lv.n_dir, lay, [&](int dd) {
     double a[D], b[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) { a[i] = lv.a[dd * D + i]; b[i] = lv.b[dd * D + i]; }
-    return line_of<T, D>(q.model, q.kq, g, a, b);
+    return line_of<T, D, M>(q, g, a, b);
   }, nullptr, T(q.kq * lv.ab2));
 }
 
@@ -814,10 +927,56 @@ __device__ __forceinline__ void inner_line_coef(int model, double kq, const doub
   }
 }
 
-// P0 = dW/dF = (1 - D(max(beta_n, psi0))) (mu G + (lambda ln J - mu) G^{-T}) in double
-// (eq. 2.12); the double-well test energy has its own gradient.
+// St. Venant-Kirchhoff: psi0 = lambda/2 (tr E)^2 + mu E:E with E = (G^T G - I)/2
+// (eq. 2.2; plane strain: in-plane block, E33 = 0), dpsi0/dG = G (lambda tr E I + 2 mu E).
 template <int D>
+__device__ __forceinline__ double stvk_strain(const double* G, double* E) {
+  double tr = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      double c = 0.0;
+#pragma unroll
+      for (int r = 0; r < D; ++r) c += G[r * D + i] * G[r * D + j];
+      E[i * D + j] = 0.5 * (c - (i == j ? 1.0 : 0.0));
+    }
+#pragma unroll
+  for (int i = 0; i < D; ++i) tr += E[i * D + i];
+  return tr;
+}
+
+template <int D>
+__device__ __forceinline__ double stvk_psi_stress(const Material& m, const double* G, double* S) {
+  double E[D * D];
+  double tr = stvk_strain<D>(G, E), ee = 0.0;
+#pragma unroll
+  for (int i = 0; i < D * D; ++i) ee += E[i] * E[i];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      double ge = 0.0;
+#pragma unroll
+      for (int r = 0; r < D; ++r) ge += G[i * D + r] * E[r * D + j];
+      S[i * D + j] = m.lambda * tr * G[i * D + j] + 2.0 * m.mu * ge;
+    }
+  return 0.5 * m.lambda * tr * tr + m.mu * ee;
+}
+
+// P0 = dW/dF = (1 - D(max(beta_n, psi0))) (mu G + (lambda ln J - mu) G^{-T}) in double
+// (eq. 2.12) for neo-Hooke, (1 - D(max(beta_n, psi0))) dpsi0/dG for St. Venant-Kirchhoff;
+// the double-well test energy has its own gradient.
+template <int D, int M = kFamNH>
 __device__ __forceinline__ void stress0(const Material& m, double bn, const double* G, double* P) {
+  if constexpr (M == kFamSTVK) {
+    double S[D * D];
+    double psi = stvk_psi_stress<D>(m, G, S);
+    double g = 1.0 - m.D_inf * (1.0 - exp(-(psi > bn ? psi : bn) / m.D0));
+#pragma unroll
+    for (int i = 0; i < D * D; ++i) P[i] = g * S[i];
+    return;
+  }
   if (m.model != 0) {
 #pragma unroll
     for (int i = 0; i < D; ++i)
@@ -845,6 +1004,15 @@ __device__ __forceinline__ void stress0(const Material& m, double bn, const doub
   double f = (m.lambda * lnJ - m.mu) / J;
 #pragma unroll
   for (int i = 0; i < D * D; ++i) P[i] = g * (m.mu * G[i] + f * cof[i]);
+}
+
+// stress0 for code whose model is known at run time only.
+template <int D>
+__device__ __forceinline__ void stress0_any(const Material& m, double bn, const double* G, double* P) {
+  if (m.model == 2)
+    stress0<D, kFamSTVK>(m, bn, G, P);
+  else
+    stress0<D, kFamNH>(m, bn, G, P);
 }
 
 }  // namespace r1d

@@ -54,20 +54,20 @@ __device__ __forceinline__ double t_of(const Level& lv, int m) {   // t at offse
 }
 
 // Inner envelope at G and its laminate stress (P^1 = xi P0(G+) + (1-xi) P0(G-)).
-template <typename T, int D, int S, int K>
+template <typename T, int D, int S, int K, int M>
 __device__ Env<T> envelope_with_stress(const KArgs& a, const Level& lv, const Layout<T, S, K>& lay,
                                        double bn, const double* G, double* P) {
-  Point<T> q = make_point<T>(a.mat, bn);
+  Point<T> q = make_point<T, M>(a.mat, bn);
   double cof[D * D];
   cofactor<D>(G, cof);
-  T wc = w_point<T, D>(q, G, cof);
+  T wc = w_point<T, D, M>(q, G, cof);
   Env<T> e = {wc, 0, 0, 0, 0, inf_v<T>()};
-  if (wc < inf_v<T>()) e = envelope_at<T, D, S, K>(q, G, wc, lv, lay);
+  if (wc < inf_v<T>()) e = envelope_at<T, D, S, K, M>(q, G, wc, lv, lay);
   double Gm[D * D], Gp[D * D], Pm[D * D], Pp[D * D];
   line_point<D>(G, lv, e.dir, -t_of(lv, e.mp), Gm);
   line_point<D>(G, lv, e.dir, t_of(lv, e.mq), Gp);
-  stress0<D>(a.mat, bn, Gm, Pm);
-  stress0<D>(a.mat, bn, Gp, Pp);
+  stress0<D, M>(a.mat, bn, Gm, Pm);
+  stress0<D, M>(a.mat, bn, Gp, Pp);
   double xi = (e.mp + e.mq) ? double(e.mp) / double(e.mp + e.mq) : 1.0;
 #pragma unroll
   for (int k = 0; k < D * D; ++k) P[k] = xi * Pp[k] + (1.0 - xi) * Pm[k];
@@ -89,20 +89,20 @@ __device__ __forceinline__ void write_bad_point(const KArgs& a, int64_t p, bool 
 
 // One-level envelope of point p on level lv, with stress, tree and flags as
 // requested by a (wave-level: every lane of the wave calls it).
-template <typename T, int D, int S, int K>
+template <typename T, int D, int S, int K, int M>
 __device__ __forceinline__ void point_depth1(const KArgs& a, int64_t p, const Level& lv) {
   double G[D * D], bn;
   bool fin = load_point<T, D>(a, p, G, bn);
   Layout<T, S, K> lay = make_layout<T, S, K>(lv.n_t, lv.tau);
-  Point<T> q = make_point<T>(a.mat, bn);
+  Point<T> q = make_point<T, M>(a.mat, bn);
   double cof[D * D];
   cofactor<D>(G, cof);
-  T wc = w_point<T, D>(q, G, cof);
+  T wc = w_point<T, D, M>(q, G, cof);
   if (!fin || !(wc < inf_v<T>())) {
     if (lane_id() == 0) write_bad_point<T, D>(a, p, !fin, a.want_stress);
     return;
   }
-  Env<T> e = envelope_at<T, D, S, K>(q, G, wc, lv, lay);
+  Env<T> e = envelope_at<T, D, S, K, M>(q, G, wc, lv, lay);
   if (lane_id() == 0) {
     static_cast<T*>(a.W)[p] = e.h;
     const int c = (lv.n_t - 1) / 2;
@@ -110,8 +110,8 @@ __device__ __forceinline__ void point_depth1(const KArgs& a, int64_t p, const Le
       double Gm[D * D], Gp[D * D], Pm[D * D], Pp[D * D];
       line_point<D>(G, lv, e.dir, -t_of(lv, e.mp), Gm);
       line_point<D>(G, lv, e.dir, t_of(lv, e.mq), Gp);
-      stress0<D>(a.mat, bn, Gm, Pm);
-      stress0<D>(a.mat, bn, Gp, Pp);
+      stress0<D, M>(a.mat, bn, Gm, Pm);
+      stress0<D, M>(a.mat, bn, Gp, Pp);
       double xi = (e.mp + e.mq) ? double(e.mp) / double(e.mp + e.mq) : 1.0;
 #pragma unroll
       for (int k = 0; k < D * D; ++k)
@@ -126,11 +126,11 @@ __device__ __forceinline__ void point_depth1(const KArgs& a, int64_t p, const Le
   }
 }
 
-template <typename T, int D, int S, int K>
+template <typename T, int D, int S, int K, int M>
 __global__ __launch_bounds__(256) void k_depth1(KArgs a) {
   const int64_t p = int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
   if (p >= a.n) return;                       // wave-uniform
-  point_depth1<T, D, S, K>(a, p, a.lv0);
+  point_depth1<T, D, S, K, M>(a, p, a.lv0);
 }
 
 // Outer hull of an LDS-resident line (wave-wide, S = 64): wl[m-1] / wr[m-1] are
@@ -213,11 +213,13 @@ __host__ __device__ inline size_t outer_lds_bytes(const Level& lo, const Level& 
 // outer hull at the centre.  w1f = W^1(F) is the centre sample; when
 // compute_centre is set it is computed here (by wave 0) instead.  Thread 0
 // writes the result to *out.  Returns the centre value used.
-template <typename T, int D, int S, int K>
+template <typename T, int D, int S, int K, int M>
 __device__ __forceinline__ T outer_line(const KArgs& a, int64_t p, int mo, const Level& lo, const Level& li, T w1f,
                         bool compute_centre, OuterRes<T>* out, char* smem_raw) {
   const int co = (lo.n_t - 1) / 2;
-  const bool tab = li.n_dir <= kMaxTabDirs;
+  // tabulated inner lines: coefficients affine in the outer t (neo-Hooke, double
+  // well); St. Venant-Kirchhoff's quartic sets each inner line up from G(t)
+  const bool tab = M != kFamSTVK && li.n_dir <= kMaxTabDirs;
   T* coef = reinterpret_cast<T*>(smem_raw);                 // 5 * n_dir_i (when tabulated)
   T* warm = coef + (tab ? 5 * li.n_dir : 0);                // kOuterWaves * n_dir_i (when tabulated)
   T* wl = warm + (tab ? kOuterWaves * li.n_dir : 0);        // outer samples at -m
@@ -244,16 +246,16 @@ __device__ __forceinline__ T outer_line(const KArgs& a, int64_t p, int mo, const
   }
   __syncthreads();
   Layout<T, S, K> lay = make_layout<T, S, K>(li.n_t, li.tau);
-  Point<T> q = make_point<T>(a.mat, bn);
+  Point<T> q = make_point<T, M>(a.mat, bn);
   const int wave = threadIdx.x / kWave, nwave = blockDim.x / kWave;
   int capped = 0;
   if (compute_centre && wave == 0) {
     double cof[D * D];
     cofactor<D>(F, cof);
-    T wc = w_point<T, D>(q, F, cof);
+    T wc = w_point<T, D, M>(q, F, cof);
     T v = wc;
     if (wc < inf_v<T>()) {
-      Env<T> e = envelope_at<T, D, S, K>(q, F, wc, li, lay);
+      Env<T> e = envelope_at<T, D, S, K, M>(q, F, wc, li, lay);
       v = e.h;
       capped |= e.capped;
     }
@@ -305,10 +307,10 @@ __device__ __forceinline__ T outer_line(const KArgs& a, int64_t p, int mo, const
     } else {
       double cof[D * D];
       cofactor<D>(G, cof);
-      T wc = w_point<T, D>(q, G, cof);
+      T wc = w_point<T, D, M>(q, G, cof);
       v = wc;
       if (wc < inf_v<T>()) {
-        Env<T> e = envelope_at<T, D, S, K>(q, G, wc, li, lay);
+        Env<T> e = envelope_at<T, D, S, K, M>(q, G, wc, li, lay);
         v = e.h;
         capped |= e.capped;
       }
@@ -326,7 +328,7 @@ __device__ __forceinline__ T outer_line(const KArgs& a, int64_t p, int mo, const
   return cv;
 }
 
-template <typename T, int D, int S, int K>
+template <typename T, int D, int S, int K, int M>
 __global__ __launch_bounds__(256, (sizeof(T) == 4 && D == 2 && K <= 16) ? 3 : 1) void k_outer(KArgs a) {
   extern __shared__ char smem_raw[];
   const int n_dir_o = a.lv0.n_dir;
@@ -338,22 +340,22 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && D == 2 && K <= 16) ? 3 : 1)
     if (threadIdx.x == 0) *out = OuterRes<T>{w1f, 0, 0, 0};
     return;
   }
-  outer_line<T, D, S, K>(a, p, mo, a.lv0, a.lv1, w1f, false, out, smem_raw);
+  outer_line<T, D, S, K, M>(a, p, mo, a.lv0, a.lv1, w1f, false, out, smem_raw);
 }
 
 // Two-level result of point p from its outer-line results res[0 .. n_dir_o):
 // min over outer directions, then stress and tree through Algorithm 3 on the
 // binary tree (wave-level).
-template <typename T, int D, int S, int K>
+template <typename T, int D, int S, int K, int M>
 __device__ __forceinline__ void finalize_point(const KArgs& a, int64_t p, const Level& lo, const Level& li,
                                const OuterRes<T>* res) {
   const int n_dir_o = lo.n_dir;
   double F[D * D], bn;
   bool fin = load_point<T, D>(a, p, F, bn);
-  Point<T> q0 = make_point<T>(a.mat, bn);
+  Point<T> q0 = make_point<T, M>(a.mat, bn);
   double cof0[D * D];
   cofactor<D>(F, cof0);
-  if (!fin || !(w_point<T, D>(q0, F, cof0) < inf_v<T>())) {
+  if (!fin || !(w_point<T, D, M>(q0, F, cof0) < inf_v<T>())) {
     if (lane_id() == 0) write_bad_point<T, D>(a, p, !fin, a.want_stress);
     return;
   }
@@ -383,12 +385,12 @@ __device__ __forceinline__ void finalize_point(const KArgs& a, int64_t p, const 
     double Gm[D * D], Gp[D * D], Pm[D * D], Pp[D * D];
     line_point<D>(F, lo, bd, -t_of(lo, bp), Gm);
     line_point<D>(F, lo, bd, t_of(lo, bq), Gp);
-    Env<T> em = envelope_with_stress<T, D, S, K>(a, li, lay, bn, Gm, Pm);
+    Env<T> em = envelope_with_stress<T, D, S, K, M>(a, li, lay, bn, Gm, Pm);
     cap |= em.capped;
     tie = tie || near_tie(em);
     Env<T> ep = em;
     if (bp + bq) {
-      ep = envelope_with_stress<T, D, S, K>(a, li, lay, bn, Gp, Pp);
+      ep = envelope_with_stress<T, D, S, K, M>(a, li, lay, bn, Gp, Pp);
       cap |= ep.capped;
       tie = tie || near_tie(ep);
     } else {
@@ -415,24 +417,24 @@ __device__ __forceinline__ void finalize_point(const KArgs& a, int64_t p, const 
   }
 }
 
-template <typename T, int D, int S, int K>
+template <typename T, int D, int S, int K, int M>
 __global__ __launch_bounds__(256) void k_finalize(KArgs a) {
   const int64_t p = int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
   if (p >= a.n) return;
-  finalize_point<T, D, S, K>(a, p, a.lv0, a.lv1,
+  finalize_point<T, D, S, K, M>(a, p, a.lv0, a.lv1,
                              static_cast<const OuterRes<T>*>(a.scratch_outer) + p * a.lv0.n_dir);
 }
 
 // ---- dispatch ------------------------------------------------------------------
 
-template <typename T, int D, int S, int K>
+template <typename T, int D, int S, int K, int M>
 hipError_t launch_T(const KArgs& a, int depth, hipStream_t st, KTimer* tm) {
   dim3 blk(256);
   unsigned per = 256 / kWave;
   if (depth == 1) {
     dim3 grd(unsigned((a.n + per - 1) / per));
     if (tm) tm->begin("depth1", st);
-    hipLaunchKernelGGL((k_depth1<T, D, S, K>), grd, blk, 0, st, a);
+    hipLaunchKernelGGL((k_depth1<T, D, S, K, M>), grd, blk, 0, st, a);
     if (tm) tm->end(st);
     return hipGetLastError();
   }
@@ -446,23 +448,23 @@ hipError_t launch_T(const KArgs& a, int depth, hipStream_t st, KTimer* tm) {
   pre.want_stress = 0;
   dim3 grd(unsigned((a.n + per - 1) / per));
   if (tm) tm->begin("depth2_centre", st);
-  hipLaunchKernelGGL((k_depth1<T, D, S, K>), grd, blk, 0, st, pre);
+  hipLaunchKernelGGL((k_depth1<T, D, S, K, M>), grd, blk, 0, st, pre);
   if (tm) tm->end(st);
   size_t lds = outer_lds_bytes<T>(a.lv0, a.lv1);
   dim3 grd_o(unsigned(a.n * a.lv0.n_dir));
   if (tm) tm->begin("outer", st);
-  hipLaunchKernelGGL((k_outer<T, D, S, K>), grd_o, blk, lds, st, a);
+  hipLaunchKernelGGL((k_outer<T, D, S, K, M>), grd_o, blk, lds, st, a);
   if (tm) tm->end(st);
   if (tm) tm->begin("finalize", st);
-  hipLaunchKernelGGL((k_finalize<T, D, S, K>), grd, blk, 0, st, a);
+  hipLaunchKernelGGL((k_finalize<T, D, S, K, M>), grd, blk, 0, st, a);
   if (tm) tm->end(st);
   return hipGetLastError();
 }
 
-template <typename T, int D>
+template <typename T, int D, int M>
 hipError_t launch_TD(const KArgs& a, int depth, int S, int K, hipStream_t st, KTimer* tm) {
 #define R1_CASE(SS, KK) \
-  if (S == SS && K == KK) return launch_T<T, D, SS, KK>(a, depth, st, tm);
+  if (S == SS && K == KK) return launch_T<T, D, SS, KK, M>(a, depth, st, tm);
   R1_CASE(8, 2) R1_CASE(8, 4) R1_CASE(8, 8) R1_CASE(8, 16) R1_CASE(8, 32)
   R1_CASE(16, 2) R1_CASE(16, 4) R1_CASE(16, 8) R1_CASE(16, 16) R1_CASE(16, 32)
   R1_CASE(32, 2) R1_CASE(32, 4) R1_CASE(32, 8) R1_CASE(32, 16) R1_CASE(32, 32)

@@ -1,15 +1,16 @@
-// Instantiation of the lamination kernels for float, 2x2 gradients.
+// Instantiation of the lamination kernels for float, 2x2 gradients (neo-Hooke damage and
+// the double-well test energy).
 #include "r1_batched_kernels.hpp"
 
 hipError_t r1_launch_f32_2d(const KArgs& a, int depth, int S, int K, hipStream_t st, KTimer* tm) {
-  return r1k::launch_TD<float, 2>(a, depth, S, K, st, tm);
+  return r1k::launch_TD<float, 2, r1d::kFamNH>(a, depth, S, K, st, tm);
 }
 
 hipError_t r1_launch_batched_f32_2d(const BArgs& b, int var, int kind, int grid, size_t lds, int* zero_p, int zero_n,
                                      hipStream_t st) {
-  return r1k::launch_batched_TD<float, 2>(b, var, kind, grid, lds, zero_p, zero_n, st);
+  return r1k::launch_batched_TD<float, 2, r1d::kFamNH>(b, var, kind, grid, lds, zero_p, zero_n, st);
 }
 
 hipError_t r1_occupancy_batched_f32_2d(int var, int kind, size_t lds, int* blocks_per_cu) {
-  return r1k::occupancy_batched_TD<float, 2>(var, kind, lds, blocks_per_cu);
+  return r1k::occupancy_batched_TD<float, 2, r1d::kFamNH>(var, kind, lds, blocks_per_cu);
 }

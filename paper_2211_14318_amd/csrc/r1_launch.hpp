@@ -76,11 +76,11 @@ hipError_t r1_launch_tangent(const KArgs& a, int depth, int dtype, const r1_lami
 
 struct BArgs;
 // Uneven-batch kernel of the given kind (kBPoint, kBOuter, kBFinal) for layout
-// variant var on `grid` blocks with `lds` bytes of dynamic LDS, preceded by
-// zeroing zero_n ints at zero_p when zero_n > 0.
-hipError_t r1_launch_batched(const BArgs& b, int dtype, int dim, int var, int kind, int grid, size_t lds,
+// variant var of the material model's kernels on `grid` blocks with `lds` bytes
+// of dynamic LDS, preceded by zeroing zero_n ints at zero_p when zero_n > 0.
+hipError_t r1_launch_batched(const BArgs& b, int dtype, int dim, int model, int var, int kind, int grid, size_t lds,
                              int* zero_p, int zero_n, hipStream_t st);
-hipError_t r1_occupancy_batched(int dtype, int dim, int var, int kind, size_t lds, int* blocks_per_cu);
+hipError_t r1_occupancy_batched(int dtype, int dim, int model, int var, int kind, size_t lds, int* blocks_per_cu);
 // Layout variants of the persistent kernel, (variant, S, K): lanes per line and
 // samples per lane of the innermost level.
 #define R1_BATCH_VARIANTS(X) \

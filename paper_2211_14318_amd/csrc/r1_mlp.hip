@@ -235,10 +235,10 @@ __global__ void k_targets(int64_t n, r1d::Material mat, const float* X, const fl
   double G[D * D], cof[D * D], P0[D * D];
   for (int k = 0; k < D * D; ++k) G[k] = X[p * DI + k];
   const double bn = X[p * DI + D * D];
-  r1d::Point<double> q = r1d::make_point<double>(mat, bn);
+  r1d::Point<double> q = r1d::make_point_any<double>(mat, bn);
   r1d::cofactor<D>(G, cof);
-  const double w = r1d::w_point<double, D>(q, G, cof);
-  r1d::stress0<D>(mat, bn, G, P0);
+  const double w = r1d::w_point_any<double, D>(q, G, cof);
+  r1d::stress0_any<D>(mat, bn, G, P0);
   T[p * DI] = float(w - double(Y[p * DI]));
   for (int k = 0; k < D * D; ++k) T[p * DI + 1 + k] = float(P0[k] - double(Y[p * DI + 1 + k]));
 }
@@ -357,7 +357,7 @@ __device__ __forceinline__ int gate_bin(const InferParams& ip, const double* F, 
 // MODE 0: gates on, rejected points appended to the fallback list.
 // MODE 1 (calibration): box gate only; the gate cell, predicted W and
 // predicted gap go to cal_bin / cal_w / cal_gap, rejected points get cell -1.
-template <typename T, int D, int WID, int MODE>
+template <typename T, int D, int WID, int MODE, int FAM>
 __global__ __launch_bounds__(256) void k_infer(InferParams ip, const T* F, const T* bn, T* W,
                                                T* P, int32_t* flags, int* fb_count,
                                                int32_t* fb_list, int* cal_bin, float* cal_w,
@@ -432,8 +432,8 @@ __global__ __launch_bounds__(256) void k_infer(InferParams ip, const T* F, const
   const float rawf = out[0] * ip.y_std[0] + ip.y_mean[0];
   const double raw = double(rawf);
   const bool convex = raw <= 0.0;
-  r1d::Point<double> q = r1d::make_point<double>(ip.mat, b);
-  const double w_un = r1d::w_point<double, D>(q, G, cof);
+  r1d::Point<double> q = r1d::make_point<double, FAM>(ip.mat, b);
+  const double w_un = r1d::w_point<double, D, FAM>(q, G, cof);
   const double wpred = convex ? w_un : w_un - raw;
   if (MODE == 1) {
     cal_bin[pt] = ok ? bin : -1;
@@ -448,7 +448,7 @@ __global__ __launch_bounds__(256) void k_infer(InferParams ip, const T* F, const
     return;
   }
   double P0[D * D];
-  r1d::stress0<D>(ip.mat, b, G, P0);
+  r1d::stress0<D, FAM>(ip.mat, b, G, P0);
   W[pt] = T(wpred);
   for (int k = 0; k < D * D; ++k)
     P[int64_t(k) * ip.n + pt] =
@@ -478,7 +478,7 @@ __host__ __device__ inline size_t infer_lds_bytes(int width, int n_hidden, int d
 //    completed by the same exchange;
 //  * gates, then W(F) (lower half) and P0(F) (upper half) in FP64.
 // MODE as in k_infer.
-template <typename T, int D, int WID, int MODE>
+template <typename T, int D, int WID, int MODE, int FAM>
 __global__ __launch_bounds__(512) void k_infer_lds(InferParams ip, const T* F, const T* bn, T* W, T* P,
                                                    int32_t* flags, int* fb_count, int32_t* fb_list,
                                                    int* cal_bin, float* cal_w, float* cal_gap) {
@@ -602,8 +602,8 @@ __global__ __launch_bounds__(512) void k_infer_lds(InferParams ip, const T* F, c
     const bool convex = raw <= 0.0;
     if (MODE == 1) {
       if (valid && half == 0) {
-        r1d::Point<double> q = r1d::make_point<double>(ip.mat, b);
-        const double w_un = r1d::w_point<double, D>(q, G, cof);
+        r1d::Point<double> q = r1d::make_point<double, FAM>(ip.mat, b);
+        const double w_un = r1d::w_point<double, D, FAM>(q, G, cof);
         cal_bin[pt] = ok ? bin : -1;
         cal_w[pt] = float(convex ? w_un : w_un - raw);
         cal_gap[pt] = rawf;
@@ -621,13 +621,13 @@ __global__ __launch_bounds__(512) void k_infer_lds(InferParams ip, const T* F, c
     if (rej) fb_list[base + __popcll(m & ((1ull << lane) - 1ull))] = int32_t(pt);
     if (!valid || !ok) continue;
     if (half == 0) {
-      r1d::Point<double> q = r1d::make_point<double>(ip.mat, b);
-      const double w_un = r1d::w_point<double, D>(q, G, cof);
+      r1d::Point<double> q = r1d::make_point<double, FAM>(ip.mat, b);
+      const double w_un = r1d::w_point<double, D, FAM>(q, G, cof);
       W[pt] = T(convex ? w_un : w_un - raw);
       if (flags) flags[pt] = 0;
     } else {
       double P0[D * D];
-      r1d::stress0<D>(ip.mat, b, G, P0);
+      r1d::stress0<D, FAM>(ip.mat, b, G, P0);
       for (int k = 0; k < D * D; ++k)
         P[int64_t(k) * ip.n + pt] =
             T(convex ? P0[k] : P0[k] - double(out[1 + k] * ip.y_std[1 + k] + ip.y_mean[1 + k]));
@@ -786,7 +786,7 @@ hipError_t r1m_pack(int dtype, int dim, int64_t n, const void* F, const void* bn
 
 size_t r1m_infer_lds(int width) { return size_t(4) * 32 * (width + 8) * 2; }
 
-template <typename T, int D>
+template <typename T, int D, int FAM>
 static hipError_t infer_TD(const InferParams& ip, int mode, const void* F, const void* bn, void* W, void* P,
                            int32_t* flags, int* fb_count, int32_t* fb_list, int* cal_bin, float* cal_w,
                            float* cal_gap, hipStream_t st) {
@@ -799,9 +799,9 @@ static hipError_t infer_TD(const InferParams& ip, int mode, const void* F, const
     if (e != hipSuccess) return e;
     const int64_t blocks = (ip.n + 255) / 256;
     dim3 grid(unsigned(blocks < n_cu ? blocks : n_cu));
-#define R1L(WID, MODE) (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_infer_lds<T, D, WID, MODE>), \
+#define R1L(WID, MODE) (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_infer_lds<T, D, WID, MODE, FAM>), \
       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds2)); \
-  hipLaunchKernelGGL((k_infer_lds<T, D, WID, MODE>), grid, dim3(512), lds2, st, ip, \
+  hipLaunchKernelGGL((k_infer_lds<T, D, WID, MODE, FAM>), grid, dim3(512), lds2, st, ip, \
       static_cast<const T*>(F), static_cast<const T*>(bn), static_cast<T*>(W), static_cast<T*>(P), flags, \
       fb_count, fb_list, cal_bin, cal_w, cal_gap)
 #define R1V(WID) if (ip.width == WID) { if (mode == 0) { R1L(WID, 0); } else { R1L(WID, 1); } return hipGetLastError(); }
@@ -812,9 +812,9 @@ static hipError_t infer_TD(const InferParams& ip, int mode, const void* F, const
   }
   dim3 grid(unsigned((ip.n + 127) / 128));
   size_t lds = r1m_infer_lds(ip.width);
-#define R1I(WID, MODE) (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_infer<T, D, WID, MODE>), \
+#define R1I(WID, MODE) (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_infer<T, D, WID, MODE, FAM>), \
       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)); \
-  hipLaunchKernelGGL((k_infer<T, D, WID, MODE>), grid, dim3(256), lds, st, ip, \
+  hipLaunchKernelGGL((k_infer<T, D, WID, MODE, FAM>), grid, dim3(256), lds, st, ip, \
       static_cast<const T*>(F), static_cast<const T*>(bn), static_cast<T*>(W), static_cast<T*>(P), flags, \
       fb_count, fb_list, cal_bin, cal_w, cal_gap)
 #define R1W(WID) if (ip.width == WID) { if (mode == 0) { R1I(WID, 0); } else { R1I(WID, 1); } return hipGetLastError(); }
@@ -827,11 +827,15 @@ static hipError_t infer_TD(const InferParams& ip, int mode, const void* F, const
 hipError_t r1m_infer(int dtype, int dim, const InferParams& ip, int mode, const void* F, const void* bn,
                      void* W, void* P, int32_t* flags, int* fb_count, int32_t* fb_list, int* cal_bin,
                      float* cal_w, float* cal_gap, hipStream_t st) {
-  if (dtype == R1_F32)
-    return dim == 2 ? infer_TD<float, 2>(ip, mode, F, bn, W, P, flags, fb_count, fb_list, cal_bin, cal_w, cal_gap, st)
-                    : infer_TD<float, 3>(ip, mode, F, bn, W, P, flags, fb_count, fb_list, cal_bin, cal_w, cal_gap, st);
-  return dim == 2 ? infer_TD<double, 2>(ip, mode, F, bn, W, P, flags, fb_count, fb_list, cal_bin, cal_w, cal_gap, st)
-                  : infer_TD<double, 3>(ip, mode, F, bn, W, P, flags, fb_count, fb_list, cal_bin, cal_w, cal_gap, st);
+  // one set of kernels per model family (exact W and P0 of the material in the epilogue)
+#define R1F(T, D) (ip.mat.model == R1_STVK_DAMAGE                                                                   \
+                       ? infer_TD<T, D, r1d::kFamSTVK>(ip, mode, F, bn, W, P, flags, fb_count, fb_list, cal_bin, \
+                                                       cal_w, cal_gap, st)                                       \
+                       : infer_TD<T, D, r1d::kFamNH>(ip, mode, F, bn, W, P, flags, fb_count, fb_list, cal_bin,   \
+                                                     cal_w, cal_gap, st))
+  if (dtype == R1_F32) return dim == 2 ? R1F(float, 2) : R1F(float, 3);
+  return dim == 2 ? R1F(double, 2) : R1F(double, 3);
+#undef R1F
 }
 
 hipError_t r1m_fb_gather(int dtype, int dim, int64_t n, int nfb, const int32_t* list, const void* F,

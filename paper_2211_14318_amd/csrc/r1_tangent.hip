@@ -9,8 +9,7 @@
 // (point, component): blockIdx.y is the component (i*d + j)*d*d + k*d + l,
 // consecutive threads are consecutive points, and the SoA output
 // A[component * n + p] is written coalesced.  The work per thread is a few
-// leaves of FP64 scalar algebra; the kernel is bound by its HBM writes
-// (d^4 values per point) for d = 3 and by FP64 issue for d = 2.
+// leaves of FP64 scalar algebra.
 #include "r1_kernels.hpp"
 
 namespace r1k {
@@ -21,10 +20,29 @@ namespace r1k {
 // with H = G^{-T}, S = d psi0 / dG = mu G + (lambda ln J - mu) H, g' = 1 - D(max(psi0, beta_n))
 // and g'' = -(D_inf / D0) e^{-psi0/D0} on the loading branch psi0 > beta_n, 0 otherwise.
 // In 2D (plane strain) G is the in-plane block; G^{-T} of the embedding keeps
-// that block as the 2x2 inverse-transpose.  Double-well test energy: 2 on the
-// diagonal, 12 G_11^2 - 4 at (11, 11).  NaN where det G <= 0.
+// that block as the 2x2 inverse-transpose.  NaN where det G <= 0.
+// St. Venant-Kirchhoff (eq. 2.2), with E = (G^T G - I)/2, B = G G^T and
+// S = dpsi0/dG = G (lambda tr E I + 2 mu E):
+//   d^2psi0/dG_ij dG_kl = lambda G_ij G_kl + lambda tr E d_ik d_jl + 2 mu d_ik E_lj
+//                         + mu (G_il G_kj + B_ik d_jl),
+// with the same damage factors g', g''.  Double-well test energy: 2 on the
+// diagonal, 12 G_11^2 - 4 at (11, 11).
 template <int D>
 __device__ __forceinline__ double tangent0_comp(const Material& m, double bn, const double* G, int ij, int kl) {
+  const int i = ij / D, j = ij % D, k = kl / D, l = kl % D;
+  if (m.model == 2) {
+    double E[D * D], S[D * D];
+    double tr = stvk_strain<D>(G, E);
+    double psi = stvk_psi_stress<D>(m, G, S);
+    double Bik = 0.0;
+#pragma unroll
+    for (int r = 0; r < D; ++r) Bik += G[i * D + r] * G[k * D + r];
+    double h = m.lambda * G[ij] * G[kl] + (i == k ? m.lambda * tr * (j == l ? 1.0 : 0.0) + 2.0 * m.mu * E[l * D + j] : 0.0)
+             + m.mu * (G[i * D + l] * G[k * D + j] + (j == l ? Bik : 0.0));
+    double g1 = 1.0 - m.D_inf * (1.0 - exp(-(psi > bn ? psi : bn) / m.D0));
+    double g2 = psi > bn ? -m.D_inf / m.D0 * exp(-psi / m.D0) : 0.0;
+    return g1 * h + g2 * S[ij] * S[kl];
+  }
   if (m.model != 0) {
     if (ij != kl) return 0.0;
     return ij == 0 ? 12.0 * G[0] * G[0] - 4.0 : 2.0;
@@ -41,7 +59,6 @@ __device__ __forceinline__ double tangent0_comp(const Material& m, double bn, co
   double g1 = 1.0 - m.D_inf * (1.0 - exp(-beta / m.D0));
   double g2 = psi > bn ? -m.D_inf / m.D0 * exp(-psi / m.D0) : 0.0;
   double c = m.lambda * lnJ - m.mu;
-  const int i = ij / D, j = ij % D, k = kl / D, l = kl % D;
   double Hij = cof[ij] / J, Hkl = cof[kl] / J, Hil = cof[i * D + l] / J, Hkj = cof[k * D + j] / J;
   double h = (ij == kl ? m.mu : 0.0) + m.lambda * Hij * Hkl - c * Hil * Hkj;
   double Sij = m.mu * G[ij] + c * Hij, Skl = m.mu * G[kl] + c * Hkl;
@@ -64,8 +81,7 @@ __device__ __forceinline__ bool node_split(const Level& lv, const r1_laminate& t
   return true;
 }
 
-// One node's modulus component: xi A(G+) + (1 - xi) A(G-) with the endpoints'
-// moduli from the leaves (inner == nullptr) or from the children on level *inner.
+// One node's modulus component over its two leaves: xi A0(G+) + (1 - xi) A0(G-).
 template <int D>
 __device__ __forceinline__ double node_tangent(const Material& mat, double bn, const Level& lv, const r1_laminate& t,
                                                const double* G, int ij, int kl, bool& ok) {

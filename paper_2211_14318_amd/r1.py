@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_PKG, "libr1.so")
 
 R1_OK = 0
 R1_F32, R1_F64 = 0, 1
-R1_NEOHOOKE_DAMAGE, R1_TEST_DOUBLEWELL = 0, 1
+R1_NEOHOOKE_DAMAGE, R1_TEST_DOUBLEWELL, R1_STVK_DAMAGE = 0, 1, 2
 PT_DETLE0, PT_NONFINITE, PT_FALLBACK, PT_ITERCAP, PT_TIE = 1, 2, 4, 8, 16
 TREE_NODES = 3
 
