@@ -15,8 +15,11 @@ sample of the same workload on the host's cores; the same oracle results give
 `surrogate` (train the MLP on 2M lamination rows, then 1M-point inference
 with routing against plain lamination of the same configuration), `batched`
 (65,536 points with uneven grids/directions/depths in one graph replay),
-`plain_3d` (262,144 3D points, 256 directions x 513 points) and
-`surrogate_3d` (a 4 x 256 network on the same 3D workload).
+`plain_3d` (262,144 3D points, 256 directions x 513 points),
+`surrogate_3d` (a 4 x 256 network on the same 3D workload), `stvk` (the
+headline shapes with the St. Venant-Kirchhoff damage model, 15 flops per
+sample) and `tangent` (Algorithm 3's tangent moduli of 1M depth-1 laminates,
+priced by its algorithmic bytes against HBM).
 """
 import argparse
 import json
@@ -313,6 +316,74 @@ def leg_3d(h, r1, WL, torch, np, n_check=64):
             "erel_vs_oracle": erel_stats(W.cpu().numpy()[sel], Wo, floor=1e-2)}
 
 
+FLOPS_PER_W_STVK = 15      # St. Venant-Kirchhoff sample: 7 FMA + 1 min, the exponential not counted
+STVK_MATERIAL = dict(mu=1.0, lam=0.5, D_inf=0.9, D0=0.3)   # Table 6.3, STVK row
+
+
+def leg_stvk(h, r1, WL, torch, np, steps=2):
+    """The headline depth-2 shapes (4096 points, outer 64 x 1025, inner 32 x 257, FP32) with the
+    St. Venant-Kirchhoff damage model: energy, laminate stress and tree."""
+    cfg = WL.config2()
+    mat = r1.material_from(STVK_MATERIAL, 2, r1.R1_STVK_DAMAGE)
+    spec = r1.LaminationSpec(cfg["levels"])
+    n = cfg["n"]
+    F = torch.tensor(cfg["F"], dtype=torch.float32, device="cuda").contiguous()
+    bn = torch.tensor(cfg["beta_n"], dtype=torch.float32, device="cuda").contiguous()
+    W = torch.empty(n, device="cuda")
+    P = torch.empty((4, n), device="cuda")
+    T = torch.empty((n, 3, 4), dtype=torch.int32, device="cuda")
+    h.envelope_into(mat, spec, F, bn, W, P, T)
+    torch.cuda.synchronize()
+    h.timing(True)
+    h.timing_reset()
+    t = timed(lambda: h.envelope_into(mat, spec, F, bn, W, P, T), steps, torch)
+    outer_ms, outer_n = h.timing_query("outer")
+    h.timing(False)
+    avg_s = outer_ms / max(outer_n, 1) / 1e3
+    flops = FLOPS_PER_W_STVK * w_samples_outer_kernel(cfg)
+    achieved = flops / avg_s / 1e12
+    return {"workload": cfg["name"].replace("plain-", "stvk-"), "material": STVK_MATERIAL,
+            "qps": round(n / t, 1), "ms": round(1e3 * t, 1),
+            "roofline": dict(bound="alu", kernel="k_outer", avg_ms=round(1e3 * avg_s, 3),
+                             achieved=round(achieved, 3), unit="TFLOP/s", peak=PEAK["f32"],
+                             frac=round(achieved / PEAK["f32"], 4), peak_nonpacked=PEAK_NONPACKED["f32"],
+                             frac_nonpacked=round(achieved / PEAK_NONPACKED["f32"], 4),
+                             flops_per_w=FLOPS_PER_W_STVK),
+            "all_finite": bool(np.isfinite(W.cpu().numpy()).all())}
+
+
+def tangent_bytes(d, depth, elem):
+    """Algorithmic bytes per point of the tangent post-pass: F, beta_n and W read, the tree
+    nodes it names read (16 B each), d^4 moduli written."""
+    return elem * (d * d + 2) + 16 * (1 if depth == 1 else 3) + elem * d ** 4
+
+
+def leg_tangent(h, r1, WL, torch, np, reps=20):
+    """Tangent moduli (Algorithm 3) of 1M depth-1 laminates (16 directions x 201 points, FP32),
+    from the trees of a plain lamination call: the post-pass kernel alone."""
+    cfg = WL.config4_inference(n=1_000_000)
+    mat = r1.material()
+    spec = r1.LaminationSpec(cfg["levels"])
+    F = torch.tensor(cfg["F"], dtype=torch.float32, device="cuda").contiguous()
+    bn = torch.tensor(cfg["beta_n"], dtype=torch.float32, device="cuda").contiguous()
+    out = h.envelope(mat, spec, F, bn, stress=False, tree=True, flags=False)
+    torch.cuda.synchronize()
+    h.timing(True)
+    h.timing_reset()
+    for _ in range(reps):
+        A = h.laminate_tangent(mat, spec, F, bn, out["W"], out["tree"])
+    ms, cnt = h.timing_query("tangent")
+    h.timing(False)
+    n = cfg["n"]
+    avg_s = ms / max(cnt, 1) / 1e3
+    per = tangent_bytes(2, 1, 4)
+    gbs = per * n / avg_s / 1e9
+    return {"workload": "tangent-2d-n%d-16x201-k1" % n, "n": n, "avg_ms": round(1e3 * avg_s, 4),
+            "roofline": dict(bound="hbm", kernel="k_tangent", achieved=round(gbs, 1), unit="GB/s", peak=8000.0,
+                             frac=round(gbs / 8000.0, 4), bytes_per_point=per),
+            "all_finite": bool(torch.isfinite(A).all().item())}
+
+
 # ---------------------------------------------------------------- main
 
 def main():
@@ -325,6 +396,8 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
+    ap.add_argument("--leg", choices=["surrogate", "batched", "plain_3d", "surrogate_3d", "stvk", "tangent"],
+                    help="only run this secondary leg and print its result (a profiling aid)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this benchmark runs on one GPU only (quadrature points are independent; "
@@ -343,6 +416,15 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": x.numel() * 4}))
+        return
+
+    if args.leg:
+        legs = dict(surrogate=leg_surrogate, batched=leg_batched, plain_3d=leg_3d,
+                    surrogate_3d=leg_surrogate_3d, stvk=leg_stvk, tangent=leg_tangent)
+        h = r1.Handle(0)
+        res = legs[args.leg](h, r1, WL, torch, np)
+        print(json.dumps({"leg": args.leg, **res}))
+        h.close()
         return
 
     cfg = WL.config2()
@@ -418,6 +500,10 @@ def main():
         log("batched leg: %.1f QP/s" % out["batched"]["qps"])
         out["plain_3d"] = leg_3d(h, r1, WL, torch, np)
         log("3d leg: %.1f QP/s" % out["plain_3d"]["qps"])
+        out["stvk"] = leg_stvk(h, r1, WL, torch, np)
+        log("stvk leg: %.1f QP/s, k_outer %.1f ms" % (out["stvk"]["qps"], out["stvk"]["roofline"]["avg_ms"]))
+        out["tangent"] = leg_tangent(h, r1, WL, torch, np)
+        log("tangent leg: %.4f ms per 1M points" % out["tangent"]["avg_ms"])
         out["surrogate_3d"] = leg_surrogate_3d(h, r1, WL, torch, np)
         log("3d surrogate leg: speedup %.3f, fallback %.3f" % (out["surrogate_3d"]["speedup"],
                                                             out["surrogate_3d"]["fallback_frac"]))

@@ -164,10 +164,21 @@ __device__ __forceinline__ double det_of(const double* G, const double* cof) {
 //   p2 = lambda/2 (e1^2 + 2 e0 e2) + mu (|G^T a|^2 |b|^2 / 2 + e1^2 / 2 + |a|^2 b.E0 b)
 //   p3 = (lambda + 2 mu) e1 e2,   p4 = (lambda/2 + mu) e2^2.
 // Coefficients are formed in double and scaled by k.
-template <typename T, int D>
-__device__ __forceinline__ Line<T> stvk_line(double lam, double mu, double k, const double* G, const double* a,
-                                             const double* b) {
-  double E0[D * D], e0 = 0.0, ee = 0.0;
+// Per-point part of the St. Venant-Kirchhoff line coefficients: G, E0, G E0,
+// tr E0 and E0:E0 (shared by every line through the point).
+template <int D>
+struct StvkGeom {
+  double G[D * D], E0[D * D], GE0[D * D];
+  double e0, ee;
+};
+
+template <int D>
+__device__ __forceinline__ StvkGeom<D> make_stvk_geom(const double* G) {
+  StvkGeom<D> g;
+  g.e0 = 0.0;
+  g.ee = 0.0;
+#pragma unroll
+  for (int k = 0; k < D * D; ++k) g.G[k] = G[k];
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
@@ -175,44 +186,60 @@ __device__ __forceinline__ Line<T> stvk_line(double lam, double mu, double k, co
       double c = 0.0;
 #pragma unroll
       for (int r = 0; r < D; ++r) c += G[r * D + i] * G[r * D + j];
-      E0[i * D + j] = 0.5 * (c - (i == j ? 1.0 : 0.0));
+      g.E0[i * D + j] = 0.5 * (c - (i == j ? 1.0 : 0.0));
     }
 #pragma unroll
-  for (int i = 0; i < D; ++i) e0 += E0[i * D + i];
+  for (int i = 0; i < D; ++i) g.e0 += g.E0[i * D + i];
 #pragma unroll
-  for (int i = 0; i < D * D; ++i) ee += E0[i] * E0[i];
-  double gta[D], e0b[D], aa = 0.0, bb = 0.0;
+  for (int i = 0; i < D * D; ++i) g.ee += g.E0[i] * g.E0[i];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      double c = 0.0;
+#pragma unroll
+      for (int r = 0; r < D; ++r) c += G[i * D + r] * g.E0[r * D + j];
+      g.GE0[i * D + j] = c;
+    }
+  return g;
+}
+
+template <typename T, int D>
+__device__ __forceinline__ Line<T> stvk_line_g(double lam, double mu, double k, const StvkGeom<D>& g,
+                                               const double* a, const double* b) {
+  double e1 = 0.0, ge0b = 0.0, beb = 0.0, gta2 = 0.0, aa = 0.0, bb = 0.0;
 #pragma unroll
   for (int j = 0; j < D; ++j) {
-    double u = 0.0, v = 0.0;
+    double gta = 0.0, e0b = 0.0, ge = 0.0;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      u += G[i * D + j] * a[i];
-      v += E0[j * D + i] * b[i];
+      gta += g.G[i * D + j] * a[i];
+      e0b += g.E0[j * D + i] * b[i];
+      ge += g.GE0[i * D + j] * a[i];
     }
-    gta[j] = u;
-    e0b[j] = v;
+    e1 += gta * b[j];
+    ge0b += ge * b[j];
+    beb += b[j] * e0b;
+    gta2 += gta * gta;
     aa += a[j] * a[j];
     bb += b[j] * b[j];
   }
-  double e1 = 0.0, ge0b = 0.0, beb = 0.0, gta2 = 0.0;
-#pragma unroll
-  for (int j = 0; j < D; ++j) {
-    e1 += gta[j] * b[j];
-    ge0b += gta[j] * e0b[j];
-    beb += b[j] * e0b[j];
-    gta2 += gta[j] * gta[j];
-  }
-  const double e2 = 0.5 * aa * bb;
+  const double e0 = g.e0, e2 = 0.5 * aa * bb;
   Line<T> L;
   L.J0 = T(0);
   L.J1 = T(0);
-  L.c0 = T(k * (0.5 * lam * e0 * e0 + mu * ee));
+  L.c0 = T(k * (0.5 * lam * e0 * e0 + mu * g.ee));
   L.c1 = T(k * (lam * e0 * e1 + 2.0 * mu * ge0b));
   L.c2 = T(k * (0.5 * lam * (e1 * e1 + 2.0 * e0 * e2) + mu * (0.5 * gta2 * bb + 0.5 * e1 * e1 + aa * beb)));
   L.c3 = T(k * ((lam + 2.0 * mu) * e1 * e2));
   L.c4 = T(k * ((0.5 * lam + mu) * e2 * e2));
   return L;
+}
+
+template <typename T, int D>
+__device__ __forceinline__ Line<T> stvk_line(double lam, double mu, double k, const double* G, const double* a,
+                                             const double* b) {
+  return stvk_line_g<T, D>(lam, mu, k, make_stvk_geom<D>(G), a, b);
 }
 
 template <typename T, int D, int M = kFamNH>
@@ -693,35 +720,52 @@ __device__ __forceinline__ PointGeom<D> make_geom(const double* G) {
   return g;
 }
 
+// Geometry of a point by model family.
+template <int D, int M>
+struct GeomOf { using type = PointGeom<D>; };
+template <int D>
+struct GeomOf<D, kFamSTVK> { using type = StvkGeom<D>; };
+
+template <int D, int M>
+__device__ __forceinline__ typename GeomOf<D, M>::type make_geom_m(const double* G) {
+  if constexpr (M == kFamSTVK)
+    return make_stvk_geom<D>(G);
+  else
+    return make_geom<D>(G);
+}
+
 template <typename T, int D, int M = kFamNH>
-__device__ __forceinline__ Line<T> line_of(const Point<T>& q, const PointGeom<D>& g, const double* a,
-                                           const double* b) {
-  if constexpr (M == kFamSTVK) return line_setup<T, D, M>(q, g.G, g.cof, a, b);
-  if (q.model != 0) return line_setup<T, D, M>(q, g.G, g.cof, a, b);
-  const double kq = q.kq;
-  Line<T> L;
-  L.c3 = T(0);
-  L.c4 = T(0);
-  double J1 = 0.0, gab = 0.0, aa = 0.0, bb = 0.0;
+__device__ __forceinline__ Line<T> line_of(const Point<T>& q, const typename GeomOf<D, M>::type& g,
+                                           const double* a, const double* b) {
+  if constexpr (M == kFamSTVK) {
+    return stvk_line_g<T, D>(q.lam, q.mu, q.kq, g, a, b);
+  } else {
+    if (q.model != 0) return line_setup<T, D, M>(q, g.G, g.cof, a, b);
+    const double kq = q.kq;
+    Line<T> L;
+    L.c3 = T(0);
+    L.c4 = T(0);
+    double J1 = 0.0, gab = 0.0, aa = 0.0, bb = 0.0;
 #pragma unroll
-  for (int i = 0; i < D; ++i) {
-    aa += a[i] * a[i];
-    bb += b[i] * b[i];
-    double ca = 0.0, ga = 0.0;
+    for (int i = 0; i < D; ++i) {
+      aa += a[i] * a[i];
+      bb += b[i] * b[i];
+      double ca = 0.0, ga = 0.0;
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
-      ca += g.cof[i * D + j] * b[j];
-      ga += g.G[i * D + j] * b[j];
+      for (int j = 0; j < D; ++j) {
+        ca += g.cof[i * D + j] * b[j];
+        ga += g.G[i * D + j] * b[j];
+      }
+      J1 += a[i] * ca;
+      gab += a[i] * ga;
     }
-    J1 += a[i] * ca;
-    gab += a[i] * ga;
+    L.J0 = T(g.det);
+    L.J1 = T(J1);
+    L.c0 = T(kq * (g.n2 - double(D)));
+    L.c1 = T(kq * 2.0 * gab);
+    L.c2 = T(kq * aa * bb);
+    return L;
   }
-  L.J0 = T(g.det);
-  L.J1 = T(J1);
-  L.c0 = T(kq * (g.n2 - double(D)));
-  L.c1 = T(kq * 2.0 * gab);
-  L.c2 = T(kq * aa * bb);
-  return L;
 }
 
 template <typename T>
@@ -860,7 +904,7 @@ __device__ Env<T> envelope_lines(const Point<T>& q, T wc, int n_dir, const Layou
 template <typename T, int D, int S, int K, int M = kFamNH>
 __device__ Env<T> envelope_at(const Point<T>& q, const double* G, T wc, const Level& lv,
                               const Layout<T, S, K>& lay) {
-  PointGeom<D> g = make_geom<D>(G);
+  const auto g = make_geom_m<D, M>(G);
   return envelope_lines<T, S, K, M>(q, wc, lv.n_dir, lay, [&](int dd) {
     double a[D], b[D];
 #pragma unroll

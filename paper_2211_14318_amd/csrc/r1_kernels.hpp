@@ -127,7 +127,7 @@ __device__ __forceinline__ void point_depth1(const KArgs& a, int64_t p, const Le
 }
 
 template <typename T, int D, int S, int K, int M>
-__global__ __launch_bounds__(256) void k_depth1(KArgs a) {
+__global__ __launch_bounds__(256, (sizeof(T) == 4 && K <= 16) ? 3 : 1) void k_depth1(KArgs a) {
   const int64_t p = int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
   if (p >= a.n) return;                       // wave-uniform
   point_depth1<T, D, S, K, M>(a, p, a.lv0);
@@ -217,14 +217,17 @@ template <typename T, int D, int S, int K, int M>
 __device__ __forceinline__ T outer_line(const KArgs& a, int64_t p, int mo, const Level& lo, const Level& li, T w1f,
                         bool compute_centre, OuterRes<T>* out, char* smem_raw) {
   const int co = (lo.n_t - 1) / 2;
-  // tabulated inner lines: coefficients affine in the outer t (neo-Hooke, double
-  // well); St. Venant-Kirchhoff's quartic sets each inner line up from G(t)
-  const bool tab = M != kFamSTVK && li.n_dir <= kMaxTabDirs;
-  T* coef = reinterpret_cast<T*>(smem_raw);                 // 5 * n_dir_i (when tabulated)
-  T* warm = coef + (tab ? 5 * li.n_dir : 0);                // kOuterWaves * n_dir_i (when tabulated)
-  T* wl = warm + (tab ? kOuterWaves * li.n_dir : 0);        // outer samples at -m
+  // Up to kMaxTabDirs inner directions the waves keep warm-start bridge slopes and
+  // visiting orders in LDS (lds_lines); the inner line coefficients are tabulated
+  // too when they are affine in the outer t (neo-Hooke, double well: tab), while
+  // St. Venant-Kirchhoff's quartic sets each inner line up from G(t).
+  const bool lds_lines = li.n_dir <= kMaxTabDirs;
+  const bool tab = M != kFamSTVK && lds_lines;
+  T* coef = reinterpret_cast<T*>(smem_raw);                 // 5 * n_dir_i (tab)
+  T* warm = coef + (tab ? 5 * li.n_dir : 0);                // kOuterWaves * n_dir_i (lds_lines)
+  T* wl = warm + (lds_lines ? kOuterWaves * li.n_dir : 0);  // outer samples at -m
   T* wr = wl + co;                                          // outer samples at +m
-  int* order = reinterpret_cast<int*>(wr + co);             // kOuterWaves * n_dir_i (when tabulated)
+  int* order = reinterpret_cast<int*>(wr + co);             // kOuterWaves * n_dir_i (lds_lines)
   __shared__ int capped_any;
   __shared__ T centre;
   double F[D * D], bn;
@@ -242,8 +245,9 @@ __device__ __forceinline__ T outer_line(const KArgs& a, int64_t p, int mo, const
     for (int i = threadIdx.x; i < li.n_dir; i += blockDim.x)
       inner_line_coef<T, D>(a.mat.model, line_scale<T>(a.mat), F, cofF, R, C1, li.a + i * D, li.b + i * D,
                             coef + 5 * i);
-    for (int i = threadIdx.x; i < kOuterWaves * li.n_dir; i += blockDim.x) warm[i] = T(__builtin_nan(""));
   }
+  if (lds_lines)
+    for (int i = threadIdx.x; i < kOuterWaves * li.n_dir; i += blockDim.x) warm[i] = T(__builtin_nan(""));
   __syncthreads();
   Layout<T, S, K> lay = make_layout<T, S, K>(li.n_t, li.tau);
   Point<T> q = make_point<T, M>(a.mat, bn);
@@ -301,6 +305,23 @@ __device__ __forceinline__ T outer_line(const KArgs& a, int64_t p, int mo, const
           const T* cf = coef + 5 * dd;
           return Line<T>{L0.J0, T(fma(tt, cf[1], cf[0])), L0.c0, T(fma(tt, cf[3], cf[2])), cf[4]};
         }, warm_w, T(q.kq * li.ab2), order_w);
+        v = e.h;
+        capped |= e.capped;
+      }
+    } else if (M == kFamSTVK && lds_lines) {
+      // inner lines set up from G's geometry, with the warm starts and visiting order
+      double cof[D * D];
+      cofactor<D>(G, cof);
+      T wc = w_point<T, D, M>(q, G, cof);
+      v = wc;
+      if (wc < inf_v<T>()) {
+        const auto g = make_geom_m<D, M>(G);
+        Env<T> e = envelope_lines<T, S, K, M>(q, wc, li.n_dir, lay, [&](int dd) {
+          double ai[D], bi[D];
+#pragma unroll
+          for (int i = 0; i < D; ++i) { ai[i] = li.a[dd * D + i]; bi[i] = li.b[dd * D + i]; }
+          return line_of<T, D, M>(q, g, ai, bi);
+        }, warm_w, T(__builtin_nan("")), order_w);
         v = e.h;
         capped |= e.capped;
       }

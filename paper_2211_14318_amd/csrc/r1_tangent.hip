@@ -6,15 +6,16 @@
 //
 // The leaves are rebuilt with the envelope kernels' own line arithmetic, so
 // they are the very points whose stress P^k was taken.  One thread per
-// (point, component): blockIdx.y is the component (i*d + j)*d*d + k*d + l,
-// consecutive threads are consecutive points, and the SoA output
-// A[component * n + p] is written coalesced.  The work per thread is a few
-// leaves of FP64 scalar algebra.
+// (point, row ij of A): each leaf's scalars (J, ln J, psi0, damage factors) are
+// formed once per row, consecutive threads are consecutive points, and the SoA
+// output A[((i*d + j)*d*d + k*d + l) * n + p] is written coalesced.
 #include "r1_kernels.hpp"
 
 namespace r1k {
 
-// d^2 W / dG_ij dG_kl at one point of the line set (ij = i*D + j, kl = k*D + l).
+// Row ij of d^2 W / dG dG at one point of the line set, weighted and added:
+// acc[kl] += w d^2 W / dG_ij dG_kl (ij = i*D + j, kl = k*D + l).  The point's
+// scalars (J, ln J, psi0, the damage factors) are formed once for the row.
 // Neo-Hooke damage (eqs. 2.3, 2.9):
 //   A0 = g' [mu d_ik d_jl + lambda H_ij H_kl - (lambda ln J - mu) H_il H_kj] + g'' S_ij S_kl
 // with H = G^{-T}, S = d psi0 / dG = mu G + (lambda ln J - mu) H, g' = 1 - D(max(psi0, beta_n))
@@ -27,42 +28,65 @@ namespace r1k {
 //                         + mu (G_il G_kj + B_ik d_jl),
 // with the same damage factors g', g''.  Double-well test energy: 2 on the
 // diagonal, 12 G_11^2 - 4 at (11, 11).
-template <int D>
-__device__ __forceinline__ double tangent0_comp(const Material& m, double bn, const double* G, int ij, int kl) {
-  const int i = ij / D, j = ij % D, k = kl / D, l = kl % D;
+template <int D, int IJ>
+__device__ __forceinline__ void tangent0_row(const Material& m, double bn, const double* G, double w, double* acc) {
+  constexpr int ij = IJ, i = IJ / D, j = IJ % D;
   if (m.model == 2) {
     double E[D * D], S[D * D];
     double tr = stvk_strain<D>(G, E);
     double psi = stvk_psi_stress<D>(m, G, S);
-    double Bik = 0.0;
-#pragma unroll
-    for (int r = 0; r < D; ++r) Bik += G[i * D + r] * G[k * D + r];
-    double h = m.lambda * G[ij] * G[kl] + (i == k ? m.lambda * tr * (j == l ? 1.0 : 0.0) + 2.0 * m.mu * E[l * D + j] : 0.0)
-             + m.mu * (G[i * D + l] * G[k * D + j] + (j == l ? Bik : 0.0));
     double g1 = 1.0 - m.D_inf * (1.0 - exp(-(psi > bn ? psi : bn) / m.D0));
     double g2 = psi > bn ? -m.D_inf / m.D0 * exp(-psi / m.D0) : 0.0;
-    return g1 * h + g2 * S[ij] * S[kl];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      double Bik = 0.0;
+#pragma unroll
+      for (int r = 0; r < D; ++r) Bik += G[i * D + r] * G[k * D + r];
+#pragma unroll
+      for (int l = 0; l < D; ++l) {
+        const int kl = k * D + l;
+        double h = m.lambda * G[ij] * G[kl] + m.mu * G[i * D + l] * G[k * D + j];
+        if (i == k) h += (j == l ? m.lambda * tr : 0.0) + 2.0 * m.mu * E[l * D + j];
+        if (j == l) h += m.mu * Bik;
+        acc[kl] += w * (g1 * h + g2 * S[ij] * S[kl]);
+      }
+    }
+    return;
   }
   if (m.model != 0) {
-    if (ij != kl) return 0.0;
-    return ij == 0 ? 12.0 * G[0] * G[0] - 4.0 : 2.0;
+#pragma unroll
+    for (int kl = 0; kl < D * D; ++kl)
+      acc[kl] += w * (kl != ij ? 0.0 : ij == 0 ? 12.0 * G[0] * G[0] - 4.0 : 2.0);
+    return;
   }
   double cof[D * D];
   cofactor<D>(G, cof);
   double J = det_of<D>(G, cof);
-  if (!(J > 0.0)) return __builtin_nan("");
+  if (!(J > 0.0)) {
+#pragma unroll
+    for (int kl = 0; kl < D * D; ++kl) acc[kl] = __builtin_nan("");
+    return;
+  }
   double lnJ = log(J), n2 = 0.0;
 #pragma unroll
-  for (int i = 0; i < D * D; ++i) n2 += G[i] * G[i];
+  for (int r = 0; r < D * D; ++r) n2 += G[r] * G[r];
   double psi = 0.5 * m.mu * (n2 - double(D)) - m.mu * lnJ + 0.5 * m.lambda * lnJ * lnJ;
   double beta = psi > bn ? psi : bn;
   double g1 = 1.0 - m.D_inf * (1.0 - exp(-beta / m.D0));
   double g2 = psi > bn ? -m.D_inf / m.D0 * exp(-psi / m.D0) : 0.0;
   double c = m.lambda * lnJ - m.mu;
-  double Hij = cof[ij] / J, Hkl = cof[kl] / J, Hil = cof[i * D + l] / J, Hkj = cof[k * D + j] / J;
-  double h = (ij == kl ? m.mu : 0.0) + m.lambda * Hij * Hkl - c * Hil * Hkj;
-  double Sij = m.mu * G[ij] + c * Hij, Skl = m.mu * G[kl] + c * Hkl;
-  return g1 * h + g2 * Sij * Skl;
+  const double iJ = 1.0 / J;
+  double Hij = cof[ij] * iJ, Sij = m.mu * G[ij] + c * Hij;
+#pragma unroll
+  for (int k = 0; k < D; ++k)
+#pragma unroll
+    for (int l = 0; l < D; ++l) {
+      const int kl = k * D + l;
+      double Hkl = cof[kl] * iJ, Hil = cof[i * D + l] * iJ, Hkj = cof[k * D + j] * iJ;
+      double h = (ij == kl ? m.mu : 0.0) + m.lambda * Hij * Hkl - c * Hil * Hkj;
+      double Skl = m.mu * G[kl] + c * Hkl;
+      acc[kl] += w * (g1 * h + g2 * Sij * Skl);
+    }
 }
 
 // Endpoints G-/+ of tree node t on level lv around G, and the volume fraction
@@ -81,52 +105,66 @@ __device__ __forceinline__ bool node_split(const Level& lv, const r1_laminate& t
   return true;
 }
 
-// One node's modulus component over its two leaves: xi A0(G+) + (1 - xi) A0(G-).
-template <int D>
-__device__ __forceinline__ double node_tangent(const Material& mat, double bn, const Level& lv, const r1_laminate& t,
-                                               const double* G, int ij, int kl, bool& ok) {
+// Row ij of a node's moduli over its two leaves, weighted by w and added:
+// acc += w (xi A0(G+) + (1 - xi) A0(G-)).
+template <int D, int IJ>
+__device__ __forceinline__ bool node_tangent(const Material& mat, double bn, const Level& lv, const r1_laminate& t,
+                                             const double* G, double w, double* acc) {
   double Gm[D * D], Gp[D * D], xi;
-  ok = node_split<D>(lv, t, G, Gm, Gp, xi);
-  if (!ok) return 0.0;
-  double am = tangent0_comp<D>(mat, bn, Gm, ij, kl);
-  double ap = tangent0_comp<D>(mat, bn, Gp, ij, kl);
-  return xi * ap + (1.0 - xi) * am;
+  if (!node_split<D>(lv, t, G, Gm, Gp, xi)) return false;
+  tangent0_row<D, IJ>(mat, bn, Gp, w * xi, acc);
+  tangent0_row<D, IJ>(mat, bn, Gm, w * (1.0 - xi), acc);
+  return true;
 }
 
+// Row IJ of point p's moduli, A[(IJ*d*d + kl) * n + p].
+template <typename T, int D, int IJ>
+__device__ __forceinline__ void tangent_point_row(const KArgs& a, int depth, const r1_laminate* tree, T* A,
+                                                  int64_t p) {
+  double F[D * D], bn;
+  bool fin = load_point<T, D>(a, p, F, bn);
+  double w = double(static_cast<const T*>(a.W)[p]);
+  double acc[D * D];
+#pragma unroll
+  for (int kl = 0; kl < D * D; ++kl) acc[kl] = 0.0;
+  bool ok = fin && isfinite(w);
+  if (ok) {
+    const r1_laminate* t = tree + p * R1_TREE_NODES;
+    if (depth == 1) {
+      ok = node_tangent<D, IJ>(a.mat, bn, a.lv0, t[0], F, 1.0, acc);
+    } else {
+      double Gm[D * D], Gp[D * D], xi;
+      ok = node_split<D>(a.lv0, t[0], F, Gm, Gp, xi);
+      ok = ok && node_tangent<D, IJ>(a.mat, bn, a.lv1, t[2], Gp, xi, acc);
+      ok = ok && node_tangent<D, IJ>(a.mat, bn, a.lv1, t[1], Gm, 1.0 - xi, acc);
+    }
+  }
+#pragma unroll
+  for (int kl = 0; kl < D * D; ++kl)
+    A[int64_t(IJ * D * D + kl) * a.n + p] = T(ok ? acc[kl] : __builtin_nan(""));
+}
+
+// One thread per (point, row ij of A), blockIdx.y = ij (block-uniform): the row is
+// a compile-time index, so every array access is static.
 template <typename T, int D>
 __global__ __launch_bounds__(256) void k_tangent(KArgs a, int depth, const r1_laminate* tree, T* A) {
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p >= a.n) return;
-  const int comp = blockIdx.y, ij = comp / (D * D), kl = comp % (D * D);
-  double F[D * D], bn;
-  bool fin = load_point<T, D>(a, p, F, bn);
-  double w = double(static_cast<const T*>(a.W)[p]);
-  double out = __builtin_nan("");
-  if (fin && isfinite(w)) {
-    const r1_laminate* t = tree + p * R1_TREE_NODES;
-    bool ok = true;
-    if (depth == 1) {
-      out = node_tangent<D>(a.mat, bn, a.lv0, t[0], F, ij, kl, ok);
-    } else {
-      double Gm[D * D], Gp[D * D], xi;
-      ok = node_split<D>(a.lv0, t[0], F, Gm, Gp, xi);
-      if (ok) {
-        bool okm, okp;
-        double am = node_tangent<D>(a.mat, bn, a.lv1, t[1], Gm, ij, kl, okm);
-        double ap = node_tangent<D>(a.mat, bn, a.lv1, t[2], Gp, ij, kl, okp);
-        ok = okm && okp;
-        out = xi * ap + (1.0 - xi) * am;
-      }
-    }
-    if (!ok) out = __builtin_nan("");
+  switch (blockIdx.y) {
+#define R1_ROW(R)                                                                   \
+    case R:                                                                         \
+      if constexpr (R < D * D) tangent_point_row<T, D, R>(a, depth, tree, A, p);    \
+      break;
+    R1_ROW(0) R1_ROW(1) R1_ROW(2) R1_ROW(3) R1_ROW(4) R1_ROW(5) R1_ROW(6) R1_ROW(7) R1_ROW(8)
+#undef R1_ROW
+    default: break;
   }
-  A[int64_t(comp) * a.n + p] = T(out);
 }
 
 template <typename T, int D>
 hipError_t launch_tangent_TD(const KArgs& a, int depth, const r1_laminate* tree, void* A, hipStream_t st,
                              KTimer* tm) {
-  dim3 blk(256), grd(unsigned((a.n + 255) / 256), D * D * D * D);
+  dim3 blk(256), grd(unsigned((a.n + 255) / 256), D * D);
   if (tm) tm->begin("tangent", st);
   hipLaunchKernelGGL((k_tangent<T, D>), grd, blk, 0, st, a, depth, tree, static_cast<T*>(A));
   if (tm) tm->end(st);
