@@ -300,7 +300,7 @@ extern "C" r1_status r1_envelope_batched(r1_handle h, const r1_material* mat,
       }
       if (b.var < 0) return R1_EUNSUPPORTED;
       if (L.depth == 2) {
-        size_t need = r1k::outer_lds_bytes(ts, L.level[0].n_t, L.level[1].n_dir);
+        size_t need = r1k::outer_lds_bytes(ts, L.level[0].n_t, L.level[1].n_dir, mat->model);
         lds[b.var] = std::max(lds[b.var], need);
       }
     }

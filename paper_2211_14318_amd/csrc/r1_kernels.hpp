@@ -193,19 +193,54 @@ constexpr int kMaxTabDirs = 512;
 // Waves of an outer-line block (blocks are 256 threads).
 constexpr int kOuterWaves = 4;
 
+// Tabulated coefficients per inner direction: 5 for the neo-Hooke family (affine
+// in the outer t), 10 for St. Venant-Kirchhoff (p1 cubic, p2 quadratic, p3 affine,
+// p4 constant in the outer t).
+__host__ __device__ constexpr int tab_coefs(int model) { return model == 2 ? 10 : 5; }
+
 // Bytes of dynamic LDS an outer line needs for samples of elem_bytes bytes:
 // the outer line's samples and, when the inner level is tabulated, its
 // coefficient table, each wave's warm-start bridge slopes and each wave's
 // direction visiting order (int).
-__host__ __device__ inline size_t outer_lds_bytes(size_t elem_bytes, int n_t_outer, int n_dir_inner) {
+__host__ __device__ inline size_t outer_lds_bytes(size_t elem_bytes, int n_t_outer, int n_dir_inner, int model) {
   const bool tab = n_dir_inner <= kMaxTabDirs;
-  return elem_bytes * (size_t(n_t_outer - 1) + (tab ? size_t(5 + kOuterWaves) * size_t(n_dir_inner) : 0)) +
+  return elem_bytes * (size_t(n_t_outer - 1) +
+                       (tab ? size_t(tab_coefs(model) + kOuterWaves) * size_t(n_dir_inner) : 0)) +
          (tab ? sizeof(int) * size_t(kOuterWaves) * size_t(n_dir_inner) : 0);
 }
 
 template <typename T>
-__host__ __device__ inline size_t outer_lds_bytes(const Level& lo, const Level& li) {
-  return outer_lds_bytes(sizeof(T), lo.n_t, li.n_dir);
+__host__ __device__ inline size_t outer_lds_bytes(const Level& lo, const Level& li, int model) {
+  return outer_lds_bytes(sizeof(T), lo.n_t, li.n_dir, model);
+}
+
+// St. Venant-Kirchhoff inner line along the outer line G(t) = F + t R: its
+// coefficients c1 .. c4 (stvk_line) are polynomials in t of degree 3, 2, 1 and 0
+// (E(t) of G(t) is quadratic in t).  Their monomial coefficients are fitted in
+// double from exact evaluations at t = tau {-1, 0, 1, 2}:
+// coef = (c1: t^0..t^3, c2: t^0..t^2, c3: t^0, t^1, c4).
+template <typename T, int D>
+__device__ __forceinline__ void stvk_inner_coef(double lam, double mu, double k, const double* F, const double* R,
+                                                double tau, const double* a, const double* b, T* coef) {
+  double y1[4], y2[4], y3[4], c4 = 0.0;
+  const double u[4] = {-1.0, 0.0, 1.0, 2.0};
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    double G[D * D];
+#pragma unroll
+    for (int r = 0; r < D * D; ++r) G[r] = F[r] + u[s] * tau * R[r];
+    Line<double> L = stvk_line_g<double, D>(lam, mu, k, make_stvk_geom<D>(G), a, b);
+    y1[s] = L.c1; y2[s] = L.c2; y3[s] = L.c3;
+    if (s == 1) c4 = L.c4;
+  }
+  // y(u) = a0 + a1 u + a2 u^2 + a3 u^3 through u = -1, 0, 1, 2; then t = tau u
+  const double a0 = y1[1], a2 = 0.5 * (y1[2] + y1[0]) - y1[1], s1 = 0.5 * (y1[2] - y1[0]);
+  const double a3 = (y1[3] - a0 - 4.0 * a2 - 2.0 * s1) / 6.0, a1 = s1 - a3;
+  const double it = 1.0 / tau;
+  coef[0] = T(a0); coef[1] = T(a1 * it); coef[2] = T(a2 * it * it); coef[3] = T(a3 * it * it * it);
+  coef[4] = T(y2[1]); coef[5] = T(0.5 * (y2[2] - y2[0]) * it); coef[6] = T((0.5 * (y2[2] + y2[0]) - y2[1]) * it * it);
+  coef[7] = T(y3[1]); coef[8] = T(0.5 * (y3[2] - y3[0]) * it);
+  coef[9] = T(c4);
 }
 
 // One outer line (block-level, every thread calls it): the samples W^1(F + t_i R_mo)
@@ -217,14 +252,14 @@ template <typename T, int D, int S, int K, int M>
 __device__ __forceinline__ T outer_line(const KArgs& a, int64_t p, int mo, const Level& lo, const Level& li, T w1f,
                         bool compute_centre, OuterRes<T>* out, char* smem_raw) {
   const int co = (lo.n_t - 1) / 2;
-  // Up to kMaxTabDirs inner directions the waves keep warm-start bridge slopes and
-  // visiting orders in LDS (lds_lines); the inner line coefficients are tabulated
-  // too when they are affine in the outer t (neo-Hooke, double well: tab), while
-  // St. Venant-Kirchhoff's quartic sets each inner line up from G(t).
+  // Up to kMaxTabDirs inner directions the waves keep warm-start bridge slopes,
+  // visiting orders and the inner lines' coefficients as polynomials in the outer t
+  // (tab_coefs) in LDS.
   const bool lds_lines = li.n_dir <= kMaxTabDirs;
-  const bool tab = M != kFamSTVK && lds_lines;
-  T* coef = reinterpret_cast<T*>(smem_raw);                 // 5 * n_dir_i (tab)
-  T* warm = coef + (tab ? 5 * li.n_dir : 0);                // kOuterWaves * n_dir_i (lds_lines)
+  const bool tab = lds_lines;
+  constexpr int NC = tab_coefs(M);
+  T* coef = reinterpret_cast<T*>(smem_raw);                 // NC * n_dir_i (tab)
+  T* warm = coef + (tab ? NC * li.n_dir : 0);               // kOuterWaves * n_dir_i (lds_lines)
   T* wl = warm + (lds_lines ? kOuterWaves * li.n_dir : 0);  // outer samples at -m
   T* wr = wl + co;                                          // outer samples at +m
   int* order = reinterpret_cast<int*>(wr + co);             // kOuterWaves * n_dir_i (lds_lines)
@@ -239,12 +274,18 @@ __device__ __forceinline__ T outer_line(const KArgs& a, int64_t p, int mo, const
     for (int j = 0; j < D; ++j) R[i * D + j] = lo.a[mo * D + i] * lo.b[mo * D + j];
   if (threadIdx.x == 0) { capped_any = 0; centre = w1f; }
   if (tab) {
-    double cofF[D * D], C1[D * D];
-    cofactor<D>(F, cofF);
-    cof_derivative<D>(F, R, C1);
-    for (int i = threadIdx.x; i < li.n_dir; i += blockDim.x)
-      inner_line_coef<T, D>(a.mat.model, line_scale<T>(a.mat), F, cofF, R, C1, li.a + i * D, li.b + i * D,
-                            coef + 5 * i);
+    if constexpr (M == kFamSTVK) {
+      const double k = line_scale<T, M>(a.mat);
+      for (int i = threadIdx.x; i < li.n_dir; i += blockDim.x)
+        stvk_inner_coef<T, D>(a.mat.lambda, a.mat.mu, k, F, R, lo.tau, li.a + i * D, li.b + i * D, coef + NC * i);
+    } else {
+      double cofF[D * D], C1[D * D];
+      cofactor<D>(F, cofF);
+      cof_derivative<D>(F, R, C1);
+      for (int i = threadIdx.x; i < li.n_dir; i += blockDim.x)
+        inner_line_coef<T, D>(a.mat.model, line_scale<T>(a.mat), F, cofF, R, C1, li.a + i * D, li.b + i * D,
+                              coef + NC * i);
+    }
   }
   if (lds_lines)
     for (int i = threadIdx.x; i < kOuterWaves * li.n_dir; i += blockDim.x) warm[i] = T(__builtin_nan(""));
@@ -278,52 +319,62 @@ __device__ __forceinline__ T outer_line(const KArgs& a, int64_t p, int mo, const
     for (int k = 0; k < D * D; ++k) G[k] = F[k] + t * R[k];
     T v;
     if (tab) {
-      // W(G) and the per-sample parts of every inner line: J0 = det G, c0 = kq (|G|^2 - d)
-      // (neo-Hooke) or G11 and the quadratic rest (double well)
-      double cof[D * D];
-      cofactor<D>(G, cof);
-      double J0, c0 = 0.0;
-      if (a.mat.model == 0) {
-        J0 = det_of<D>(G, cof);
-#pragma unroll
-        for (int k = 0; k < D * D; ++k) c0 += G[k] * G[k];
-        c0 = q.kq * (c0 - double(D));
+      if constexpr (M == kFamSTVK) {
+        // W(G) and c0 = k psi0(G), shared by every inner line; c1 .. c4 from the table
+        double cof[D * D];
+        cofactor<D>(G, cof);
+        const double zero[D] = {};
+        const Line<T> L0 = line_setup<T, D, M>(q, G, cof, zero, zero);
+        T wc = w_sample_stvk<T>(T(0), L0, q);
+        v = wc;
+        if (wc < inf_v<T>()) {
+          const T tt = T(t);
+          Env<T> e = envelope_lines<T, S, K, M>(q, wc, li.n_dir, lay, [&](int dd) {
+            const T* cf = coef + NC * dd;
+            Line<T> L;
+            L.J0 = T(0);
+            L.J1 = T(0);
+            L.c0 = L0.c0;
+            L.c1 = fma(tt, fma(tt, fma(tt, cf[3], cf[2]), cf[1]), cf[0]);
+            L.c2 = fma(tt, fma(tt, cf[6], cf[5]), cf[4]);
+            L.c3 = fma(tt, cf[8], cf[7]);
+            L.c4 = cf[9];
+            return L;
+          }, warm_w, T(__builtin_nan("")), order_w);
+          v = e.h;
+          capped |= e.capped;
+        }
       } else {
-        J0 = G[0];
+        // W(G) and the per-sample parts of every inner line: J0 = det G, c0 = kq (|G|^2 - d)
+        // (neo-Hooke) or G11 and the quadratic rest (double well)
+        double cof[D * D];
+        cofactor<D>(G, cof);
+        double J0, c0 = 0.0;
+        if (a.mat.model == 0) {
+          J0 = det_of<D>(G, cof);
 #pragma unroll
-        for (int i = 0; i < D; ++i)
+          for (int k = 0; k < D * D; ++k) c0 += G[k] * G[k];
+          c0 = q.kq * (c0 - double(D));
+        } else {
+          J0 = G[0];
 #pragma unroll
-          for (int j = 0; j < D; ++j)
-            if (i || j) c0 += (G[i * D + j] - (i == j ? 1.0 : 0.0)) * (G[i * D + j] - (i == j ? 1.0 : 0.0));
-      }
-      Line<T> L0 = {T(J0), T(0), T(c0), T(0), T(0)};
-      T wc = q.model == 0 ? w_sample<T>(T(0), L0, q) : w_sample_doublewell<T>(T(0), L0);
-      v = wc;
-      if (wc < inf_v<T>()) {
-        const T tt = T(t);
-        Env<T> e = envelope_lines<T, S, K>(q, wc, li.n_dir, lay, [&](int dd) {
-          const T* cf = coef + 5 * dd;
-          return Line<T>{L0.J0, T(fma(tt, cf[1], cf[0])), L0.c0, T(fma(tt, cf[3], cf[2])), cf[4]};
-        }, warm_w, T(q.kq * li.ab2), order_w);
-        v = e.h;
-        capped |= e.capped;
-      }
-    } else if (M == kFamSTVK && lds_lines) {
-      // inner lines set up from G's geometry, with the warm starts and visiting order
-      double cof[D * D];
-      cofactor<D>(G, cof);
-      T wc = w_point<T, D, M>(q, G, cof);
-      v = wc;
-      if (wc < inf_v<T>()) {
-        const auto g = make_geom_m<D, M>(G);
-        Env<T> e = envelope_lines<T, S, K, M>(q, wc, li.n_dir, lay, [&](int dd) {
-          double ai[D], bi[D];
+          for (int i = 0; i < D; ++i)
 #pragma unroll
-          for (int i = 0; i < D; ++i) { ai[i] = li.a[dd * D + i]; bi[i] = li.b[dd * D + i]; }
-          return line_of<T, D, M>(q, g, ai, bi);
-        }, warm_w, T(__builtin_nan("")), order_w);
-        v = e.h;
-        capped |= e.capped;
+            for (int j = 0; j < D; ++j)
+              if (i || j) c0 += (G[i * D + j] - (i == j ? 1.0 : 0.0)) * (G[i * D + j] - (i == j ? 1.0 : 0.0));
+        }
+        Line<T> L0 = {T(J0), T(0), T(c0), T(0), T(0)};
+        T wc = q.model == 0 ? w_sample<T>(T(0), L0, q) : w_sample_doublewell<T>(T(0), L0);
+        v = wc;
+        if (wc < inf_v<T>()) {
+          const T tt = T(t);
+          Env<T> e = envelope_lines<T, S, K>(q, wc, li.n_dir, lay, [&](int dd) {
+            const T* cf = coef + NC * dd;
+            return Line<T>{L0.J0, T(fma(tt, cf[1], cf[0])), L0.c0, T(fma(tt, cf[3], cf[2])), cf[4]};
+          }, warm_w, T(q.kq * li.ab2), order_w);
+          v = e.h;
+          capped |= e.capped;
+        }
       }
     } else {
       double cof[D * D];
@@ -471,7 +522,7 @@ hipError_t launch_T(const KArgs& a, int depth, hipStream_t st, KTimer* tm) {
   if (tm) tm->begin("depth2_centre", st);
   hipLaunchKernelGGL((k_depth1<T, D, S, K, M>), grd, blk, 0, st, pre);
   if (tm) tm->end(st);
-  size_t lds = outer_lds_bytes<T>(a.lv0, a.lv1);
+  size_t lds = outer_lds_bytes<T>(a.lv0, a.lv1, M);
   dim3 grd_o(unsigned(a.n * a.lv0.n_dir));
   if (tm) tm->begin("outer", st);
   hipLaunchKernelGGL((k_outer<T, D, S, K, M>), grd_o, blk, lds, st, a);
