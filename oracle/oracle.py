@@ -15,7 +15,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
-SOURCES = ["energy.c", "hull.c", "lamination.c", "mlp.c"]
+SOURCES = ["energy.c", "hull.c", "lamination.c", "mlp.c", "grid.c"]
 
 MODEL_NH_DAMAGE = 0
 MODEL_DOUBLEWELL = 1
@@ -105,6 +105,21 @@ def lib():
         L.orc_mlp_forward.argtypes = [ctypes.c_int] * 4 + [dp, ctypes.c_long, dp, dp, dp]
         L.orc_mlp_loss_grad.restype = ctypes.c_double
         L.orc_mlp_loss_grad.argtypes = [ctypes.c_int] * 4 + [dp, ctypes.c_long, dp, dp, dp]
+        gp = ctypes.POINTER(Grid)
+        L.orc_grid_size.restype = ctypes.c_long
+        L.orc_grid_size.argtypes = [gp]
+        L.orc_grid_node.restype = None
+        L.orc_grid_node.argtypes = [gp, ctypes.c_long, dp]
+        L.orc_grid_r11.restype = ctypes.c_int
+        L.orc_grid_r11.argtypes = [ctypes.c_int, ip]
+        L.orc_grid_energy.restype = None
+        L.orc_grid_energy.argtypes = [ctypes.POINTER(Material), gp, ctypes.c_double, dp]
+        L.orc_grid_sweep.restype = ctypes.c_double
+        L.orc_grid_sweep.argtypes = [gp, ctypes.c_int, ip, dp, dp]
+        L.orc_grid_laminate.restype = ctypes.c_int
+        L.orc_grid_laminate.argtypes = [gp, ctypes.c_int, ip, dp, ctypes.c_int, ctypes.c_double, dp]
+        L.orc_grid_interpolate.restype = ctypes.c_double
+        L.orc_grid_interpolate.argtypes = [gp, dp, dp]
         _lib = L
     return _lib
 
@@ -296,3 +311,70 @@ def mlp_loss_grad(shape, params, x, y):
     loss = lib().orc_mlp_loss_grad(d_in, width, n_hidden, d_out, _dp(params), x.shape[0], _dp(x),
                                    _dp(y), _dp(g))
     return loss, g
+
+
+# ---- global lamination on a deformation-gradient mesh (grid.c)
+
+class Grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 9), ("lo", ctypes.c_double * 9),
+                ("delta", ctypes.c_double)]
+
+
+def grid(dim, n, lo, delta):
+    """Mesh with n[c] nodes lo[c] + k delta per component c = i*d + j."""
+    g = Grid()
+    g.dim = dim
+    for c in range(dim * dim):
+        g.n[c] = int(n[c])
+        g.lo[c] = float(lo[c])
+    g.delta = float(delta)
+    return g
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def grid_size(g):
+    return lib().orc_grid_size(ctypes.byref(g))
+
+
+def grid_node(g, p):
+    F = np.empty(g.dim * g.dim)
+    lib().orc_grid_node(ctypes.byref(g), ctypes.c_long(p), _dp(F))
+    return F.reshape(g.dim, g.dim)
+
+
+def grid_r11(dim):
+    steps = np.zeros((729, dim * dim), dtype=np.int32)
+    k = lib().orc_grid_r11(dim, _ip(steps))
+    return steps[:k].copy()
+
+
+def grid_energy(mat, g, beta_n):
+    W = np.empty(grid_size(g))
+    lib().orc_grid_energy(ctypes.byref(mat), ctypes.byref(g), float(beta_n), _dp(W))
+    return W
+
+
+def grid_sweep(g, steps, Win):
+    steps = np.ascontiguousarray(steps, dtype=np.int32)
+    Win = np.ascontiguousarray(Win, dtype=np.float64)
+    Wout = np.empty_like(Win)
+    md = lib().orc_grid_sweep(ctypes.byref(g), len(steps), _ip(steps), _dp(Win), _dp(Wout))
+    return Wout, md
+
+
+def grid_laminate(g, steps, W, k_max=20, tol=1e-4):
+    steps = np.ascontiguousarray(steps, dtype=np.int32)
+    W = np.array(W, dtype=np.float64)
+    hist = np.zeros(max(k_max, 1))
+    k = lib().orc_grid_laminate(ctypes.byref(g), len(steps), _ip(steps), _dp(W), int(k_max), float(tol), _dp(hist))
+    return W, hist[:k].copy()
+
+
+def grid_interpolate(g, W, F):
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    return lib().orc_grid_interpolate(ctypes.byref(g), _dp(W), _dp(F))
+

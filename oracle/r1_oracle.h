@@ -129,6 +129,27 @@ double orc_mlp_forward(int d_in, int width, int n_hidden, int d_out, const doubl
 double orc_mlp_loss_grad(int d_in, int width, int n_hidden, int d_out, const double* params,
                          long B, const double* x, const double* y, double* grad);
 
+/* ---- global lamination on a deformation-gradient mesh (grid.c) ---- */
+
+/* Mesh of Section 5.2 with one mesh width for every component: component c =
+ * i*d + j takes the values lo[c] + k delta, k = 0..n[c]-1.  Node p enumerates
+ * the components with component 0 varying slowest. */
+typedef struct {
+    int dim;
+    int n[9];
+    double lo[9];
+    double delta;
+} orc_grid;
+
+long orc_grid_size(const orc_grid* g);
+void orc_grid_node(const orc_grid* g, long p, double* F);
+int orc_grid_r11(int dim, int* steps);
+void orc_grid_energy(const orc_material* mat, const orc_grid* g, double beta_n, double* W);
+double orc_grid_sweep(const orc_grid* g, int n_dir, const int* steps, const double* Win, double* Wout);
+int orc_grid_laminate(const orc_grid* g, int n_dir, const int* steps, double* W, int k_max, double tol,
+                      double* hist);
+double orc_grid_interpolate(const orc_grid* g, const double* W, const double* F);
+
 #ifdef __cplusplus
 }
 #endif

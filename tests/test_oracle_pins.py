@@ -636,3 +636,127 @@ def test_mlp_oracle_forward_small_closed_form():
     out, _ = O.mlp_forward(shape, params, x)
     z = 0.7 * 0.4 - 0.2
     assert abs(out[0, 0] - (1.5 * z / (1 + math.exp(-z)) + 0.3)) < 1e-15
+
+
+# ---------------------------------------------------------------- global lamination on a mesh
+
+def test_grid_reduced_direction_set():
+    """Eq. 5.1: a (x) b with a, b in {-1, 0, 1}^d is 16 distinct rank-one directions in 2D
+    when the sign is not counted (stated in Section 5.1); in 3D (3^3 - 1)^2 / 4 = 169."""
+    for dim, count in ((2, 16), (3, 169)):
+        S = O.grid_r11(dim)
+        assert len(S) == count
+        seen = set()
+        for s in S:
+            M = s.reshape(dim, dim)
+            assert np.linalg.matrix_rank(M) == 1 and set(np.unique(M)) <= {-1, 0, 1}
+            key, neg = tuple(s), tuple(-s)
+            assert key not in seen and neg not in seen
+            seen.add(key)
+
+
+def brute_sweep(g, steps, W):
+    """Eq. 4.3 by its definition: at every node and direction, the minimum over all pairs
+    of finite line nodes l1 < 0 < l2 of the chord value at l = 0 (exact rationals), the node
+    itself included; non-finite nodes stay non-finite."""
+    dd = g.dim * g.dim
+    dims = [g.n[c] for c in range(dd)]
+    out = np.array(W, dtype=np.float64)
+    for p, I in enumerate(np.ndindex(*dims)):
+        if not np.isfinite(W[p]):
+            continue
+        best = Fraction(W[p])
+        for s in steps:
+            line = {}
+            for l in range(-max(dims), max(dims) + 1):
+                J = [I[c] + l * s[c] for c in range(dd)]
+                if all(0 <= J[c] < dims[c] for c in range(dd)):
+                    q = int(np.ravel_multi_index(J, dims))
+                    if np.isfinite(W[q]):
+                        line[l] = Fraction(W[q])
+            for l1 in [l for l in line if l < 0]:
+                for l2 in [l for l in line if l > 0]:
+                    best = min(best, (line[l1] * l2 - line[l2] * l1) / (l2 - l1))
+        out[p] = float(best)
+    return out
+
+
+@pytest.mark.parametrize("dim,n", [(2, (4, 3, 3, 5)), (3, (3, 2, 2, 2, 3, 2, 2, 2, 2))])
+def test_grid_sweep_against_brute_force(dim, n):
+    """One iteration of eq. 4.3 on small meshes with random node values (some +inf) equals
+    the definition evaluated by brute force over all chords of every line."""
+    rng = np.random.default_rng(31 + dim)
+    g = O.grid(dim, n, [0.0] * (dim * dim), 0.5)
+    N = O.grid_size(g)
+    W = rng.normal(size=N)
+    W[rng.random(N) < 0.1] = np.inf
+    steps = O.grid_r11(dim)
+    Wout, md = O.grid_sweep(g, steps, W)
+    ref = brute_sweep(g, steps, W)
+    fin = np.isfinite(W)
+    assert np.array_equal(np.isfinite(Wout), fin)
+    assert np.max(np.abs(Wout[fin] - ref[fin])) <= 1e-14
+    assert abs(md - np.max(W[fin] - ref[fin])) <= 1e-14
+    assert np.sum(Wout[fin] < W[fin]) > N // 10
+
+
+def test_grid_double_well_reaches_its_envelope():
+    """Double-well test energy on a mesh whose F11 values include +-1: the rank-one convex
+    envelope is max(F11^2 - 1, 0)^2 + the convex rest; the direction e1 (x) e1 reaches it at
+    every node in the first iteration, and the second changes nothing."""
+    mat = O.material(dim=2, model=O.MODEL_DOUBLEWELL)
+    g = O.grid(2, [9, 3, 3, 5], [-2.0, -0.5, -0.5, 0.0], 0.5)
+    W0 = O.grid_energy(mat, g, 0.0)
+    W, hist = O.grid_laminate(g, O.grid_r11(2), W0, k_max=5, tol=0.0)
+    env = np.array([max(F[0, 0] ** 2 - 1.0, 0.0) ** 2 + F[0, 1] ** 2 + F[1, 0] ** 2 + (F[1, 1] - 1.0) ** 2
+                    for F in (O.grid_node(g, p) for p in range(O.grid_size(g)))])
+    Wk, h1 = O.grid_laminate(g, O.grid_r11(2), W0, k_max=1, tol=0.0)
+    assert np.max(np.abs(Wk - env)) < 1e-14 and h1[0] > 0.5
+    assert np.max(np.abs(W - env)) < 1e-14 and hist[1] == 0.0 and len(hist) == 2
+
+
+def test_grid_stvk_convergence_matches_printed_table():
+    """Section 6.1, STVK: the maximal decrease per iteration on the paper's mesh with R^1_1.
+    Readings: the printed rows count two start-value rows (the first informative row, k = 3,
+    is our second iteration), and the history value is the one the printed STVK curves
+    carry (0.0799, recovered from the 3D figure's W(I); the tables' 0.07 gives 0.18628 here).
+    The first informative value agrees to the printed digits' order (1e-4 relative), the
+    second to 0.3%, later ones within 13%, and the run stops one iteration after the last
+    printed row, as the paper's does."""
+    g = O.grid(2, [20, 41, 41, 20], [0.1, -2.0, -2.0, 0.1], 0.1)
+    assert O.grid_size(g) == 672400
+    mat = O.material(dim=2, model=O.MODEL_STVK_DAMAGE, mu=1.0, lam=0.5, D_inf=0.9, D0=0.3)
+    gold = load_golden("stvk2d_grid_convergence.txt")
+    printed = gold[2:, 2]
+    printed = printed[np.isfinite(printed)]
+    beta_k = recover_beta(stvk(3), load_golden("stvk3d_rankd_paths.txt")[9, 1])
+    _, hist = O.grid_laminate(g, O.grid_r11(2), O.grid_energy(mat, g, beta_k), k_max=20, tol=1e-4)
+    ours = hist[1:]
+    assert len(ours) == len(printed) + 1 and ours[-1] <= 1e-4 < ours[-2]
+    rel = np.abs(ours[:-1] - printed) / printed
+    assert rel[0] < 1e-4 and rel[1] < 3e-3 and np.all(np.abs(ours[:-1] - printed) <= 0.13 * printed + 5e-6), rel
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_grid_interpolation_is_multilinear(dim):
+    """Off-mesh values (Section 4.1): node values at nodes; an affine function of F is
+    reproduced exactly anywhere in the box, and so is a product of one affine factor per
+    component (multilinear); NaN outside the box."""
+    rng = np.random.default_rng(40 + dim)
+    dd = dim * dim
+    n = [3] * dd if dim == 2 else [2, 3, 2, 2, 3, 2, 2, 2, 3]
+    lo = rng.uniform(-1, 1, dd)
+    g = O.grid(dim, n, lo, 0.4)
+    nodes = np.array([O.grid_node(g, p).ravel() for p in range(O.grid_size(g))])
+    c = rng.normal(size=dd)
+    affine = nodes @ c + 0.3
+    multi = np.prod(1.0 + 0.5 * (nodes - lo) * c, axis=1)
+    for p in rng.choice(len(nodes), 5, replace=False):
+        assert O.grid_interpolate(g, affine, nodes[p]) == pytest.approx(affine[p], abs=1e-14)
+    hi = lo + 0.4 * (np.array(n) - 1)
+    for _ in range(20):
+        F = rng.uniform(lo, hi)
+        assert abs(O.grid_interpolate(g, affine, F) - (F @ c + 0.3)) < 1e-13
+        assert abs(O.grid_interpolate(g, multi, F) - np.prod(1.0 + 0.5 * (F - lo) * c)) < 1e-13
+    out = hi + 0.1
+    assert np.isnan(O.grid_interpolate(g, affine, out))
