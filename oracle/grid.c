@@ -92,13 +92,20 @@ int orc_grid_r11(int dim, int* steps)
     return count;
 }
 
-void orc_grid_energy(const orc_material* mat, const orc_grid* g, double beta_n, double* W)
+/* W^0 = W at every node and, if P != NULL, P^0 = dW/dF (eq. 2.12), component-major
+ * P[c * nodes + p]. */
+void orc_grid_energy(const orc_material* mat, const orc_grid* g, double beta_n, double* W, double* P)
 {
     long n = orc_grid_size(g);
-    double F[9];
+    double F[9], S[9];
     for (long p = 0; p < n; ++p) {
         orc_grid_node(g, p, F);
         W[p] = orc_energy(mat, F, beta_n);
+        if (P) {
+            orc_stress0(mat, F, beta_n, S);
+            for (int c = 0; c < g->dim * g->dim; ++c)
+                P[c * n + p] = S[c];
+        }
     }
 }
 
@@ -107,8 +114,15 @@ void orc_grid_energy(const orc_material* mat, const orc_grid* g, double beta_n, 
  * line reads the hull at its own position; Wout is the
  * minimum over directions, starting from Win (every node is a sample of each of
  * its lines; a non-finite node stays so).  Returns max over nodes with finite
- * Win of Win - Wout. */
-double orc_grid_sweep(const orc_grid* g, int n_dir, const int* steps, const double* Win, double* Wout)
+ * Win of Win - Wout.
+ *
+ * With Pin/Pout (node stresses, component-major, nullable) the laminate that
+ * lowers a node carries the stress of eq. 5.2 (first case): a node q inside the
+ * hull segment [a, b] takes ((b - q) P_a + (q - a) P_b) / (b - a), the weights of
+ * its value.  Only a strictly lower value replaces the node's current one, so a
+ * tie keeps the first direction's laminate. */
+double orc_grid_sweep(const orc_grid* g, int n_dir, const int* steps, const double* Win, double* Wout,
+                      const double* Pin, double* Pout)
 {
     const int dd = g->dim * g->dim;
     const long n = orc_grid_size(g);
@@ -122,6 +136,8 @@ double orc_grid_sweep(const orc_grid* g, int n_dir, const int* steps, const doub
     double* v = (double*)malloc(sizeof(double) * (size_t)maxlen);
     int* vert = (int*)malloc(sizeof(int) * (size_t)maxlen);
     memcpy(Wout, Win, sizeof(double) * (size_t)n);
+    if (Pin && Pout)
+        memcpy(Pout, Pin, sizeof(double) * (size_t)n * (size_t)dd);
     for (int m = 0; m < n_dir; ++m) {
         const int* s = steps + m * dd;
         int zero = 1;
@@ -171,8 +187,13 @@ double orc_grid_sweep(const orc_grid* g, int n_dir, const int* steps, const doub
                     if (!isfinite(w[q]))
                         continue;
                     double val = ((double)(b - q) * w[a] + (double)(q - a) * w[b]) / (double)(b - a);
-                    if (val < Wout[node[q]])
+                    if (val < Wout[node[q]]) {
                         Wout[node[q]] = val;
+                        if (Pin && Pout)
+                            for (int c = 0; c < dd; ++c)
+                                Pout[c * n + node[q]] = ((double)(b - q) * Pin[c * n + node[a]] +
+                                                         (double)(q - a) * Pin[c * n + node[b]]) / (double)(b - a);
+                    }
                 }
             }
         }
@@ -189,23 +210,73 @@ double orc_grid_sweep(const orc_grid* g, int n_dir, const int* steps, const doub
     return md;
 }
 
+/* Eq. 4.3 at one node p: the minimum over directions of the lower hull of the
+ * line through p read at p (orc_hull_at_centre), and W[p] itself. */
+double orc_grid_update_node(const orc_grid* g, int n_dir, const int* steps, const double* W, long p)
+{
+    const int dd = g->dim * g->dim;
+    int maxlen = 1;
+    for (int c = 0; c < dd; ++c)
+        if (g->n[c] > maxlen)
+            maxlen = g->n[c];
+    double* w = (double*)malloc(sizeof(double) * (size_t)(2 * maxlen + 1));
+    int I[9];
+    unflatten(g, p, I);
+    double best = W[p];
+    for (int m = 0; m < n_dir && isfinite(best); ++m) {
+        const int* s = steps + m * dd;
+        int lo = -2 * maxlen, hi = 2 * maxlen;
+        for (int c = 0; c < dd; ++c) {
+            if (s[c] > 0) {
+                int a = -I[c] / s[c], b = (g->n[c] - 1 - I[c]) / s[c];
+                if (a > lo) lo = a;
+                if (b < hi) hi = b;
+            } else if (s[c] < 0) {
+                int a = -(g->n[c] - 1 - I[c]) / (-s[c]), b = I[c] / (-s[c]);
+                if (a > lo) lo = a;
+                if (b < hi) hi = b;
+            }
+        }
+        if (lo == -2 * maxlen)
+            continue;                       /* the zero step */
+        int L = 0, J[9];
+        for (int l = lo; l <= hi; ++l) {
+            for (int c = 0; c < dd; ++c)
+                J[c] = I[c] + l * s[c];
+            w[L++] = W[flatten(g, J)];
+        }
+        int im, ip;
+        double v = orc_hull_at_centre(L, w, -lo, &im, &ip, NULL);
+        if (v < best)
+            best = v;
+    }
+    free(w);
+    return best;
+}
+
 /* Iterates eq. 4.3 in place until the maximal decrease of an iteration is at
  * most tol or k_max iterations are done (Section 6).  hist[k-1] receives the
- * maximal decrease of iteration k.  Returns the number of iterations done. */
-int orc_grid_laminate(const orc_grid* g, int n_dir, const int* steps, double* W, int k_max, double tol,
-                      double* hist)
+ * maximal decrease of iteration k.  P (nullable): node stresses carried along
+ * (see orc_grid_sweep).  Returns the number of iterations done. */
+int orc_grid_laminate(const orc_grid* g, int n_dir, const int* steps, double* W, double* P, int k_max,
+                      double tol, double* hist)
 {
     long n = orc_grid_size(g);
+    size_t np = P ? (size_t)n * (size_t)(g->dim * g->dim) : 0;
     double* next = (double*)malloc(sizeof(double) * (size_t)n);
+    double* pnext = P ? (double*)malloc(sizeof(double) * np) : NULL;
     int k = 0;
     while (k < k_max) {
-        double md = orc_grid_sweep(g, n_dir, steps, W, next);
+        double md = orc_grid_sweep(g, n_dir, steps, W, next, P, pnext);
         memcpy(W, next, sizeof(double) * (size_t)n);
+        if (P)
+            memcpy(P, pnext, sizeof(double) * np);
         hist[k++] = md;
         if (md <= tol)
             break;
     }
     free(next);
+    free(pnext);
     return k;
 }
 

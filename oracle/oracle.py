@@ -113,11 +113,13 @@ def lib():
         L.orc_grid_r11.restype = ctypes.c_int
         L.orc_grid_r11.argtypes = [ctypes.c_int, ip]
         L.orc_grid_energy.restype = None
-        L.orc_grid_energy.argtypes = [ctypes.POINTER(Material), gp, ctypes.c_double, dp]
+        L.orc_grid_energy.argtypes = [ctypes.POINTER(Material), gp, ctypes.c_double, dp, dp]
         L.orc_grid_sweep.restype = ctypes.c_double
-        L.orc_grid_sweep.argtypes = [gp, ctypes.c_int, ip, dp, dp]
+        L.orc_grid_sweep.argtypes = [gp, ctypes.c_int, ip, dp, dp, dp, dp]
+        L.orc_grid_update_node.restype = ctypes.c_double
+        L.orc_grid_update_node.argtypes = [gp, ctypes.c_int, ip, dp, ctypes.c_long]
         L.orc_grid_laminate.restype = ctypes.c_int
-        L.orc_grid_laminate.argtypes = [gp, ctypes.c_int, ip, dp, ctypes.c_int, ctypes.c_double, dp]
+        L.orc_grid_laminate.argtypes = [gp, ctypes.c_int, ip, dp, dp, ctypes.c_int, ctypes.c_double, dp]
         L.orc_grid_interpolate.restype = ctypes.c_double
         L.orc_grid_interpolate.argtypes = [gp, dp, dp]
         _lib = L
@@ -351,30 +353,47 @@ def grid_r11(dim):
     return steps[:k].copy()
 
 
-def grid_energy(mat, g, beta_n):
+def grid_energy(mat, g, beta_n, stress=False):
+    """W^0 at the nodes; with stress=True also P^0, shape (d*d, nodes)."""
     W = np.empty(grid_size(g))
-    lib().orc_grid_energy(ctypes.byref(mat), ctypes.byref(g), float(beta_n), _dp(W))
-    return W
+    P = np.empty((g.dim * g.dim, grid_size(g))) if stress else None
+    lib().orc_grid_energy(ctypes.byref(mat), ctypes.byref(g), float(beta_n), _dp(W), _dp(P) if stress else None)
+    return (W, P) if stress else W
 
 
-def grid_sweep(g, steps, Win):
+def grid_sweep(g, steps, Win, Pin=None):
     steps = np.ascontiguousarray(steps, dtype=np.int32)
     Win = np.ascontiguousarray(Win, dtype=np.float64)
     Wout = np.empty_like(Win)
-    md = lib().orc_grid_sweep(ctypes.byref(g), len(steps), _ip(steps), _dp(Win), _dp(Wout))
-    return Wout, md
+    if Pin is None:
+        md = lib().orc_grid_sweep(ctypes.byref(g), len(steps), _ip(steps), _dp(Win), _dp(Wout), None, None)
+        return Wout, md
+    Pin = np.ascontiguousarray(Pin, dtype=np.float64)
+    Pout = np.empty_like(Pin)
+    md = lib().orc_grid_sweep(ctypes.byref(g), len(steps), _ip(steps), _dp(Win), _dp(Wout), _dp(Pin), _dp(Pout))
+    return Wout, md, Pout
 
 
-def grid_laminate(g, steps, W, k_max=20, tol=1e-4):
+def grid_laminate(g, steps, W, k_max=20, tol=1e-4, P=None):
+    """Returns (W, hist) or, with node stresses P, (W, hist, P)."""
     steps = np.ascontiguousarray(steps, dtype=np.int32)
     W = np.array(W, dtype=np.float64)
     hist = np.zeros(max(k_max, 1))
-    k = lib().orc_grid_laminate(ctypes.byref(g), len(steps), _ip(steps), _dp(W), int(k_max), float(tol), _dp(hist))
-    return W, hist[:k].copy()
+    Pc = None if P is None else np.array(P, dtype=np.float64)
+    k = lib().orc_grid_laminate(ctypes.byref(g), len(steps), _ip(steps), _dp(W), None if Pc is None else _dp(Pc),
+                                int(k_max), float(tol), _dp(hist))
+    return (W, hist[:k].copy()) if Pc is None else (W, hist[:k].copy(), Pc)
 
 
 def grid_interpolate(g, W, F):
     W = np.ascontiguousarray(W, dtype=np.float64)
     F = np.ascontiguousarray(F, dtype=np.float64)
     return lib().orc_grid_interpolate(ctypes.byref(g), _dp(W), _dp(F))
+
+
+def grid_update_node(g, steps, W, p):
+    """Eq. 4.3 at node p alone (for sampled checks of large meshes)."""
+    steps = np.ascontiguousarray(steps, dtype=np.int32)
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    return lib().orc_grid_update_node(ctypes.byref(g), len(steps), _ip(steps), _dp(W), ctypes.c_long(p))
 

@@ -698,6 +698,10 @@ def test_grid_sweep_against_brute_force(dim, n):
     assert np.max(np.abs(Wout[fin] - ref[fin])) <= 1e-14
     assert abs(md - np.max(W[fin] - ref[fin])) <= 1e-14
     assert np.sum(Wout[fin] < W[fin]) > N // 10
+    # the single-node form of the same update
+    for p in rng.choice(N, 20, replace=False):
+        v = O.grid_update_node(g, steps, W, int(p))
+        assert (not np.isfinite(W[p]) and not np.isfinite(v)) or abs(v - ref[p]) <= 1e-14
 
 
 def test_grid_double_well_reaches_its_envelope():
@@ -760,3 +764,77 @@ def test_grid_interpolation_is_multilinear(dim):
         assert abs(O.grid_interpolate(g, multi, F) - np.prod(1.0 + 0.5 * (F - lo) * c)) < 1e-13
     out = hi + 0.1
     assert np.isnan(O.grid_interpolate(g, affine, out))
+
+
+def test_grid_stress_follows_the_lowering_laminate():
+    """Eq. 5.2 (first case) on the mesh: after one iteration a lowered node's stress is the
+    chord-weighted stress of the minimising chord's endpoints in the first direction that
+    reaches the node's new value; other nodes keep theirs (brute force over all chords)."""
+    rng = np.random.default_rng(33)
+    g = O.grid(2, (4, 3, 3, 5), [0.0] * 4, 0.5)
+    N = O.grid_size(g)
+    W = rng.normal(size=N)
+    P = rng.normal(size=(4, N))
+    steps = O.grid_r11(2)
+    Wn, md, Pn = O.grid_sweep(g, steps, W, P)
+    dims = [g.n[c] for c in range(4)]
+    lowered = 0
+    for p, I in enumerate(np.ndindex(*dims)):
+        best, arg = Fraction(W[p]), None
+        for s in steps:
+            line = {}
+            for l in range(-6, 7):
+                J = [I[c] + l * s[c] for c in range(4)]
+                if all(0 <= J[c] < dims[c] for c in range(4)):
+                    line[l] = int(np.ravel_multi_index(J, dims))
+            for l1 in [l for l in line if l < 0]:
+                for l2 in [l for l in line if l > 0]:
+                    v = (Fraction(W[line[l1]]) * l2 - Fraction(W[line[l2]]) * l1) / (l2 - l1)
+                    if v < best:
+                        best, arg = v, (line[l1], line[l2], l1, l2)
+        if arg is None:
+            assert np.array_equal(Pn[:, p], P[:, p])
+        else:
+            a, b, l1, l2 = arg
+            ref = (l2 * P[:, a] - l1 * P[:, b]) / (l2 - l1)
+            assert np.max(np.abs(Pn[:, p] - ref)) <= 1e-14, (p, Pn[:, p], ref)
+            lowered += 1
+    assert lowered > N // 10
+
+
+def test_grid_double_well_stress_is_the_envelope_gradient():
+    """Double-well energy: the stress carried to the nodes through the lamination is the
+    gradient of its envelope, (d/dF11 max(F11^2 - 1, 0)^2, 2(F_ij - delta_ij))."""
+    mat = O.material(dim=2, model=O.MODEL_DOUBLEWELL)
+    g = O.grid(2, [9, 3, 3, 5], [-2.0, -0.5, -0.5, 0.0], 0.5)
+    W0, P0 = O.grid_energy(mat, g, 0.0, stress=True)
+    W, hist, P = O.grid_laminate(g, O.grid_r11(2), W0, k_max=5, tol=0.0, P=P0)
+    for p in range(O.grid_size(g)):
+        F = O.grid_node(g, p)
+        ref = 2.0 * (F - np.eye(2))
+        ref[0, 0] = 4.0 * F[0, 0] * (F[0, 0] ** 2 - 1.0) if abs(F[0, 0]) > 1.0 else 0.0
+        assert np.max(np.abs(P[:, p] - ref.ravel())) < 1e-13, (F, P[:, p])
+
+
+def test_grid_stress_tie_keeps_the_first_direction():
+    """Two directions lowering a node to exactly the same value (e1 (x) e1 and e2 (x) e2 on a
+    mesh where only they have lines through the centre): the node keeps the laminate of the
+    direction that comes first in the direction list (R11's smallest index)."""
+    g = O.grid(2, (3, 1, 1, 3), [0.0] * 4, 1.0)
+    steps = O.grid_r11(2)
+    W = np.full(9, 5.0)
+    P = np.zeros((4, 9))
+    idx = lambda i, l: int(np.ravel_multi_index((i, 0, 0, l), (3, 1, 1, 3)))
+    W[idx(1, 1)] = 1.0
+    for i in (0, 2):
+        W[idx(i, 1)] = 0.0
+        P[0, idx(i, 1)] = 1.0           # along F11
+        W[idx(1, i)] = 0.0
+        P[0, idx(1, i)] = -1.0          # along F22
+    order = [tuple(s) for s in steps]
+    first = 1.0 if order.index((1, 0, 0, 0)) < order.index((0, 0, 0, 1)) else -1.0
+    for st in (steps, steps[::-1]):
+        Wn, md, Pn = O.grid_sweep(g, st, W, P)
+        assert Wn[idx(1, 1)] == 0.0
+        expect = first if st is steps else -first
+        assert Pn[0, idx(1, 1)] == expect
