@@ -18,8 +18,9 @@ with routing against plain lamination of the same configuration), `batched`
 `plain_3d` (262,144 3D points, 256 directions x 513 points),
 `surrogate_3d` (a 4 x 256 network on the same 3D workload), `stvk` (the
 headline shapes with the St. Venant-Kirchhoff damage model, 15 flops per
-sample) and `tangent` (Algorithm 3's tangent moduli of 1M depth-1 laminates,
-priced by its algorithmic bytes against HBM).
+sample), `tangent` (Algorithm 3's tangent moduli of 1M depth-1 laminates,
+priced by its algorithmic bytes against HBM) and `grid` (the paper's own grid
+variant of the method on its 2D and 3D meshes, to the stopping rule).
 """
 import argparse
 import json
@@ -384,6 +385,52 @@ def leg_tangent(h, r1, WL, torch, np, reps=20):
             "all_finite": bool(torch.isfinite(A).all().item())}
 
 
+def grid_bytes(n_nodes, n_dir, elem):
+    """Algorithmic HBM bytes of one mesh iteration: every direction reads each node once
+    along its line and writes the next iterate once; plus the iterate copy and the
+    maximal-decrease pass (two node arrays each)."""
+    return elem * n_nodes * (2 * n_dir + 4)
+
+
+def leg_grid(h, r1, WL, torch, np):
+    """Global lamination on the paper's meshes (FP64, reduced direction set R^1_1):
+    Table 6.1's 2D STVK and NH meshes run to the stopping rule (max decrease <= 1e-4,
+    at most 20 iterations), and Table 6.3's 3D STVK mesh for 3 iterations."""
+    mat_t = dict(mu=1.0, lam=0.5, D_inf=0.9, D0=0.3)
+    cases = [("stvk-2d-672400", 2, r1.R1_STVK_DAMAGE, (20, 41, 41, 20), (0.1, -2.0, -2.0, 0.1), 0.1,
+              0.07986236557499998, 20),
+             ("nh-2d-648025", 2, r1.R1_NEOHOOKE_DAMAGE, (23, 35, 35, 23), (0.1, -2.55, -2.55, 0.1), 0.15, 0.06, 20),
+             ("stvk-3d-5832000", 3, r1.R1_STVK_DAMAGE, (20, 3, 3, 3, 20, 3, 3, 3, 20),
+              (0.1, -0.1, -0.1, -0.1, 0.1, -0.1, -0.1, -0.1, 0.1), 0.1, 0.07986236557499998, 3)]
+    out = []
+    for name, dim, model, n, lo, delta, beta, k_max in cases:
+        g = r1.grid(dim, n, lo, delta)
+        steps = r1.grid_r11(dim)
+        mat = r1.material_from(mat_t, dim, model)
+        W = h.grid_energy(mat, g, beta, torch.float64)
+        torch.cuda.synchronize()
+        h.timing(True)
+        h.timing_reset()
+        t0 = time.perf_counter()
+        hist = h.grid_laminate(g, steps, W, k_max=k_max, tol=1e-4)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        ms, cnt = h.timing_query("grid_lines")
+        h.timing(False)
+        nodes = r1.grid_size(g)
+        per_it = t / len(hist)
+        gbs = grid_bytes(nodes, len(steps), 8) / per_it / 1e9
+        out.append({"mesh": name, "nodes": nodes, "directions": len(steps), "iterations": len(hist),
+                    "decrease": [float("%.6g" % v) for v in hist], "ms_total": round(1e3 * t, 2),
+                    "ms_per_iteration": round(1e3 * per_it, 3),
+                    "node_updates_per_s": float(nodes * len(hist) / t),
+                    "lines_kernel_ms_per_launch": round(ms / max(cnt, 1), 4),
+                    "roofline": dict(bound="hbm", kernel="k_grid_lines", achieved=round(gbs, 1), unit="GB/s",
+                                     peak=8000.0, frac=round(gbs / 8000.0, 4),
+                                     bytes_per_iteration=grid_bytes(nodes, len(steps), 8))})
+    return {"workload": "global lamination on the paper's meshes (Tables 6.1, 6.3), FP64, R^1_1", "meshes": out}
+
+
 # ---------------------------------------------------------------- main
 
 def main():
@@ -396,7 +443,7 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
-    ap.add_argument("--leg", choices=["surrogate", "batched", "plain_3d", "surrogate_3d", "stvk", "tangent"],
+    ap.add_argument("--leg", choices=["surrogate", "batched", "plain_3d", "surrogate_3d", "stvk", "tangent", "grid"],
                     help="only run this secondary leg and print its result (a profiling aid)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -420,7 +467,7 @@ def main():
 
     if args.leg:
         legs = dict(surrogate=leg_surrogate, batched=leg_batched, plain_3d=leg_3d,
-                    surrogate_3d=leg_surrogate_3d, stvk=leg_stvk, tangent=leg_tangent)
+                    surrogate_3d=leg_surrogate_3d, stvk=leg_stvk, tangent=leg_tangent, grid=leg_grid)
         h = r1.Handle(0)
         res = legs[args.leg](h, r1, WL, torch, np)
         print(json.dumps({"leg": args.leg, **res}))
@@ -504,6 +551,9 @@ def main():
         log("stvk leg: %.1f QP/s, k_outer %.1f ms" % (out["stvk"]["qps"], out["stvk"]["roofline"]["avg_ms"]))
         out["tangent"] = leg_tangent(h, r1, WL, torch, np)
         log("tangent leg: %.4f ms per 1M points" % out["tangent"]["avg_ms"])
+        out["grid"] = leg_grid(h, r1, WL, torch, np)
+        log("grid leg: " + ", ".join("%s %d it %.1f ms" % (m["mesh"], m["iterations"], m["ms_total"])
+                                     for m in out["grid"]["meshes"]))
         out["surrogate_3d"] = leg_surrogate_3d(h, r1, WL, torch, np)
         log("3d surrogate leg: speedup %.3f, fallback %.3f" % (out["surrogate_3d"]["speedup"],
                                                             out["surrogate_3d"]["fallback_frac"]))

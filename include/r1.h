@@ -216,6 +216,65 @@ r1_status r1_autotune(r1_handle handle, const r1_material* material, int32_t n_t
 r1_status r1_autotune_inner(r1_handle handle, const r1_material* material, int32_t n_t, r1_dtype dtype,
                             void* stream, int32_t* lanes);
 
+/* ---- global lamination on a deformation-gradient mesh -------------------------
+ *
+ * The grid variant of Section 4.1: node values on the mesh of Section 5.2 (one
+ * mesh width for every component, as in all the paper's examples), iterations
+ * of eq. 4.3 -- every node takes the minimum over the directions of the lower
+ * hull (Algorithm 1) of its line (eq. 4.4) through the previous iterate,
+ * clipped to the mesh's box -- and off-mesh values by multilinear
+ * interpolation.
+ *
+ * Component c = i*dim + j of node k_c takes the value lo[c] + k_c*delta,
+ * k_c = 0..n[c]-1 (1 <= n[c] <= 512, at most 2^31 nodes).  Nodes are numbered
+ * with component 0 varying slowest: p = ((k_0*n_1 + k_1)*n_2 + ...).  Node
+ * arrays are dtype[nodes] on the device.  A direction is an integer step
+ * s in Z^{dim x dim} (dim*dim int32, host, not all zero, |s_c| <= 512): the line
+ * through node F holds the nodes F + l*delta*s, l integer, inside the box.
+ * Non-finite node values are absent from every hull and stay as they are. */
+typedef struct {
+    int32_t dim;      /* 2 or 3 */
+    int32_t n[9];     /* nodes per component (first dim*dim entries) */
+    double lo[9];     /* first node value per component */
+    double delta;     /* mesh width, > 0 */
+} r1_grid;
+
+/* The reduced direction set of eq. 5.1, a (x) b with a, b in {-1, 0, 1}^dim
+ * non-zero, one step per line (s and -s are the same line; the kept one has a
+ * positive first non-zero entry): 16 steps in 2D, 169 in 3D, written to steps
+ * (host, capacity 169*9 int32) in a fixed order; *n_dir receives the count. */
+r1_status r1_grid_r11(int32_t dim, int32_t* steps, int32_t* n_dir);
+
+/* W^0: the material's W (eq. 2.9; neo-Hooke: +inf where det F <= 0) at every
+ * node, with history beta_n shared by all nodes (material->dim == grid->dim);
+ * P (nullable, device, dim*dim x nodes component-major) receives P^0 = dW/dF
+ * (eq. 2.12; NaN where W is +inf). */
+r1_status r1_grid_energy(r1_handle handle, const r1_material* material, const r1_grid* grid, double beta_n,
+                         r1_dtype dtype, void* W, void* P, void* stream);
+
+/* Iterates eq. 4.3 in place on W (device node array) until the maximal decrease
+ * max_F (W^k(F) - W^{k+1}(F)) over nodes with finite W^k of an iteration is at
+ * most tol, or k_max iterations are done (Section 6).  iterations (host,
+ * nullable) receives the count; decrease (host, nullable, k_max doubles) the
+ * maximal decrease of each iteration.  P (nullable; node stresses as written by
+ * r1_grid_energy) is carried along: a node lowered by the hull segment [F_a, F_b]
+ * of its line takes the stress of that laminate with the weights of its value
+ * (eq. 5.2, first case).  A laminate replaces a node's value only when it is
+ * lower by more than 4 units of rounding (of dtype) times max(|W|, 1e-3): a node
+ * on a straight hull run reads its own value back up to rounding, and of
+ * directions that tie to rounding the first in `steps` keeps the node.  Interpolating P (r1_grid_interpolate per component) gives
+ * eq. 5.2's second case off the mesh.  Uses handle workspace of one node array
+ * (plus one stress array with P); synchronizes `stream` once per iteration. */
+r1_status r1_grid_laminate(r1_handle handle, const r1_grid* grid, int32_t n_dir, const int32_t* steps,
+                           r1_dtype dtype, void* W, void* P, int32_t k_max, double tol, int32_t* iterations,
+                           double* decrease, void* stream);
+
+/* out[p] = multilinear interpolation of the node values W at F_p (device, SoA
+ * dim*dim x n, dtype); corners of zero weight do not take part; NaN outside the
+ * box (beyond a rounding margin of 1e-9 mesh widths). */
+r1_status r1_grid_interpolate(r1_handle handle, const r1_grid* grid, r1_dtype dtype, const void* W, int64_t n,
+                              const void* F, void* out, void* stream);
+
 /* ---- learned surrogate ---------------------------------------------------------
  *
  * A multilayer perceptron (F, beta_n) -> (W^k, P^k) trained on lamination
@@ -326,7 +385,8 @@ r1_status r1_surrogate_load(r1_handle handle, r1_surrogate* surrogate, const cha
 
 /* When enabled, every kernel launch of the handle is bracketed by HIP events
  * recorded on its launch stream.  Kernel names: "depth1" (one-level envelope),
- * "depth2_centre", "outer", "finalize" (two-level envelope), "tangent" (tangent moduli), "batched".
+ * "depth2_centre", "outer", "finalize" (two-level envelope), "tangent" (tangent moduli),
+ * "grid_lines" (one direction of a mesh iteration), "batched".
  * r1_timing_query waits for the recorded events and returns the summed elapsed
  * milliseconds and the launch count of `kernel` since the last reset. */
 r1_status r1_timing_enable(r1_handle handle, int32_t on);

@@ -14,6 +14,7 @@
  *
  * Test infrastructure only (see r1_oracle.h).
  */
+#include <float.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -116,11 +117,15 @@ void orc_grid_energy(const orc_material* mat, const orc_grid* g, double beta_n, 
  * its lines; a non-finite node stays so).  Returns max over nodes with finite
  * Win of Win - Wout.
  *
+ * A hull value replaces the node's current value only when it is lower by more
+ * than four units of rounding, 4 eps max(|W|, 1e-3): a node on a straight hull
+ * run reads its own value back up to rounding, which is no lamination, and of
+ * directions that tie to rounding the first keeps the node.
+ *
  * With Pin/Pout (node stresses, component-major, nullable) the laminate that
  * lowers a node carries the stress of eq. 5.2 (first case): a node q inside the
  * hull segment [a, b] takes ((b - q) P_a + (q - a) P_b) / (b - a), the weights of
- * its value.  Only a strictly lower value replaces the node's current one, so a
- * tie keeps the first direction's laminate. */
+ * its value. */
 double orc_grid_sweep(const orc_grid* g, int n_dir, const int* steps, const double* Win, double* Wout,
                       const double* Pin, double* Pout)
 {
@@ -187,7 +192,8 @@ double orc_grid_sweep(const orc_grid* g, int n_dir, const int* steps, const doub
                     if (!isfinite(w[q]))
                         continue;
                     double val = ((double)(b - q) * w[a] + (double)(q - a) * w[b]) / (double)(b - a);
-                    if (val < Wout[node[q]]) {
+                    double cur = Wout[node[q]];
+                    if (val < cur - 4.0 * DBL_EPSILON * fmax(fabs(cur), 1e-3)) {
                         Wout[node[q]] = val;
                         if (Pin && Pout)
                             for (int c = 0; c < dd; ++c)

@@ -60,6 +60,39 @@ class TrainReport(ctypes.Structure):
                 ("val_loss", ctypes.c_float), ("ms", ctypes.c_double)]
 
 
+class Grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32 * 9), ("lo", ctypes.c_double * 9),
+                ("delta", ctypes.c_double)]
+
+
+def grid(dim, n, lo, delta):
+    """Mesh description (r1_grid): n[c] nodes lo[c] + k*delta for component c = i*dim + j."""
+    g = Grid()
+    g.dim = dim
+    for c in range(dim * dim):
+        g.n[c] = int(n[c])
+        g.lo[c] = float(lo[c])
+    g.delta = float(delta)
+    return g
+
+
+def grid_size(g):
+    s = 1
+    for c in range(g.dim * g.dim):
+        s *= g.n[c]
+    return s
+
+
+def grid_r11(dim):
+    """Steps of the reduced direction set (eq. 5.1), (count, dim*dim) int32."""
+    buf = (ctypes.c_int32 * (169 * 9))()
+    cnt = ctypes.c_int32()
+    s = _lib.r1_grid_r11(int(dim), buf, ctypes.byref(cnt))
+    if s != 0:
+        raise R1Error(s, "r1_grid_r11", "")
+    return np.array(buf[:cnt.value * dim * dim], dtype=np.int32).reshape(cnt.value, dim * dim)
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libr1.so is not built (%s); run __graft_entry__.build() or "
@@ -80,6 +113,12 @@ def _load():
                                       i32, vp, vp, vp, vp, vp, vp, vp, vp]
     L.r1_laminate_tangent.argtypes = [vp, ctypes.POINTER(Material), ctypes.POINTER(Lamination), i64,
                                       i32, vp, vp, vp, vp, vp, vp]
+    L.r1_grid_r11.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.r1_grid_energy.argtypes = [vp, ctypes.POINTER(Material), ctypes.POINTER(Grid), ctypes.c_double, i32, vp, vp,
+                                 vp]
+    L.r1_grid_laminate.argtypes = [vp, ctypes.POINTER(Grid), i32, ctypes.POINTER(i32), i32, vp, vp, i32,
+                                   ctypes.c_double, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double), vp]
+    L.r1_grid_interpolate.argtypes = [vp, ctypes.POINTER(Grid), i32, vp, i64, vp, vp, vp]
     L.r1_envelope_batched.argtypes = [vp, ctypes.POINTER(Material), ctypes.POINTER(Lamination), i32,
                                       i64, vp, i32, vp, vp, vp, vp, vp, vp, vp]
     L.r1_set_segment_width.argtypes = [vp, i32, i32]
@@ -114,7 +153,8 @@ def _load():
                  "r1_surrogate_loss_grad", "r1_surrogate_save", "r1_surrogate_load"):
         getattr(L, name).restype = i32
     for name in ("r1_autotune", "r1_autotune_inner", "r1_get_inner_segment_width", "r1_timing_enable", "r1_timing_reset", "r1_timing_query", "r1_create", "r1_destroy", "r1_envelope", "r1_envelope_stress",
-                 "r1_envelope_tangent", "r1_laminate_tangent", "r1_envelope_batched", "r1_set_segment_width", "r1_get_segment_width"):
+                 "r1_envelope_tangent", "r1_laminate_tangent", "r1_envelope_batched", "r1_grid_r11",
+                 "r1_grid_energy", "r1_grid_laminate", "r1_grid_interpolate", "r1_set_segment_width", "r1_get_segment_width"):
         getattr(L, name).restype = i32
     return L
 
@@ -288,6 +328,39 @@ class Handle:
                                             _ptr(P), _ptr(tree), _ptr(flags),
                                             self._stream(stream)),
                     "r1_envelope_stress")
+
+    def grid_energy(self, mat, g, beta_n, dtype, stress=False, stream=None):
+        """W^0 at every node of mesh g: (nodes,) device tensor of torch dtype; with
+        stress=True also P^0, (d*d, nodes)."""
+        W = self.torch.empty(grid_size(g), dtype=dtype, device="cuda")
+        P = self.torch.empty((g.dim * g.dim, grid_size(g)), dtype=dtype, device="cuda") if stress else None
+        dt = R1_F32 if dtype == self.torch.float32 else R1_F64
+        self._check(_lib.r1_grid_energy(self.h, ctypes.byref(mat), ctypes.byref(g), float(beta_n), dt, _ptr(W),
+                                        _ptr(P), self._stream(stream)), "r1_grid_energy")
+        return (W, P) if stress else W
+
+    def grid_laminate(self, g, steps, W, k_max=20, tol=1e-4, P=None, stream=None):
+        """Iterates eq. 4.3 in place on W (and the node stresses P); returns the
+        per-iteration maximal decreases."""
+        steps = np.ascontiguousarray(steps, dtype=np.int32)
+        assert W.is_contiguous() and W.numel() == grid_size(g)
+        assert P is None or (P.is_contiguous() and P.shape == (g.dim * g.dim, grid_size(g)) and P.dtype == W.dtype)
+        it = ctypes.c_int32()
+        dec = (ctypes.c_double * int(k_max))()
+        self._check(_lib.r1_grid_laminate(self.h, ctypes.byref(g), len(steps),
+                                          steps.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                          self._dtype_code(W), _ptr(W), _ptr(P), int(k_max), float(tol),
+                                          ctypes.byref(it), dec, self._stream(stream)), "r1_grid_laminate")
+        return np.array(dec[:it.value])
+
+    def grid_interpolate(self, g, W, F, stream=None):
+        """Multilinear interpolation of node values W at points F (d*d, n)."""
+        assert F.is_contiguous() and F.dtype == W.dtype
+        n = F.shape[1]
+        out = self.torch.empty(n, dtype=W.dtype, device=W.device)
+        self._check(_lib.r1_grid_interpolate(self.h, ctypes.byref(g), self._dtype_code(W), _ptr(W), n, _ptr(F),
+                                             _ptr(out), self._stream(stream)), "r1_grid_interpolate")
+        return out
 
     def envelope_batched(self, mat, table_specs, lam_idx, F, beta_n, stress=False, tree=False,
                          flags=True, stream=None):

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -45,3 +46,12 @@ def test_argument_checks_need_no_gpu():
     L = r1.lib()
     assert L.r1_envelope(None, None, None, 1, 0, None, None, None, None, None) == -1
     assert L.r1_create(None, 0) == -1
+
+
+def test_grid_reduced_directions_match_oracle():
+    """r1_grid_r11 is host code: the library's reduced direction set (eq. 5.1) equals the
+    oracle's, in the same order (16 steps in 2D, 169 in 3D)."""
+    from oracle import oracle as O
+    from paper_2211_14318_amd import r1
+    for dim in (2, 3):
+        assert np.array_equal(r1.grid_r11(dim), O.grid_r11(dim))
