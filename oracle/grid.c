@@ -93,19 +93,27 @@ int orc_grid_r11(int dim, int* steps)
     return count;
 }
 
-/* W^0 = W at every node and, if P != NULL, P^0 = dW/dF (eq. 2.12), component-major
- * P[c * nodes + p]. */
-void orc_grid_energy(const orc_material* mat, const orc_grid* g, double beta_n, double* W, double* P)
+/* W^0 = W at every node; if P != NULL, P^0 = dW/dF (eq. 2.12), component-major
+ * P[c * nodes + p]; if A != NULL, the moduli d^2W/dF dF (orc_tangent0),
+ * A[c * nodes + p] with c = (i*d + j)*d*d + k*d + l. */
+void orc_grid_energy(const orc_material* mat, const orc_grid* g, double beta_n, double* W, double* P,
+                     double* A)
 {
     long n = orc_grid_size(g);
-    double F[9], S[9];
+    int dd = g->dim * g->dim;
+    double F[9], S[9], T[81];
     for (long p = 0; p < n; ++p) {
         orc_grid_node(g, p, F);
         W[p] = orc_energy(mat, F, beta_n);
         if (P) {
             orc_stress0(mat, F, beta_n, S);
-            for (int c = 0; c < g->dim * g->dim; ++c)
+            for (int c = 0; c < dd; ++c)
                 P[c * n + p] = S[c];
+        }
+        if (A) {
+            orc_tangent0(mat, F, beta_n, T);
+            for (int c = 0; c < dd * dd; ++c)
+                A[c * n + p] = T[c];
         }
     }
 }
@@ -122,12 +130,12 @@ void orc_grid_energy(const orc_material* mat, const orc_grid* g, double beta_n, 
  * run reads its own value back up to rounding, which is no lamination, and of
  * directions that tie to rounding the first keeps the node.
  *
- * With Pin/Pout (node stresses, component-major, nullable) the laminate that
- * lowers a node carries the stress of eq. 5.2 (first case): a node q inside the
- * hull segment [a, b] takes ((b - q) P_a + (q - a) P_b) / (b - a), the weights of
- * its value. */
-double orc_grid_sweep(const orc_grid* g, int n_dir, const int* steps, const double* Win, double* Wout,
-                      const double* Pin, double* Pout)
+ * Cin/Cout (nullable) hold m per-node quantities, component-major C[c * nodes + p]
+ * -- the stresses (eq. 5.2, first case) and the tangent moduli (Algorithm 3) --
+ * that the laminate lowering a node carries: a node q inside the hull segment
+ * [a, b] takes ((b - q) C_a + (q - a) C_b) / (b - a), the weights of its value. */
+double orc_grid_sweep(const orc_grid* g, int n_dir, const int* steps, const double* Win, double* Wout, int m,
+                      const double* Cin, double* Cout)
 {
     const int dd = g->dim * g->dim;
     const long n = orc_grid_size(g);
@@ -141,10 +149,10 @@ double orc_grid_sweep(const orc_grid* g, int n_dir, const int* steps, const doub
     double* v = (double*)malloc(sizeof(double) * (size_t)maxlen);
     int* vert = (int*)malloc(sizeof(int) * (size_t)maxlen);
     memcpy(Wout, Win, sizeof(double) * (size_t)n);
-    if (Pin && Pout)
-        memcpy(Pout, Pin, sizeof(double) * (size_t)n * (size_t)dd);
-    for (int m = 0; m < n_dir; ++m) {
-        const int* s = steps + m * dd;
+    if (Cin && Cout)
+        memcpy(Cout, Cin, sizeof(double) * (size_t)n * (size_t)m);
+    for (int r = 0; r < n_dir; ++r) {
+        const int* s = steps + r * dd;
         int zero = 1;
         for (int c = 0; c < dd; ++c)
             zero &= s[c] == 0;
@@ -195,10 +203,10 @@ double orc_grid_sweep(const orc_grid* g, int n_dir, const int* steps, const doub
                     double cur = Wout[node[q]];
                     if (val < cur - 4.0 * DBL_EPSILON * fmax(fabs(cur), 1e-3)) {
                         Wout[node[q]] = val;
-                        if (Pin && Pout)
-                            for (int c = 0; c < dd; ++c)
-                                Pout[c * n + node[q]] = ((double)(b - q) * Pin[c * n + node[a]] +
-                                                         (double)(q - a) * Pin[c * n + node[b]]) / (double)(b - a);
+                        if (Cin && Cout)
+                            for (int c = 0; c < m; ++c)
+                                Cout[c * n + node[q]] = ((double)(b - q) * Cin[c * n + node[a]] +
+                                                         (double)(q - a) * Cin[c * n + node[b]]) / (double)(b - a);
                     }
                 }
             }
@@ -262,21 +270,21 @@ double orc_grid_update_node(const orc_grid* g, int n_dir, const int* steps, cons
 
 /* Iterates eq. 4.3 in place until the maximal decrease of an iteration is at
  * most tol or k_max iterations are done (Section 6).  hist[k-1] receives the
- * maximal decrease of iteration k.  P (nullable): node stresses carried along
- * (see orc_grid_sweep).  Returns the number of iterations done. */
-int orc_grid_laminate(const orc_grid* g, int n_dir, const int* steps, double* W, double* P, int k_max,
+ * maximal decrease of iteration k.  C (nullable): m per-node quantities carried
+ * along (see orc_grid_sweep).  Returns the number of iterations done. */
+int orc_grid_laminate(const orc_grid* g, int n_dir, const int* steps, double* W, int m, double* C, int k_max,
                       double tol, double* hist)
 {
     long n = orc_grid_size(g);
-    size_t np = P ? (size_t)n * (size_t)(g->dim * g->dim) : 0;
+    size_t np = C ? (size_t)n * (size_t)m : 0;
     double* next = (double*)malloc(sizeof(double) * (size_t)n);
-    double* pnext = P ? (double*)malloc(sizeof(double) * np) : NULL;
+    double* pnext = C ? (double*)malloc(sizeof(double) * np) : NULL;
     int k = 0;
     while (k < k_max) {
-        double md = orc_grid_sweep(g, n_dir, steps, W, next, P, pnext);
+        double md = orc_grid_sweep(g, n_dir, steps, W, next, m, C, pnext);
         memcpy(W, next, sizeof(double) * (size_t)n);
-        if (P)
-            memcpy(P, pnext, sizeof(double) * np);
+        if (C)
+            memcpy(C, pnext, sizeof(double) * np);
         hist[k++] = md;
         if (md <= tol)
             break;

@@ -113,13 +113,13 @@ def lib():
         L.orc_grid_r11.restype = ctypes.c_int
         L.orc_grid_r11.argtypes = [ctypes.c_int, ip]
         L.orc_grid_energy.restype = None
-        L.orc_grid_energy.argtypes = [ctypes.POINTER(Material), gp, ctypes.c_double, dp, dp]
+        L.orc_grid_energy.argtypes = [ctypes.POINTER(Material), gp, ctypes.c_double, dp, dp, dp]
         L.orc_grid_sweep.restype = ctypes.c_double
-        L.orc_grid_sweep.argtypes = [gp, ctypes.c_int, ip, dp, dp, dp, dp]
+        L.orc_grid_sweep.argtypes = [gp, ctypes.c_int, ip, dp, dp, ctypes.c_int, dp, dp]
         L.orc_grid_update_node.restype = ctypes.c_double
         L.orc_grid_update_node.argtypes = [gp, ctypes.c_int, ip, dp, ctypes.c_long]
         L.orc_grid_laminate.restype = ctypes.c_int
-        L.orc_grid_laminate.argtypes = [gp, ctypes.c_int, ip, dp, dp, ctypes.c_int, ctypes.c_double, dp]
+        L.orc_grid_laminate.argtypes = [gp, ctypes.c_int, ip, dp, ctypes.c_int, dp, ctypes.c_int, ctypes.c_double, dp]
         L.orc_grid_interpolate.restype = ctypes.c_double
         L.orc_grid_interpolate.argtypes = [gp, dp, dp]
         _lib = L
@@ -353,35 +353,42 @@ def grid_r11(dim):
     return steps[:k].copy()
 
 
-def grid_energy(mat, g, beta_n, stress=False):
-    """W^0 at the nodes; with stress=True also P^0, shape (d*d, nodes)."""
-    W = np.empty(grid_size(g))
-    P = np.empty((g.dim * g.dim, grid_size(g))) if stress else None
-    lib().orc_grid_energy(ctypes.byref(mat), ctypes.byref(g), float(beta_n), _dp(W), _dp(P) if stress else None)
-    return (W, P) if stress else W
+def grid_energy(mat, g, beta_n, stress=False, tangent=False):
+    """W^0 at the nodes; with stress=True also P^0 (d*d, nodes), with tangent=True also
+    the moduli (d^4, nodes)."""
+    n, dd = grid_size(g), g.dim * g.dim
+    W = np.empty(n)
+    P = np.empty((dd, n)) if stress else None
+    A = np.empty((dd * dd, n)) if tangent else None
+    lib().orc_grid_energy(ctypes.byref(mat), ctypes.byref(g), float(beta_n), _dp(W), _dp(P) if stress else None,
+                          _dp(A) if tangent else None)
+    out = (W,) + ((P,) if stress else ()) + ((A,) if tangent else ())
+    return out if len(out) > 1 else W
 
 
 def grid_sweep(g, steps, Win, Pin=None):
+    """One iteration; Pin (m, nodes): per-node quantities carried by the laminates."""
     steps = np.ascontiguousarray(steps, dtype=np.int32)
     Win = np.ascontiguousarray(Win, dtype=np.float64)
     Wout = np.empty_like(Win)
     if Pin is None:
-        md = lib().orc_grid_sweep(ctypes.byref(g), len(steps), _ip(steps), _dp(Win), _dp(Wout), None, None)
+        md = lib().orc_grid_sweep(ctypes.byref(g), len(steps), _ip(steps), _dp(Win), _dp(Wout), 0, None, None)
         return Wout, md
     Pin = np.ascontiguousarray(Pin, dtype=np.float64)
     Pout = np.empty_like(Pin)
-    md = lib().orc_grid_sweep(ctypes.byref(g), len(steps), _ip(steps), _dp(Win), _dp(Wout), _dp(Pin), _dp(Pout))
+    md = lib().orc_grid_sweep(ctypes.byref(g), len(steps), _ip(steps), _dp(Win), _dp(Wout), Pin.shape[0],
+                              _dp(Pin), _dp(Pout))
     return Wout, md, Pout
 
 
 def grid_laminate(g, steps, W, k_max=20, tol=1e-4, P=None):
-    """Returns (W, hist) or, with node stresses P, (W, hist, P)."""
+    """Returns (W, hist) or, with carried per-node quantities P (m, nodes), (W, hist, P)."""
     steps = np.ascontiguousarray(steps, dtype=np.int32)
     W = np.array(W, dtype=np.float64)
     hist = np.zeros(max(k_max, 1))
     Pc = None if P is None else np.array(P, dtype=np.float64)
-    k = lib().orc_grid_laminate(ctypes.byref(g), len(steps), _ip(steps), _dp(W), None if Pc is None else _dp(Pc),
-                                int(k_max), float(tol), _dp(hist))
+    k = lib().orc_grid_laminate(ctypes.byref(g), len(steps), _ip(steps), _dp(W), 0 if Pc is None else Pc.shape[0],
+                                None if Pc is None else _dp(Pc), int(k_max), float(tol), _dp(hist))
     return (W, hist[:k].copy()) if Pc is None else (W, hist[:k].copy(), Pc)
 
 

@@ -144,11 +144,12 @@ typedef struct {
 long orc_grid_size(const orc_grid* g);
 void orc_grid_node(const orc_grid* g, long p, double* F);
 int orc_grid_r11(int dim, int* steps);
-void orc_grid_energy(const orc_material* mat, const orc_grid* g, double beta_n, double* W, double* P);
-double orc_grid_sweep(const orc_grid* g, int n_dir, const int* steps, const double* Win, double* Wout,
-                      const double* Pin, double* Pout);
+void orc_grid_energy(const orc_material* mat, const orc_grid* g, double beta_n, double* W, double* P,
+                     double* A);
+double orc_grid_sweep(const orc_grid* g, int n_dir, const int* steps, const double* Win, double* Wout, int m,
+                      const double* Cin, double* Cout);
 double orc_grid_update_node(const orc_grid* g, int n_dir, const int* steps, const double* W, long p);
-int orc_grid_laminate(const orc_grid* g, int n_dir, const int* steps, double* W, double* P, int k_max,
+int orc_grid_laminate(const orc_grid* g, int n_dir, const int* steps, double* W, int m, double* C, int k_max,
                       double tol, double* hist);
 double orc_grid_interpolate(const orc_grid* g, const double* W, const double* F);
 

@@ -838,3 +838,19 @@ def test_grid_stress_tie_keeps_the_first_direction():
         assert Wn[idx(1, 1)] == 0.0
         expect = first if st is steps else -first
         assert Pn[0, idx(1, 1)] == expect
+
+
+def test_grid_double_well_tangent_is_the_leaf_moduli():
+    """Tangent moduli carried through the mesh iterations (Algorithm 3 on the grid):
+    for the double-well energy every laminated node (|F11| < 1) holds the leaves'
+    d^2W/dF11^2 = 12 - 4 = 8 (R17: the leaf moduli, not the zero curvature of the
+    envelope), the others their own 12 F11^2 - 4; the other diagonal entries are 2."""
+    mat = O.material(dim=2, model=O.MODEL_DOUBLEWELL)
+    g = O.grid(2, [9, 3, 3, 5], [-2.0, -0.5, -0.5, 0.0], 0.5)
+    W0, P0, A0 = O.grid_energy(mat, g, 0.0, stress=True, tangent=True)
+    C0 = np.concatenate([P0, A0])
+    W, hist, C = O.grid_laminate(g, O.grid_r11(2), W0, k_max=5, tol=0.0, P=C0)
+    for p in range(O.grid_size(g)):
+        F11 = O.grid_node(g, p)[0, 0]
+        ref = np.diag([8.0 if abs(F11) < 1.0 else 12.0 * F11 ** 2 - 4.0, 2.0, 2.0, 2.0]).ravel()
+        assert np.max(np.abs(C[4:, p] - ref)) < 1e-13, (F11, C[4:, p])
