@@ -385,49 +385,98 @@ def leg_tangent(h, r1, WL, torch, np, reps=20):
             "all_finite": bool(torch.isfinite(A).all().item())}
 
 
-def grid_bytes(n_nodes, n_dir, elem):
-    """Algorithmic HBM bytes of one mesh iteration: every direction reads each node once
-    along its line and writes the next iterate once; plus the iterate copy and the
-    maximal-decrease pass (two node arrays each)."""
-    return elem * n_nodes * (2 * n_dir + 4)
+def grid_lines_at_least(n, s, m):
+    """Lines of step s with at least m nodes on a mesh of n[c] nodes per component: the
+    nodes whose m-1 steps ahead stay inside, minus those whose one step back does too
+    (each set a box, the product of per-component interval lengths)."""
+    ahead = back = 1
+    for nc, v in zip(n, s):
+        lo, hi = max(0, -(m - 1) * v), min(nc, nc - (m - 1) * v)
+        ahead *= max(hi - lo, 0)
+        back *= max(min(hi, nc + v) - max(lo, v), 0)
+    return ahead - back
+
+
+def grid_line_nodes(n, steps):
+    """Direction-node pairs on lines of at least 3 nodes (only those can lower a node)."""
+    import numpy as np
+    total = 0
+    for s in np.asarray(steps).reshape(len(steps), -1):
+        s = [int(v) for v in s]
+        m = 3
+        while True:
+            c = grid_lines_at_least(n, s, m)
+            if c == 0:
+                break
+            total += c * (3 if m == 3 else 1)
+            m += 1
+    return total
+
+
+def grid_bytes(n_nodes, line_nodes, elem):
+    """Algorithmic HBM bytes of one mesh iteration: every node of every line that can
+    lower a node (at least 3 nodes) read once per direction, the previous iterate read
+    and the next one written once."""
+    return elem * (line_nodes + 2 * n_nodes)
 
 
 def leg_grid(h, r1, WL, torch, np):
     """Global lamination on the paper's meshes (FP64, reduced direction set R^1_1):
     Table 6.1's 2D STVK and NH meshes run to the stopping rule (max decrease <= 1e-4,
-    at most 20 iterations), and Table 6.3's 3D STVK mesh for 3 iterations."""
+    at most 20 iterations), and Table 6.3's 3D STVK mesh for 3 iterations; the 2D STVK
+    mesh once more carrying the node stresses and tangent moduli (eq. 5.2, Algorithm 3)."""
     mat_t = dict(mu=1.0, lam=0.5, D_inf=0.9, D0=0.3)
-    cases = [("stvk-2d-672400", 2, r1.R1_STVK_DAMAGE, (20, 41, 41, 20), (0.1, -2.0, -2.0, 0.1), 0.1,
-              0.07986236557499998, 20),
-             ("nh-2d-648025", 2, r1.R1_NEOHOOKE_DAMAGE, (23, 35, 35, 23), (0.1, -2.55, -2.55, 0.1), 0.15, 0.06, 20),
+    stvk2 = ((20, 41, 41, 20), (0.1, -2.0, -2.0, 0.1), 0.1, 0.07986236557499998, 20)
+    cases = [("stvk-2d-672400", 2, r1.R1_STVK_DAMAGE) + stvk2 + (False,),
+             ("nh-2d-648025", 2, r1.R1_NEOHOOKE_DAMAGE, (23, 35, 35, 23), (0.1, -2.55, -2.55, 0.1), 0.15, 0.06, 20,
+              False),
              ("stvk-3d-5832000", 3, r1.R1_STVK_DAMAGE, (20, 3, 3, 3, 20, 3, 3, 3, 20),
-              (0.1, -0.1, -0.1, -0.1, 0.1, -0.1, -0.1, -0.1, 0.1), 0.1, 0.07986236557499998, 3)]
+              (0.1, -0.1, -0.1, -0.1, 0.1, -0.1, -0.1, -0.1, 0.1), 0.1, 0.07986236557499998, 3, False),
+             ("stvk-2d-672400+stress+tangent", 2, r1.R1_STVK_DAMAGE) + stvk2 + (True,)]
     out = []
-    for name, dim, model, n, lo, delta, beta, k_max in cases:
+    for name, dim, model, n, lo, delta, beta, k_max, carry in cases:
         g = r1.grid(dim, n, lo, delta)
         steps = r1.grid_r11(dim)
         mat = r1.material_from(mat_t, dim, model)
-        W = h.grid_energy(mat, g, beta, torch.float64)
+        P = A = None
+        if carry:
+            W, P, A = h.grid_energy(mat, g, beta, torch.float64, stress=True, tangent=True)
+        else:
+            W = h.grid_energy(mat, g, beta, torch.float64)
+        W0 = W.clone()
         torch.cuda.synchronize()
-        h.timing(True)
-        h.timing_reset()
         t0 = time.perf_counter()
-        hist = h.grid_laminate(g, steps, W, k_max=k_max, tol=1e-4)
+        hist = h.grid_laminate(g, steps, W, k_max=k_max, tol=1e-4, P=P, A=A)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
-        ms, cnt = h.timing_query("grid_lines")
-        h.timing(False)
+        # per-launch kernel time from HIP events, in a second run (the events add gaps
+        # between the launches, so the whole-run time above is taken without them)
+        if not carry:
+            W.copy_(W0)
+            torch.cuda.synchronize()
+            h.timing(True)
+            h.timing_reset()
+            h.grid_laminate(g, steps, W, k_max=k_max, tol=1e-4)
+            torch.cuda.synchronize()
+            ms, cnt = h.timing_query("grid_lines")
+            h.timing(False)
+        else:
+            ms, cnt = 0.0, 0
         nodes = r1.grid_size(g)
         per_it = t / len(hist)
-        gbs = grid_bytes(nodes, len(steps), 8) / per_it / 1e9
+        line_nodes = grid_line_nodes(n, steps)
+        gbs = grid_bytes(nodes, line_nodes, 8) / per_it / 1e9
         out.append({"mesh": name, "nodes": nodes, "directions": len(steps), "iterations": len(hist),
                     "decrease": [float("%.6g" % v) for v in hist], "ms_total": round(1e3 * t, 2),
                     "ms_per_iteration": round(1e3 * per_it, 3),
                     "node_updates_per_s": float(nodes * len(hist) / t),
-                    "lines_kernel_ms_per_launch": round(ms / max(cnt, 1), 4),
-                    "roofline": dict(bound="hbm", kernel="k_grid_lines", achieved=round(gbs, 1), unit="GB/s",
-                                     peak=8000.0, frac=round(gbs / 8000.0, 4),
-                                     bytes_per_iteration=grid_bytes(nodes, len(steps), 8))})
+                    "lines_kernel_ms_per_launch": round(ms / cnt, 4) if cnt else None})
+        if not carry:
+            out[-1]["roofline"] = dict(bound="hbm", kernel="k_grid_hulls + k_grid_pick", achieved=round(gbs, 1),
+                                       unit="GB/s", peak=8000.0, frac=round(gbs / 8000.0, 4),
+                                       bytes_per_iteration=grid_bytes(nodes, line_nodes, 8),
+                                       line_nodes_per_iteration=line_nodes)
+        del W, W0, P, A
     return {"workload": "global lamination on the paper's meshes (Tables 6.1, 6.3), FP64, R^1_1", "meshes": out}
 
 

@@ -248,9 +248,10 @@ r1_status r1_grid_r11(int32_t dim, int32_t* steps, int32_t* n_dir);
 /* W^0: the material's W (eq. 2.9; neo-Hooke: +inf where det F <= 0) at every
  * node, with history beta_n shared by all nodes (material->dim == grid->dim);
  * P (nullable, device, dim*dim x nodes component-major) receives P^0 = dW/dF
- * (eq. 2.12; NaN where W is +inf). */
+ * (eq. 2.12); A (nullable, device, dim^4 x nodes, component (i*dim + j)*dim*dim
+ * + k*dim + l) the moduli d^2W/dF_ij dF_kl; both NaN where W is +inf. */
 r1_status r1_grid_energy(r1_handle handle, const r1_material* material, const r1_grid* grid, double beta_n,
-                         r1_dtype dtype, void* W, void* P, void* stream);
+                         r1_dtype dtype, void* W, void* P, void* A, void* stream);
 
 /* Iterates eq. 4.3 in place on W (device node array) until the maximal decrease
  * max_F (W^k(F) - W^{k+1}(F)) over nodes with finite W^k of an iteration is at
@@ -259,15 +260,21 @@ r1_status r1_grid_energy(r1_handle handle, const r1_material* material, const r1
  * maximal decrease of each iteration.  P (nullable; node stresses as written by
  * r1_grid_energy) is carried along: a node lowered by the hull segment [F_a, F_b]
  * of its line takes the stress of that laminate with the weights of its value
- * (eq. 5.2, first case).  A laminate replaces a node's value only when it is
+ * (eq. 5.2, first case); A (nullable; node moduli as written by r1_grid_energy)
+ * likewise, which makes A the tangent of Algorithm 3: the laminate-weighted
+ * moduli of the mesh nodes whose values built the node's value (the derivative
+ * of the carried stress with the laminates held fixed).  A laminate replaces a
+ * node's value only when it is
  * lower by more than 4 units of rounding (of dtype) times max(|W|, 1e-3): a node
  * on a straight hull run reads its own value back up to rounding, and of
- * directions that tie to rounding the first in `steps` keeps the node.  Interpolating P (r1_grid_interpolate per component) gives
- * eq. 5.2's second case off the mesh.  Uses handle workspace of one node array
- * (plus one stress array with P); synchronizes `stream` once per iteration. */
+ * directions that tie to rounding the first in `steps` keeps the node.
+ * Interpolating P or A (r1_grid_interpolate per component) gives eq. 5.2's
+ * second case off the mesh.  Uses handle workspace of one node array (plus one
+ * array like P and one like A when given); synchronizes `stream` once per
+ * iteration. */
 r1_status r1_grid_laminate(r1_handle handle, const r1_grid* grid, int32_t n_dir, const int32_t* steps,
-                           r1_dtype dtype, void* W, void* P, int32_t k_max, double tol, int32_t* iterations,
-                           double* decrease, void* stream);
+                           r1_dtype dtype, void* W, void* P, void* A, int32_t k_max, double tol,
+                           int32_t* iterations, double* decrease, void* stream);
 
 /* out[p] = multilinear interpolation of the node values W at F_p (device, SoA
  * dim*dim x n, dtype); corners of zero weight do not take part; NaN outside the
@@ -386,7 +393,8 @@ r1_status r1_surrogate_load(r1_handle handle, r1_surrogate* surrogate, const cha
 /* When enabled, every kernel launch of the handle is bracketed by HIP events
  * recorded on its launch stream.  Kernel names: "depth1" (one-level envelope),
  * "depth2_centre", "outer", "finalize" (two-level envelope), "tangent" (tangent moduli),
- * "grid_lines" (one direction of a mesh iteration), "batched".
+ * "grid_lines" (the hulls of a group of up to 16
+ * directions of a mesh iteration), "grid_pick" (the choice among them), "batched".
  * r1_timing_query waits for the recorded events and returns the summed elapsed
  * milliseconds and the launch count of `kernel` since the last reset. */
 r1_status r1_timing_enable(r1_handle handle, int32_t on);

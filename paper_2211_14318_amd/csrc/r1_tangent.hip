@@ -13,82 +13,6 @@
 
 namespace r1k {
 
-// Row ij of d^2 W / dG dG at one point of the line set, weighted and added:
-// acc[kl] += w d^2 W / dG_ij dG_kl (ij = i*D + j, kl = k*D + l).  The point's
-// scalars (J, ln J, psi0, the damage factors) are formed once for the row.
-// Neo-Hooke damage (eqs. 2.3, 2.9):
-//   A0 = g' [mu d_ik d_jl + lambda H_ij H_kl - (lambda ln J - mu) H_il H_kj] + g'' S_ij S_kl
-// with H = G^{-T}, S = d psi0 / dG = mu G + (lambda ln J - mu) H, g' = 1 - D(max(psi0, beta_n))
-// and g'' = -(D_inf / D0) e^{-psi0/D0} on the loading branch psi0 > beta_n, 0 otherwise.
-// In 2D (plane strain) G is the in-plane block; G^{-T} of the embedding keeps
-// that block as the 2x2 inverse-transpose.  NaN where det G <= 0.
-// St. Venant-Kirchhoff (eq. 2.2), with E = (G^T G - I)/2, B = G G^T and
-// S = dpsi0/dG = G (lambda tr E I + 2 mu E):
-//   d^2psi0/dG_ij dG_kl = lambda G_ij G_kl + lambda tr E d_ik d_jl + 2 mu d_ik E_lj
-//                         + mu (G_il G_kj + B_ik d_jl),
-// with the same damage factors g', g''.  Double-well test energy: 2 on the
-// diagonal, 12 G_11^2 - 4 at (11, 11).
-template <int D, int IJ>
-__device__ __forceinline__ void tangent0_row(const Material& m, double bn, const double* G, double w, double* acc) {
-  constexpr int ij = IJ, i = IJ / D, j = IJ % D;
-  if (m.model == 2) {
-    double E[D * D], S[D * D];
-    double tr = stvk_strain<D>(G, E);
-    double psi = stvk_psi_stress<D>(m, G, S);
-    double g1 = 1.0 - m.D_inf * (1.0 - exp(-(psi > bn ? psi : bn) / m.D0));
-    double g2 = psi > bn ? -m.D_inf / m.D0 * exp(-psi / m.D0) : 0.0;
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      double Bik = 0.0;
-#pragma unroll
-      for (int r = 0; r < D; ++r) Bik += G[i * D + r] * G[k * D + r];
-#pragma unroll
-      for (int l = 0; l < D; ++l) {
-        const int kl = k * D + l;
-        double h = m.lambda * G[ij] * G[kl] + m.mu * G[i * D + l] * G[k * D + j];
-        if (i == k) h += (j == l ? m.lambda * tr : 0.0) + 2.0 * m.mu * E[l * D + j];
-        if (j == l) h += m.mu * Bik;
-        acc[kl] += w * (g1 * h + g2 * S[ij] * S[kl]);
-      }
-    }
-    return;
-  }
-  if (m.model != 0) {
-#pragma unroll
-    for (int kl = 0; kl < D * D; ++kl)
-      acc[kl] += w * (kl != ij ? 0.0 : ij == 0 ? 12.0 * G[0] * G[0] - 4.0 : 2.0);
-    return;
-  }
-  double cof[D * D];
-  cofactor<D>(G, cof);
-  double J = det_of<D>(G, cof);
-  if (!(J > 0.0)) {
-#pragma unroll
-    for (int kl = 0; kl < D * D; ++kl) acc[kl] = __builtin_nan("");
-    return;
-  }
-  double lnJ = log(J), n2 = 0.0;
-#pragma unroll
-  for (int r = 0; r < D * D; ++r) n2 += G[r] * G[r];
-  double psi = 0.5 * m.mu * (n2 - double(D)) - m.mu * lnJ + 0.5 * m.lambda * lnJ * lnJ;
-  double beta = psi > bn ? psi : bn;
-  double g1 = 1.0 - m.D_inf * (1.0 - exp(-beta / m.D0));
-  double g2 = psi > bn ? -m.D_inf / m.D0 * exp(-psi / m.D0) : 0.0;
-  double c = m.lambda * lnJ - m.mu;
-  const double iJ = 1.0 / J;
-  double Hij = cof[ij] * iJ, Sij = m.mu * G[ij] + c * Hij;
-#pragma unroll
-  for (int k = 0; k < D; ++k)
-#pragma unroll
-    for (int l = 0; l < D; ++l) {
-      const int kl = k * D + l;
-      double Hkl = cof[kl] * iJ, Hil = cof[i * D + l] * iJ, Hkj = cof[k * D + j] * iJ;
-      double h = (ij == kl ? m.mu : 0.0) + m.lambda * Hij * Hkl - c * Hil * Hkj;
-      double Skl = m.mu * G[kl] + c * Hkl;
-      acc[kl] += w * (g1 * h + g2 * Sij * Skl);
-    }
-}
-
 // Endpoints G-/+ of tree node t on level lv around G, and the volume fraction
 // xi of G+.  False when the node does not name a laminate of lv (direction or
 // sample index out of range, or not straddling the centre).

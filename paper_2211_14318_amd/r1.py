@@ -115,8 +115,8 @@ def _load():
                                       i32, vp, vp, vp, vp, vp, vp]
     L.r1_grid_r11.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.r1_grid_energy.argtypes = [vp, ctypes.POINTER(Material), ctypes.POINTER(Grid), ctypes.c_double, i32, vp, vp,
-                                 vp]
-    L.r1_grid_laminate.argtypes = [vp, ctypes.POINTER(Grid), i32, ctypes.POINTER(i32), i32, vp, vp, i32,
+                                 vp, vp]
+    L.r1_grid_laminate.argtypes = [vp, ctypes.POINTER(Grid), i32, ctypes.POINTER(i32), i32, vp, vp, vp, i32,
                                    ctypes.c_double, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double), vp]
     L.r1_grid_interpolate.argtypes = [vp, ctypes.POINTER(Grid), i32, vp, i64, vp, vp, vp]
     L.r1_envelope_batched.argtypes = [vp, ctypes.POINTER(Material), ctypes.POINTER(Lamination), i32,
@@ -329,27 +329,33 @@ class Handle:
                                             self._stream(stream)),
                     "r1_envelope_stress")
 
-    def grid_energy(self, mat, g, beta_n, dtype, stress=False, stream=None):
+    def grid_energy(self, mat, g, beta_n, dtype, stress=False, tangent=False, stream=None):
         """W^0 at every node of mesh g: (nodes,) device tensor of torch dtype; with
-        stress=True also P^0, (d*d, nodes)."""
-        W = self.torch.empty(grid_size(g), dtype=dtype, device="cuda")
-        P = self.torch.empty((g.dim * g.dim, grid_size(g)), dtype=dtype, device="cuda") if stress else None
+        stress=True also P^0, (d*d, nodes); with tangent=True also the moduli,
+        (d^4, nodes).  Returns W alone or the tuple (W[, P][, A])."""
+        n, dd = grid_size(g), g.dim * g.dim
+        W = self.torch.empty(n, dtype=dtype, device="cuda")
+        P = self.torch.empty((dd, n), dtype=dtype, device="cuda") if stress else None
+        A = self.torch.empty((dd * dd, n), dtype=dtype, device="cuda") if tangent else None
         dt = R1_F32 if dtype == self.torch.float32 else R1_F64
         self._check(_lib.r1_grid_energy(self.h, ctypes.byref(mat), ctypes.byref(g), float(beta_n), dt, _ptr(W),
-                                        _ptr(P), self._stream(stream)), "r1_grid_energy")
-        return (W, P) if stress else W
+                                        _ptr(P), _ptr(A), self._stream(stream)), "r1_grid_energy")
+        out = (W,) + ((P,) if stress else ()) + ((A,) if tangent else ())
+        return out if len(out) > 1 else W
 
-    def grid_laminate(self, g, steps, W, k_max=20, tol=1e-4, P=None, stream=None):
-        """Iterates eq. 4.3 in place on W (and the node stresses P); returns the
-        per-iteration maximal decreases."""
+    def grid_laminate(self, g, steps, W, k_max=20, tol=1e-4, P=None, A=None, stream=None):
+        """Iterates eq. 4.3 in place on W (and the node stresses P and moduli A);
+        returns the per-iteration maximal decreases."""
         steps = np.ascontiguousarray(steps, dtype=np.int32)
-        assert W.is_contiguous() and W.numel() == grid_size(g)
-        assert P is None or (P.is_contiguous() and P.shape == (g.dim * g.dim, grid_size(g)) and P.dtype == W.dtype)
+        n, dd = grid_size(g), g.dim * g.dim
+        assert W.is_contiguous() and W.numel() == n
+        assert P is None or (P.is_contiguous() and P.shape == (dd, n) and P.dtype == W.dtype)
+        assert A is None or (A.is_contiguous() and A.shape == (dd * dd, n) and A.dtype == W.dtype)
         it = ctypes.c_int32()
         dec = (ctypes.c_double * int(k_max))()
         self._check(_lib.r1_grid_laminate(self.h, ctypes.byref(g), len(steps),
                                           steps.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                                          self._dtype_code(W), _ptr(W), _ptr(P), int(k_max), float(tol),
+                                          self._dtype_code(W), _ptr(W), _ptr(P), _ptr(A), int(k_max), float(tol),
                                           ctypes.byref(it), dec, self._stream(stream)), "r1_grid_laminate")
         return np.array(dec[:it.value])
 

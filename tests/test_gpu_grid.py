@@ -247,3 +247,53 @@ def test_grid_double_well_stress_on_gpu(lib):
         ref = 2.0 * (F - np.eye(2))
         ref[0, 0] = 4.0 * F[0, 0] * (F[0, 0] ** 2 - 1.0) if abs(F[0, 0]) > 1.0 else 0.0
         assert np.max(np.abs(Pg[:, p] - ref.ravel())) < 1e-13
+
+
+@pytest.mark.parametrize("model,dim", [(0, 2), (2, 2), (2, 3), (0, 3)])
+def test_grid_tangent_matches_oracle(lib, model, dim):
+    """Moduli carried through the iterations with the stresses (Algorithm 3's tangent on the
+    mesh) equal the oracle's (FP64), node by node, including the untouched A^0."""
+    r1, h, torch = lib
+    n, lo, delta = lam_meshes(dim)
+    g, og = both_grids(r1, dim, n, lo, delta)
+    W, P, A = h.grid_energy(r1.material_from(NH, dim, model), g, 0.04, torch.float64, stress=True, tangent=True)
+    W0g, A0g = W.cpu().numpy(), A.cpu().numpy()
+    hist = h.grid_laminate(g, r1.grid_r11(dim), W, k_max=20, tol=1e-6, P=P, A=A)
+    torch.cuda.synchronize()
+    W0, P0, A0 = O.grid_energy(PA.orc_material(NH, dim, model), og, 0.04, stress=True, tangent=True)
+    fin0 = np.isfinite(W0)
+    sc0 = max(np.max(np.abs(A0[:, fin0])), 1.0)
+    assert np.max(np.abs(A0g[:, fin0] - A0[:, fin0])) <= 1e-12 * sc0
+    assert np.all(np.isnan(A0g[:, ~fin0])) and np.all(np.isnan(A0[:, ~fin0]))
+    Wo, ho, Co = O.grid_laminate(og, O.grid_r11(dim), W0, k_max=20, tol=1e-6, P=np.concatenate([P0, A0]))
+    dd = dim * dim
+    Po, Ao = Co[:dd], Co[dd:]
+    assert len(hist) == len(ho)
+    fin = np.isfinite(Wo)
+    Pg, Ag = P.cpu().numpy(), A.cpu().numpy()
+    assert np.max(np.abs(Pg[:, fin] - Po[:, fin])) <= 1e-11 * max(np.max(np.abs(Po[:, fin])), 1.0)
+    scale = max(np.max(np.abs(Ao[:, fin])), 1.0)
+    assert np.max(np.abs(Ag[:, fin] - Ao[:, fin])) <= 1e-11 * scale
+    assert np.all(np.isnan(Ag[:, ~fin]))
+    changed = np.sum(np.any(np.abs(Ao - A0) > 1e-12, axis=0) & fin)
+    assert changed > 10
+    # the carried moduli stay symmetric (each leaf's d^2W is)
+    Asq = Ag[:, fin].reshape(dd, dd, -1)
+    assert np.max(np.abs(Asq - Asq.transpose(1, 0, 2))) <= 1e-11 * scale
+    print("model %d %dD: %d iterations, %d node moduli changed" % (model, dim, len(hist), changed))
+
+
+def test_grid_double_well_tangent_on_gpu(lib):
+    """Double-well moduli on the mesh: laminated nodes (|F11| < 1) hold the leaves' 8 at
+    (11, 11), the others 12 F11^2 - 4; 2 elsewhere on the diagonal (FP32 and FP64)."""
+    r1, h, torch = lib
+    g, og = both_grids(r1, 2, (9, 3, 3, 5), (-2.0, -0.5, -0.5, 0.0), 0.5)
+    for dt, tol in ((torch.float64, 1e-13), (torch.float32, 1e-5)):
+        W, A = h.grid_energy(r1.material(model=r1.R1_TEST_DOUBLEWELL), g, 0.0, dt, tangent=True)
+        h.grid_laminate(g, r1.grid_r11(2), W, k_max=5, tol=0.0, A=A)
+        torch.cuda.synchronize()
+        Ag = A.double().cpu().numpy()
+        for p in range(O.grid_size(og)):
+            F11 = O.grid_node(og, p)[0, 0]
+            ref = np.diag([8.0 if abs(F11) < 1.0 else 12.0 * F11 ** 2 - 4.0, 2.0, 2.0, 2.0]).ravel()
+            assert np.max(np.abs(Ag[:, p] - ref)) < tol * 50, (dt, F11)

@@ -55,3 +55,58 @@ def test_grid_reduced_directions_match_oracle():
     from paper_2211_14318_amd import r1
     for dim in (2, 3):
         assert np.array_equal(r1.grid_r11(dim), O.grid_r11(dim))
+
+
+def test_grid_line_starts_match_brute_force(tmp_path):
+    """The grid kernels' line-start decoding (host/device header, built here with the host
+    compiler): for random meshes and steps -- zero components, steps longer than the box --
+    the decoded starts are exactly the nodes whose predecessor lies outside the box (of the
+    lines with at least min_len nodes), each once, with the right line lengths, index step
+    and longest line; stepping from a start
+    to a later one (mixed-radix add with carry within a slab, by 1 and by 5) agrees with
+    decoding."""
+    import subprocess
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    exe = tmp_path / "check"
+    subprocess.check_call(["g++", "-std=c++17", "-O1", "-Wall", "-Wno-unknown-pragmas", "-D__HIP_PLATFORM_AMD__",
+                           "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "paper_2211_14318_amd", "csrc"),
+                           "-I" + os.path.join(ROOT, "include"),
+                           os.path.join(ROOT, "tests", "grid_lines_check.cpp"), "-o", str(exe)])
+    rng = np.random.default_rng(5)
+    for trial in range(36):
+        dim = 2 if trial % 3 else 3
+        dd = dim * dim
+        min_len = 1 + trial % 4
+        n = [int(v) for v in rng.integers(1, 7 if dim == 2 else 4, size=dd)]
+        steps = [[int(v) for v in rng.integers(-3, 4, size=dd)] for _ in range(6)]
+        steps = [s for s in steps if any(s)] + [[1] + [0] * (dd - 1), [0] * (dd - 1) + [-7], [1] * dd]
+        text = " ".join(map(str, [dim] + n + [len(steps), min_len] + sum(steps, [])))
+        out = subprocess.run([str(exe)], input=text, capture_output=True, text=True, check=True).stdout.split()
+        vals = list(map(int, out))
+        pos = 0
+        strides = [int(np.prod(n[c + 1:])) for c in range(dd)]
+        for s in steps:
+            count, longest, ds = vals[pos:pos + 3]
+            pos += 3
+            got = {}
+            for _ in range(count):
+                assert vals[pos] not in got
+                got[vals[pos]] = vals[pos + 1]
+                assert vals[pos + 2] == 1                           # stepping agrees with decoding
+                pos += 3
+            every = {}
+            for I in np.ndindex(*n):
+                if all(0 <= I[c] - s[c] < n[c] for c in range(dd)):
+                    continue
+                L = 0
+                while all(0 <= I[c] + L * s[c] < n[c] for c in range(dd)):
+                    L += 1
+                every[int(np.ravel_multi_index(I, n))] = L
+            assert sum(every.values()) == int(np.prod(n))         # the lines partition the mesh
+            assert longest == max(every.values())
+            assert got == {p: L for p, L in every.items() if L >= min_len}, (n, s, min_len)
+            assert count == bench.grid_lines_at_least(n, s, min_len)  # the bench's closed form
+            assert ds == sum(s[c] * strides[c] for c in range(dd))
+        assert pos == len(vals)
