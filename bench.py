@@ -444,6 +444,11 @@ def leg_grid(h, r1, WL, torch, np):
         else:
             W = h.grid_energy(mat, g, beta, torch.float64)
         W0 = W.clone()
+        # one untimed iteration first: it sizes the handle's workspace for this mesh
+        Wc = W0.clone()
+        h.grid_laminate(g, steps, Wc, k_max=1, tol=0.0, P=None if P is None else P.clone(),
+                        A=None if A is None else A.clone())
+        del Wc
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         hist = h.grid_laminate(g, steps, W, k_max=k_max, tol=1e-4, P=P, A=A)
