@@ -269,9 +269,12 @@ r1_status r1_grid_energy(r1_handle handle, const r1_material* material, const r1
  * on a straight hull run reads its own value back up to rounding, and of
  * directions that tie to rounding the first in `steps` keeps the node.
  * Interpolating P or A (r1_grid_interpolate per component) gives eq. 5.2's
- * second case off the mesh.  Uses handle workspace of one node array (plus one
- * array like P and one like A when given); synchronizes `stream` once per
- * iteration. */
+ * second case off the mesh.  Uses handle workspace of up to 17 node arrays of
+ * dtype (the other iterate and the candidates of up to 16 directions); when P or
+ * A is given, also one array like each, one uint32 per node and candidate slot
+ * and two int32 per node for the laminates; and one uint32 mask per node on
+ * meshes where the lines of at least 3 nodes are a minority.  Synchronizes
+ * `stream` once per iteration. */
 r1_status r1_grid_laminate(r1_handle handle, const r1_grid* grid, int32_t n_dir, const int32_t* steps,
                            r1_dtype dtype, void* W, void* P, void* A, int32_t k_max, double tol,
                            int32_t* iterations, double* decrease, void* stream);
