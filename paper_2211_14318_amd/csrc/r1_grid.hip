@@ -106,6 +106,11 @@ __global__ __launch_bounds__(256) void k_grid_energy(GridArgs g, r1d::Material m
 constexpr int kGroupMax = 16;
 constexpr int kShortLine = 8;  // lines of at most this many nodes go to their own hull launch
 constexpr int kShortRun = 8;   // line starts per thread there
+constexpr int kLenClasses = 6; // hull launches per group: lines of <= 8, 16, 32, 64, 128 nodes, longer
+
+inline int len_class(int len) {
+  return len <= kShortLine ? 0 : len <= 16 ? 1 : len <= 32 ? 2 : len <= 64 ? 3 : len <= 128 ? 4 : 5;
+}
 
 struct Group {
   int d0;                      // first direction of the group
@@ -410,17 +415,17 @@ hipError_t grid_sweep(const GridArgs& g, const std::vector<Step>& steps, const G
   const bool carry = cy.Pout || cy.Aout;
   for (int d0 = 0; d0 < n_dir; d0 += kGroupMax) {
     const int nd = std::min(kGroupMax, n_dir - d0);
-    // two hull launches per group, short lines and the rest, each with the LDS of
+    // one hull launch per length class of the group's lines, each with the LDS of
     // its own longest line (short lines would otherwise run at the occupancy of the
     // longest); the candidates keep their group slots, so the order is unchanged
-    for (int part = 0; part < 2; ++part) {
+    for (int part = 0; part < kLenClasses; ++part) {
       const int R = part == 0 ? kShortRun : 1;
       Group grp{};
       grp.d0 = d0;
       int blocks = 0, len = 1;
       for (int j = 0; j < nd; ++j) {
         const Step& s = steps[d0 + j];
-        if ((s.len <= kShortLine) != (part == 0)) continue;
+        if (len_class(s.len) != part) continue;
         blocks += int(blocks_of(s.count, kLineThreads * R));
         grp.slot[grp.n] = j;
         grp.block_end[grp.n] = blocks;
