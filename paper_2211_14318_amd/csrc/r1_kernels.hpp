@@ -103,15 +103,22 @@ __device__ __forceinline__ void point_depth1(const KArgs& a, int64_t p, const Le
     return;
   }
   Env<T> e = envelope_at<T, D, S, K, M>(q, G, wc, lv, lay);
+  // the laminate's endpoint stresses, P(F-) on lane 0 and P(F+) on lane 1 at once
+  const bool stress = a.want_stress && a.P;
+  double Pm[D * D] = {}, Pp[D * D];
+  if (stress) {
+    if (lane_id() < 2) {
+      double Ge[D * D];
+      line_point<D>(G, lv, e.dir, lane_id() == 0 ? -t_of(lv, e.mp) : t_of(lv, e.mq), Ge);
+      stress0<D, M>(a.mat, bn, Ge, Pm);
+    }
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) Pp[k] = __shfl(Pm[k], 1, kWave);
+  }
   if (lane_id() == 0) {
     static_cast<T*>(a.W)[p] = e.h;
     const int c = (lv.n_t - 1) / 2;
-    if (a.want_stress && a.P) {
-      double Gm[D * D], Gp[D * D], Pm[D * D], Pp[D * D];
-      line_point<D>(G, lv, e.dir, -t_of(lv, e.mp), Gm);
-      line_point<D>(G, lv, e.dir, t_of(lv, e.mq), Gp);
-      stress0<D, M>(a.mat, bn, Gm, Pm);
-      stress0<D, M>(a.mat, bn, Gp, Pp);
+    if (stress) {
       double xi = (e.mp + e.mq) ? double(e.mp) / double(e.mp + e.mq) : 1.0;
 #pragma unroll
       for (int k = 0; k < D * D; ++k)
