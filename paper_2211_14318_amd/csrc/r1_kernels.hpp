@@ -545,7 +545,7 @@ hipError_t launch_TD(const KArgs& a, int depth, int S, int K, hipStream_t st, KT
 #define R1_CASE(SS, KK) \
   if (S == SS && K == KK) return launch_T<T, D, SS, KK, M>(a, depth, st, tm);
   R1_CASE(8, 2) R1_CASE(8, 4) R1_CASE(8, 8) R1_CASE(8, 16) R1_CASE(8, 32)
-  R1_CASE(16, 2) R1_CASE(16, 4) R1_CASE(16, 8) R1_CASE(16, 16) R1_CASE(16, 32)
+  R1_CASE(16, 2) R1_CASE(16, 4) R1_CASE(16, 8) R1_CASE(16, 14) R1_CASE(16, 16) R1_CASE(16, 32)
   R1_CASE(32, 2) R1_CASE(32, 4) R1_CASE(32, 8) R1_CASE(32, 16) R1_CASE(32, 32)
   R1_CASE(64, 2) R1_CASE(64, 4) R1_CASE(64, 8) R1_CASE(64, 16) R1_CASE(64, 32)
 #undef R1_CASE
