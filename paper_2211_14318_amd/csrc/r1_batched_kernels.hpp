@@ -44,7 +44,7 @@ constexpr int kBPoint = 0, kBOuter = 1, kBFinal = 2;
 namespace r1k {
 
 namespace {
-__global__ void k_zero_ints(int* p, int64_t n) {
+__global__ __attribute__((unused)) void k_zero_ints(int* p, int64_t n) {
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
     p[i] = 0;
 }
