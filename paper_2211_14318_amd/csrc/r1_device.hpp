@@ -1081,8 +1081,10 @@ __device__ __forceinline__ void tangent0_row(const Material& m, double bn, const
     double E[D * D], S[D * D];
     double tr = stvk_strain<D>(G, E);
     double psi = stvk_psi_stress<D>(m, G, S);
-    double g1 = 1.0 - m.D_inf * (1.0 - exp(-(psi > bn ? psi : bn) / m.D0));
-    double g2 = psi > bn ? -m.D_inf / m.D0 * exp(-psi / m.D0) : 0.0;
+    // on the loading branch max(psi, beta_n) = psi: one exponential serves both factors
+    const double e = exp(-(psi > bn ? psi : bn) / m.D0);
+    double g1 = 1.0 - m.D_inf * (1.0 - e);
+    double g2 = psi > bn ? -m.D_inf / m.D0 * e : 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       double Bik = 0.0;
@@ -1117,9 +1119,9 @@ __device__ __forceinline__ void tangent0_row(const Material& m, double bn, const
 #pragma unroll
   for (int r = 0; r < D * D; ++r) n2 += G[r] * G[r];
   double psi = 0.5 * m.mu * (n2 - double(D)) - m.mu * lnJ + 0.5 * m.lambda * lnJ * lnJ;
-  double beta = psi > bn ? psi : bn;
-  double g1 = 1.0 - m.D_inf * (1.0 - exp(-beta / m.D0));
-  double g2 = psi > bn ? -m.D_inf / m.D0 * exp(-psi / m.D0) : 0.0;
+  const double e = exp(-(psi > bn ? psi : bn) / m.D0);   // = exp(-psi/D0) on the loading branch
+  double g1 = 1.0 - m.D_inf * (1.0 - e);
+  double g2 = psi > bn ? -m.D_inf / m.D0 * e : 0.0;
   double c = m.lambda * lnJ - m.mu;
   const double iJ = 1.0 / J;
   double Hij = cof[ij] * iJ, Sij = m.mu * G[ij] + c * Hij;
