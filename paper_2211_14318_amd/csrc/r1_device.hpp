@@ -1059,9 +1059,53 @@ __device__ __forceinline__ void stress0_any(const Material& m, double bn, const 
     stress0<D, kFamNH>(m, bn, G, P);
 }
 
+// The per-point factors of the leaf moduli, formed once and shared by its rows.
+template <int D>
+struct Leaf0 {
+  int kind;          // 0 neo-Hooke, 1 double-well, 2 St. Venant-Kirchhoff, -1 det G <= 0 (NaN)
+  double g1, g2;     // damage factors g', g''
+  double c, iJ, tr;  // neo-Hooke: lambda ln J - mu, 1/J; St. Venant-Kirchhoff: tr E
+  double X[D * D];   // neo-Hooke: cof G (H = cof G / J); St. Venant-Kirchhoff: E
+  double S[D * D];   // d psi0 / dG
+};
+
+template <int D>
+__device__ __forceinline__ Leaf0<D> leaf0(const Material& m, double bn, const double* G) {
+  Leaf0<D> f;
+  f.kind = m.model == 2 ? 2 : (m.model != 0 ? 1 : 0);
+  f.g1 = f.g2 = f.c = f.iJ = f.tr = 0.0;
+  if (f.kind == 1) return f;
+  double psi;
+  if (f.kind == 2) {
+    f.tr = stvk_strain<D>(G, f.X);
+    psi = stvk_psi_stress<D>(m, G, f.S);
+  } else {
+    cofactor<D>(G, f.X);
+    const double J = det_of<D>(G, f.X);
+    if (!(J > 0.0)) {
+      f.kind = -1;
+      return f;
+    }
+    const double lnJ = log(J);
+    double n2 = 0.0;
+#pragma unroll
+    for (int r = 0; r < D * D; ++r) n2 += G[r] * G[r];
+    psi = 0.5 * m.mu * (n2 - double(D)) - m.mu * lnJ + 0.5 * m.lambda * lnJ * lnJ;
+    f.c = m.lambda * lnJ - m.mu;
+    f.iJ = 1.0 / J;
+#pragma unroll
+    for (int r = 0; r < D * D; ++r) f.S[r] = m.mu * G[r] + f.c * (f.X[r] * f.iJ);
+  }
+  // on the loading branch max(psi, beta_n) = psi: one exponential serves both factors
+  const double e = exp(-(psi > bn ? psi : bn) / m.D0);
+  f.g1 = 1.0 - m.D_inf * (1.0 - e);
+  f.g2 = psi > bn ? -m.D_inf / m.D0 * e : 0.0;
+  return f;
+}
+
 // Row ij of d^2 W / dG dG (the leaf moduli of Algorithm 3) at one point G, weighted and added:
-// acc[kl] += w d^2 W / dG_ij dG_kl (ij = i*D + j, kl = k*D + l).  The point's
-// scalars (J, ln J, psi0, the damage factors) are formed once for the row.
+// acc[kl] += w d^2 W / dG_ij dG_kl (ij = i*D + j, kl = k*D + l), from the point's
+// factors f = leaf0(G).
 // Neo-Hooke damage (eqs. 2.3, 2.9):
 //   A0 = g' [mu d_ik d_jl + lambda H_ij H_kl - (lambda ln J - mu) H_il H_kj] + g'' S_ij S_kl
 // with H = G^{-T}, S = d psi0 / dG = mu G + (lambda ln J - mu) H, g' = 1 - D(max(psi0, beta_n))
@@ -1075,16 +1119,10 @@ __device__ __forceinline__ void stress0_any(const Material& m, double bn, const 
 // with the same damage factors g', g''.  Double-well test energy: 2 on the
 // diagonal, 12 G_11^2 - 4 at (11, 11).
 template <int D, int IJ>
-__device__ __forceinline__ void tangent0_row(const Material& m, double bn, const double* G, double w, double* acc) {
+__device__ __forceinline__ void leaf0_row(const Leaf0<D>& f, const Material& m, const double* G, double w,
+                                          double* acc) {
   constexpr int ij = IJ, i = IJ / D, j = IJ % D;
-  if (m.model == 2) {
-    double E[D * D], S[D * D];
-    double tr = stvk_strain<D>(G, E);
-    double psi = stvk_psi_stress<D>(m, G, S);
-    // on the loading branch max(psi, beta_n) = psi: one exponential serves both factors
-    const double e = exp(-(psi > bn ? psi : bn) / m.D0);
-    double g1 = 1.0 - m.D_inf * (1.0 - e);
-    double g2 = psi > bn ? -m.D_inf / m.D0 * e : 0.0;
+  if (f.kind == 2) {
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       double Bik = 0.0;
@@ -1094,62 +1132,71 @@ __device__ __forceinline__ void tangent0_row(const Material& m, double bn, const
       for (int l = 0; l < D; ++l) {
         const int kl = k * D + l;
         double h = m.lambda * G[ij] * G[kl] + m.mu * G[i * D + l] * G[k * D + j];
-        if (i == k) h += (j == l ? m.lambda * tr : 0.0) + 2.0 * m.mu * E[l * D + j];
+        if (i == k) h += (j == l ? m.lambda * f.tr : 0.0) + 2.0 * m.mu * f.X[l * D + j];
         if (j == l) h += m.mu * Bik;
-        acc[kl] += w * (g1 * h + g2 * S[ij] * S[kl]);
+        acc[kl] += w * (f.g1 * h + f.g2 * f.S[ij] * f.S[kl]);
       }
     }
     return;
   }
-  if (m.model != 0) {
+  if (f.kind == 1) {
 #pragma unroll
     for (int kl = 0; kl < D * D; ++kl)
       acc[kl] += w * (kl != ij ? 0.0 : ij == 0 ? 12.0 * G[0] * G[0] - 4.0 : 2.0);
     return;
   }
-  double cof[D * D];
-  cofactor<D>(G, cof);
-  double J = det_of<D>(G, cof);
-  if (!(J > 0.0)) {
+  if (f.kind < 0) {
 #pragma unroll
     for (int kl = 0; kl < D * D; ++kl) acc[kl] = __builtin_nan("");
     return;
   }
-  double lnJ = log(J), n2 = 0.0;
-#pragma unroll
-  for (int r = 0; r < D * D; ++r) n2 += G[r] * G[r];
-  double psi = 0.5 * m.mu * (n2 - double(D)) - m.mu * lnJ + 0.5 * m.lambda * lnJ * lnJ;
-  const double e = exp(-(psi > bn ? psi : bn) / m.D0);   // = exp(-psi/D0) on the loading branch
-  double g1 = 1.0 - m.D_inf * (1.0 - e);
-  double g2 = psi > bn ? -m.D_inf / m.D0 * e : 0.0;
-  double c = m.lambda * lnJ - m.mu;
-  const double iJ = 1.0 / J;
-  double Hij = cof[ij] * iJ, Sij = m.mu * G[ij] + c * Hij;
+  const double Hij = f.X[ij] * f.iJ;
 #pragma unroll
   for (int k = 0; k < D; ++k)
 #pragma unroll
     for (int l = 0; l < D; ++l) {
       const int kl = k * D + l;
-      double Hkl = cof[kl] * iJ, Hil = cof[i * D + l] * iJ, Hkj = cof[k * D + j] * iJ;
-      double h = (ij == kl ? m.mu : 0.0) + m.lambda * Hij * Hkl - c * Hil * Hkj;
-      double Skl = m.mu * G[kl] + c * Hkl;
-      acc[kl] += w * (g1 * h + g2 * Sij * Skl);
+      const double Hkl = f.X[kl] * f.iJ, Hil = f.X[i * D + l] * f.iJ, Hkj = f.X[k * D + j] * f.iJ;
+      const double h = (ij == kl ? m.mu : 0.0) + m.lambda * Hij * Hkl - f.c * Hil * Hkj;
+      acc[kl] += w * (f.g1 * h + f.g2 * f.S[ij] * f.S[kl]);
     }
+}
+
+// Rows IJ.. D*D - 1 of the same, row r added to acc + r*D*D.
+template <int D, int IJ = 0>
+__device__ __forceinline__ void leaf0_rows(const Leaf0<D>& f, const Material& m, const double* G, double w,
+                                           double* acc) {
+  if constexpr (IJ < D * D) {
+    leaf0_row<D, IJ>(f, m, G, w, acc + IJ * D * D);
+    leaf0_rows<D, IJ + 1>(f, m, G, w, acc);
+  }
+}
+
+// One row at G with the point's factors formed for it alone.
+template <int D, int IJ>
+__device__ __forceinline__ void tangent0_row(const Material& m, double bn, const double* G, double w, double* acc) {
+  leaf0_row<D, IJ>(leaf0<D>(m, bn, G), m, G, w, acc);
 }
 
 // All rows of d^2 W / dG dG at G, written to A[(ij*D*D + kl) * stride] (a
 // node's column of a component-major array).
 template <int D, int IJ = 0, typename T>
-__device__ __forceinline__ void tangent0_store(const Material& m, double bn, const double* G, T* A, int64_t stride) {
+__device__ __forceinline__ void tangent0_store_rows(const Leaf0<D>& f, const Material& m, const double* G, T* A,
+                                                    int64_t stride) {
   if constexpr (IJ < D * D) {
     double acc[D * D];
 #pragma unroll
     for (int kl = 0; kl < D * D; ++kl) acc[kl] = 0.0;
-    tangent0_row<D, IJ>(m, bn, G, 1.0, acc);
+    leaf0_row<D, IJ>(f, m, G, 1.0, acc);
 #pragma unroll
     for (int kl = 0; kl < D * D; ++kl) A[int64_t(IJ * D * D + kl) * stride] = T(acc[kl]);
-    tangent0_store<D, IJ + 1>(m, bn, G, A, stride);
+    tangent0_store_rows<D, IJ + 1>(f, m, G, A, stride);
   }
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void tangent0_store(const Material& m, double bn, const double* G, T* A, int64_t stride) {
+  tangent0_store_rows<D>(leaf0<D>(m, bn, G), m, G, A, stride);
 }
 
 }  // namespace r1d
