@@ -88,21 +88,22 @@ __global__ __launch_bounds__(256) void k_grid_energy(GridArgs g, r1d::Material m
 
 // Hulls of some directions of a group of up to kGroupMax directions of one
 // iteration.  A block takes R * 64 consecutive line starts of one direction, its
-// lanes R of them 64 apart (lanes on consecutive starts, so accesses coalesce; the
-// first decoded, the next ones stepped to by a mixed-radix add); the blocks of the
-// launch's i-th
-// direction, group slot slot[i], are block_end[i-1] .. block_end[i]-1, so a
-// block's direction (and its Step, read through scalar loads) is uniform.
+// lanes R of them 64 apart (lanes on consecutive starts, so accesses coalesce;
+// the first decoded, the next ones stepped to by a mixed-radix add).  The blocks
+// of the launch's i-th direction, group slot slot[i], are block_end[i-1] ..
+// block_end[i]-1, so a block's direction (and its Step, read through scalar
+// loads) is uniform.
 // A node's candidate is the hull value ((b - q) w_a + (q - a) w_b) / (b - a)
 // where it lies strictly inside a hull segment [a, b] and its own value is
 // finite, +inf otherwise; with offs, also the offsets (q - a) | (b - q) << 16 of
-// its laminate.  Dense (mask null): the launch covers every line and writes every
-// slot (the lines of a direction partition the mesh, so each once).  Sparse: it
-// covers only the lines of at least 3 nodes (shorter ones hold no node strictly
-// inside a segment), writes the finite candidates only and marks them in the
-// node's mask (bit = group slot); unmarked slots are never read.  Non-finite values are
-// absent from a hull.  STAGED: the line's values sit in the thread's LDS column
-// (entry q at [q * kLineThreads]); otherwise they are read in place.
+// its laminate.  Dense (mask null): the launch covers every line and writes
+// every slot (the lines of a direction partition the mesh, so each once).
+// Sparse: it covers only the lines of at least 3 nodes (shorter ones hold no
+// node strictly inside a segment), writes the finite candidates only and marks
+// them in the node's mask (bit = group slot); unmarked slots are never read.
+// Non-finite values are absent from a hull.  STAGED: the line's values sit in
+// the thread's LDS column (entry q at [q * kLineThreads]); otherwise they are
+// read in place.
 constexpr int kGroupMax = 16;
 constexpr int kShortLine = 8;  // lines of at most this many nodes go to their own hull launch
 constexpr int kShortRun = 8;   // line starts per thread there
@@ -543,6 +544,18 @@ r1_status grid_laminate_T(r1_handle h, const GridArgs& g, const std::vector<Step
   return R1_OK;
 }
 
+template <typename T>
+void launch_energy(int dim, dim3 grd, hipStream_t st, const GridArgs& g, const r1d::Material& m, double beta_n,
+                   void* W, void* P, void* A) {
+  T* w = static_cast<T*>(W);
+  T* p = static_cast<T*>(P);
+  T* a = static_cast<T*>(A);
+  if (dim == 2)
+    hipLaunchKernelGGL((k_grid_energy<T, 2>), grd, dim3(256), 0, st, g, m, beta_n, w, p, a);
+  else
+    hipLaunchKernelGGL((k_grid_energy<T, 3>), grd, dim3(256), 0, st, g, m, beta_n, w, p, a);
+}
+
 }  // namespace
 
 extern "C" {
@@ -599,17 +612,10 @@ r1_status r1_grid_energy(r1_handle h, const r1_material* mat, const r1_grid* gri
   const r1d::Material m{mat->dim, mat->model, mat->mu, mat->lambda, mat->D_inf, mat->D0};
   hipStream_t st = static_cast<hipStream_t>(stream);
   const dim3 grd(blocks_of(g.size, 256));
-  if (dtype == R1_F32) {
-    if (grid->dim == 2) hipLaunchKernelGGL((k_grid_energy<float, 2>), grd, dim3(256), 0, st, g, m, beta_n, static_cast<float*>(W), static_cast<float*>(P),
-                                 static_cast<float*>(A));
-    else hipLaunchKernelGGL((k_grid_energy<float, 3>), grd, dim3(256), 0, st, g, m, beta_n, static_cast<float*>(W), static_cast<float*>(P),
-                                 static_cast<float*>(A));
-  } else {
-    if (grid->dim == 2) hipLaunchKernelGGL((k_grid_energy<double, 2>), grd, dim3(256), 0, st, g, m, beta_n, static_cast<double*>(W), static_cast<double*>(P),
-                                 static_cast<double*>(A));
-    else hipLaunchKernelGGL((k_grid_energy<double, 3>), grd, dim3(256), 0, st, g, m, beta_n, static_cast<double*>(W), static_cast<double*>(P),
-                                 static_cast<double*>(A));
-  }
+  if (dtype == R1_F32)
+    launch_energy<float>(grid->dim, grd, st, g, m, beta_n, W, P, A);
+  else
+    launch_energy<double>(grid->dim, grd, st, g, m, beta_n, W, P, A);
   e = hipGetLastError();
   return e == hipSuccess ? R1_OK : r1h::fail(h, e, "kernel launch");
 }
