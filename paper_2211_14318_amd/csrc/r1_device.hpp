@@ -1162,13 +1162,14 @@ __device__ __forceinline__ void leaf0_row(const Leaf0<D>& f, const Material& m, 
     }
 }
 
-// Rows IJ.. D*D - 1 of the same, row r added to acc + r*D*D.
-template <int D, int IJ = 0>
+// Rows IJ .. END - 1 of the same, row r added to acc + (r - IJ0)*D*D (IJ0 = the
+// first row of the range).
+template <int D, int IJ = 0, int END = D * D, int IJ0 = IJ>
 __device__ __forceinline__ void leaf0_rows(const Leaf0<D>& f, const Material& m, const double* G, double w,
                                            double* acc) {
-  if constexpr (IJ < D * D) {
-    leaf0_row<D, IJ>(f, m, G, w, acc + IJ * D * D);
-    leaf0_rows<D, IJ + 1>(f, m, G, w, acc);
+  if constexpr (IJ < END) {
+    leaf0_row<D, IJ>(f, m, G, w, acc + (IJ - IJ0) * D * D);
+    leaf0_rows<D, IJ + 1, END, IJ0>(f, m, G, w, acc);
   }
 }
 
