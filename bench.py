@@ -501,8 +501,8 @@ def main():
                     help="only run this secondary leg and print its result (a profiling aid)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this benchmark runs on one GPU only (quadrature points are independent; "
-              "the multi-GPU split is described in DESIGN.md); got --gpus %d" % args.gpus,
+        print("bench.py: this benchmark runs on one GPU only (quadrature points are independent, so "
+              "several GPUs would each take a cost-balanced share of them); got --gpus %d" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 

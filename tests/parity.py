@@ -1,6 +1,6 @@
 """Helpers comparing the GPU path with the FP64 oracle (test infrastructure).
 
-Tolerances (the derivation is in DESIGN.md, "Parity bar"):
+Tolerances:
   energy  |W_gpu - W_orc| <= RTOL * max(|W_orc|, W_FLOOR)
           RTOL = 1e-12 (FP64 path) / 1e-5 (FP32 path).  W is a difference of
           O(1) terms (mu/2 |F|^2, mu ln J, lambda/2 ln^2 J, D_inf D0 e^...), so

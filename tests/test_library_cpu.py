@@ -110,3 +110,34 @@ def test_grid_line_starts_match_brute_force(tmp_path):
             assert count == bench.grid_lines_at_least(n, s, min_len)  # the bench's closed form
             assert ds == sum(s[c] * strides[c] for c in range(dd))
         assert pos == len(vals)
+
+
+def test_bench_contract_without_gpu(tmp_path):
+    """bench.py's host logic: it refuses more than one GPU with a message and a non-zero
+    status; the committed HBM traffic figure is reported only while the kernel sources
+    hash to the fingerprint it was measured on; the algorithmic byte counts of the
+    tangent and grid legs."""
+    import subprocess
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True)
+    assert r.returncode != 0 and "one GPU" in r.stderr and r.stdout == ""
+    assert isinstance(bench.measured_traffic(), int)        # sources unchanged since the counters
+    text = open(bench.TRAFFIC_FILE).read()
+    stale = tmp_path / "hbm.txt"
+    stale.write_text(text.replace("source_fingerprint = ", "source_fingerprint = 0"))
+    old = bench.TRAFFIC_FILE
+    try:
+        bench.TRAFFIC_FILE = str(stale)
+        assert bench.measured_traffic() is None
+    finally:
+        bench.TRAFFIC_FILE = old
+    # 2D depth 1, FP32: F (4), beta_n, W, one tree node of 16 B, 16 moduli
+    assert bench.tangent_bytes(2, 1, 4) == 4 * (4 + 2) + 16 + 4 * 16
+    # a 2D mesh whose lines along component 0 have 5 nodes and no other line has 3
+    n = [5, 1, 1, 1]
+    steps = [[1, 0, 0, 0], [0, 1, 0, 0]]
+    assert bench.grid_line_nodes(n, steps) == 5
+    assert bench.grid_bytes(5, 5, 8) == 8 * (5 + 2 * 5)
