@@ -35,7 +35,7 @@ if ROOT not in sys.path:
 
 FLOPS_PER_W = 18           # algorithmic flops per W sample (FMA = 2), transcendentals not counted
 PEAK = {"f32": 157.3, "f64": 78.6}   # MI355X vector peak, TFLOP/s
-PEAK_NONPACKED = {"f32": 78.6, "f64": 78.6}   # without packed FP32 (this build does not emit it)
+PEAK_NONPACKED = {"f32": 78.6, "f64": 78.6}   # without packed FP32 (the library is compiled without it)
 GAMMA = 1e-8               # relative error E_rel = |a - b| / (gamma + |b|)
 
 

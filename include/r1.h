@@ -51,7 +51,7 @@ typedef int32_t r1_status;
 #define R1_ENOMEM (-2)        /* device workspace could not be allocated */
 #define R1_EDEVICE (-3)       /* a HIP call failed (message via r1_last_error) */
 #define R1_ENOTTRAINED (-4)   /* surrogate used before training or loading */
-#define R1_EUNSUPPORTED (-5)  /* valid request that this build does not implement */
+#define R1_EUNSUPPORTED (-5)  /* valid request that this library does not implement */
 #define R1_EIO (-6)           /* surrogate file could not be read or written */
 
 typedef int32_t r1_dtype;
