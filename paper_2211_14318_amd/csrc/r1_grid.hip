@@ -125,6 +125,26 @@ template <typename T, bool STAGED, int CHUNK>
 __device__ __forceinline__ void hull_line(const T* __restrict__ Win, T* __restrict__ cd, uint32_t* __restrict__ od,
                                           uint32_t* __restrict__ mask, uint32_t bit, int64_t p, int64_t ds, int L,
                                           T* vin, uint16_t* st) {
+  if (L == 3) {
+    // three nodes (most lines of the 9-D meshes): the chain pops the middle one
+    // exactly when it lies on or above the chord, and its candidate is the chord's
+    // midpoint -- the general path's arithmetic, without its loops
+    const T w0 = Win[p], w1 = Win[p + ds], w2 = Win[p + 2 * ds];
+    const bool fin = w0 < inf_t<T>() && w1 < inf_t<T>() && w2 < inf_t<T>();
+    const bool cand1 = fin && (w1 - w0) * T(1) >= (w2 - w1) * T(1);
+    const T val = cand1 ? (T(1) * w0 + T(1) * w2) / T(2) : inf_t<T>();
+    if (!mask) {
+      cd[p] = inf_t<T>();
+      cd[p + 2 * ds] = inf_t<T>();
+      if (od) od[p] = od[p + 2 * ds] = 0u;
+    }
+    if (!mask || cand1) {
+      cd[p + ds] = val;
+      if (od) od[p + ds] = cand1 ? (1u | (1u << 16)) : 0u;
+      if (mask) atomicOr(mask + p + ds, bit);
+    }
+    return;
+  }
   auto win = [&](int q) -> T { return STAGED ? vin[q * kLineThreads] : Win[p + q * ds]; };
   if constexpr (STAGED) {
     // chunks of independent loads: a line costs one or two memory round trips, not L
