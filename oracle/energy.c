@@ -5,7 +5,19 @@
  */
 #include <math.h>
 #include <stddef.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include "r1_oracle.h"
+
+void* orc_alloc(size_t bytes)
+{
+    void* p = malloc(bytes ? bytes : 1);
+    if (!p) {
+        fprintf(stderr, "oracle: cannot allocate %zu bytes\n", bytes);
+        abort();
+    }
+    return p;
+}
 
 /* Plane-strain embedding: the 3x3 gradient of a 2D state has G33 = 1. */
 static void embed3(int d, const double* G, double F3[3][3])

@@ -143,11 +143,11 @@ double orc_grid_sweep(const orc_grid* g, int n_dir, const int* steps, const doub
     for (int c = 0; c < dd; ++c)
         if (g->n[c] > maxlen)
             maxlen = g->n[c];
-    long* node = (long*)malloc(sizeof(long) * (size_t)maxlen);
-    double* w = (double*)malloc(sizeof(double) * (size_t)maxlen);
-    double* x = (double*)malloc(sizeof(double) * (size_t)maxlen);
-    double* v = (double*)malloc(sizeof(double) * (size_t)maxlen);
-    int* vert = (int*)malloc(sizeof(int) * (size_t)maxlen);
+    long* node = (long*)orc_alloc(sizeof(long) * (size_t)maxlen);
+    double* w = (double*)orc_alloc(sizeof(double) * (size_t)maxlen);
+    double* x = (double*)orc_alloc(sizeof(double) * (size_t)maxlen);
+    double* v = (double*)orc_alloc(sizeof(double) * (size_t)maxlen);
+    int* vert = (int*)orc_alloc(sizeof(int) * (size_t)maxlen);
     memcpy(Wout, Win, sizeof(double) * (size_t)n);
     if (Cin && Cout)
         memcpy(Cout, Cin, sizeof(double) * (size_t)n * (size_t)m);
@@ -233,7 +233,7 @@ double orc_grid_update_node(const orc_grid* g, int n_dir, const int* steps, cons
     for (int c = 0; c < dd; ++c)
         if (g->n[c] > maxlen)
             maxlen = g->n[c];
-    double* w = (double*)malloc(sizeof(double) * (size_t)(2 * maxlen + 1));
+    double* w = (double*)orc_alloc(sizeof(double) * (size_t)(2 * maxlen + 1));
     int I[9];
     unflatten(g, p, I);
     double best = W[p];
@@ -277,8 +277,8 @@ int orc_grid_laminate(const orc_grid* g, int n_dir, const int* steps, double* W,
 {
     long n = orc_grid_size(g);
     size_t np = C ? (size_t)n * (size_t)m : 0;
-    double* next = (double*)malloc(sizeof(double) * (size_t)n);
-    double* pnext = C ? (double*)malloc(sizeof(double) * np) : NULL;
+    double* next = (double*)orc_alloc(sizeof(double) * (size_t)n);
+    double* pnext = C ? (double*)orc_alloc(sizeof(double) * np) : NULL;
     int k = 0;
     while (k < k_max) {
         double md = orc_grid_sweep(g, n_dir, steps, W, next, m, C, pnext);

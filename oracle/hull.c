@@ -24,8 +24,8 @@ int orc_convexify(int L, const double* x, const double* w, int* vert)
         return 1;
     }
     /* y[k], c[k]: abscissa and value of hull vertex k (0-based, n entries) */
-    double* y = (double*)malloc(sizeof(double) * (size_t)L);
-    double* c = (double*)malloc(sizeof(double) * (size_t)L);
+    double* y = (double*)orc_alloc(sizeof(double) * (size_t)L);
+    double* c = (double*)orc_alloc(sizeof(double) * (size_t)L);
     y[0] = x[0]; c[0] = w[0]; vert[0] = 0;
     y[1] = x[1]; c[1] = w[1]; vert[1] = 1;
     int n = 2;
@@ -47,10 +47,10 @@ int orc_convexify(int L, const double* x, const double* w, int* vert)
 double orc_hull_at_centre(int n, const double* w, int c, int* i_minus, int* i_plus,
                           double* bridge_gap)
 {
-    int* idx = (int*)malloc(sizeof(int) * (size_t)n);
-    double* x = (double*)malloc(sizeof(double) * (size_t)n);
-    double* v = (double*)malloc(sizeof(double) * (size_t)n);
-    int* vert = (int*)malloc(sizeof(int) * (size_t)n);
+    int* idx = (int*)orc_alloc(sizeof(int) * (size_t)n);
+    double* x = (double*)orc_alloc(sizeof(double) * (size_t)n);
+    double* v = (double*)orc_alloc(sizeof(double) * (size_t)n);
+    int* vert = (int*)orc_alloc(sizeof(int) * (size_t)n);
     int L = 0;
     for (int i = 0; i < n; ++i)
         if (isfinite(w[i])) {

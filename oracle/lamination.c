@@ -48,7 +48,7 @@ static double level_value(const orc_material* mat, const orc_lamination* lam, in
     }
     const orc_level* lv = &lam->level[ell];
     int n = lv->n_t, c = (n - 1) / 2;
-    double* w = (double*)malloc(sizeof(double) * (size_t)n);
+    double* w = (double*)orc_alloc(sizeof(double) * (size_t)n);
     double Gi[9];
     double best = INFINITY, second = INFINITY, best_gap = INFINITY;
     double vertex_gap = INFINITY;   /* how close any direction is to laminating */

@@ -36,8 +36,8 @@ static double silu_prime(double z)
 double orc_mlp_forward(int d_in, int width, int n_hidden, int d_out, const double* params,
                        long B, const double* x, const double* y, double* out)
 {
-    double* h = (double*)malloc(sizeof(double) * (size_t)width);
-    double* hn = (double*)malloc(sizeof(double) * (size_t)width);
+    double* h = (double*)orc_alloc(sizeof(double) * (size_t)width);
+    double* hn = (double*)orc_alloc(sizeof(double) * (size_t)width);
     double loss = 0.0;
     for (long b = 0; b < B; ++b) {
         const double* p = params;
@@ -83,12 +83,12 @@ double orc_mlp_loss_grad(int d_in, int width, int n_hidden, int d_out, const dou
     long np = orc_mlp_param_count(d_in, width, n_hidden, d_out);
     memset(grad, 0, sizeof(double) * (size_t)np);
     /* pre-activations and activations of every hidden layer for one row */
-    double* z = (double*)malloc(sizeof(double) * (size_t)width * n_hidden);
-    double* a = (double*)malloc(sizeof(double) * (size_t)width * n_hidden);
-    double* delta = (double*)malloc(sizeof(double) * (size_t)width);
-    double* dprev = (double*)malloc(sizeof(double) * (size_t)width);
-    double* gout = (double*)malloc(sizeof(double) * (size_t)d_out);
-    long* off = (long*)malloc(sizeof(long) * (size_t)(n_hidden + 1));
+    double* z = (double*)orc_alloc(sizeof(double) * (size_t)width * n_hidden);
+    double* a = (double*)orc_alloc(sizeof(double) * (size_t)width * n_hidden);
+    double* delta = (double*)orc_alloc(sizeof(double) * (size_t)width);
+    double* dprev = (double*)orc_alloc(sizeof(double) * (size_t)width);
+    double* gout = (double*)orc_alloc(sizeof(double) * (size_t)d_out);
+    long* off = (long*)orc_alloc(sizeof(long) * (size_t)(n_hidden + 1));
     /* offsets of W_l in the flat layout */
     long o = 0;
     for (int l = 0; l < n_hidden; ++l) {

@@ -22,6 +22,8 @@
 #ifndef R1_ORACLE_H
 #define R1_ORACLE_H
 
+#include <stddef.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -32,6 +34,10 @@ extern "C" {
 
 #define ORC_MAX_DEPTH 2
 #define ORC_TREE_NODES 3        /* 2^ORC_MAX_DEPTH - 1 */
+
+/* malloc that reports the request and aborts when it cannot be met (the oracle
+ * has no partial results to return). */
+void* orc_alloc(size_t bytes);
 
 typedef struct {
     int dim;       /* 2 or 3 */
