@@ -198,7 +198,7 @@ r1_status r1_get_inner_segment_width(r1_handle handle, int32_t n_t, r1_dtype dty
                                      int32_t* lanes);
 
 /* Autotuner: times every admissible segment width for lines of n_t points on a
- * synthetic one-level batch of 2048 points (32 directions) with the given
+ * synthetic one-level batch of 16384 points (32 directions) with the given
  * material and dtype on `stream` (synchronizes it), records the fastest for
  * one-level lines of (n_t, dtype, material->dim) in the handle and returns it
  * in *lanes (nullable).  r1_envelope_batched runs it on first use of each
@@ -209,7 +209,7 @@ r1_status r1_autotune(r1_handle handle, const r1_material* material, int32_t n_t
 /* Same for the inner level of depth-2 laminations, whose lines are sampled
  * along outer lines (the bridge searches start from the previous outer
  * sample's result, which favours other widths than independent lines): times
- * the depth-2 path on a synthetic batch of 128 points (outer level 8
+ * the depth-2 path on a synthetic batch of 1024 points (outer level 8
  * directions x 129 points, inner level 32 directions x n_t points).  Used by
  * r1_envelope_stress at depth 2 and by r1_envelope_batched (which runs it on
  * first use of each inner grid size without a user setting or tuned value). */

@@ -77,10 +77,13 @@ void r1h::release_batched(r1_handle h) {
 
 // Times every admissible segment width for lines of n_t points and records
 // the fastest for (n_t, dtype, dim, role).  Role kRoleLevel: a synthetic
-// one-level batch (2048 points near the identity, 32 directions).  Role
+// one-level batch (16384 points near the identity, 32 directions).  Role
 // kRoleInner: the same 32 directions as the inner level of a depth-2 batch
-// (128 points, outer level of 8 directions x 129 points), timed through the
-// depth-2 path, whose inner lines are sampled along outer lines.
+// (1024 points, outer level of 8 directions x 129 points), timed through the
+// depth-2 path, whose inner lines are sampled along outer lines.  Both batches
+// launch several thousand blocks, many times what the chip holds at once, so
+// the last partly filled round of blocks does not decide between layouts of
+// different occupancy.
 r1_status r1h::autotune(r1_handle h, const r1_material* mat, int n_t, int dtype, int dim, int role,
                         hipStream_t st, int* lanes) {
   const int key_dim = dim;
@@ -94,7 +97,7 @@ r1_status r1h::autotune(r1_handle h, const r1_material* mat, int n_t, int dtype,
     return R1_OK;
   }
   const bool inner = role == kRoleInner;
-  const int n = inner ? 128 : 2048, na = 8, nb = 4, dd = dim * dim;
+  const int n = inner ? 1024 : 16384, na = 8, nb = 4, dd = dim * dim;
   const int nao = 4, nbo = 2, nt_o = 129;
   const size_t ts = dtype == R1_F32 ? 4 : 8;
   std::vector<double> Fd(size_t(dd) * n), bnd(n), a(size_t(na * nb) * dim, 0.0), b(size_t(na * nb) * dim, 0.0);
