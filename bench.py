@@ -304,15 +304,16 @@ def leg_3d(h, r1, WL, torch, np, n_check=64):
     n = cfg["n"]
     W = torch.empty(n, device="cuda")
     P = torch.empty((9, n), device="cuda")
-    t = timed(lambda: h.envelope_into(mat, spec, F, bn, W, P), 3, torch)
     lv = cfg["levels"][0]
+    lanes = h.autotune(mat, lv["n_t"], r1.R1_F32)              # untimed, as a caller would once
+    t = timed(lambda: h.envelope_into(mat, spec, F, bn, W, P), 3, torch)
     om = O.material(dim=3)
     ospec = O.LaminationSpec([(lv["a"], lv["b"], lv["n_t"], lv["tau"])])
     sel = np.linspace(0, n - 1, n_check).astype(int)
     Fin = F.double().cpu().numpy()
     bin_ = bn.double().cpu().numpy()
     Wo, _, _ = O.envelope_batch(om, ospec, Fin[:, sel], bin_[sel], want_stress=False)
-    return {"workload": cfg["name"], "qps": round(n / t, 1), "ms": round(1e3 * t, 2),
+    return {"workload": cfg["name"], "qps": round(n / t, 1), "ms": round(1e3 * t, 2), "lanes_per_line": lanes,
             "w_samples_per_s": float(n * len(lv["a"]) * (lv["n_t"] - 1) / t),
             "erel_vs_oracle": erel_stats(W.cpu().numpy()[sel], Wo, floor=1e-2)}
 
