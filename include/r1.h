@@ -288,7 +288,7 @@ r1_status r1_grid_interpolate(r1_handle handle, const r1_grid* grid, r1_dtype dt
 /* ---- learned surrogate ---------------------------------------------------------
  *
  * A multilayer perceptron (F, beta_n) -> (W^k, P^k) trained on lamination
- * results, with plain lamination as fallback and judge.  Inputs x = (F_11 ..
+ * results; plain lamination is the fallback and the measure of its error.  Inputs x = (F_11 ..
  * F_dd, beta_n) (d_in = d*d + 1), standardized with training statistics.  The
  * network predicts the relaxation gap g = W(F) - W^k(F) >= 0 and dP = P0(F) -
  * P^k(F); inference returns W(F) - max(g, 0) and P0(F) - dP with W(F) and
