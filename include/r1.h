@@ -173,14 +173,36 @@ r1_status r1_laminate_tangent(r1_handle handle, const r1_material* material,
                               const void* F, const void* beta_n, const void* W,
                               const r1_laminate* tree, void* A, void* stream);
 
-/* Uneven batch in one persistent launch: point p uses table[lam_idx[p]]
- * (lam_idx: device int32[n], each in [0, n_table)).  P and tree are nullable
- * (no stress when P == NULL).  The launch sequence is captured once into a
- * HIP graph per (table, n, dtype, buffers) and replayed; the work split and the
- * segment width are chosen by the built-in autotuner on first use.  lam_idx is
- * read by the host planner on the first call for a given buffer (one
- * device-to-host copy); later calls with the same buffers reuse the plan, so
- * its contents must not change between calls that share lam_idx. */
+/* Uneven batch in one persistent launch (the per-point tasks of Section 5.5,
+ * each point with its own lamination): point p uses table[lam_idx[p]]
+ * (lam_idx: device int32[n], each in [0, n_table), else R1_EINVAL).  P and tree
+ * are nullable (no stress when P == NULL).
+ *
+ * A plan is built once for a table and a set of table indices:
+ * r1_batched_plan_create reads lam_idx (one device-to-host copy; synchronizes
+ * `stream`), runs the built-in autotuner for grid sizes that have neither a
+ * user setting nor a tuned value, orders the work (largest points first) and
+ * keeps its own device copies of the work lists, the indices and the table's
+ * directions, so later changes to lam_idx or to the direction arrays do not
+ * affect it.  r1_batched_plan_execute replays the plan's launch sequence as one
+ * HIP graph on `stream`; a graph is captured on first use of a set of buffers
+ * (F, beta_n, W, P, tree, flags) and up to 4 such sets are kept per plan.
+ * Replays of one plan must not overlap in time (they share its work queues and
+ * partial results): issue them on one stream.  A plan is freed by
+ * r1_batched_plan_destroy, or by r1_destroy of its handle (which frees every
+ * plan left; their pointers are invalid afterwards). */
+typedef struct r1_batched_plan_s* r1_batched_plan;
+r1_status r1_batched_plan_create(r1_handle handle, const r1_material* material,
+                                 const r1_lamination* table, int32_t n_table, int64_t n,
+                                 const int32_t* lam_idx, r1_dtype dtype, void* stream,
+                                 r1_batched_plan* plan);
+r1_status r1_batched_plan_execute(r1_batched_plan plan, const void* F, const void* beta_n, void* W,
+                                  void* P, r1_laminate* tree, int32_t* flags, void* stream);
+r1_status r1_batched_plan_destroy(r1_batched_plan plan);
+
+/* One-call form: reads lam_idx on every call (one device-to-host copy;
+ * synchronizes `stream`), finds or builds the plan for the contents of the
+ * table and the indices (up to 8 plans are kept per handle) and executes it. */
 r1_status r1_envelope_batched(r1_handle handle, const r1_material* material,
                               const r1_lamination* table, int32_t n_table, int64_t n,
                               const int32_t* lam_idx, r1_dtype dtype, const void* F,

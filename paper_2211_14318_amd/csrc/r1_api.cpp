@@ -65,38 +65,11 @@ r1_status r1h::check_lamination(const r1_lamination* lam) {
   return R1_OK;
 }
 
-// Device copy of a level's directions, cached by content.
-r1_status r1h::device_level(r1_handle h, const r1_level& lv, int dim, r1d::Level* out) {
-  size_t bytes = sizeof(double) * size_t(lv.n_dir) * size_t(dim);
-  uint64_t key = 1469598103934665603ull;
-  int32_t hdr[2] = {lv.n_dir, dim};
-  key = fnv1a(hdr, sizeof(hdr), key);
-  key = fnv1a(lv.a, bytes, key);
-  key = fnv1a(lv.b, bytes, key);
-  auto it = h->dirs.find(key);
-  if (it == h->dirs.end()) {
-    if (h->dirs.size() >= 512) {
-      hipError_t e = hipDeviceSynchronize();
-      if (e != hipSuccess) return fail(h, e, "hipDeviceSynchronize");
-      for (auto& kv : h->dirs) (void)hipFree(kv.second);
-      h->dirs.clear();
-    }
-    void* d = nullptr;
-    hipError_t e = hipMalloc(&d, 2 * bytes);
-    if (e != hipSuccess) return R1_ENOMEM;
-    std::vector<double> host(2 * size_t(lv.n_dir) * size_t(dim));
-    std::memcpy(host.data(), lv.a, bytes);
-    std::memcpy(host.data() + size_t(lv.n_dir) * dim, lv.b, bytes);
-    e = hipMemcpy(d, host.data(), 2 * bytes, hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-      (void)hipFree(d);
-      return fail(h, e, "hipMemcpy(directions)");
-    }
-    it = h->dirs.emplace(key, d).first;
-  }
-  const double* base = static_cast<const double*>(it->second);
-  out->a = base;
-  out->b = base + size_t(lv.n_dir) * dim;
+// Host part of a level's device description: sizes, grid and |a|^2 |b|^2
+// (the a, b pointers are filled by the caller).
+void r1h::level_meta(const r1_level& lv, int dim, r1d::Level* out) {
+  out->a = nullptr;
+  out->b = nullptr;
   out->n_dir = lv.n_dir;
   out->n_t = lv.n_t;
   out->tau = lv.tau;
@@ -113,6 +86,68 @@ r1_status r1h::device_level(r1_handle h, const r1_level& lv, int dim, r1d::Level
     dev = std::max(dev, std::fabs(aa * bb - ab0));
   }
   out->ab2 = (lv.n_dir > 0 && dev <= 8.0 * 2.220446049250313e-16 * ab0) ? ab0 : std::nan("");
+}
+
+namespace {
+
+uint64_t level_key(const r1_level& lv, int dim) {
+  size_t bytes = sizeof(double) * size_t(lv.n_dir) * size_t(dim);
+  uint64_t key = 1469598103934665603ull;
+  int32_t hdr[2] = {lv.n_dir, dim};
+  key = fnv1a(hdr, sizeof(hdr), key);
+  key = fnv1a(lv.a, bytes, key);
+  return fnv1a(lv.b, bytes, key);
+}
+
+}  // namespace
+
+// Device copies of the directions of `count` levels, cached by content.  All
+// levels of the call are looked up before anything is evicted, and eviction
+// (when the cache would pass 512 entries) spares them, so no pointer handed out
+// by this call is freed by it.  Only plain launches use these copies, and
+// eviction waits for the device first; batched plans keep their own copies.
+r1_status r1h::device_levels(r1_handle h, const r1_level* const* lv, int count, int dim, r1d::Level* out) {
+  uint64_t keys[R1_MAX_DEPTH + 2];
+  if (count < 1 || count > R1_MAX_DEPTH + 2) return R1_EINVAL;
+  int missing = 0;
+  for (int k = 0; k < count; ++k) {
+    keys[k] = level_key(*lv[k], dim);
+    missing += h->dirs.count(keys[k]) == 0;
+  }
+  if (missing && h->dirs.size() + size_t(missing) > 512) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return fail(h, e, "hipDeviceSynchronize");
+    for (auto it = h->dirs.begin(); it != h->dirs.end();) {
+      if (std::find(keys, keys + count, it->first) != keys + count) {
+        ++it;
+        continue;
+      }
+      (void)hipFree(it->second);
+      it = h->dirs.erase(it);
+    }
+  }
+  for (int k = 0; k < count; ++k) {
+    const size_t bytes = sizeof(double) * size_t(lv[k]->n_dir) * size_t(dim);
+    auto it = h->dirs.find(keys[k]);
+    if (it == h->dirs.end()) {
+      void* d = nullptr;
+      hipError_t e = hipMalloc(&d, 2 * bytes);
+      if (e != hipSuccess) return R1_ENOMEM;
+      std::vector<double> host(2 * size_t(lv[k]->n_dir) * size_t(dim));
+      std::memcpy(host.data(), lv[k]->a, bytes);
+      std::memcpy(host.data() + size_t(lv[k]->n_dir) * dim, lv[k]->b, bytes);
+      e = hipMemcpy(d, host.data(), 2 * bytes, hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        (void)hipFree(d);
+        return fail(h, e, "hipMemcpy(directions)");
+      }
+      it = h->dirs.emplace(keys[k], d).first;
+    }
+    level_meta(*lv[k], dim, &out[k]);
+    const double* base = static_cast<const double*>(it->second);
+    out[k].a = base;
+    out[k].b = base + size_t(lv[k]->n_dir) * dim;
+  }
   return R1_OK;
 }
 
@@ -249,10 +284,13 @@ r1_status fill_args(r1_handle h, const r1_material* mat, const r1_lamination* la
   if (n == 0) return R1_OK;
   hipError_t e = hipSetDevice(h->device);
   if (e != hipSuccess) return r1h::fail(h, e, "hipSetDevice");
-  s = r1h::device_level(h, lam->level[0], mat->dim, &a->lv0);
+  const r1_level* lvs[2] = {&lam->level[0], &lam->level[1]};
+  r1d::Level out[2];
+  s = r1h::device_levels(h, lvs, lam->depth, mat->dim, out);
   if (s) return s;
-  if (lam->depth == 2) s = r1h::device_level(h, lam->level[1], mat->dim, &a->lv1);
-  return s;
+  a->lv0 = out[0];
+  if (lam->depth == 2) a->lv1 = out[1];
+  return R1_OK;
 }
 
 // Envelope with optional stress, tree, flags and tangent moduli (A != nullptr:

@@ -1,6 +1,7 @@
-// Host side of the uneven batch (r1_envelope_batched): the planner that turns
-// the per-point table indices into an ordered work list, the captured HIP graph
-// that replays the persistent launch, and the segment-width autotuner.
+// Host side of the uneven batch (r1_batched_plan_*, r1_envelope_batched): the
+// plan that owns the ordered work lists, the table's directions and a copy of
+// the per-point table indices, the captured HIP graphs that replay its
+// persistent launches, and the segment-width autotuner.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -10,16 +11,32 @@
 #include <vector>
 
 #include "r1_batched_kernels.hpp"
+#include "r1_batched_plan.hpp"
 #include "r1_handle.hpp"
 
-struct BatchedPlan {
-  uint64_t key = 0;
+struct r1_batched_plan_s {
+  r1_handle h = nullptr;
+  uint64_t key = 0;             // content key (r1_envelope_batched's cache)
   uint64_t serial = 0;
-  void* dev = nullptr;          // table, items, order, pbase, counters, outer results
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  int64_t n_items = 0;
-  int64_t n_outer = 0;
+  int dtype = 0;
+  int64_t n = 0;
+  void* dev = nullptr;          // table, directions, table indices, items, order, pbase, counters, results
+  int* counters = nullptr;      // queue heads, cleared at the start of every replay
+  int n_counters = 0;
+  struct Launch {
+    BArgs b;                    // plan-owned pointers; the caller's buffers are set at capture
+    int var, kind, grid;
+    size_t lds;
+  };
+  std::vector<Launch> launches;
+  struct Graph {                // one captured sequence per set of caller buffers
+    const void* ptrs[6];
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    uint64_t used;
+  };
+  std::vector<Graph> graphs;
+  uint64_t clock = 0;
 };
 
 namespace {
@@ -36,10 +53,17 @@ uint64_t mix(uint64_t h, const void* p, size_t n) {
 template <typename V>
 uint64_t mixv(uint64_t h, const V& v) { return mix(h, &v, sizeof(v)); }
 
-void free_plan(BatchedPlan* pl) {
+void free_graph(r1_batched_plan_s::Graph& g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.graph) (void)hipGraphDestroy(g.graph);
+  g.exec = nullptr;
+  g.graph = nullptr;
+}
+
+// Frees a plan; the caller has made sure no replay of it is still running.
+void free_plan(r1_batched_plan_s* pl) {
   if (!pl) return;
-  if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
-  if (pl->graph) (void)hipGraphDestroy(pl->graph);
+  for (auto& g : pl->graphs) free_graph(g);
   if (pl->dev) (void)hipFree(pl->dev);
   delete pl;
 }
@@ -69,6 +93,8 @@ int r1h::batch_samples_per_lane(int S, int n_t) {
 void r1h::release_batched(r1_handle h) {
   for (auto& kv : h->plans) free_plan(kv.second);
   h->plans.clear();
+  for (r1_batched_plan_s* pl : h->user_plans) free_plan(pl);
+  h->user_plans.clear();
   if (h->capture_stream) {
     (void)hipStreamDestroy(h->capture_stream);
     h->capture_stream = nullptr;
@@ -162,10 +188,14 @@ r1_status r1h::autotune(r1_handle h, const r1_material* mat, int n_t, int dtype,
   if (!s && inner) {
     ka.scratch_w1f = static_cast<char*>(dW) + align_up(ts * n);
     ka.scratch_outer = static_cast<char*>(ka.scratch_w1f) + align_up(ts * n);
-    s = device_level(h, lvo, dim, &ka.lv0);
-    if (!s) s = device_level(h, lv, dim, &ka.lv1);
+    const r1_level* lvs[2] = {&lvo, &lv};
+    r1d::Level out[2];
+    s = device_levels(h, lvs, 2, dim, out);
+    ka.lv0 = out[0];
+    ka.lv1 = out[1];
   } else if (!s) {
-    s = device_level(h, lv, dim, &ka.lv0);
+    const r1_level* lvs[1] = {&lv};
+    s = device_levels(h, lvs, 1, dim, &ka.lv0);
   }
   const int depth = inner ? 2 : 1;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -224,12 +254,10 @@ extern "C" r1_status r1_autotune_inner(r1_handle h, const r1_material* mat, int3
   return s;
 }
 
-extern "C" r1_status r1_envelope_batched(r1_handle h, const r1_material* mat,
-                                         const r1_lamination* table, int32_t n_table, int64_t n,
-                                         const int32_t* lam_idx, r1_dtype dtype, const void* F,
-                                         const void* beta_n, void* W, void* P, r1_laminate* tree,
-                                         int32_t* flags, void* stream) {
-  if (!h) return R1_EINVAL;
+
+namespace {
+
+r1_status check_table(const r1_material* mat, const r1_lamination* table, int32_t n_table) {
   r1_status s = r1h::check_material(mat);
   if (s) return s;
   if (!table || n_table < 1 || n_table > 4096) return R1_EINVAL;
@@ -237,6 +265,303 @@ extern "C" r1_status r1_envelope_batched(r1_handle h, const r1_material* mat,
     s = r1h::check_lamination(&table[k]);
     if (s) return s;
   }
+  return R1_OK;
+}
+
+// Reads the caller's per-point table indices (device) into idx and checks them.
+r1_status read_indices(r1_handle h, const int32_t* lam_idx, int64_t n, int32_t n_table, hipStream_t st,
+                       std::vector<int32_t>* idx) {
+  idx->resize(static_cast<size_t>(n));
+  hipError_t e = hipMemcpyAsync(idx->data(), lam_idx, sizeof(int32_t) * size_t(n), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return r1h::fail(h, e, "read lam_idx");
+  for (int64_t p = 0; p < n; ++p)
+    if ((*idx)[size_t(p)] < 0 || (*idx)[size_t(p)] >= n_table) return R1_EINVAL;
+  return R1_OK;
+}
+
+// Builds a plan for table indices idx (host copy, checked): tunes the segment
+// widths it needs, orders the work, and uploads the table (with its own copy of
+// every level's directions), the indices and the work lists into one device
+// buffer owned by the plan.  No graph is captured yet.
+r1_status make_plan(r1_handle h, const r1_material* mat, const r1_lamination* table, int32_t n_table,
+                    const std::vector<int32_t>& idx, r1_dtype dtype, hipStream_t st, r1_batched_plan_s** out) {
+  const int dim = mat->dim;
+  const int64_t n = int64_t(idx.size());
+  constexpr int NV = R1_N_BATCH_VARIANTS;
+  const size_t ts = dtype == R1_F32 ? 4 : 8;
+  std::vector<BEntry> ent(static_cast<size_t>(n_table));
+  std::vector<r1plan::Entry> pent(static_cast<size_t>(n_table));
+  std::vector<size_t> dir_off(static_cast<size_t>(2 * n_table), 0);   // doubles into the direction block
+  std::vector<double> dirs;
+  size_t lds[NV] = {};
+  r1_status s = R1_OK;
+  for (int k = 0; k < n_table; ++k) {
+    const r1_lamination& L = table[k];
+    BEntry& b = ent[size_t(k)];
+    std::memset(&b, 0, sizeof(b));
+    b.depth = L.depth;
+    for (int l = 0; l < L.depth; ++l) {
+      const r1_level& lv = L.level[l];
+      r1h::level_meta(lv, dim, l == 0 ? &b.lv0 : &b.lv1);
+      dir_off[size_t(2 * k + l)] = dirs.size();
+      dirs.insert(dirs.end(), lv.a, lv.a + size_t(lv.n_dir) * dim);
+      dirs.insert(dirs.end(), lv.b, lv.b + size_t(lv.n_dir) * dim);
+    }
+    const int nti = L.level[L.depth - 1].n_t;
+    const int role = L.depth == 2 ? r1h::kRoleInner : r1h::kRoleLevel;
+    if (!h->seg_override.count(nti) && !h->seg_tuned.count(r1h::tune_key(nti, dtype, dim, role))) {
+      s = r1h::autotune(h, mat, nti, dtype, dim, role, st, nullptr);
+      if (s) return s;
+    }
+    const int S = r1h::segment_width(h, nti, dtype, dim, role);
+    const int K = r1h::batch_samples_per_lane(S, nti);
+    b.var = K > 0 ? r1_batch_variant(S, K) : -1;
+    for (int S2 = 16; b.var < 0 && S2 <= 64; S2 *= 2) {   // width outside the variant set
+      const int K2 = r1h::batch_samples_per_lane(S2, nti);
+      if (K2 > 0) b.var = r1_batch_variant(S2, K2);
+    }
+    if (b.var < 0) return R1_EUNSUPPORTED;
+    if (L.depth == 2) {
+      const size_t need = r1k::outer_lds_bytes(ts, L.level[0].n_t, L.level[1].n_dir, mat->model);
+      lds[b.var] = std::max(lds[b.var], need);
+    }
+    pent[size_t(k)] = r1plan::Entry{L.depth, L.level[0].n_dir, L.level[0].n_t,
+                                    L.depth == 2 ? L.level[1].n_dir : 0, L.depth == 2 ? L.level[1].n_t : 0, b.var};
+  }
+  const r1plan::Plan wk = r1plan::plan_work(pent, idx, NV);
+  if (int64_t(wk.items.size()) >= (int64_t(1) << 31) || int64_t(wk.order.size()) >= (int64_t(1) << 31) ||
+      wk.n_outer >= (int64_t(1) << 31))
+    return R1_EINVAL;
+  const size_t res_sz = r1_outer_res_bytes(dtype);
+  const size_t off_tab = 0;
+  const size_t off_dirs = off_tab + align_up(sizeof(BEntry) * ent.size());
+  const size_t off_idx = off_dirs + align_up(sizeof(double) * std::max<size_t>(dirs.size(), 1));
+  const size_t off_items = off_idx + align_up(sizeof(int32_t) * size_t(n));
+  const size_t off_order = off_items + align_up(sizeof(int4) * std::max<size_t>(wk.items.size(), 1));
+  const size_t off_pbase = off_order + align_up(sizeof(int32_t) * std::max<size_t>(wk.order.size(), 1));
+  const size_t off_cnt = off_pbase + align_up(sizeof(int64_t) * size_t(n));
+  const size_t off_w1f = off_cnt + align_up(sizeof(int) * size_t(2 * NV));
+  const size_t off_outer = off_w1f + align_up(ts * size_t(n));
+  const size_t total = off_outer + align_up(res_sz * size_t(std::max<int64_t>(wk.n_outer, 1)));
+  r1_batched_plan_s* pl = new (std::nothrow) r1_batched_plan_s();
+  if (!pl) return R1_ENOMEM;
+  if (hipMalloc(&pl->dev, total) != hipSuccess) {
+    pl->dev = nullptr;
+    free_plan(pl);
+    return R1_ENOMEM;
+  }
+  char* base = static_cast<char*>(pl->dev);
+  const double* ddirs = reinterpret_cast<const double*>(base + off_dirs);
+  for (int k = 0; k < n_table; ++k) {
+    BEntry& b = ent[size_t(k)];
+    for (int l = 0; l < b.depth; ++l) {
+      r1d::Level& lv = l == 0 ? b.lv0 : b.lv1;
+      lv.a = ddirs + dir_off[size_t(2 * k + l)];
+      lv.b = lv.a + size_t(lv.n_dir) * dim;
+    }
+  }
+  static_assert(sizeof(r1plan::Item) == sizeof(int4), "work item layout");
+  hipError_t e = hipMemcpy(base + off_tab, ent.data(), sizeof(BEntry) * ent.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !dirs.empty())
+    e = hipMemcpy(base + off_dirs, dirs.data(), sizeof(double) * dirs.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(base + off_idx, idx.data(), sizeof(int32_t) * size_t(n), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !wk.items.empty())
+    e = hipMemcpy(base + off_items, wk.items.data(), sizeof(int4) * wk.items.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !wk.order.empty())
+    e = hipMemcpy(base + off_order, wk.order.data(), sizeof(int32_t) * wk.order.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(base + off_pbase, wk.pbase.data(), sizeof(int64_t) * size_t(n), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_plan(pl);
+    return r1h::fail(h, e, "upload plan");
+  }
+  int n_cu = 0;
+  e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, h->device);
+  if (e != hipSuccess || n_cu < 1) {
+    free_plan(pl);
+    return e != hipSuccess ? r1h::fail(h, e, "device attribute") : R1_EUNSUPPORTED;
+  }
+  // launches: per variant k_bpoint, k_bouter, k_bfinal; counters [2c + kind]
+  for (int c = 0; c < NV; ++c) {
+    for (int kind = 0; kind < 3; ++kind) {
+      const int64_t first = wk.first[size_t(c) * 3 + kind], count = wk.count[size_t(c) * 3 + kind];
+      if (count == 0) continue;
+      r1_batched_plan_s::Launch L{};
+      BArgs& b = L.b;
+      b.base.n = n;
+      b.base.mat = r1d::Material{mat->dim, mat->model, mat->mu, mat->lambda, mat->D_inf, mat->D0};
+      b.table = reinterpret_cast<const BEntry*>(base + off_tab);
+      b.lam_idx = reinterpret_cast<const int32_t*>(base + off_idx);
+      b.pbase = reinterpret_cast<const int64_t*>(base + off_pbase);
+      b.outer = base + off_outer;
+      b.w1f = base + off_w1f;
+      b.n_items = int(count);
+      if (kind == kBFinal) {
+        b.order = reinterpret_cast<const int32_t*>(base + off_order) + first;
+        L.grid = int((count + 3) / 4);
+      } else {
+        b.order = reinterpret_cast<const int32_t*>(base + off_order);
+        b.items = reinterpret_cast<const int4*>(base + off_items) + first;
+        b.counter = reinterpret_cast<int*>(base + off_cnt) + 2 * c + kind;
+        L.lds = kind == kBOuter ? lds[c] : 0;
+        int per_cu = 0;
+        e = r1_occupancy_batched(dtype, dim, mat->model, c, kind, L.lds, &per_cu);
+        if (e != hipSuccess || per_cu < 1) {
+          free_plan(pl);
+          return e != hipSuccess ? r1h::fail(h, e, "occupancy") : R1_EUNSUPPORTED;
+        }
+        L.grid = int(std::min<int64_t>(int64_t(per_cu) * n_cu, count));
+      }
+      L.var = c;
+      L.kind = kind;
+      pl->launches.push_back(L);
+    }
+  }
+  pl->h = h;
+  pl->dtype = dtype;
+  pl->n = n;
+  pl->counters = reinterpret_cast<int*>(base + off_cnt);
+  pl->n_counters = 2 * NV;
+  *out = pl;
+  return R1_OK;
+}
+
+// Captures the plan's launch sequence for the given caller buffers into a graph
+// (the queue heads are cleared by a fill kernel at its start, no memset node).
+r1_status capture(r1_batched_plan_s* pl, const void* const ptrs[6], r1_batched_plan_s::Graph* g) {
+  r1_handle h = pl->h;
+  hipError_t e = hipSuccess;
+  if (!h->capture_stream) {
+    e = hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      h->capture_stream = nullptr;
+      return r1h::fail(h, e, "hipStreamCreate");
+    }
+  }
+  *g = r1_batched_plan_s::Graph{};
+  for (int k = 0; k < 6; ++k) g->ptrs[k] = ptrs[k];
+  e = hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t le = hipSuccess;
+    int zero_n = pl->n_counters;             // every queue head, once
+    for (size_t k = 0; k < pl->launches.size() && le == hipSuccess; ++k) {
+      const r1_batched_plan_s::Launch& L = pl->launches[k];
+      BArgs b = L.b;
+      b.base.F = ptrs[0];
+      b.base.beta_n = ptrs[1];
+      b.base.W = const_cast<void*>(ptrs[2]);
+      b.base.P = const_cast<void*>(ptrs[3]);
+      b.base.tree = static_cast<r1_laminate*>(const_cast<void*>(ptrs[4]));
+      b.base.flags = static_cast<int32_t*>(const_cast<void*>(ptrs[5]));
+      b.base.want_stress = ptrs[3] != nullptr;
+      le = r1_launch_batched(b, pl->dtype, b.base.mat.dim, b.base.mat.model, L.var, L.kind, L.grid, L.lds,
+                             pl->counters, zero_n, h->capture_stream);
+      zero_n = 0;
+    }
+    e = hipStreamEndCapture(h->capture_stream, &g->graph);
+    if (le != hipSuccess) e = le;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    free_graph(*g);
+    return r1h::fail(h, e, "graph capture");
+  }
+  return R1_OK;
+}
+
+// Replays the plan for the given buffers on st; up to 4 captured graphs (one per
+// set of buffers) are kept, the least recently used one is replaced.
+r1_status execute(r1_batched_plan_s* pl, const void* F, const void* beta_n, void* W, void* P, r1_laminate* tree,
+                  int32_t* flags, hipStream_t st) {
+  r1_handle h = pl->h;
+  if (!F || !beta_n || !W) return R1_EINVAL;
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return r1h::fail(h, e, "hipSetDevice");
+  const void* ptrs[6] = {F, beta_n, W, P, tree, flags};
+  r1_batched_plan_s::Graph* g = nullptr;
+  for (auto& x : pl->graphs)
+    if (std::equal(ptrs, ptrs + 6, x.ptrs)) g = &x;
+  if (!g) {
+    r1_batched_plan_s::Graph ng;
+    r1_status s = capture(pl, ptrs, &ng);
+    if (s) return s;
+    if (pl->graphs.size() >= 4) {
+      auto old = std::min_element(pl->graphs.begin(), pl->graphs.end(),
+                                  [](const r1_batched_plan_s::Graph& a, const r1_batched_plan_s::Graph& b) {
+                                    return a.used < b.used;
+                                  });
+      e = hipDeviceSynchronize();             // a replay of it may still run
+      if (e != hipSuccess) {
+        free_graph(ng);
+        return r1h::fail(h, e, "hipDeviceSynchronize");
+      }
+      free_graph(*old);
+      *old = ng;
+      g = &*old;
+    } else {
+      pl->graphs.push_back(ng);
+      g = &pl->graphs.back();
+    }
+  }
+  g->used = ++pl->clock;
+  if (h->timer.on) h->timer.begin("batched", st);
+  e = hipGraphLaunch(g->exec, st);
+  if (h->timer.on) h->timer.end(st);
+  if (e != hipSuccess) return r1h::fail(h, e, "hipGraphLaunch");
+  return R1_OK;
+}
+
+}  // namespace
+
+extern "C" r1_status r1_batched_plan_create(r1_handle h, const r1_material* mat, const r1_lamination* table,
+                                            int32_t n_table, int64_t n, const int32_t* lam_idx, r1_dtype dtype,
+                                            void* stream, r1_batched_plan* plan) {
+  if (!h || !plan) return R1_EINVAL;
+  *plan = nullptr;
+  r1_status s = check_table(mat, table, n_table);
+  if (s) return s;
+  if (dtype != R1_F32 && dtype != R1_F64) return R1_EINVAL;
+  if (n < 1 || n >= (int64_t(1) << 31) || !lam_idx) return R1_EINVAL;
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return r1h::fail(h, e, "hipSetDevice");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<int32_t> idx;
+  s = read_indices(h, lam_idx, n, n_table, st, &idx);
+  if (s) return s;
+  r1_batched_plan_s* pl = nullptr;
+  s = make_plan(h, mat, table, n_table, idx, dtype, st, &pl);
+  if (s) return s;
+  h->user_plans.insert(pl);
+  *plan = pl;
+  return R1_OK;
+}
+
+extern "C" r1_status r1_batched_plan_execute(r1_batched_plan plan, const void* F, const void* beta_n, void* W,
+                                             void* P, r1_laminate* tree, int32_t* flags, void* stream) {
+  if (!plan) return R1_EINVAL;
+  return execute(plan, F, beta_n, W, P, tree, flags, static_cast<hipStream_t>(stream));
+}
+
+extern "C" r1_status r1_batched_plan_destroy(r1_batched_plan plan) {
+  if (!plan) return R1_EINVAL;
+  r1_handle h = plan->h;
+  if (!h->user_plans.erase(plan)) return R1_EINVAL;
+  (void)hipSetDevice(h->device);
+  (void)hipDeviceSynchronize();           // replays of it may still run
+  free_plan(plan);
+  return R1_OK;
+}
+
+extern "C" r1_status r1_envelope_batched(r1_handle h, const r1_material* mat,
+                                         const r1_lamination* table, int32_t n_table, int64_t n,
+                                         const int32_t* lam_idx, r1_dtype dtype, const void* F,
+                                         const void* beta_n, void* W, void* P, r1_laminate* tree,
+                                         int32_t* flags, void* stream) {
+  if (!h) return R1_EINVAL;
+  r1_status s = check_table(mat, table, n_table);
+  if (s) return s;
   if (dtype != R1_F32 && dtype != R1_F64) return R1_EINVAL;
   if (n < 0 || n >= (int64_t(1) << 31)) return R1_EINVAL;
   if (n == 0) return R1_OK;
@@ -245,14 +570,15 @@ extern "C" r1_status r1_envelope_batched(r1_handle h, const r1_material* mat,
   if (e != hipSuccess) return r1h::fail(h, e, "hipSetDevice");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int dim = mat->dim;
+  std::vector<int32_t> idx;
+  s = read_indices(h, lam_idx, n, n_table, st, &idx);
+  if (s) return s;
 
-  // plan key: everything the captured launch bakes in
+  // plan key: the contents that decide the plan (material, sizes, table, indices)
   uint64_t key = 1469598103934665603ull;
   key = mixv(key, *mat);
   key = mixv(key, n);
   key = mixv(key, dtype);
-  const void* ptrs[8] = {F, beta_n, W, P, tree, flags, lam_idx, nullptr};
-  key = mix(key, ptrs, sizeof(ptrs));
   for (int k = 0; k < n_table; ++k) {
     const r1_lamination& L = table[k];
     key = mixv(key, L.depth);
@@ -265,201 +591,13 @@ extern "C" r1_status r1_envelope_batched(r1_handle h, const r1_material* mat,
       key = mix(key, lv.b, sizeof(double) * size_t(lv.n_dir) * dim);
     }
   }
+  key = mix(key, idx.data(), sizeof(int32_t) * idx.size());
   auto found = h->plans.find(key);
-  BatchedPlan* pl = found == h->plans.end() ? nullptr : found->second;
-
+  r1_batched_plan_s* pl = found == h->plans.end() ? nullptr : found->second;
   if (!pl) {
-    // ---- plan: read the table indices, order the work, upload
-    std::vector<int32_t> idx(static_cast<size_t>(n));
-    e = hipMemcpyAsync(idx.data(), lam_idx, sizeof(int32_t) * size_t(n), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return r1h::fail(h, e, "read lam_idx");
-    for (int64_t p = 0; p < n; ++p)
-      if (idx[p] < 0 || idx[p] >= n_table) return R1_EINVAL;
-    std::vector<BEntry> ent(static_cast<size_t>(n_table));
-    constexpr int NV = R1_N_BATCH_VARIANTS;
-    size_t lds[NV] = {};
-    const size_t ts = dtype == R1_F32 ? 4 : 8;
-    for (int k = 0; k < n_table; ++k) {
-      const r1_lamination& L = table[k];
-      BEntry& b = ent[k];
-      std::memset(&b, 0, sizeof(b));
-      b.depth = L.depth;
-      s = r1h::device_level(h, L.level[0], dim, &b.lv0);
-      if (!s && L.depth == 2) s = r1h::device_level(h, L.level[1], dim, &b.lv1);
-      if (s) return s;
-      const int nti = L.level[L.depth - 1].n_t;
-      const int role = L.depth == 2 ? r1h::kRoleInner : r1h::kRoleLevel;
-      if (!h->seg_override.count(nti) && !h->seg_tuned.count(r1h::tune_key(nti, dtype, dim, role))) {
-        s = r1h::autotune(h, mat, nti, dtype, dim, role, st, nullptr);
-        if (s) return s;
-      }
-      int S = r1h::segment_width(h, nti, dtype, dim, role);
-      int K = r1h::batch_samples_per_lane(S, nti);
-      b.var = K > 0 ? r1_batch_variant(S, K) : -1;
-      for (int S2 = 16; b.var < 0 && S2 <= 64; S2 *= 2) {   // width outside the variant set
-        int K2 = r1h::batch_samples_per_lane(S2, nti);
-        if (K2 > 0) b.var = r1_batch_variant(S2, K2);
-      }
-      if (b.var < 0) return R1_EUNSUPPORTED;
-      if (L.depth == 2) {
-        size_t need = r1k::outer_lds_bytes(ts, L.level[0].n_t, L.level[1].n_dir, mat->model);
-        lds[b.var] = std::max(lds[b.var], need);
-      }
-    }
-    // work lists per layout variant, each ordered largest first: point items
-    // (groups of up to 4 depth-1 points; groups of up to 4 depth-2 points for
-    // the centre values), outer lines of depth-2 points, depth-2 points to finalize
-    std::vector<int64_t> d2[NV], d1[NV];
-    for (int64_t p = 0; p < n; ++p) {
-      const int c = ent[idx[p]].var;
-      (table[idx[p]].depth == 2 ? d2[c] : d1[c]).push_back(p);
-    }
-    auto cost = [&](int64_t p) {
-      const r1_lamination& L = table[idx[p]];
-      if (L.depth == 1) return double(L.level[0].n_dir) * double(L.level[0].n_t - 1);
-      return double(L.level[0].n_t - 1) *
-             (double(L.level[1].n_dir) * double(L.level[1].n_t - 1) + 1.0);
-    };
-    std::vector<int64_t> pbase(static_cast<size_t>(n), 0);
-    std::vector<int4> items;
-    std::vector<int32_t> order;
-    int64_t n_outer = 0;
-    // per variant and kind: first item (or order entry for kBFinal) and count
-    int64_t first[NV][3] = {}, count[NV][3] = {};
-    for (int c = 0; c < NV; ++c) {
-      std::stable_sort(d2[c].begin(), d2[c].end(), [&](int64_t x, int64_t y) { return cost(x) > cost(y); });
-      std::stable_sort(d1[c].begin(), d1[c].end(), [&](int64_t x, int64_t y) { return cost(x) > cost(y); });
-      first[c][kBPoint] = int64_t(items.size());
-      for (int kind = 0; kind < 2; ++kind) {
-        const std::vector<int64_t>& pts = kind == 0 ? d1[c] : d2[c];
-        const int64_t o0 = int64_t(order.size());
-        order.insert(order.end(), pts.begin(), pts.end());
-        for (int64_t g = 0; 4 * g < int64_t(pts.size()); ++g) {
-          int cnt = int(std::min<int64_t>(4, int64_t(pts.size()) - 4 * g));
-          items.push_back(int4{kind == 0 ? 0 : 2, int(o0 + 4 * g), cnt, 0});
-        }
-      }
-      count[c][kBPoint] = int64_t(items.size()) - first[c][kBPoint];
-      first[c][kBOuter] = int64_t(items.size());
-      for (int64_t p : d2[c]) {
-        pbase[p] = n_outer;
-        n_outer += table[idx[p]].level[0].n_dir;
-        for (int mo = 0; mo < table[idx[p]].level[0].n_dir; ++mo) items.push_back(int4{1, int(p), mo, 0});
-      }
-      count[c][kBOuter] = int64_t(items.size()) - first[c][kBOuter];
-      first[c][kBFinal] = int64_t(order.size());
-      order.insert(order.end(), d2[c].begin(), d2[c].end());
-      count[c][kBFinal] = int64_t(d2[c].size());
-    }
-    const int64_t n_items = int64_t(items.size());
-    if (n_items >= (int64_t(1) << 31) || int64_t(order.size()) >= (int64_t(1) << 31)) return R1_EINVAL;
-    const size_t res_sz = r1_outer_res_bytes(dtype);
-    size_t off_tab = 0;
-    size_t off_items = off_tab + align_up(sizeof(BEntry) * ent.size());
-    size_t off_order = off_items + align_up(sizeof(int4) * std::max<size_t>(items.size(), 1));
-    size_t off_pbase = off_order + align_up(sizeof(int32_t) * std::max<size_t>(order.size(), 1));
-    size_t off_cnt = off_pbase + align_up(sizeof(int64_t) * size_t(n));
-    size_t off_w1f = off_cnt + align_up(sizeof(int) * size_t(2 * NV));
-    size_t off_outer = off_w1f + align_up(ts * size_t(n));
-    size_t total = off_outer + align_up(res_sz * std::max<int64_t>(n_outer, 1));
-    pl = new BatchedPlan();
-    if (hipMalloc(&pl->dev, total) != hipSuccess) {
-      free_plan(pl);
-      return R1_ENOMEM;
-    }
-    char* base = static_cast<char*>(pl->dev);
-    e = hipMemcpy(base + off_tab, ent.data(), sizeof(BEntry) * ent.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess && !items.empty())
-      e = hipMemcpy(base + off_items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess && !order.empty())
-      e = hipMemcpy(base + off_order, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-      e = hipMemcpy(base + off_pbase, pbase.data(), sizeof(int64_t) * size_t(n), hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-      free_plan(pl);
-      return r1h::fail(h, e, "upload plan");
-    }
-    int n_cu = 0;
-    e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, h->device);
-    if (e != hipSuccess || n_cu < 1) {
-      free_plan(pl);
-      return e != hipSuccess ? r1h::fail(h, e, "device attribute") : R1_EUNSUPPORTED;
-    }
-    // launches: per variant k_bpoint, k_bouter, k_bfinal; counters [2c + kind]
-    struct Launch { BArgs b; int var, kind, grid; size_t lds; };
-    std::vector<Launch> launches;
-    for (int c = 0; c < NV; ++c) {
-      for (int kind = 0; kind < 3; ++kind) {
-        if (count[c][kind] == 0) continue;
-        Launch L{};
-        BArgs& b = L.b;
-        b.base.n = n;
-        b.base.F = F;
-        b.base.beta_n = beta_n;
-        b.base.W = W;
-        b.base.P = P;
-        b.base.tree = tree;
-        b.base.flags = flags;
-        b.base.mat = r1d::Material{mat->dim, mat->model, mat->mu, mat->lambda, mat->D_inf, mat->D0};
-        b.base.want_stress = P != nullptr;
-        b.table = reinterpret_cast<const BEntry*>(base + off_tab);
-        b.lam_idx = lam_idx;
-        b.pbase = reinterpret_cast<const int64_t*>(base + off_pbase);
-        b.outer = base + off_outer;
-        b.w1f = base + off_w1f;
-        b.n_items = int(count[c][kind]);
-        if (kind == kBFinal) {
-          b.order = reinterpret_cast<const int32_t*>(base + off_order) + first[c][kind];
-          L.grid = int((count[c][kind] + 3) / 4);
-        } else {
-          b.order = reinterpret_cast<const int32_t*>(base + off_order);
-          b.items = reinterpret_cast<const int4*>(base + off_items) + first[c][kind];
-          b.counter = reinterpret_cast<int*>(base + off_cnt) + 2 * c + kind;
-          L.lds = kind == kBOuter ? lds[c] : 0;
-          int per_cu = 0;
-          e = r1_occupancy_batched(dtype, dim, mat->model, c, kind, L.lds, &per_cu);
-          if (e != hipSuccess || per_cu < 1) {
-            free_plan(pl);
-            return e != hipSuccess ? r1h::fail(h, e, "occupancy") : R1_EUNSUPPORTED;
-          }
-          L.grid = int(std::min<int64_t>(int64_t(per_cu) * n_cu, count[c][kind]));
-        }
-        L.var = c;
-        L.kind = kind;
-        launches.push_back(L);
-      }
-    }
-    // capture the launch sequence once; replays run it unchanged
-    if (!h->capture_stream) {
-      e = hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking);
-      if (e != hipSuccess) {
-        h->capture_stream = nullptr;
-        free_plan(pl);
-        return r1h::fail(h, e, "hipStreamCreate");
-      }
-    }
-    e = hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-      hipError_t le = hipSuccess;
-      int zero_n = 2 * NV;                     // every queue head, once, by a fill kernel
-      for (size_t k = 0; k < launches.size() && le == hipSuccess; ++k) {
-        const Launch& L = launches[k];
-        le = r1_launch_batched(L.b, dtype, dim, L.b.base.mat.model, L.var, L.kind, L.grid, L.lds, reinterpret_cast<int*>(base + off_cnt),
-                               zero_n, h->capture_stream);
-        zero_n = 0;
-      }
-      e = hipStreamEndCapture(h->capture_stream, &pl->graph);
-      if (le != hipSuccess) e = le;
-    }
-    if (e == hipSuccess) e = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-      free_plan(pl);
-      return r1h::fail(h, e, "graph capture");
-    }
+    s = make_plan(h, mat, table, n_table, idx, dtype, st, &pl);
+    if (s) return s;
     pl->key = key;
-    pl->n_items = n_items;
-    pl->n_outer = n_outer;
     pl->serial = ++h->plan_serial;
     if (h->plans.size() >= 8) {          // evict the oldest plan
       auto old = h->plans.begin();
@@ -471,9 +609,5 @@ extern "C" r1_status r1_envelope_batched(r1_handle h, const r1_material* mat,
     }
     h->plans[key] = pl;
   }
-  if (h->timer.on) h->timer.begin("batched", st);
-  e = hipGraphLaunch(pl->exec, st);
-  if (h->timer.on) h->timer.end(st);
-  if (e != hipSuccess) return r1h::fail(h, e, "hipGraphLaunch");
-  return R1_OK;
+  return execute(pl, F, beta_n, W, P, tree, flags, st);
 }

@@ -28,7 +28,7 @@ struct BEntry {          // one lamination table entry on the device
 struct BArgs {
   KArgs base;              // n, F, beta_n, W, P, tree, flags, material, want_stress
   const BEntry* table;
-  const int32_t* lam_idx;  // caller's per-point table index
+  const int32_t* lam_idx;  // per-point table index: the plan's own copy
   const int4* items;       // this launch's work list (persistent kernels)
   int n_items;
   int* counter;            // this launch's queue head, zeroed before the launches

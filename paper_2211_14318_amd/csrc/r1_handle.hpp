@@ -4,13 +4,14 @@
 
 #include <cstdint>
 #include <map>
+#include <set>
 #include <string>
 
 #include "r1.h"
 #include "r1_device.hpp"
 #include "r1_launch.hpp"
 
-struct BatchedPlan;
+struct r1_batched_plan_s;
 
 struct r1_handle_s {
   int device = 0;
@@ -20,7 +21,8 @@ struct r1_handle_s {
   size_t scratch_bytes = 0;
   std::map<int, int> seg_override;         // n_t -> lanes per line (user setting)
   std::map<int64_t, int> seg_tuned;        // (n_t, dtype, dim, role) -> lanes per line (autotuner)
-  std::map<uint64_t, BatchedPlan*> plans;  // batched launches: plan + captured graph
+  std::map<uint64_t, r1_batched_plan_s*> plans;  // r1_envelope_batched: plans by content
+  std::set<r1_batched_plan_s*> user_plans;        // plans created by r1_batched_plan_create
   KTimer timer;                            // optional per-kernel event timing
   hipStream_t capture_stream = nullptr;    // private stream for graph capture
   uint64_t plan_serial = 0;
@@ -31,7 +33,8 @@ r1_status fail(r1_handle h, hipError_t e, const char* what);
 r1_status check_material(const r1_material* m);
 r1_status check_level(const r1_level& lv);
 r1_status check_lamination(const r1_lamination* lam);
-r1_status device_level(r1_handle h, const r1_level& lv, int dim, r1d::Level* out);
+void level_meta(const r1_level& lv, int dim, r1d::Level* out);
+r1_status device_levels(r1_handle h, const r1_level* const* lv, int count, int dim, r1d::Level* out);
 r1_status scratch(r1_handle h, size_t bytes, void** p);
 int samples_per_lane(int S, int n_t);
 int batch_samples_per_lane(int S, int n_t);

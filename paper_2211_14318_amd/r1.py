@@ -121,6 +121,10 @@ def _load():
     L.r1_grid_interpolate.argtypes = [vp, ctypes.POINTER(Grid), i32, vp, i64, vp, vp, vp]
     L.r1_envelope_batched.argtypes = [vp, ctypes.POINTER(Material), ctypes.POINTER(Lamination), i32,
                                       i64, vp, i32, vp, vp, vp, vp, vp, vp, vp]
+    L.r1_batched_plan_create.argtypes = [vp, ctypes.POINTER(Material), ctypes.POINTER(Lamination), i32,
+                                         i64, vp, i32, vp, ctypes.POINTER(vp)]
+    L.r1_batched_plan_execute.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    L.r1_batched_plan_destroy.argtypes = [vp]
     L.r1_set_segment_width.argtypes = [vp, i32, i32]
     L.r1_get_segment_width.argtypes = [vp, i32, i32, i32, ctypes.POINTER(i32)]
     L.r1_autotune.argtypes = [vp, ctypes.POINTER(Material), i32, i32, vp, ctypes.POINTER(i32)]
@@ -154,6 +158,7 @@ def _load():
         getattr(L, name).restype = i32
     for name in ("r1_autotune", "r1_autotune_inner", "r1_get_inner_segment_width", "r1_timing_enable", "r1_timing_reset", "r1_timing_query", "r1_create", "r1_destroy", "r1_envelope", "r1_envelope_stress",
                  "r1_envelope_tangent", "r1_laminate_tangent", "r1_envelope_batched", "r1_grid_r11",
+                 "r1_batched_plan_create", "r1_batched_plan_execute", "r1_batched_plan_destroy",
                  "r1_grid_energy", "r1_grid_laminate", "r1_grid_interpolate", "r1_set_segment_width", "r1_get_segment_width"):
         getattr(L, name).restype = i32
     return L
@@ -368,6 +373,9 @@ class Handle:
                                              _ptr(out), self._stream(stream)), "r1_grid_interpolate")
         return out
 
+    def batched_plan(self, mat, table_specs, lam_idx, dtype, stream=None):
+        return BatchedPlan(self, mat, table_specs, lam_idx, dtype, stream)
+
     def envelope_batched(self, mat, table_specs, lam_idx, F, beta_n, stress=False, tree=False,
                          flags=True, stream=None):
         torch = self.torch
@@ -385,6 +393,53 @@ class Handle:
                                              _ptr(P), _ptr(T), _ptr(fl), self._stream(stream)),
                     "r1_envelope_batched")
         return dict(W=W, P=P, tree=T, flags=fl)
+
+
+class BatchedPlan:
+    """A plan of the uneven batch (r1_batched_plan_*): the table, the table indices
+    (read once at creation) and the ordered work lists; execute() replays it."""
+
+    def __init__(self, handle, mat, table_specs, lam_idx, dtype, stream=None):
+        self.hd = handle
+        self.mat = mat
+        self.dim = mat.dim
+        self.n = int(lam_idx.numel())
+        self.dtype = dtype
+        self._specs = list(table_specs)
+        arr = (Lamination * len(self._specs))(*[s.c for s in self._specs])
+        p = ctypes.c_void_p()
+        code = R1_F32 if dtype == handle.torch.float32 else R1_F64
+        handle._check(_lib.r1_batched_plan_create(handle.h, ctypes.byref(mat), arr, len(self._specs), self.n,
+                                                  _ptr(lam_idx), code, handle._stream(stream), ctypes.byref(p)),
+                      "r1_batched_plan_create")
+        self.p = p
+
+    def execute(self, F, beta_n, W, P=None, tree=None, flags=None, stream=None):
+        """Writes into the given device tensors (graphs are kept per set of buffers)."""
+        assert F.shape == (self.dim * self.dim, self.n) and F.dtype == self.dtype and F.is_contiguous()
+        assert beta_n.shape == (self.n,) and W.shape == (self.n,)
+        self.hd._check(_lib.r1_batched_plan_execute(self.p, _ptr(F), _ptr(beta_n), _ptr(W), _ptr(P), _ptr(tree),
+                                                    _ptr(flags), self.hd._stream(stream)),
+                       "r1_batched_plan_execute")
+
+    def outputs(self, stress=False, tree=False, flags=True):
+        torch = self.hd.torch
+        d = self.dim
+        return dict(W=torch.empty(self.n, dtype=self.dtype, device="cuda"),
+                    P=torch.empty((d * d, self.n), dtype=self.dtype, device="cuda") if stress else None,
+                    tree=torch.empty((self.n, TREE_NODES, 4), dtype=torch.int32, device="cuda") if tree else None,
+                    flags=torch.empty(self.n, dtype=torch.int32, device="cuda") if flags else None)
+
+    def close(self):
+        if getattr(self, "p", None) and getattr(self.hd, "h", None):
+            _lib.r1_batched_plan_destroy(self.p)
+        self.p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def tree_view(T):

@@ -153,3 +153,105 @@ def test_autotuner_returns_admissible_width(lib):
         assert inner in (8, 16, 32, 64)
         assert h.inner_segment_width(nt, r1.R1_F32, 2) == inner
         assert h.segment_width(nt, r1.R1_F32, 2) == lanes
+
+
+def _eager(lib, table, Ft, bt, it):
+    """One plain launch per table entry on its points (torch tensors)."""
+    r1, h, torch = lib
+    mat = r1.material()
+    n = Ft.shape[1]
+    W = torch.empty(n, dtype=Ft.dtype, device="cuda")
+    P = torch.empty((4, n), dtype=Ft.dtype, device="cuda")
+    T = torch.empty((n, 3, 4), dtype=torch.int32, device="cuda")
+    for k, lv in enumerate(table):
+        sel = torch.nonzero(it == k).flatten()
+        if sel.numel() == 0:
+            continue
+        out = h.envelope(mat, r1.LaminationSpec(lv), Ft[:, sel].contiguous(), bt[sel].contiguous(),
+                         stress=True, tree=True)
+        W[sel], P[:, sel], T[sel] = out["W"], out["P"], out["tree"]
+    torch.cuda.synchronize()
+    return W, P, T
+
+
+def test_batched_follows_new_indices_in_the_same_buffer(lib):
+    """r1_envelope_batched plans by the contents of lam_idx: new indices written
+    into the same device buffer give the results of the new indices."""
+    r1, h, torch = lib
+    table = small_table()
+    F, bn, idx = make_batch(64, 703, table)
+    Ft = torch.tensor(F, dtype=torch.float32, device="cuda").contiguous()
+    bt = torch.tensor(bn, dtype=torch.float32, device="cuda").contiguous()
+    it = torch.tensor(idx, dtype=torch.int32, device="cuda")
+    mat = r1.material()
+    specs = [r1.LaminationSpec(t) for t in table]
+    rng = np.random.default_rng(704)
+    for rep in range(3):
+        out = h.envelope_batched(mat, specs, it, Ft, bt, stress=True, tree=True)
+        torch.cuda.synchronize()
+        W, P, T = _eager(lib, table, Ft, bt, it)
+        assert torch.equal(out["W"], W) and torch.equal(out["P"], P) and torch.equal(out["tree"], T), rep
+        # depth-1 points become depth-2 points and back, in place
+        it.copy_(torch.tensor(rng.integers(0, len(table), size=64).astype(np.int32), device="cuda"))
+
+
+def test_plan_keeps_its_own_indices_and_directions(lib):
+    """A plan built from lam_idx is not affected by later writes to lam_idx, nor by
+    the handle's direction cache evicting (600 plain calls with distinct
+    directions pass its 512-entry limit) between replays."""
+    r1, h, torch = lib
+    table = small_table()
+    F, bn, idx = make_batch(56, 705, table)
+    Ft = torch.tensor(F, dtype=torch.float64, device="cuda").contiguous()
+    bt = torch.tensor(bn, dtype=torch.float64, device="cuda").contiguous()
+    it = torch.tensor(idx, dtype=torch.int32, device="cuda")
+    mat = r1.material()
+    plan = h.batched_plan(mat, [r1.LaminationSpec(t) for t in table], it, torch.float64)
+    o = plan.outputs(stress=True, tree=True)
+    plan.execute(Ft, bt, o["W"], o["P"], o["tree"], o["flags"])
+    torch.cuda.synchronize()
+    W0, P0, T0 = o["W"].clone(), o["P"].clone(), o["tree"].clone()
+    We, Pe, Te = _eager(lib, table, Ft, bt, it)
+    assert torch.equal(W0, We) and torch.equal(P0, Pe) and torch.equal(T0, Te)
+    it.fill_(0)                                  # the plan keeps its own copy
+    Fs = torch.tensor(WL.small_random(2, 4, (1, 1), 3, seed_tag=706)["F"], dtype=torch.float64, device="cuda")
+    bs = torch.zeros(4, dtype=torch.float64, device="cuda")
+    for k in range(600):                         # distinct directions: new cache entries
+        th = 0.001 * (k + 1)
+        a = np.array([[np.cos(th), np.sin(th)]])
+        lv = [WL.level(a, a.copy(), 9, 0.5)]
+        if k % 7 == 0:                           # depth 2 while the cache is full
+            lv.append(WL.level(a[:, ::-1].copy(), a.copy(), 9, 0.5))
+        h.envelope(mat, r1.LaminationSpec(lv), Fs, bs, stress=False)
+    torch.cuda.synchronize()
+    for rep in range(2):
+        o["W"].fill_(-7.0)
+        plan.execute(Ft, bt, o["W"], o["P"], o["tree"], o["flags"])
+        torch.cuda.synchronize()
+        assert torch.equal(o["W"], W0) and torch.equal(o["P"], P0) and torch.equal(o["tree"], T0), rep
+    # other output buffers: a second captured graph of the same plan
+    o2 = plan.outputs(stress=False, tree=False, flags=False)
+    plan.execute(Ft, bt, o2["W"])
+    torch.cuda.synchronize()
+    assert torch.equal(o2["W"], W0)
+    plan.close()
+
+
+def test_depth2_after_cache_eviction_matches_oracle(lib):
+    """A depth-2 call whose two levels are both new while the direction cache is
+    full: both levels are resolved before anything is evicted."""
+    r1, h, torch = lib
+    mat = r1.material()
+    Fs = torch.tensor(WL.small_random(2, 4, (1, 1), 3, seed_tag=707)["F"], dtype=torch.float64, device="cuda")
+    bs = torch.zeros(4, dtype=torch.float64, device="cuda")
+    for k in range(520):
+        th = 0.002 * (k + 1)
+        a = np.array([[np.cos(th), np.sin(th)]])
+        h.envelope(mat, r1.LaminationSpec([WL.level(a, a.copy(), 9, 0.5)]), Fs, bs, stress=False)
+    cfg = WL.small_random(2, 24, (2, 2), 17, tau=1.2, depth=2, inner=(2, 2, 17), seed_tag=708)
+    out = h.envelope(mat, r1.LaminationSpec(cfg["levels"]), torch.tensor(cfg["F"], device="cuda"),
+                     torch.tensor(cfg["beta_n"], device="cuda"), stress=True)
+    torch.cuda.synchronize()
+    om = PA.orc_material(WL.MATERIAL, 2)
+    W, _, _ = O.envelope_batch(om, PA.orc_spec(cfg["levels"]), cfg["F"], cfg["beta_n"], want_stress=True)
+    assert PA.energy_errors(out["W"].cpu().numpy(), W, "f64").max() <= PA.RTOL["f64"]
