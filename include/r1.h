@@ -146,6 +146,24 @@ r1_status r1_envelope_stress(r1_handle handle, const r1_material* material,
                              const void* F, const void* beta_n, void* W, void* P,
                              r1_laminate* tree, int32_t* flags, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): r1_envelope_stress (depth 1
+ * or 2) with nothing allocated.  The levels' directions, and at depth 2 W^1 per
+ * point and one hull result per (point, outer direction), are kept in a fixed
+ * per-device workspace of 64 MiB that the library holds until the process ends
+ * (looked up by r1_create); the caller passes inputs and outputs as for
+ * r1_envelope_stress.  Needs 2*n_dir*dim*8 bytes per level (each rounded up
+ * to 256) plus, at depth 2, n*sizeof(dtype) (rounded up to 256) + 16 (FP32) or
+ * 24 (FP64) bytes per (point, outer direction); a larger request fails with
+ * R1_EINVAL and the sizes in r1_last_error, nothing launched.  Every call on one
+ * device shares that device's workspace: calls that overlap in time on one
+ * device (different streams, threads or handles) race; calls on one stream are
+ * ordered.  The directions are copied from host memory on `stream`. */
+r1_status r1_envelope_stress_noalloc(r1_handle handle, const r1_material* material,
+                                     const r1_lamination* lamination, int64_t n, r1_dtype dtype,
+                                     const void* F, const void* beta_n, void* W, void* P,
+                                     r1_laminate* tree, int32_t* flags, void* stream);
+
 /* As r1_envelope_stress, plus the tangent moduli of the laminate (Algorithm 3,
  * third output; the consistent tangent of the relaxed stress used in Section 5):
  * A = dP^k/dF as the tree-weighted sum of the leaf moduli d^2W/dF dF of eq. 2.9,

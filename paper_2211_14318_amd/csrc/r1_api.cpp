@@ -208,6 +208,11 @@ r1_status r1_create(r1_handle* handle, int32_t device) {
   r1_handle h = new (std::nothrow) r1_handle_s();
   if (!h) return R1_ENOMEM;
   h->device = device;
+  // the fixed workspace of the allocation-free entry point, once per device
+  if (r1h::noalloc_scratch(device, &h->noalloc) != R1_OK) {
+    h->noalloc = nullptr;
+    h->err = "hipGetSymbolAddress(fixed workspace) failed";
+  }
   *handle = h;
   return R1_OK;
 }

@@ -26,6 +26,7 @@ struct r1_handle_s {
   KTimer timer;                            // optional per-kernel event timing
   hipStream_t capture_stream = nullptr;    // private stream for graph capture
   uint64_t plan_serial = 0;
+  void* noalloc = nullptr;                 // device address of the fixed workspace (r1_envelope_stress_noalloc)
 };
 
 namespace r1h {
@@ -47,6 +48,10 @@ inline int64_t tune_key(int n_t, int dtype, int dim, int role) {
   return (int64_t(n_t) << 8) | (role << 6) | (dtype << 4) | dim;
 }
 void release_batched(r1_handle h);
+// Device address of the fixed workspace on `device` (current), looked up once per
+// device; its size in bytes.
+r1_status noalloc_scratch(int device, void** ptr);
+size_t noalloc_capacity();
 r1_status autotune(r1_handle h, const r1_material* mat, int n_t, int dtype, int dim, int role, hipStream_t st,
                    int* lanes);
 }  // namespace r1h

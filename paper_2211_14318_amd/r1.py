@@ -109,6 +109,8 @@ def _load():
                               vp, vp, vp, vp, vp]
     L.r1_envelope_stress.argtypes = [vp, ctypes.POINTER(Material), ctypes.POINTER(Lamination), i64,
                                      i32, vp, vp, vp, vp, vp, vp, vp]
+    L.r1_envelope_stress_noalloc.argtypes = [vp, ctypes.POINTER(Material), ctypes.POINTER(Lamination), i64,
+                                             i32, vp, vp, vp, vp, vp, vp, vp]
     L.r1_envelope_tangent.argtypes = [vp, ctypes.POINTER(Material), ctypes.POINTER(Lamination), i64,
                                       i32, vp, vp, vp, vp, vp, vp, vp, vp]
     L.r1_laminate_tangent.argtypes = [vp, ctypes.POINTER(Material), ctypes.POINTER(Lamination), i64,
@@ -158,6 +160,7 @@ def _load():
         getattr(L, name).restype = i32
     for name in ("r1_autotune", "r1_autotune_inner", "r1_get_inner_segment_width", "r1_timing_enable", "r1_timing_reset", "r1_timing_query", "r1_create", "r1_destroy", "r1_envelope", "r1_envelope_stress",
                  "r1_envelope_tangent", "r1_laminate_tangent", "r1_envelope_batched", "r1_grid_r11",
+                 "r1_envelope_stress_noalloc",
                  "r1_batched_plan_create", "r1_batched_plan_execute", "r1_batched_plan_destroy",
                  "r1_grid_energy", "r1_grid_laminate", "r1_grid_interpolate", "r1_set_segment_width", "r1_get_segment_width"):
         getattr(L, name).restype = i32
@@ -333,6 +336,15 @@ class Handle:
                                             _ptr(P), _ptr(tree), _ptr(flags),
                                             self._stream(stream)),
                     "r1_envelope_stress")
+
+    def envelope_noalloc_into(self, mat, spec, F, beta_n, W, P=None, tree=None, flags=None, stream=None):
+        """r1_envelope_stress_noalloc into caller-provided tensors (the library
+        allocates nothing; its fixed per-device workspace is used)."""
+        self._check(_lib.r1_envelope_stress_noalloc(self.h, ctypes.byref(mat), ctypes.byref(spec.c),
+                                                    F.shape[1], self._dtype_code(F), _ptr(F), _ptr(beta_n),
+                                                    _ptr(W), _ptr(P), _ptr(tree), _ptr(flags),
+                                                    self._stream(stream)),
+                    "r1_envelope_stress_noalloc")
 
     def grid_energy(self, mat, g, beta_n, dtype, stress=False, tangent=False, stream=None):
         """W^0 at every node of mesh g: (nodes,) device tensor of torch dtype; with
