@@ -84,8 +84,15 @@ def check_tie_flags(trees_orc, depth, W_orc, flags_gpu, kind):
     return n_flag, n_mid
 
 
-def check_stress(mat, spec, depth, F_soa, beta_n, W_orc, P_orc, trees_orc, P_gpu, tree_gpu, kind):
-    """Returns (n_checked_exact, n_ties).  tree_gpu: (n, 3, 4) int32 array."""
+def check_stress(mat, spec, depth, F_soa, beta_n, W_orc, P_orc, trees_orc, P_gpu, tree_gpu, kind, stats=None):
+    """Returns (n_checked_exact, n_ties).  tree_gpu: (n, 3, 4) int32 array.  stats
+    (nullable dict) receives under "tie_w" the largest relative energy difference
+    between the GPU's tree (evaluated by the oracle) and the oracle's W at ties.
+
+    At fine FP32 grids most points count as ties: the samples beside a bridge's
+    tangent point lie within a few 1e-5 of the bridge line, so either may be the
+    laminate's endpoint.  There the GPU's tree must be a laminate whose exact energy
+    is within 10x the energy bar of the minimum, and the GPU's stress that tree's."""
     d = mat.dim
     n = F_soa.shape[1]
     n_exact = n_ties = 0
@@ -103,7 +110,10 @@ def check_stress(mat, spec, depth, F_soa, beta_n, W_orc, P_orc, trees_orc, P_gpu
             n_ties += 1
             F = F_soa[:, p].reshape(d, d)
             We, Pe = O.eval_tree(mat, spec, F, beta_n[p], g_nodes)
-            assert abs(We - W_orc[p]) <= RTOL[kind] * 10 * max(abs(W_orc[p]), W_FLOOR[kind]), (p, We, W_orc[p])
+            dev = abs(We - W_orc[p]) / max(abs(W_orc[p]), W_FLOOR[kind])
+            if stats is not None:
+                stats["tie_w"] = max(stats.get("tie_w", 0.0), dev)
+            assert dev <= RTOL[kind] * 10, (p, We, W_orc[p])
             assert np.max(np.abs(Pe.ravel() - P_gpu[:, p])) <= PTOL[kind] * scale, (p, Pe, P_gpu[:, p])
         else:
             n_exact += 1
@@ -134,3 +144,39 @@ def oracle_pool_map(mat_dict, dim, levels, F_soa, beta_n, workers):
     P = np.concatenate([r[1] for r in res], axis=1)
     trees = [r[2][0] for r in res]
     return W, P, trees
+
+
+def load_oracle_golden(name):
+    """Stored oracle values written by tests/golden/make_oracle_golden.py (which calls
+    only the oracle): the header dict and the points, each with p, F, beta_n, W, P,
+    tree (per node [dir, i_minus, i_plus]), dir_gap and bridge_gap."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    with open(path) as f:
+        d = json.load(f)
+
+    def num(v):
+        if isinstance(v, str):
+            return float(v)
+        if isinstance(v, list):
+            return [num(x) for x in v]
+        return v
+
+    pts = []
+    for q in d["points"]:
+        q = {k: num(v) for k, v in q.items()}
+        q["nodes"] = [dict(dir=t[0], i_minus=t[1], i_plus=t[2], dir_gap=g, bridge_gap=b)
+                      for t, g, b in zip(q["tree"], q["dir_gap"], q["bridge_gap"])]
+        pts.append(q)
+    hdr = {k: v for k, v in d.items() if k != "points"}
+    return hdr, pts
+
+
+def golden_arrays(pts, dim=2):
+    """F (d*d, m), beta_n (m,), W (m,), P (d*d, m) and the tree dicts of stored points."""
+    F = np.array([q["F"] for q in pts], dtype=np.float64).T.copy()
+    bn = np.array([q["beta_n"] for q in pts], dtype=np.float64)
+    W = np.array([q["W"] for q in pts], dtype=np.float64)
+    P = np.array([q["P"] for q in pts], dtype=np.float64).T.copy()
+    return F, bn, W, P, [q["nodes"] for q in pts]

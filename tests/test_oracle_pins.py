@@ -230,6 +230,120 @@ def test_hull_against_brute_force(seed):
         assert not any(im < k < ip for k in verts)
 
 
+def brute_gap(w, c):
+    """Exact tie diagnostics of the hull at c (the oracle's bridge_gap), O(n^2) over
+    rationals.  If c is a strict hull vertex: the hull value at c of the other samples
+    (min over finite pairs a < c < b, a, b != c) minus w_c, +inf when c has no finite
+    sample on one side.  Else the bridge over c is the line through the min-chord
+    pairs (all on one line); its endpoints are the outermost such a and b, and the
+    gap is the least height of any other finite sample above that line (0 when a
+    sample lies on it).  Returns (kind, gap, a, b)."""
+    idx = [i for i, v in enumerate(w) if v is not None]
+    chords = {}
+    for a in idx:
+        for b in idx:
+            if a < c < b:
+                chords[(a, b)] = Fraction(w[a]) * Fraction(b - c, b - a) + Fraction(w[b]) * Fraction(c - a, b - a)
+    best = min(chords.values()) if chords else None
+    if best is None or Fraction(w[c]) < best:
+        return "vertex", (best - Fraction(w[c])) if best is not None else math.inf, c, c
+    pairs = [k for k, v in chords.items() if v == best]
+    a, b = min(k[0] for k in pairs), max(k[1] for k in pairs)
+    slope = (Fraction(w[b]) - Fraction(w[a])) / (b - a)
+    gap = min((Fraction(w[i]) - (Fraction(w[a]) + slope * (i - a)) for i in idx if i not in (a, b)),
+              default=math.inf)
+    return "bridge", gap, a, b
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_bridge_gap_against_exact_brute_force(seed):
+    """The oracle's bridge_gap (used to tell ties from unambiguous laminates) equals its
+    exact definition on integer lines: random, with inadmissible ends, with collinear
+    runs through the bridge, and with the centre a vertex or on a straight run."""
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(2, 12)) * 2 + 1
+    c = (n - 1) // 2
+    kind = seed % 5
+    if kind == 0:
+        w = [int(v) for v in rng.integers(-2 ** 18, 2 ** 18, size=n)]
+    elif kind == 1:      # convex parabola: the centre is a vertex
+        w = [int(3 * (i - c) ** 2 + rng.integers(0, 2)) for i in range(n)]
+    elif kind == 2:      # flat bottom: samples on the bridge line
+        w = [(abs(i - c) - 3) ** 2 if abs(i - c) > 3 else 0 for i in range(n)]
+    elif kind == 3:      # straight run through the centre
+        w = [5 * i + (int(rng.integers(1, 9)) if i in (0, n - 1) else 0) for i in range(n)]
+    else:                # a V: the centre is a vertex whose neighbours are collinear arms
+        w = [abs(i - c) * 7 for i in range(n)]
+    lo = int(rng.integers(0, c + 1)) if seed % 2 else 0
+    hi = int(rng.integers(c, n)) if seed % 3 else n - 1
+    wm = [w[i] if lo <= i <= hi else None for i in range(n)]
+    warr = np.array([np.inf if v is None else float(v) for v in wm])
+    v, im, ip, gap = O.hull_at_centre(warr, c)
+    kind_b, gap_b, a, b = brute_gap(wm, c)
+    assert (im, ip) == (a, b), (wm, im, ip, a, b)
+    if gap_b == math.inf:
+        assert gap == math.inf
+    else:
+        assert gap >= 0.0
+        assert abs(Fraction(gap) - gap_b) <= Fraction(1, 2 ** 30) * (1 + abs(gap_b)), (wm, gap, gap_b)
+
+
+def test_bridge_gap_collinear_cases():
+    """Named cases: samples on the bridge line give gap 0; a V's centre has gap equal to
+    its depth below the chord of the samples beside it; the nearest other sample sets
+    the gap of a bridge; an inadmissible sample takes no part."""
+    assert O.hull_at_centre(np.array([9.0, 0, 0, 0, 0, 0, 9]))[3] == 0.0        # flat bridge, samples on it
+    assert O.hull_at_centre(np.array([4.0, 3, 2, 1, 0, 1, 2, 3, 4]))[3] == 1.0  # V: its neighbours' chord (1) minus 0
+    v, im, ip, gap = O.hull_at_centre(np.array([9.0, 0, 5, 6, 5, 0, 9]))
+    assert (im, ip) == (1, 5) and gap == 5.0                                    # nearest other sample: 5 above
+    assert O.hull_at_centre(np.array([np.inf, 1.0, 0.0, 1.0, 2.0]))[3] == 1.0    # inadmissible end is absent
+
+
+def test_dir_gap_and_node_bridge_gap_against_single_direction_hulls():
+    """The tree's dir_gap is the second-smallest minus the smallest direction value when
+    the winner laminates (+inf when it does not), and its bridge_gap is that winner's
+    line gap (or, when no direction laminates, the least vertex gap over directions),
+    with each direction's line and hull computed here from W samples (eq. 2.9, pinned
+    above) and the exact brute force."""
+    mat = O.material(dim=2)
+    a, b = WL.angle_directions(3, 2)
+    n_t, tau = 21, 1.0
+    spec = O.LaminationSpec([(a, b, n_t, tau)])
+    t = np.array([tau * (2 * i - (n_t - 1)) / (n_t - 1) for i in range(n_t)])
+    cfg = WL.small_random(2, 40, (1, 1), 3, seed_tag=1100, sigma=0.35, beta_max=0.3)
+    n_lam = n_vert = 0
+    for p in range(cfg["n"]):
+        F = cfg["F"][:, p].reshape(2, 2)
+        bn = cfg["beta_n"][p]
+        W, _, tree = O.envelope(mat, spec, F, bn, want_tree=True)
+        vals, gaps, lams = [], [], []
+        for m in range(len(a)):
+            w = [O.energy(mat, F + tt * np.outer(a[m], b[m]), bn) for tt in t]
+            wm = [v if np.isfinite(v) else None for v in w]
+            kind, gap, ia, ib = brute_gap([Fraction(v) if v is not None else None for v in wm], (n_t - 1) // 2)
+            c = (n_t - 1) // 2
+            val = Fraction(wm[c]) if kind == "vertex" else \
+                Fraction(wm[ia]) * Fraction(ib - c, ib - ia) + Fraction(wm[ib]) * Fraction(c - ia, ib - ia)
+            vals.append(float(val))
+            gaps.append(float(gap))
+            lams.append(kind == "bridge")
+        order = sorted(range(len(vals)), key=lambda m: (vals[m], m))
+        best = order[0]
+        assert tree[0]["dir"] == best
+        assert abs(W - vals[best]) <= 1e-14 * max(1.0, abs(W))
+        scale = 1e-13 * max(1.0, abs(W))
+        if lams[best]:
+            n_lam += 1
+            assert abs(tree[0]["dir_gap"] - (vals[order[1]] - vals[best])) <= scale
+            assert abs(tree[0]["bridge_gap"] - gaps[best]) <= scale
+        else:
+            n_vert += 1
+            assert tree[0]["dir_gap"] == math.inf
+            vg = min(gaps[m] for m in range(len(vals)) if not lams[m])
+            assert abs(tree[0]["bridge_gap"] - vg) <= scale or (vg == math.inf and tree[0]["bridge_gap"] == math.inf)
+    assert n_lam >= 5 and n_vert >= 5, (n_lam, n_vert)
+
+
 # ---------------------------------------------------------------- P4, P5: closed forms
 
 def test_double_well_1d_closed_form():
