@@ -42,6 +42,48 @@ def both_grids(r1, dim, n, lo, delta):
     return r1.grid(dim, n, lo, delta), O.grid(dim, n, lo, delta)
 
 
+def _line_through(n, steps_r, p):
+    """Node indices of the mesh line through node p with integer step steps_r (component
+    0 slowest, as the nodes are numbered), in order of l, and p's position on it."""
+    n = np.asarray(n)
+    I = np.array(np.unravel_index(p, tuple(n)))
+    s = np.asarray(steps_r)
+    lo, hi = -10 ** 6, 10 ** 6
+    for c in range(len(n)):
+        if s[c] > 0:
+            lo, hi = max(lo, -(I[c] // s[c])), min(hi, (n[c] - 1 - I[c]) // s[c])
+        elif s[c] < 0:
+            lo, hi = max(lo, -((n[c] - 1 - I[c]) // -s[c])), min(hi, I[c] // -s[c])
+    ls = np.arange(lo, hi + 1)
+    J = I[None, :] + ls[:, None] * s[None, :]
+    return np.ravel_multi_index(tuple(J.T), tuple(n)), -lo
+
+
+def check_laminate_validity(n, steps, W_prev, C_prev, W_new, C_new, nodes, eps, ctol):
+    """Eq. 5.2 (first case) as a validity check, independent of how ties are broken: at
+    each given node the new value is the minimum over its own value and every
+    direction's hull value (Algorithm 1 on the node's mesh line through the previous
+    iterate, orc_hull_at_centre) to within 16 eps max(|W|, 1e-3), and the carried
+    quantities C_new (stresses, moduli) are those of one laminate attaining that
+    minimum to within the same margin: the node's own C_prev if no lowering is needed,
+    else the hull segment's endpoints' C_prev with the weights of the value."""
+    for p in nodes:
+        cands = [(W_prev[p], None)]
+        for r in range(len(steps)):
+            line, c = _line_through(n, steps[r], p)
+            v, im, ip, _ = O.hull_at_centre(W_prev[line], c)
+            if im != ip:
+                xi = (c - im) / (ip - im)
+                cands.append((v, xi * C_prev[:, line[ip]] + (1 - xi) * C_prev[:, line[im]]))
+        m = min(v for v, _ in cands)
+        margin = 16 * eps * max(abs(m), 1e-3)
+        assert abs(W_new[p] - m) <= margin, (p, W_new[p], m)
+        sc = max(np.max(np.abs(C_new[:, p])), 1.0)
+        ok = [v <= m + margin and np.max(np.abs((C_prev[:, p] if c is None else c) - C_new[:, p])) <= ctol * sc
+              for v, c in cands]
+        assert any(ok), (p, W_new[p], [v for v, _ in cands])
+
+
 @pytest.mark.parametrize("kind", ["f64", "f32"])
 @pytest.mark.parametrize("model", [0, 2])
 @pytest.mark.parametrize("dim", [2, 3])
@@ -123,13 +165,14 @@ def test_grid_every_hull_path_on_random_values(lib, kind, n):
     assert len(hist) == 1 and abs(hist[0] - md) <= tol
     lowered = fin & (ref < Wi)
     assert lowered.sum() > N // 20
-    # the stress of a lowered node follows its laminate; where two directions tie to
-    # rounding in FP32 the laminate may differ, so FP32 compares the nodes both lower alike
-    if kind == "f64":
-        assert np.max(np.abs(Pg[:, fin] - Pref[:, fin])) <= 1e-14
-    else:
-        same = np.all(np.abs(Pg - Pref) <= 1e-5, axis=0)
-        assert same[fin].mean() > 0.99
+    # the stress of a node is its laminate's: equal to the oracle's, or (where the
+    # directions tie to rounding) that of another laminate attaining the minimum
+    ctol = 1e-14 if kind == "f64" else 2e-6
+    differ = np.nonzero(fin & np.any(np.abs(Pg - Pref) > ctol * np.maximum(np.abs(Pref).max(axis=0), 1.0), axis=0))[0]
+    eps = 2.0 ** -52 if kind == "f64" else 2.0 ** -23
+    check_laminate_validity(n, O.grid_r11(2), Wi, Pi, Wg, Pg, differ, eps, ctol)
+    print("%s: %d of %d nodes lowered, %d with another laminate than the oracle's" % (kind, lowered.sum(), N,
+                                                                                       len(differ)))
 
 
 @pytest.mark.parametrize("model,dim", [(0, 2), (2, 2), (2, 3), (0, 3)])
@@ -239,26 +282,58 @@ def test_grid_invalid_arguments(lib):
         h.grid_laminate(r1.grid(2, (3, 3, 3, 3), (0, 0, 0, 0), 0.0), r1.grid_r11(2), W)
 
 
+def _iterate_with_validity(h, r1, torch, g, og, dim, n, W, P, A, k_max, tol):
+    """Runs the GPU iteration one step at a time (same stopping rule); after each step the
+    carried stresses (and moduli) must equal the oracle sweep's from the same previous
+    state, or else be those of another laminate attaining the minimum
+    (check_laminate_validity).  Returns the decreases and the count of such nodes."""
+    steps = O.grid_r11(dim)
+    hist, n_other = [], 0
+    dd = dim * dim
+    for _ in range(k_max):
+        Wp = W.cpu().numpy().copy()
+        Cp = np.concatenate([P.cpu().numpy()] + ([A.cpu().numpy()] if A is not None else []))
+        d = h.grid_laminate(g, r1.grid_r11(dim), W, k_max=1, tol=0.0, P=P, A=A)
+        torch.cuda.synchronize()
+        hist.append(d[0])
+        Wn = W.cpu().numpy()
+        Cn = np.concatenate([P.cpu().numpy()] + ([A.cpu().numpy()] if A is not None else []))
+        Wr, md, Cr = O.grid_sweep(og, steps, Wp, Cp)
+        fin = np.isfinite(Wr)
+        assert np.max(np.abs(Wn[fin] - Wr[fin]) / np.maximum(np.abs(Wr[fin]), 1e-3)) <= 1e-14
+        assert abs(d[0] - md) <= 1e-14 * max(abs(md), 1e-3)
+        sc = np.maximum(np.abs(Cr).max(axis=0), 1.0)
+        differ = np.nonzero(fin & np.any(np.abs(Cn - Cr) > 1e-11 * sc, axis=0))[0]
+        check_laminate_validity(n, steps, Wp, Cp, Wn, Cn, differ, 2.0 ** -52, 1e-11)
+        n_other += len(differ)
+        assert np.all(np.isnan(Cn[:dd, ~fin]))
+        if d[0] <= tol:
+            break
+    return hist, n_other
+
+
 @pytest.mark.parametrize("model,dim", [(0, 2), (2, 2), (2, 3), (0, 3)])
 def test_grid_stress_matches_oracle(lib, model, dim):
-    """Node stresses carried through the iterations (eq. 5.2, first case) equal the oracle's
-    (FP64), and their interpolation gives the oracle's off-mesh stress (second case)."""
+    """Node stresses carried through the iterations (eq. 5.2, first case): after every
+    iteration each node's stress is its laminate's (the oracle's, or another laminate
+    attaining the minimum), and their interpolation off the mesh is the oracle's
+    interpolation of them (second case)."""
     r1, h, torch = lib
     n, lo, delta = lam_meshes(dim)
     g, og = both_grids(r1, dim, n, lo, delta)
     W, P = h.grid_energy(r1.material_from(NH, dim, model), g, 0.04, torch.float64, stress=True)
-    hist = h.grid_laminate(g, r1.grid_r11(dim), W, k_max=20, tol=1e-6, P=P)
-    torch.cuda.synchronize()
     W0, P0 = O.grid_energy(PA.orc_material(NH, dim, model), og, 0.04, stress=True)
-    Wo, ho, Po = O.grid_laminate(og, O.grid_r11(dim), W0, k_max=20, tol=1e-6, P=P0)
+    Wo, ho, Po = O.grid_laminate(og, O.grid_r11(dim), W0.copy(), k_max=20, tol=1e-6, P=P0.copy())
+    hist, n_other = _iterate_with_validity(h, r1, torch, g, og, dim, n, W, P, None, k_max=20, tol=1e-6)
     assert len(hist) == len(ho)
     Pg = P.cpu().numpy()
     fin = np.isfinite(Wo)
     scale = max(np.max(np.abs(Po[:, fin])), 1.0)
-    assert np.max(np.abs(Pg[:, fin] - Po[:, fin])) <= 1e-11 * scale
+    assert np.max(np.abs(W.cpu().numpy()[fin] - Wo[fin]) / np.maximum(np.abs(Wo[fin]), 1e-3)) <= 1e-12
     assert np.all(np.isnan(Pg[:, ~fin])) and np.all(np.isnan(Po[:, ~fin]))
     changed = np.sum(np.any(np.abs(Po - P0) > 1e-12, axis=0) & fin)
     assert changed > 10
+    print("   %d node laminates other than the oracle's, each valid" % n_other)
     # off-mesh: interpolate each stress component at points inside cells of finite nodes
     rng = np.random.default_rng(90 + dim)
     hi = np.array(lo) + delta * (np.array(n) - 1)
@@ -266,7 +341,7 @@ def test_grid_stress_matches_oracle(lib, model, dim):
     Ft = torch.tensor(pts.T.copy(), dtype=torch.float64, device="cuda").contiguous()
     for c in range(dim * dim):
         got = h.grid_interpolate(g, P[c].contiguous(), Ft).cpu().numpy()
-        ref = np.array([O.grid_interpolate(og, Po[c], pts[k]) for k in range(len(pts))])
+        ref = np.array([O.grid_interpolate(og, Pg[c], pts[k]) for k in range(len(pts))])
         ok = np.isfinite(ref)
         assert np.array_equal(np.isfinite(got), ok)
         assert np.max(np.abs(got[ok] - ref[ok]), initial=0.0) <= 1e-11 * scale
@@ -291,14 +366,15 @@ def test_grid_double_well_stress_on_gpu(lib):
 @pytest.mark.parametrize("model,dim", [(0, 2), (2, 2), (2, 3), (0, 3)])
 def test_grid_tangent_matches_oracle(lib, model, dim):
     """Moduli carried through the iterations with the stresses (Algorithm 3's tangent on the
-    mesh) equal the oracle's (FP64), node by node, including the untouched A^0."""
+    mesh): A^0 equals the oracle's node by node, and after every iteration each node's
+    stress and moduli are those of its laminate (the oracle's, or another laminate
+    attaining the minimum)."""
     r1, h, torch = lib
     n, lo, delta = lam_meshes(dim)
     g, og = both_grids(r1, dim, n, lo, delta)
     W, P, A = h.grid_energy(r1.material_from(NH, dim, model), g, 0.04, torch.float64, stress=True, tangent=True)
     W0g, A0g = W.cpu().numpy(), A.cpu().numpy()
-    hist = h.grid_laminate(g, r1.grid_r11(dim), W, k_max=20, tol=1e-6, P=P, A=A)
-    torch.cuda.synchronize()
+    hist, n_other = _iterate_with_validity(h, r1, torch, g, og, dim, n, W, P, A, k_max=20, tol=1e-6)
     W0, P0, A0 = O.grid_energy(PA.orc_material(NH, dim, model), og, 0.04, stress=True, tangent=True)
     fin0 = np.isfinite(W0)
     sc0 = max(np.max(np.abs(A0[:, fin0])), 1.0)
@@ -310,10 +386,9 @@ def test_grid_tangent_matches_oracle(lib, model, dim):
     assert len(hist) == len(ho)
     fin = np.isfinite(Wo)
     Pg, Ag = P.cpu().numpy(), A.cpu().numpy()
-    assert np.max(np.abs(Pg[:, fin] - Po[:, fin])) <= 1e-11 * max(np.max(np.abs(Po[:, fin])), 1.0)
     scale = max(np.max(np.abs(Ao[:, fin])), 1.0)
-    assert np.max(np.abs(Ag[:, fin] - Ao[:, fin])) <= 1e-11 * scale
     assert np.all(np.isnan(Ag[:, ~fin]))
+    print("   %d node laminates other than the oracle's, each valid" % n_other)
     changed = np.sum(np.any(np.abs(Ao - A0) > 1e-12, axis=0) & fin)
     assert changed > 10
     # the carried moduli stay symmetric (each leaf's d^2W is)
