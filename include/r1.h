@@ -177,6 +177,25 @@ r1_status r1_envelope_tangent(r1_handle handle, const r1_material* material,
                               const void* F, const void* beta_n, void* W, void* P, void* A,
                               r1_laminate* tree, int32_t* flags, void* stream);
 
+/* Relax-then-fix driver of quadrature points, one pseudo-time step (the procedure
+ * of the biaxial test, Section 6.6, with the damage history of Section 2).  The
+ * state of point p is its history beta[p] (device, dtype[n]: the largest psi0 it
+ * has seen) and fixed[p] (device, int32[n]: 0 while its envelope is relaxed anew
+ * in each step, 1 once it has been fixed).  The step's relaxed potential at F
+ * is W^k(F) (eq. 3.3 on the given levels) with the history entering the step
+ * as beta_n, written to W, P, tree and flags as by r1_envelope_stress (P, tree
+ * and flags nullable; without a tree the library keeps one in workspace).  Then
+ * for each point with fixed[p] == 0 and finite W: if the root laminate
+ * laminates (i_minus != i_plus), the non-convex regime is reached and the
+ * envelope is fixed with its history (fixed[p] = 1, beta[p] unchanged, reused
+ * by every later step); otherwise (W^k = W at F, the convex regime) beta[p]
+ * becomes max(beta[p], psi0(F)) (rounded to dtype; the double-well test energy
+ * has no history).  Points with fixed[p] != 0 or W not finite keep their state.
+ * beta and fixed are read and written in stream order. */
+r1_status r1_path_step(r1_handle handle, const r1_material* material, const r1_lamination* lamination,
+                       int64_t n, r1_dtype dtype, const void* F, void* beta, int32_t* fixed, void* W,
+                       void* P, r1_laminate* tree, int32_t* flags, void* stream);
+
 /* Tangent moduli A (layout of r1_envelope_tangent) of given lamination trees
  * (Algorithm 3 on tree[p*R1_TREE_NODES ..], nodes as written by the envelope
  * calls for the same lamination): leaves F^-/+ of each node rebuilt from its

@@ -15,7 +15,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
-SOURCES = ["energy.c", "hull.c", "lamination.c", "mlp.c", "grid.c"]
+SOURCES = ["energy.c", "hull.c", "lamination.c", "mlp.c", "grid.c", "path.c"]
 
 MODEL_NH_DAMAGE = 0
 MODEL_DOUBLEWELL = 1
@@ -122,6 +122,9 @@ def lib():
         L.orc_grid_laminate.argtypes = [gp, ctypes.c_int, ip, dp, ctypes.c_int, dp, ctypes.c_int, ctypes.c_double, dp]
         L.orc_grid_interpolate.restype = ctypes.c_double
         L.orc_grid_interpolate.argtypes = [gp, dp, dp]
+        L.orc_path_relax.restype = ctypes.c_int
+        L.orc_path_relax.argtypes = [ctypes.POINTER(Material), ctypes.POINTER(Lamination), ctypes.c_int, dp,
+                                     ctypes.c_double, ctypes.c_int, dp, dp, dp, ip]
         _lib = L
     return _lib
 
@@ -404,3 +407,17 @@ def grid_update_node(g, steps, W, p):
     W = np.ascontiguousarray(W, dtype=np.float64)
     return lib().orc_grid_update_node(ctypes.byref(g), len(steps), _ip(steps), _dp(W), ctypes.c_long(p))
 
+
+def path_relax(mat, spec, F_steps, beta0, fixed0=0):
+    """Relax-then-fix driver of one point (path.c): F_steps (n_steps, d, d).  Returns
+    W (n_steps,), P (n_steps, d, d), beta (n_steps,), fixed (n_steps,) and the step at
+    which the envelope was fixed (-1 if never)."""
+    F = np.ascontiguousarray(F_steps, dtype=np.float64)
+    ns = F.shape[0]
+    W = np.empty(ns)
+    P = np.empty_like(F)
+    beta = np.empty(ns)
+    fixed = np.empty(ns, dtype=np.int32)
+    first = lib().orc_path_relax(ctypes.byref(mat), ctypes.byref(spec.c), ns, _dp(F), float(beta0), int(fixed0),
+                                 _dp(W), _dp(P), _dp(beta), fixed.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    return W, P, beta, fixed, first

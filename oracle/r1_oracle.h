@@ -159,6 +159,15 @@ int orc_grid_laminate(const orc_grid* g, int n_dir, const int* steps, double* W,
                       double tol, double* hist);
 double orc_grid_interpolate(const orc_grid* g, const double* W, const double* F);
 
+/* Relax-then-fix driver of one point (Section 6.6, history of Section 2; see
+ * path.c): n_steps gradients F_steps (step-major, d*d each), initial history
+ * beta0 and status fixed0 (1: the envelope is already fixed with beta0).  Per
+ * step: W[s], P[s*d*d ..] (nullable), the history after the step beta[s] and the
+ * status fixed[s] (both nullable).  Returns the step at which the envelope was
+ * fixed, or -1. */
+int orc_path_relax(const orc_material* mat, const orc_lamination* lam, int n_steps, const double* F_steps,
+                   double beta0, int fixed0, double* W, double* P, double* beta, int* fixed);
+
 #ifdef __cplusplus
 }
 #endif

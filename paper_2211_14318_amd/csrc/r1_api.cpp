@@ -298,11 +298,13 @@ r1_status fill_args(r1_handle h, const r1_material* mat, const r1_lamination* la
   return R1_OK;
 }
 
-// Envelope with optional stress, tree, flags and tangent moduli (A != nullptr:
-// the tree goes to workspace when the caller passes none).
+// Envelope with optional stress, tree, flags and tangent moduli.  When the tree
+// is needed (A != nullptr, or need_tree) and the caller passes none, it goes to
+// workspace; *tree_used (nullable) receives the tree written.
 r1_status envelope_impl(r1_handle h, const r1_material* mat, const r1_lamination* lam, int64_t n,
                         r1_dtype dtype, const void* F, const void* beta_n, void* W, void* P,
-                        r1_laminate* tree, int32_t* flags, void* A, void* stream) {
+                        r1_laminate* tree, int32_t* flags, void* A, void* stream, bool need_tree = false,
+                        r1_laminate** tree_used = nullptr) {
   if (!h) return R1_EINVAL;
   KArgs a;
   r1_status s = fill_args(h, mat, lam, n, dtype, F, beta_n, &a);
@@ -323,7 +325,8 @@ r1_status envelope_impl(r1_handle h, const r1_material* mat, const r1_lamination
     bytes = w1 + r1_outer_res_bytes(dtype) * size_t(n) * size_t(lam->level[0].n_dir);
   }
   size_t tree_off = (bytes + 255) & ~size_t(255);
-  if (A && !tree) bytes = tree_off + sizeof(r1_laminate) * R1_TREE_NODES * size_t(n);
+  const bool tree_ws = (A || need_tree) && !tree;
+  if (tree_ws) bytes = tree_off + sizeof(r1_laminate) * R1_TREE_NODES * size_t(n);
   if (bytes) {
     void* base = nullptr;
     s = r1h::scratch(h, bytes, &base);
@@ -332,8 +335,9 @@ r1_status envelope_impl(r1_handle h, const r1_material* mat, const r1_lamination
       a.scratch_w1f = base;
       a.scratch_outer = static_cast<char*>(base) + w1;
     }
-    if (A && !tree) a.tree = reinterpret_cast<r1_laminate*>(static_cast<char*>(base) + tree_off);
+    if (tree_ws) a.tree = reinterpret_cast<r1_laminate*>(static_cast<char*>(base) + tree_off);
   }
+  if (tree_used) *tree_used = a.tree;
   int S = r1h::segment_width(h, inner.n_t, dtype, mat->dim, lam->depth == 2 ? r1h::kRoleInner : r1h::kRoleLevel);
   int K = r1h::samples_per_lane(S, inner.n_t);
   if (K == 0) return R1_EINVAL;
@@ -364,6 +368,20 @@ r1_status r1_envelope_tangent(r1_handle h, const r1_material* mat, const r1_lami
                               void* stream) {
   if (!A && n > 0) return R1_EINVAL;
   return envelope_impl(h, mat, lam, n, dtype, F, beta_n, W, P, tree, flags, A, stream);
+}
+
+r1_status r1_path_step(r1_handle h, const r1_material* mat, const r1_lamination* lam, int64_t n,
+                       r1_dtype dtype, const void* F, void* beta, int32_t* fixed, void* W, void* P,
+                       r1_laminate* tree, int32_t* flags, void* stream) {
+  if (!h) return R1_EINVAL;
+  if (n > 0 && (!beta || !fixed)) return R1_EINVAL;
+  r1_laminate* used = nullptr;
+  r1_status s = envelope_impl(h, mat, lam, n, dtype, F, beta, W, P, tree, flags, nullptr, stream, true, &used);
+  if (s || n == 0) return s;
+  const r1d::Material m{mat->dim, mat->model, mat->mu, mat->lambda, mat->D_inf, mat->D0};
+  hipError_t e = r1_launch_path_update(dtype, n, F, W, used, beta, fixed, m, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return r1h::fail(h, e, "kernel launch");
+  return R1_OK;
 }
 
 r1_status r1_laminate_tangent(r1_handle h, const r1_material* mat, const r1_lamination* lam,

@@ -74,6 +74,13 @@ size_t r1_outer_res_bytes(int dtype);
 hipError_t r1_launch_tangent(const KArgs& a, int depth, int dtype, const r1_laminate* tree, void* A, hipStream_t st,
                              KTimer* tm);
 
+// State update of the relax-then-fix driver after the step's envelope (r1_path_step):
+// per point, fix the envelope where the root laminate laminates, else raise the
+// history beta to psi0(F); points already fixed and points with W not finite keep
+// their state.
+hipError_t r1_launch_path_update(int dtype, int64_t n, const void* F, const void* W, const r1_laminate* tree,
+                                 void* beta, int32_t* fixed, const r1d::Material& m, hipStream_t st);
+
 struct BArgs;
 // Uneven-batch kernel of the given kind (kBPoint, kBOuter, kBFinal) for layout
 // variant var of the material model's kernels on `grid` blocks with `lds` bytes

@@ -111,6 +111,8 @@ def _load():
                                      i32, vp, vp, vp, vp, vp, vp, vp]
     L.r1_envelope_stress_noalloc.argtypes = [vp, ctypes.POINTER(Material), ctypes.POINTER(Lamination), i64,
                                              i32, vp, vp, vp, vp, vp, vp, vp]
+    L.r1_path_step.argtypes = [vp, ctypes.POINTER(Material), ctypes.POINTER(Lamination), i64, i32, vp, vp, vp,
+                               vp, vp, vp, vp, vp]
     L.r1_envelope_tangent.argtypes = [vp, ctypes.POINTER(Material), ctypes.POINTER(Lamination), i64,
                                       i32, vp, vp, vp, vp, vp, vp, vp, vp]
     L.r1_laminate_tangent.argtypes = [vp, ctypes.POINTER(Material), ctypes.POINTER(Lamination), i64,
@@ -160,7 +162,7 @@ def _load():
         getattr(L, name).restype = i32
     for name in ("r1_autotune", "r1_autotune_inner", "r1_get_inner_segment_width", "r1_timing_enable", "r1_timing_reset", "r1_timing_query", "r1_create", "r1_destroy", "r1_envelope", "r1_envelope_stress",
                  "r1_envelope_tangent", "r1_laminate_tangent", "r1_envelope_batched", "r1_grid_r11",
-                 "r1_envelope_stress_noalloc",
+                 "r1_envelope_stress_noalloc", "r1_path_step",
                  "r1_batched_plan_create", "r1_batched_plan_execute", "r1_batched_plan_destroy",
                  "r1_grid_energy", "r1_grid_laminate", "r1_grid_interpolate", "r1_set_segment_width", "r1_get_segment_width"):
         getattr(L, name).restype = i32
@@ -313,6 +315,17 @@ class Handle:
                                             _ptr(fl), self._stream(stream)),
                     "r1_envelope_stress")
         return dict(W=W, P=P, tree=T, flags=fl)
+
+    def path_step(self, mat, spec, F, beta, fixed, W, P=None, tree=None, flags=None, stream=None):
+        """One step of the relax-then-fix driver (r1_path_step): the relaxed potential
+        at F with the history beta into W (and P, tree, flags); beta (n,) and fixed
+        (n,) int32 are updated in place."""
+        n = F.shape[1]
+        assert F.is_contiguous() and beta.shape == (n,) and beta.dtype == F.dtype
+        assert fixed.shape == (n,) and fixed.dtype == self.torch.int32 and W.shape == (n,)
+        self._check(_lib.r1_path_step(self.h, ctypes.byref(mat), ctypes.byref(spec.c), n, self._dtype_code(F),
+                                      _ptr(F), _ptr(beta), _ptr(fixed), _ptr(W), _ptr(P), _ptr(tree), _ptr(flags),
+                                      self._stream(stream)), "r1_path_step")
 
     def laminate_tangent(self, mat, spec, F, beta_n, W, tree, stream=None):
         """Tangent moduli (d**4, n) of the given (n, 3, 4) int32 trees (Algorithm 3)."""

@@ -214,3 +214,49 @@ def small_random(dim, n, n_dir_ab, n_t, tau=1.0, depth=1, inner=None, seed_tag=1
         ai, bi = angle_directions(na, nb) if dim == 2 else fibonacci_directions(na, nb)
         levels.append(level(ai, bi, nt2, tau))
     return _cfg("small-%dd-n%d" % (dim, n), dim, F, beta_n, levels, "f64")
+
+
+PATH_AMPLITUDES = (0.0, 0.15, 0.3, 0.45, 0.6, 0.75, 0.9, 1.0, 0.85, 0.7, 0.55, 0.7, 0.9, 1.1, 1.3, 1.45)
+
+
+BIAXIAL_MATERIAL = dict(mu=1.0, lam=0.5, D_inf=0.9, D0=0.3)    # neo-Hooke row of the biaxial test's table
+
+
+def path_config(dim, n, n_dir_ab, n_t, tau=1.0, depth=1, inner=None, seed_tag=300, sigma=0.25,
+                amplitudes=PATH_AMPLITUDES, beta_max=0.02, material=None):
+    """Quadrature points driven along prescribed deformation paths (relax-then-fix
+    driver): F_s = I + a_s H_p with one random H_p = sigma N(0,1) per point and a
+    loading, unloading and reloading amplitude schedule a_s; H_p is redrawn until
+    det F_s > 0.1 at every step.  beta_0 ~ U[0, beta_max].  F_steps has shape
+    (n_steps, d*d, n), SoA per step.  Material: the biaxial test's neo-Hooke
+    parameters unless given."""
+    rng = rng_for(seed_tag)
+    amp = np.asarray(amplitudes, dtype=np.float64)
+    H = np.empty((n, dim, dim))
+    filled = 0
+    while filled < n:
+        m = max(2 * (n - filled), 16)
+        G = sigma * rng.standard_normal((m, dim, dim))
+        ok = np.ones(m, dtype=bool)
+        for a in amp:
+            ok &= np.linalg.det(np.eye(dim)[None] + a * G) > 0.1
+        G = G[ok]
+        k = min(len(G), n - filled)
+        H[filled:filled + k] = G[:k]
+        filled += k
+    F = np.eye(dim)[None, None] + amp[:, None, None, None] * H[None]      # (steps, n, d, d)
+    F_steps = np.ascontiguousarray(F.reshape(len(amp), n, dim * dim).transpose(0, 2, 1))
+    beta0 = rng.uniform(0.0, beta_max, size=n)
+    if dim == 2:
+        a, b = angle_directions(*n_dir_ab)
+    else:
+        a, b = fibonacci_directions(*n_dir_ab)
+    levels = [level(a, b, n_t, tau)]
+    if depth == 2:
+        na, nb, nt2 = inner
+        ai, bi = angle_directions(na, nb) if dim == 2 else fibonacci_directions(na, nb)
+        levels.append(level(ai, bi, nt2, tau))
+    d = dict(name="path-%dd-n%d-steps%d" % (dim, n, len(amp)), dim=dim,
+             material=dict(BIAXIAL_MATERIAL if material is None else material),
+             F_steps=F_steps, beta0=beta0, levels=levels, n=n, amplitudes=amp)
+    return d

@@ -1,0 +1,129 @@
+"""Relax-then-fix driver (r1_path_step; Section 6.6 with the history of Section 2)
+against the oracle's driver (orc_path_relax), step by step through the C-ABI:
+points driven along loading, unloading and reloading paths, depths 1 and 2, both
+precisions; and the printed relaxed curve of Section 6.6 reproduced on the GPU.
+
+At every step: W and the history (a psi0 value) within the energy bar, the same
+fixed status.  In FP32 a point whose lamination
+decision is a near-tie (the oracle's vertex or bridge gap within the FP32 tie
+margin at the step where the statuses first differ) may fix one step apart; such
+points are compared up to that step and counted."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2211_14318_amd import workloads as WL
+from tests import parity as PA
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_14318_amd import r1
+    h = r1.Handle(0)
+    yield r1, h, torch
+    h.close()
+
+
+def run_gpu(lib, cfg, kind, beta0=None, fixed0=None):
+    r1, h, torch = lib
+    dt = torch.float64 if kind == "f64" else torch.float32
+    d, n = cfg["dim"], cfg["n"]
+    mat = r1.material_from(cfg["material"], d)
+    spec = r1.LaminationSpec(cfg["levels"])
+    beta = torch.tensor(cfg["beta0"] if beta0 is None else beta0, dtype=dt, device="cuda").contiguous()
+    fixed = torch.tensor(np.zeros(n, np.int32) if fixed0 is None else fixed0, dtype=torch.int32, device="cuda")
+    W = torch.empty(n, dtype=dt, device="cuda")
+    P = torch.empty((d * d, n), dtype=dt, device="cuda")
+    out = dict(W=[], P=[], beta=[], fixed=[], F=[])
+    for s in range(cfg["F_steps"].shape[0]):
+        F = torch.tensor(cfg["F_steps"][s], dtype=dt, device="cuda").contiguous()
+        h.path_step(mat, spec, F, beta, fixed, W, P)
+        torch.cuda.synchronize()
+        out["W"].append(W.double().cpu().numpy())
+        out["P"].append(P.double().cpu().numpy())
+        out["beta"].append(beta.double().cpu().numpy())
+        out["fixed"].append(fixed.cpu().numpy().copy())
+        out["F"].append(F.double().cpu().numpy())
+    return {k: np.array(v) for k, v in out.items()}
+
+
+def compare(cfg, g, kind):
+    d, n = cfg["dim"], cfg["n"]
+    om, ospec = PA.orc_material(cfg["material"], d), PA.orc_spec(cfg["levels"])
+    depth = len(cfg["levels"])
+    b0 = cfg["beta0"] if kind == "f64" else np.float32(cfg["beta0"]).astype(np.float64)
+    n_fixed = n_tie = 0
+    for p in range(n):
+        Fs = g["F"][:, :, p].reshape(-1, d, d)
+        W, P, beta, fixed, first = O.path_relax(om, ospec, Fs, b0[p])
+        upto = len(W)
+        diff = np.nonzero(fixed != g["fixed"][:, p])[0]
+        if len(diff):
+            s = diff[0]
+            bprev = b0[p] if s == 0 else beta[s - 1]
+            _, _, tree = O.envelope(om, ospec, Fs[s], bprev, want_tree=True)
+            assert kind == "f32" and PA.is_tie(tree, depth, W[s], kind), (p, s, fixed, g["fixed"][:, p])
+            n_tie += 1
+            upto = s            # the states agree before this step
+        err = PA.energy_errors(g["W"][:upto, p], W[:upto], kind)
+        assert err.max(initial=0.0) <= PA.RTOL[kind], (p, err)
+        # the history is a psi0 value: the energy bar (psi0 is a sum of O(1) terms)
+        bt = PA.RTOL[kind] * np.maximum(np.abs(beta[:upto]), PA.W_FLOOR[kind])
+        assert np.all(np.abs(g["beta"][:upto, p] - beta[:upto]) <= bt), (p, g["beta"][:upto, p], beta[:upto])
+        n_fixed += first >= 0
+    return n_fixed, n_tie
+
+
+@pytest.mark.parametrize("kind", ["f64", "f32"])
+@pytest.mark.parametrize("depth", [1, 2])
+def test_path_step_against_oracle_driver(lib, kind, depth):
+    if depth == 1:
+        cfg = WL.path_config(2, 96, (4, 4), 201, seed_tag=310)
+    else:
+        cfg = WL.path_config(2, 24, (4, 2), 33, tau=1.2, depth=2, inner=(4, 2, 33), seed_tag=311)
+    g = run_gpu(lib, cfg, kind)
+    n_fixed, n_tie = compare(cfg, g, kind)
+    print("%s depth %d: %d of %d points fixed their envelope on the path, %d near-tie decisions"
+          % (kind, depth, n_fixed, cfg["n"], n_tie))
+    assert n_fixed >= cfg["n"] // 4 and n_fixed < cfg["n"]
+
+
+def test_path_step_3d_against_oracle_driver(lib):
+    cfg = WL.path_config(3, 24, (4, 4), 65, seed_tag=312, sigma=0.3)
+    g = run_gpu(lib, cfg, "f64")
+    n_fixed, _ = compare(cfg, g, "f64")
+    assert n_fixed >= 1
+
+
+def test_path_step_reproduces_printed_relaxed_curve(lib):
+    """Section 6.6's printed relaxed curve along the rank-one path: the point carries the
+    printed curves' history, fixes its envelope at the first step and follows the
+    printed values up the path and back to F = I."""
+    import os
+    g = np.array([[float(v) for v in l.split()] for l in open(os.path.join(os.path.dirname(__file__), "golden",
+                                                                           "nh2d_biaxial_paths.txt"))
+                  if l.strip() and not l.startswith("#")])
+    mat_d = dict(mu=1.0, lam=0.5, D_inf=0.9, D0=0.3)
+    om = O.material(dim=2, **mat_d)
+    f = lambda b: -(1.0 - O.damage(om, b)) * b - g[0, 1]
+    lo, hi = 0.0, 1.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if f(mid) > 0 else (lo, mid)
+    bk = 0.5 * (lo + hi)
+    k0 = int(np.nonzero(g[:, 2] < g[:, 1] - 1e-9)[0][0])
+    path = list(range(k0, len(g))) + list(range(len(g) - 2, -1, -1))
+    e1 = np.array([[1.0, 0.0]])
+    F_steps = np.array([np.diag([g[k, 0], 1.0]).reshape(4, 1) for k in path])
+    cfg = dict(dim=2, n=1, material=mat_d, levels=[WL.level(e1, e1, 49, 0.15 * 24)], F_steps=F_steps,
+               beta0=np.array([bk]))
+    out = run_gpu(lib, cfg, "f64")
+    ref = np.array([g[k, 2] - g[0, 1] for k in path])
+    assert np.all(out["fixed"][:, 0] == 1)
+    assert np.all(out["beta"][:, 0] == bk)
+    assert np.max(np.abs(out["W"][:, 0] - ref)) < 1e-9

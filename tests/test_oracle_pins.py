@@ -719,6 +719,77 @@ def test_direction_ties_take_the_smallest_index():
         assert vals.count(min(vals)) >= 2       # the case really is a tie
 
 
+# ---------------------------------------------------------------- relax-then-fix driver (Section 6.6)
+
+@pytest.mark.parametrize("fname,dim,wcol,rccol,tol", [
+    ("nh2d_biaxial_paths.txt", 2, 1, 2, 1e-9),
+    ("nh3d_rankd_paths.txt", 3, 1, 2, 1e-11),
+])
+def test_path_relax_reproduces_printed_relaxed_curve(fname, dim, wcol, rccol, tol):
+    """Section 6.6: the envelope is relaxed in the first non-convex step and then fixed
+    and reused.  A point with the printed curves' history beta_k driven along the
+    rank-one path F = diag(s, 1[, 1]) from the first laminating printed sample up to
+    the last and back to F = I (direction e1 (x) e1, line grid on the printed samples)
+    fixes its envelope at the first step and returns the printed relaxed values at
+    every step; its history stays beta_k (a driver that kept updating the history, or
+    froze it after the update, misses the curve by 1e-2 or more)."""
+    g = load_golden(fname)
+    mat = O.material(dim=dim, mu=1.0, lam=0.5, D_inf=0.9, D0=0.3)
+    bk = recover_beta(mat, g[0, wcol])
+    e1 = np.eye(dim)[:1]
+    spec = O.LaminationSpec([(e1, e1, 49, 0.15 * 24)])        # samples 0.15 apart, +-3.6
+    s_vals = g[:, 0]
+    k0 = int(np.nonzero(g[:, rccol] < g[:, wcol] - 1e-9)[0][0])
+    path = list(range(k0, len(s_vals))) + list(range(len(s_vals) - 2, -1, -1))
+    Fs = np.array([np.diag([s_vals[k]] + [1.0] * (dim - 1)) for k in path])
+    W, P, beta, fixed, first = O.path_relax(mat, spec, Fs, bk)
+    ref = np.array([g[k, rccol] - g[0, wcol] for k in path])
+    assert first == 0 and np.all(fixed == 1)
+    assert np.all(beta == bk)
+    assert np.max(np.abs(W - ref)) < tol, np.max(np.abs(W - ref))
+
+
+def test_path_relax_unrelaxed_steps_follow_the_printed_W_and_update_the_history():
+    """A step that does not laminate is the unrelaxed incremental potential with the
+    entering history (the printed W of Section 6.6 at the samples where the printed
+    relaxed curve touches W), and it updates the history to max(beta, psi0(F))
+    (Section 2)."""
+    g = load_golden("nh2d_biaxial_paths.txt")
+    mat = O.material(dim=2, mu=1.0, lam=0.5, D_inf=0.9, D0=0.3)
+    bk = recover_beta(mat, g[0, 1])
+    e1 = np.eye(2)[:1]
+    spec = O.LaminationSpec([(e1, e1, 49, 0.15 * 24)])
+    touch = [k for k in range(len(g)) if abs(g[k, 2] - g[k, 1]) < 1e-12]
+    assert len(touch) >= 10
+    for k in touch:
+        F = np.diag([g[k, 0], 1.0])
+        W, _, beta, fixed, first = O.path_relax(mat, spec, F[None], bk)
+        assert first == -1 and fixed[0] == 0
+        assert abs(W[0] - (g[k, 1] - g[0, 1])) < 1e-12
+        assert beta[0] == max(bk, O.psi0(mat, F))
+
+
+@pytest.mark.parametrize("D_inf", [0.0, 0.9])
+def test_path_relax_history_is_the_running_maximum_of_psi0(D_inf):
+    """On a loading-unloading-reloading cycle that never laminates, the history after
+    each step is the running maximum of psi0 over the steps so far (Section 2), and W
+    at each step is eq. 2.9 with the history entering the step."""
+    mat = O.material(dim=2, mu=1.0, lam=2.0, D_inf=D_inf, D0=0.1)
+    a, b = WL.angle_directions(4, 4)
+    spec = O.LaminationSpec([(a, b, 41, 0.2)])
+    G = np.array([[0.3, 0.1], [-0.05, 0.2]])
+    amp = np.concatenate([np.linspace(0.0, 0.12, 7), np.linspace(0.1, 0.02, 5), np.linspace(0.05, 0.15, 6)])
+    Fs = np.array([np.eye(2) + x * G for x in amp])
+    beta0 = 0.003
+    W, P, beta, fixed, first = O.path_relax(mat, spec, Fs, beta0)
+    assert first == -1
+    psi = np.array([O.psi0(mat, F) for F in Fs])
+    run = np.maximum.accumulate(np.concatenate([[beta0], psi]))
+    assert np.array_equal(beta, run[1:])
+    assert np.array_equal(W, np.array([O.energy(mat, F, bb) for F, bb in zip(Fs, run[:-1])]))
+    assert np.ptp(beta) > 0 and np.any(np.diff(psi) < 0)        # it loads and unloads
+
+
 # ---------------------------------------------------------------- surrogate network oracle
 
 def test_mlp_oracle_gradient_matches_finite_differences():
