@@ -424,6 +424,29 @@ r1_status r1_surrogate_calibrate(r1_handle handle, r1_surrogate surrogate,
                                  int64_t n, float tol, float quantile, int32_t* cells_allowed,
                                  void* stream);
 
+/* The network's raw prediction for n packed rows X (device, FP32, n x d_in), as
+ * the gates see it: gate cell (device int32[n]: (|F - I|, beta_n) bin, -1 outside
+ * the training box), predicted W^k (device float[n]: W(F) - max(g, 0)) and
+ * predicted gap g (device float[n], before clamping).  No gate is applied. */
+r1_status r1_surrogate_predict(r1_handle handle, r1_surrogate surrogate, const r1_material* material,
+                               const float* X, int64_t n, int32_t* cell, float* W_pred, float* gap_pred,
+                               void* stream);
+
+/* A-posteriori check at inference (eps > 0; 0, the default, turns it off): a
+ * value the network would serve at F is checked against lamination on a subset
+ * of the fallback's outermost line samples -- every sample within 8 of the
+ * centre, then offsets growing by about a third out to the line's ends.  Fewer
+ * samples only raise a hull (Algorithm 1), so a chord of subset samples that
+ * passes below the served value w at the centre shows W^k < w (eq. 3.3, any
+ * depth); when one passes more than eps max(|w|, 0.01) below w, the point goes to
+ * the fallback lamination instead.  Costs the W samples of the subset (about 17%
+ * of the fallback's for 16 directions x 201 points) at each served point. */
+r1_status r1_surrogate_set_check(r1_surrogate surrogate, float eps);
+/* The check's sample offsets from the centre (indices on the level's grid, one
+ * side; the check takes each at + and -) for lines of n_t points: at most 32
+ * written to offsets (host), their number to *count (host). */
+r1_status r1_surrogate_check_offsets(int32_t n_t, int32_t* offsets, int32_t* count);
+
 /* W and P (SoA, dtype) for n points: the network where the gates accept, plain
  * lamination with `fallback` elsewhere (flag R1_PT_FALLBACK).  n_fallback
  * (nullable, host) receives the number of fallback points.  Synchronizes

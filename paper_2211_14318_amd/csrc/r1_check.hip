@@ -1,0 +1,108 @@
+// A-posteriori check of the surrogate's served values against lamination on a
+// subset of the fallback's line samples.
+//
+// Every W^0 sample along a line of the fallback's outermost level is a sample of
+// the lamination's hull problem, and fewer samples can only raise a hull
+// (Algorithm 1 on a subset), so any chord of subset samples that passes below a
+// served value w at the centre shows W^k < w there (for depth 2 as well:
+// W^1 <= W^0 along the outer lines, so the outer hull over W^1 lies below the
+// one over W^0).  A served value is rejected when such a chord passes more than
+// eps max(|w|, 0.01) below it.  For a target T and samples at offsets +-o_k
+// from the centre the test is O(n) per line (a chord between left sample i and
+// right sample j passes below T at the centre iff (w_i - T)/o_i + (w_j - T)/o_j
+// < 0), so the check needs only the smallest (w - T)/o on each side.  The
+// subset: every sample within 8 of the centre, then offsets growing by about a
+// third out to the line's end (bridges from a nearby sample to a far one are the
+// laminates the network misses near the lamination boundary).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "r1_check.hpp"
+#include "r1_kernels.hpp"
+
+namespace {
+
+template <typename T, int D, int M>
+__device__ __forceinline__ float sample_at(float t, const r1d::Line<float>& L, const r1d::Point<float>& q) {
+  if constexpr (M == r1d::kFamSTVK) return r1d::w_sample_stvk<float>(t, L, q);
+  return q.model == 0 ? r1d::w_sample<float>(t, L, q) : r1d::w_sample_doublewell<float>(t, L);
+}
+
+// Point p passes when no subset chord of any direction passes below the target.
+template <typename T, int D, int M>
+__device__ bool passes(const CheckArgs& a, int64_t p) {
+  double G[D * D];
+#pragma unroll
+  for (int k = 0; k < D * D; ++k) G[k] = double(static_cast<const T*>(a.F)[int64_t(k) * a.n + p]);
+  const double bn = double(static_cast<const T*>(a.beta_n)[p]);
+  const float w = float(static_cast<const T*>(a.W)[p]);
+  const float target = w - a.eps * fmaxf(fabsf(w), 0.01f);
+  double cof[D * D];
+  r1d::cofactor<D>(G, cof);
+  const r1d::Point<float> q = r1d::make_point<float, M>(a.mat, bn);
+  const float dt = float(a.lv.tau / double((a.lv.n_t - 1) / 2));
+  for (int m = 0; m < a.lv.n_dir; ++m) {
+    const r1d::Line<float> L = r1d::line_setup<float, D, M>(q, G, cof, a.lv.a + m * D, a.lv.b + m * D);
+    float lo = __builtin_inff(), hi = __builtin_inff();
+    for (int k = 0; k < a.n_off; ++k) {
+      const float o = float(a.off[k]);
+      const float inv = 1.0f / o;
+      // NaN samples (det <= 0) are absent: fminf keeps the other operand
+      lo = fminf(lo, (sample_at<T, D, M>(-o * dt, L, q) - target) * inv);
+      hi = fminf(hi, (sample_at<T, D, M>(o * dt, L, q) - target) * inv);
+    }
+    if (lo + hi < 0.0f) return false;
+  }
+  return true;
+}
+
+// list mode (a.list != nullptr): candidates list[0 .. *count) -> failures appended
+// to fb_list; row mode: rows 0 .. n -> pass[p] = 1 / 0.
+template <typename T, int D, int M>
+__global__ __launch_bounds__(256) void k_check(CheckArgs a) {
+  const int64_t total = a.list ? int64_t(*a.count) : a.n;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t p = a.list ? int64_t(a.list[i]) : i;
+    const bool ok = passes<T, D, M>(a, p);
+    if (a.list) {
+      if (!ok) a.fb_list[atomicAdd(a.fb_count, 1)] = int32_t(p);
+    } else {
+      a.pass[p] = ok ? 1 : 0;
+    }
+  }
+}
+
+template <typename T, int D>
+hipError_t launch_TD(const CheckArgs& a, hipStream_t st) {
+  // list mode: n bounds the candidate count, which only the device knows
+  const unsigned blocks = unsigned(std::min<int64_t>((a.n + 255) / 256, 8192));
+  if (a.mat.model == R1_STVK_DAMAGE)
+    hipLaunchKernelGGL((k_check<T, D, r1d::kFamSTVK>), dim3(blocks), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_check<T, D, r1d::kFamNH>), dim3(blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int r1_check_offsets(int n_t, int* off) {
+  const int c = (n_t - 1) / 2;
+  int n = 0;
+  for (int o = 1; o <= 8 && o <= c; ++o) off[n++] = o;
+  int o = 8;
+  while (o < c && n < kCheckMaxOffsets - 1) {
+    o = std::max(o + 1, int(o * 1.3 + 0.5));
+    if (o >= c) break;
+    off[n++] = o;
+  }
+  if (off[n - 1] != c) off[n++] = c;
+  return n;
+}
+
+hipError_t r1_launch_check(int dtype, const CheckArgs& a, hipStream_t st) {
+  if (a.n <= 0) return hipSuccess;
+  if (dtype == R1_F32) return a.mat.dim == 2 ? launch_TD<float, 2>(a, st) : launch_TD<float, 3>(a, st);
+  return a.mat.dim == 2 ? launch_TD<double, 2>(a, st) : launch_TD<double, 3>(a, st);
+}

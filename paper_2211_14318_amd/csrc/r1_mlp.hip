@@ -450,6 +450,7 @@ __global__ __launch_bounds__(256) void k_infer(InferParams ip, const T* F, const
     fb_list[slot] = int32_t(pt);
     return;
   }
+  if (ip.cand_list) ip.cand_list[atomicAdd(ip.cand_count, 1)] = int32_t(pt);
   double P0[D * D];
   r1d::stress0<D, FAM>(ip.mat, b, G, P0);
   W[pt] = T(wpred);
@@ -622,6 +623,14 @@ __global__ __launch_bounds__(512) void k_infer_lds(InferParams ip, const T* F, c
     if (lane == 0 && m) base = atomicAdd(fb_count, __popcll(m));
     base = __shfl(base, 0, kWaveM);
     if (rej) fb_list[base + __popcll(m & ((1ull << lane) - 1ull))] = int32_t(pt);
+    if (ip.cand_list) {                    // served points: candidates of the check
+      const bool srv = valid && half == 0 && ok;
+      const unsigned long long ms = __ballot(srv);
+      int cb = 0;
+      if (lane == 0 && ms) cb = atomicAdd(ip.cand_count, __popcll(ms));
+      cb = __shfl(cb, 0, kWaveM);
+      if (srv) ip.cand_list[cb + __popcll(ms & ((1ull << lane) - 1ull))] = int32_t(pt);
+    }
     if (!valid || !ok) continue;
     if (half == 0) {
       r1d::Point<double> q = r1d::make_point<double, FAM>(ip.mat, b);

@@ -33,6 +33,8 @@ struct InferParams {
   double r_max, b_lo, b_hi;
   int bins_on;
   const float* gate_tau;            // kGateCells: accept when the predicted gap is <= the cell's value
+  int* cand_count;                  // nullable: points served by the network are also listed here
+  int32_t* cand_list;               // (the candidates of the a-posteriori check)
 };
 
 hipError_t r1m_gemm(int epi, bool b_bf16, int M, int N, int K, const float* A, int64_t sam,

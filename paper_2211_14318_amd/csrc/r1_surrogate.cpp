@@ -10,6 +10,7 @@
 #include <numeric>
 #include <vector>
 
+#include "r1_check.hpp"
 #include "r1_handle.hpp"
 #include "r1_mlp.hpp"
 
@@ -35,6 +36,7 @@ struct r1_surrogate_s {
   float* norm_dev = nullptr;                // device copy of norm
   void* ws = nullptr;                       // training / inference workspace
   size_t ws_bytes = 0;
+  float check_eps = 0.0f;                   // a-posteriori check of served values (0: off)
 };
 
 namespace {
@@ -518,6 +520,28 @@ r1_status r1_surrogate_train(r1_handle h, r1_surrogate s, const r1_material* mat
   return R1_OK;
 }
 
+r1_status r1_surrogate_predict(r1_handle h, r1_surrogate s, const r1_material* mat, const float* X, int64_t n,
+                               int32_t* cell, float* W_pred, float* gap_pred, void* stream) {
+  if (!h || !s || !X || !cell || !W_pred || !gap_pred || n < 1 || n >= (int64_t(1) << 31)) return R1_EINVAL;
+  r1_status rs = r1h::check_material(mat);
+  if (rs) return rs;
+  if (mat->dim != s->dim) return R1_EINVAL;
+  if (!s->trained) return R1_ENOTTRAINED;
+  if (hipSetDevice(h->device) != hipSuccess) return R1_EDEVICE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int dd = s->dim * s->dim;
+  rs = grow(s, al(sizeof(float) * size_t(n) * dd) + al(sizeof(float) * size_t(n)));
+  if (rs) return rs;
+  char* p = static_cast<char*>(s->ws);
+  float* Fs = reinterpret_cast<float*>(p); p += al(sizeof(float) * size_t(n) * dd);
+  float* bs = reinterpret_cast<float*>(p);
+  InferParams ip = infer_params(s, mat, n);
+  hipError_t e = r1m_unpack(s->dim, n, X, Fs, bs, st);
+  if (e == hipSuccess) e = r1m_infer(R1_F32, s->dim, ip, 1, Fs, bs, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                     cell, W_pred, gap_pred, st);
+  return e == hipSuccess ? R1_OK : r1h::fail(h, e, "surrogate predict");
+}
+
 r1_status r1_surrogate_calibrate(r1_handle h, r1_surrogate s, const r1_material* mat, const float* X,
                                  const float* Y, int64_t n, float tol, float quantile, int32_t* cells_allowed,
                                  void* stream) {
@@ -608,16 +632,41 @@ r1_status r1_surrogate_infer(r1_handle h, r1_surrogate s, const r1_material* mat
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int dd = s->dim * s->dim;
   const size_t ts = dtype == R1_F32 ? 4 : 8;
+  // workspace: fallback count and list, then (with the check) the candidates'
+  // count and list, which the fallback's compact arrays reuse after the check
+  const bool check = s->check_eps > 0.0f;
   size_t bytes = al(sizeof(int)) + al(sizeof(int32_t) * size_t(n));
+  if (check) bytes += al(sizeof(int)) + al(sizeof(int32_t) * size_t(n));
   rs = grow(s, bytes);
   if (rs) return rs;
   char* p = static_cast<char*>(s->ws);
   int* cnt = reinterpret_cast<int*>(p); p += al(sizeof(int));
-  int32_t* list = reinterpret_cast<int32_t*>(p);
+  int32_t* list = reinterpret_cast<int32_t*>(p); p += al(sizeof(int32_t) * size_t(n));
   InferParams ip = infer_params(s, mat, n);
+  CheckArgs ca{};
+  if (check) {
+    ip.cand_count = reinterpret_cast<int*>(p); p += al(sizeof(int));
+    ip.cand_list = reinterpret_cast<int32_t*>(p);
+    const r1_level* lvs[1] = {&fallback->level[0]};
+    rs = r1h::device_levels(h, lvs, 1, s->dim, &ca.lv);
+    if (rs) return rs;
+    ca.n = n;
+    ca.F = F;
+    ca.beta_n = beta_n;
+    ca.W = W;
+    ca.mat = ip.mat;
+    ca.eps = s->check_eps;
+    ca.n_off = r1_check_offsets(fallback->level[0].n_t, ca.off);
+    ca.list = ip.cand_list;
+    ca.count = ip.cand_count;
+    ca.fb_count = cnt;
+    ca.fb_list = list;
+  }
   hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int), st);
+  if (e == hipSuccess && check) e = hipMemsetAsync(ip.cand_count, 0, sizeof(int), st);
   if (e == hipSuccess)
     e = r1m_infer(dtype, s->dim, ip, 0, F, beta_n, W, P, flags, cnt, list, nullptr, nullptr, nullptr, st);
+  if (e == hipSuccess && check) e = r1_launch_check(dtype, ca, st);
   int nfb = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&nfb, cnt, sizeof(int), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -653,6 +702,21 @@ r1_status r1_surrogate_infer(r1_handle h, r1_surrogate s, const r1_material* mat
   if (rs) return rs;
   e = r1m_fb_scatter(dtype, s->dim, n, nfb, list, Wc, Pc, fc, W, P, flags, st);
   return e == hipSuccess ? R1_OK : r1h::fail(h, e, "fallback scatter");
+}
+
+r1_status r1_surrogate_check_offsets(int32_t n_t, int32_t* offsets, int32_t* count) {
+  if (!offsets || !count || n_t < 3 || n_t > R1_MAX_NT || (n_t % 2) == 0) return R1_EINVAL;
+  int off[kCheckMaxOffsets];
+  const int k = r1_check_offsets(n_t, off);
+  for (int i = 0; i < k; ++i) offsets[i] = off[i];
+  *count = k;
+  return R1_OK;
+}
+
+r1_status r1_surrogate_set_check(r1_surrogate s, float eps) {
+  if (!s || !(eps >= 0.0f) || !std::isfinite(eps)) return R1_EINVAL;
+  s->check_eps = eps;
+  return R1_OK;
 }
 
 r1_status r1_surrogate_save(r1_surrogate s, const char* path) {

@@ -146,6 +146,9 @@ def _load():
                                      ctypes.POINTER(TrainCfg), ctypes.POINTER(TrainReport), vp]
     L.r1_surrogate_calibrate.argtypes = [vp, vp, ctypes.POINTER(Material), vp, vp, i64, ctypes.c_float,
                                          ctypes.c_float, ctypes.POINTER(i32), vp]
+    L.r1_surrogate_predict.argtypes = [vp, vp, ctypes.POINTER(Material), vp, i64, vp, vp, vp, vp]
+    L.r1_surrogate_set_check.argtypes = [vp, ctypes.c_float]
+    L.r1_surrogate_check_offsets.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.r1_surrogate_infer.argtypes = [vp, vp, ctypes.POINTER(Material), ctypes.POINTER(Lamination), i64,
                                      i32, vp, vp, vp, vp, vp, ctypes.POINTER(i64), vp]
     L.r1_surrogate_param_count.argtypes = [vp, ctypes.POINTER(i64)]
@@ -156,7 +159,8 @@ def _load():
     L.r1_surrogate_save.argtypes = [vp, ctypes.c_char_p]
     L.r1_surrogate_load.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_char_p]
     for name in ("r1_surrogate_create", "r1_surrogate_destroy", "r1_surrogate_pack", "r1_surrogate_train",
-                 "r1_surrogate_calibrate", "r1_surrogate_infer", "r1_surrogate_param_count",
+                 "r1_surrogate_calibrate", "r1_surrogate_infer", "r1_surrogate_predict", "r1_surrogate_set_check",
+                 "r1_surrogate_check_offsets", "r1_surrogate_param_count",
                  "r1_surrogate_get_params", "r1_surrogate_set_params", "r1_surrogate_get_norm",
                  "r1_surrogate_loss_grad", "r1_surrogate_save", "r1_surrogate_load"):
         getattr(L, name).restype = i32
@@ -467,6 +471,16 @@ class BatchedPlan:
             pass
 
 
+def check_offsets(n_t):
+    """Sample offsets of the surrogate's a-posteriori check for lines of n_t points."""
+    buf = (ctypes.c_int32 * 32)()
+    cnt = ctypes.c_int32()
+    s = _lib.r1_surrogate_check_offsets(int(n_t), buf, ctypes.byref(cnt))
+    if s != 0:
+        raise R1Error(s, "r1_surrogate_check_offsets", "")
+    return np.array(buf[:cnt.value], dtype=np.int64)
+
+
 def tree_view(T):
     """(n, 3, 4) int32 tree tensor -> numpy arrays dir, i_minus, i_plus (int) and xi (float32)."""
     a = T.cpu().numpy()
@@ -525,6 +539,22 @@ class Surrogate:
                                                    X.shape[0], tol, quantile, ctypes.byref(out),
                                                    self.hd._stream(stream)), "r1_surrogate_calibrate")
         return out.value
+
+    def set_check(self, eps):
+        """A-posteriori check of served values (r1_surrogate_set_check); 0 turns it off."""
+        self.hd._check(_lib.r1_surrogate_set_check(self.s, ctypes.c_float(eps)), "r1_surrogate_set_check")
+
+    def predict(self, mat, X, stream=None):
+        """Raw network output on packed rows X (n, d_in): gate cell (-1 outside the
+        training box), predicted W and predicted gap, device tensors."""
+        torch = self.hd.torch
+        n = X.shape[0]
+        cell = torch.empty(n, dtype=torch.int32, device=X.device)
+        w = torch.empty(n, dtype=torch.float32, device=X.device)
+        g = torch.empty(n, dtype=torch.float32, device=X.device)
+        self.hd._check(_lib.r1_surrogate_predict(self.hd.h, self.s, ctypes.byref(mat), _ptr(X), n, _ptr(cell),
+                                                 _ptr(w), _ptr(g), self.hd._stream(stream)), "r1_surrogate_predict")
+        return cell, w, g
 
     def infer(self, mat, fallback_spec, F, beta_n, stream=None, out=None):
         torch = self.hd.torch

@@ -25,6 +25,23 @@ def lib():
     h.close()
 
 
+# Element-wise bounds, in BF16 units (2^-8 relative) of an entry plus its layer's
+# mean entry (gradients) or of the output's standard deviation (inference).
+# Measured worst gradient entries: 2.6 (width 32), 5.2 (128), 8.0 (256) units,
+# growing like the square root of the width (the sums each rounding enters).
+def grad_bf16_units(width):
+    return 4.0 * np.sqrt(width / 32.0)
+
+
+# Outputs of the fused inference against the FP64 forward of the same network
+# (BF16 hidden weights): measured worst 0.45 units on served points of the 2D and
+# 3D networks, 6.3 on the raw predicted gap of every point of a batch (including
+# points far outside the serving region, where a trained network's activations
+# are large).
+INFER_BF16_UNITS = 2.0
+PREDICT_BF16_UNITS = 10.0
+
+
 def bf16_round(a):
     """Round FP32 values to BF16 (round to nearest even), as the matrix cores see them."""
     a = np.ascontiguousarray(a, dtype=np.float32)
@@ -40,6 +57,15 @@ def hidden_blocks(d_in, width, n_hidden, d_out):
         out.append((o, o + width * width))
         o += width * width + width
     return out
+
+
+def matrix_core_params(s, shape):
+    """The network as the GPU runs it: FP64 copy of the master weights with the
+    width x width blocks rounded to BF16."""
+    p = s.get_params().astype(np.float64)
+    for a, b in hidden_blocks(*shape):
+        p[a:b] = bf16_round(p[a:b])
+    return p
 
 
 @pytest.mark.parametrize("dim,width", [(2, 32), (2, 128), (3, 256)])
@@ -61,19 +87,28 @@ def test_gradients_match_fp64_oracle(lib, dim, width):
     g_g = g_g.cpu().numpy().astype(np.float64)
     loss_c, g_c = O.mlp_loss_grad(shape, p_bf, Xn.astype(np.float64), Yn.astype(np.float64))
     rel = np.linalg.norm(g_g - g_c) / np.linalg.norm(g_c)
-    print("dim %d width %d: loss gpu %.6f cpu %.6f, gradient rel err %.3e" % (dim, width, loss_g, loss_c, rel))
     assert abs(loss_g - loss_c) <= 1e-2 * abs(loss_c)
-    assert rel < 2e-2
+    assert rel < 2e-3
     # every layer's gradient points the same way
     offs = [0]
     for l in range(5):
         n_in = d if l == 0 else width
         n_out = d if l == 4 else width
         offs.append(offs[-1] + n_out * n_in + n_out)
+    # element by element: the GPU rounds the activations entering each matrix-core
+    # layer to BF16 (relative 2^-9) and the oracle does not, so each entry may differ
+    # by a few BF16 units of its own size plus a few of its layer's typical entry
+    worst = 0.0
     for l in range(5):
         a, b = offs[l], offs[l + 1]
+        scale = np.mean(np.abs(g_c[a:b]))
+        r = np.abs(g_g[a:b] - g_c[a:b]) / (2.0 ** -8 * (np.abs(g_c[a:b]) + scale))
+        worst = max(worst, r.max())
         cos = g_g[a:b] @ g_c[a:b] / (np.linalg.norm(g_g[a:b]) * np.linalg.norm(g_c[a:b]))
-        assert cos > 0.999, (l, cos)
+        assert cos > 0.99999, (l, cos)
+    print("dim %d width %d: loss gpu %.6f cpu %.6f, gradient rel err %.3e, worst entry %.2f BF16 units"
+          % (dim, width, loss_g, loss_c, rel, worst))
+    assert worst <= grad_bf16_units(width)
     s.close()
 
 
@@ -101,10 +136,10 @@ def trained(lib):
     rep = s.train(mat, X, Y, epochs=150, batch=4096, lr=2e-3, seed=2)
     print("training: 1 epoch loss %.4e / val %.4e; +150 epochs loss %.4e / val %.4e (%d steps, %.0f ms)" % (
         rep1["train_loss"], rep1["val_loss"], rep["train_loss"], rep["val_loss"], rep["steps"], rep["ms"]))
-    cal = WL.config4_training(n=65536, seed_tag=61)
+    cal = WL.config4_training(n=262144, seed_tag=61)
     Fc, bc, oc = laminate(lib, cal["F"], cal["beta_n"], cal["levels"], torch.float32)
     Xc, Yc = s.pack(Fc, bc, oc["W"], oc["P"])
-    allowed = s.calibrate(mat, Xc, Yc, tol=1e-3, quantile=0.99)
+    allowed = s.calibrate(mat, Xc, Yc, tol=2.5e-4, quantile=1.0)
     print("calibration: %d of %d gate cells with a threshold" % (allowed, 16 * 8))
     yield s, rep1, rep, allowed, cfg["levels"]
     s.close()
@@ -115,6 +150,29 @@ def test_training_reduces_loss(trained):
     assert rep["val_loss"] < 0.5 * rep1["val_loss"]
     assert rep["train_loss"] < 0.5 * rep1["train_loss"]
     assert allowed > 0
+
+
+def test_prediction_matches_oracle_forward_at_every_point(lib, trained):
+    """The network's raw predicted gap (r1_surrogate_predict, no gate) equals the FP64
+    network oracle's forward on the same standardized inputs at every point of a
+    batch, element by element to PREDICT_BF16_UNITS BF16 units of the output's spread."""
+    r1, h, torch = lib
+    s, _, _, _, levels = trained
+    cfg = WL.config4_training(n=4096, seed_tag=67)
+    Ft, bt, out = laminate(lib, cfg["F"], cfg["beta_n"], levels, torch.float32)
+    X, _ = s.pack(Ft, bt, out["W"], out["P"])
+    cell, wp, gp = s.predict(r1.material(), X)
+    torch.cuda.synchronize()
+    nm = s.norm()
+    params = matrix_core_params(s, (5, 128, 4, 5))
+    x = X.cpu().numpy()
+    xn = (x - nm["x_mean"]) / nm["x_std"]
+    y, _ = O.mlp_forward((5, 128, 4, 5), params, xn.astype(np.float64))
+    g_ref = y[:, 0] * nm["y_std"][0] + nm["y_mean"][0]
+    u = np.abs(gp.cpu().numpy() - g_ref) / (2.0 ** -8 * nm["y_std"][0])
+    print("predicted gap vs network oracle at %d points: within %.2f BF16 units of y_std" % (len(u), u.max()))
+    assert u.max() <= PREDICT_BF16_UNITS
+    assert np.all(cell.cpu().numpy() >= 0)          # training-distribution rows lie in the box
 
 
 def test_inference_matches_oracle_forward(lib, trained):
@@ -132,7 +190,7 @@ def test_inference_matches_oracle_forward(lib, trained):
     ok = np.nonzero((fl & r1.PT_FALLBACK) == 0)[0][:256]
     assert len(ok) > 50
     nm = s.norm()
-    params = s.get_params().astype(np.float64)
+    params = matrix_core_params(s, (5, 128, 4, 5))
     Fi, bi = Ft.double().cpu().numpy(), bt.double().cpu().numpy()
     x = np.concatenate([Fi[:, ok].T, bi[ok, None]], axis=1)
     xn = (x.astype(np.float32) - nm["x_mean"]) / nm["x_std"]
@@ -150,19 +208,26 @@ def test_inference_matches_oracle_forward(lib, trained):
     near = np.abs(y[:, 0]) < 0.02 * nm["y_std"][0]
     far = ~near
     assert far.sum() > 40
-    assert np.max(np.abs(Wg - W_ref)[far]) < 0.02 * nm["y_std"][0] + 1e-6
-    assert np.max(np.abs(Pg - P_ref)[far]) < 0.02 * np.max(nm["y_std"][1:]) + 1e-6
+    uw = np.abs(Wg - W_ref)[far] / (2.0 ** -8 * nm["y_std"][0])
+    up = np.abs(Pg - P_ref)[far] / (2.0 ** -8 * nm["y_std"][1:][None, :])
+    print("2d inference vs network oracle: %d points, W within %.2f, P within %.2f BF16 units of y_std"
+          % (far.sum(), uw.max(), up.max()))
+    assert uw.max() <= INFER_BF16_UNITS and up.max() <= INFER_BF16_UNITS
 
 
 def test_routing_fallback_and_accuracy(lib, trained):
     """Inference points from the inference distribution (beta_n up to 1.1, a wider F
-    spread): out-of-box points fall back and equal plain lamination exactly; accepted
-    points are within the calibrated 1e-3 relative energy error of plain lamination."""
+    spread), with the a-posteriori check on: out-of-box points fall back and equal
+    plain lamination exactly; every served point is within 1e-3 relative energy
+    error (|W| floored at 1e-2) of FP64 plain lamination."""
     r1, h, torch = lib
     s, _, _, _, levels = trained
     cfg = WL.config4_inference(n=32768, seed_tag=63)
     Ft, bt, plain = laminate(lib, cfg["F"], cfg["beta_n"], levels, torch.float32)
+    _, _, p64 = laminate(lib, cfg["F"], cfg["beta_n"], levels, torch.float64)
+    s.set_check(5e-4)
     out = s.infer(r1.material(), r1.LaminationSpec(levels), Ft, bt)
+    s.set_check(0.0)
     torch.cuda.synchronize()
     fl = out["flags"].cpu().numpy()
     fb = (fl & r1.PT_FALLBACK) != 0
@@ -173,12 +238,12 @@ def test_routing_fallback_and_accuracy(lib, trained):
     bi = bt.cpu().numpy()
     assert np.all(fb[bi > 1.0])                     # beta_n outside the training range
     acc = ~fb
-    err = np.abs(Wg[acc] - Wp[acc]) / np.maximum(np.abs(Wp[acc]), 1e-2)
-    print("fallback %.1f%%, accepted: max rel err %.2e, p99 %.2e, frac > 1e-3: %.4f" % (
-        100 * fb.mean(), err.max(), np.percentile(err, 99), np.mean(err > 1e-3)))
+    W64 = p64["W"].cpu().numpy()
+    err = np.abs(Wg[acc] - W64[acc]) / np.maximum(np.abs(W64[acc]), 1e-2)
+    print("fallback %.1f%%, served: max rel err %.2e, p99 %.2e" % (100 * fb.mean(), err.max(),
+                                                                    np.percentile(err, 99)))
     assert acc.sum() > 0.2 * len(fl)
-    assert np.mean(err > 1e-3) < 0.01
-    assert np.all(Wg[acc] <= (Wp[acc] + 1e-2 * np.maximum(np.abs(Wp[acc]), 1e-2)) + 1.0)  # finite, sane
+    assert err.max() <= 1e-3
 
 
 def test_save_load_roundtrip(lib, trained):
@@ -257,7 +322,7 @@ def test_3d_inference_matches_oracle_forward(lib, width):
     ok = np.nonzero((fl & r1.PT_FALLBACK) == 0)[0][:256]
     assert len(ok) > 100
     nm = s.norm()
-    params = s.get_params().astype(np.float64)
+    params = matrix_core_params(s, (10, width, 4, 10))
     Fn, bn = Fi.double().cpu().numpy(), bi.double().cpu().numpy()
     x = np.concatenate([Fn[:, ok].T, bn[ok, None]], axis=1)
     xn = (x.astype(np.float32) - nm["x_mean"]) / nm["x_std"]
@@ -272,11 +337,70 @@ def test_3d_inference_matches_oracle_forward(lib, width):
     Pg = res["P"].cpu().numpy()[:, ok].T
     near = np.abs(y[:, 0]) < 0.02 * nm["y_std"][0]
     far = ~near
-    err_w = np.max(np.abs(Wg - W_ref)[far])
-    err_p = np.max(np.abs(Pg - P_ref)[far])
-    print("3d width %d: %d accepted points, max |dW| %.2e, max |dP| %.2e (y_std %.2e)" % (
-        width, far.sum(), err_w, err_p, nm["y_std"][0]))
+    uw = np.abs(Wg - W_ref)[far] / (2.0 ** -8 * nm["y_std"][0])
+    up = np.abs(Pg - P_ref)[far] / (2.0 ** -8 * nm["y_std"][1:][None, :])
+    print("3d width %d: %d accepted points, W within %.2f, P within %.2f BF16 units of y_std"
+          % (width, far.sum(), uw.max(), up.max()))
     assert far.sum() > 80
-    assert err_w < 0.02 * nm["y_std"][0] + 1e-6
-    assert err_p < 0.02 * np.max(nm["y_std"][1:]) + 1e-6
+    assert uw.max() <= INFER_BF16_UNITS and up.max() <= INFER_BF16_UNITS
+    s.close()
+
+
+def test_check_sends_exactly_the_points_with_a_low_subset_chord(lib, trained):
+    """The a-posteriori check against its definition, evaluated with the FP64 oracle's W
+    along the fallback's directions at the check's sample offsets: of the points the
+    gates serve, those with a chord of subset samples more than eps max(|w|, 0.01)
+    below the served value w go to the fallback, the others stay (decisions within
+    rounding of the criterion are not compared)."""
+    r1, h, torch = lib
+    _, _, _, _, levels = trained
+    # an uncalibrated network (box gate only) serves laminating points too, so the
+    # check has work to do
+    tr = WL.config4_training(n=65536, seed_tag=68)
+    Ftr, btr, otr = laminate(lib, tr["F"], tr["beta_n"], levels, torch.float32)
+    s = r1.Surrogate(h, dim=2, n_hidden=4, width=128, seed=7)
+    Xtr, Ytr = s.pack(Ftr, btr, otr["W"], otr["P"])
+    s.train(r1.material(), Xtr, Ytr, epochs=20, batch=4096, lr=2e-3, seed=3)
+    cfg = WL.config4_inference(n=8192, seed_tag=66)
+    Ft = torch.tensor(cfg["F"], dtype=torch.float32, device="cuda").contiguous()
+    bt = torch.tensor(cfg["beta_n"], dtype=torch.float32, device="cuda").contiguous()
+    mat, spec = r1.material(), r1.LaminationSpec(levels)
+    eps = 5e-4
+    s.set_check(0.0)
+    a = s.infer(mat, spec, Ft, bt)
+    s.set_check(eps)
+    b = s.infer(mat, spec, Ft, bt)
+    s.set_check(0.0)
+    torch.cuda.synchronize()
+    served0 = (a["flags"].cpu().numpy() & r1.PT_FALLBACK) == 0
+    served1 = (b["flags"].cpu().numpy() & r1.PT_FALLBACK) == 0
+    assert not np.any(served1 & ~served0)
+    W0 = a["W"].cpu().numpy().astype(np.float64)
+    lv = levels[0]
+    c = (lv["n_t"] - 1) // 2
+    offs = r1.check_offsets(lv["n_t"])
+    assert offs[0] == 1 and offs[-1] == c and len(offs) <= 32
+    om = O.material(dim=2)
+    Fn, bn = Ft.double().cpu().numpy(), bt.double().cpu().numpy()
+    n_rej = n_keep = n_skip = 0
+    for p in np.nonzero(served0)[0][:1500]:
+        G = Fn[:, p].reshape(2, 2)
+        T = W0[p] - eps * max(abs(W0[p]), 0.01)
+        crit = np.inf
+        for m in range(len(lv["a"])):
+            R = np.outer(lv["a"][m], lv["b"][m])
+            lo = min((O.energy(om, G - lv["tau"] * o / c * R, bn[p]) - T) / o for o in offs)
+            hi = min((O.energy(om, G + lv["tau"] * o / c * R, bn[p]) - T) / o for o in offs)
+            crit = min(crit, lo + hi)
+        if abs(crit) < 1e-5 * max(abs(W0[p]), 0.01):
+            n_skip += 1
+            continue
+        if crit < 0:
+            n_rej += 1
+            assert not served1[p], (p, crit)
+        else:
+            n_keep += 1
+            assert served1[p], (p, crit)
+    print("check: %d kept, %d sent to the fallback, %d within rounding of the criterion" % (n_keep, n_rej, n_skip))
+    assert n_keep > 100 and n_rej > 50
     s.close()
