@@ -105,7 +105,7 @@ def cpu_baseline(workers):
     wall = time.time() - t0
     per = [r[1] for r in res]
     w_per_point = w_samples_outer_kernel(_cfg2_shape()) / 4096.0
-    base = dict(value=workers / wall, unit="QP/s", cores=workers, kind="oracle",
+    base = dict(value=workers / wall, unit="QP/s", cores=workers, nproc=os.cpu_count(), kind="oracle",
                 sample="first %d points of the workload, one point per process (energy, stress and "
                        "tree, FP64 serial oracle), %.1f s wall, %.1f s per point" %
                        (workers, wall, sum(per) / len(per)),
@@ -204,16 +204,11 @@ def leg_surrogate(h, r1, WL, torch, np, n_train=2_000_000, n_cal=2_000_000, n_in
     acc = ~fb
     Wp = W.cpu().numpy()
     Ws = so["W"].cpu().numpy()
-    # the FP64 oracle on a subset of the inference points
-    from oracle import oracle as O
-    n_o = 2000
-    lv = inf["levels"][0]
-    om = O.material(dim=2)
-    ospec = O.LaminationSpec([(lv["a"], lv["b"], lv["n_t"], lv["tau"])])
-    Wo, _, _ = O.envelope_batch(om, ospec, Fi[:, :n_o].double().cpu().numpy(), bi[:n_o].double().cpu().numpy(),
-                                want_stress=False)
-    eo = np.abs(Ws[:n_o] - Wo) / np.maximum(np.abs(Wo), 1e-2)
-    acc_o = acc[:n_o]
+    # stored FP64 oracle values at the first inference points
+    Wo, sel = golden_energies("config4_infer_oracle_f32in.json", inf)
+    n_o = len(sel)
+    eo = np.abs(Ws[sel] - Wo) / np.maximum(np.abs(Wo), 1e-2)
+    acc_o = acc[sel]
     s.close()
     return {
         "workload": "surrogate-2d: train 2M rows (16 dirs x 201 pts, k=1), infer 1M points",
@@ -288,6 +283,104 @@ def leg_surrogate_3d(h, r1, WL, torch, np, n_train=1_000_000, n_cal=1_000_000, e
     }
 
 
+def load_golden(name):
+    """Stored FP64 oracle values (tests/golden/, written by make_oracle_golden.py from the
+    oracle alone): the points with p, F, beta_n, W, P and tree."""
+    with open(os.path.join(ROOT, "tests", "golden", name)) as f:
+        d = json.load(f)
+    return d["points"]
+
+
+def golden_error(W_gpu, tree_gpu, pts, floor):
+    """Energy error of GPU results at stored oracle points, relative with |W| floored, and
+    how many of the points have the oracle's tree."""
+    import numpy as np
+    sel = np.array([q["p"] for q in pts])
+    Wo = np.array([float(q["W"]) for q in pts])
+    e = np.abs(W_gpu[sel] - Wo) / np.maximum(np.abs(Wo), floor)
+    same = sum(all(list(tree_gpu[q["p"], k, :3]) == q["tree"][k] for k in range(len(q["tree"]))) for q in pts)
+    return {"n": int(len(pts)), "energy_max": float(e.max()), "energy_p50": float(np.median(e)),
+            "erel_floor": floor, "same_tree": int(same)}
+
+
+def golden_energies(name, cfg):
+    """Stored oracle energies W[p] for the points p of a workload (FP32-rounded inputs), after
+    checking that the workload generator still draws the inputs they were computed at."""
+    import hashlib
+    import numpy as np
+    with open(os.path.join(ROOT, "tests", "golden", name)) as f:
+        d = json.load(f)
+    sel = np.array([q["p"] for q in d["points"]])
+    fp = hashlib.sha256(np.float32(cfg["F"][:, sel]).tobytes() +
+                        np.float32(cfg["beta_n"][sel]).tobytes()).hexdigest()[:16]
+    if fp != d["inputs_sha256_16"]:
+        raise RuntimeError("%s was computed for other inputs than the workload generator draws" % name)
+    return np.array([float(q["W"]) for q in d["points"]]), sel
+
+
+def w_samples_depth1(n, lv):
+    return n * (len(lv["a"]) * (lv["n_t"] - 1) + 1)
+
+
+def leg_plain_2d(h, r1, WL, torch, np, reps=10):
+    """Depth 1, 16 directions x 201 points (the surrogate's fallback lamination), on the
+    1M inference points of the surrogate workload, with stress: one-level kernel alone."""
+    cfg = WL.config4_inference(n=1_000_000)
+    mat = r1.material()
+    spec = r1.LaminationSpec(cfg["levels"])
+    n = cfg["n"]
+    F = torch.tensor(cfg["F"], dtype=torch.float32, device="cuda").contiguous()
+    bn = torch.tensor(cfg["beta_n"], dtype=torch.float32, device="cuda").contiguous()
+    W = torch.empty(n, device="cuda")
+    P = torch.empty((4, n), device="cuda")
+    h.envelope_into(mat, spec, F, bn, W, P)
+    torch.cuda.synchronize()
+    h.timing(True)
+    h.timing_reset()
+    t = timed(lambda: h.envelope_into(mat, spec, F, bn, W, P), reps, torch)
+    ms, cnt = h.timing_query("depth1")
+    h.timing(False)
+    avg_s = ms / max(cnt, 1) / 1e3
+    ws = w_samples_depth1(n, cfg["levels"][0])
+    ach = FLOPS_PER_W * ws / avg_s / 1e12
+    return {"workload": "plain-2d-n%d-16x201-k1 (stress on)" % n, "qps": round(n / t, 1), "ms": round(1e3 * t, 3),
+            "roofline": dict(bound="alu", kernel="k_depth1", avg_ms=round(1e3 * avg_s, 4), achieved=round(ach, 2),
+                             unit="TFLOP/s", peak=PEAK["f32"], frac=round(ach / PEAK["f32"], 4),
+                             peak_nonpacked=PEAK_NONPACKED["f32"], frac_nonpacked=round(ach / PEAK_NONPACKED["f32"], 4),
+                             w_samples_per_launch=ws, flops_per_w=FLOPS_PER_W),
+            "all_finite": bool(torch.isfinite(W).all().item())}
+
+
+def leg_headline_f64(h, r1, WL, torch, np):
+    """The depth-2 workload in FP64, once, against the 64 stored FP64 oracle points."""
+    cfg = WL.config2()
+    n = cfg["n"]
+    mat = r1.material_from(cfg["material"], 2)
+    spec = r1.LaminationSpec(cfg["levels"])
+    dt = torch.float64
+    F = torch.tensor(cfg["F"], dtype=dt, device="cuda").contiguous()
+    bn = torch.tensor(cfg["beta_n"], dtype=dt, device="cuda").contiguous()
+    W = torch.empty(n, dtype=dt, device="cuda")
+    P = torch.empty((4, n), dtype=dt, device="cuda")
+    T = torch.empty((n, 3, 4), dtype=torch.int32, device="cuda")
+    h.timing(True)
+    h.timing_reset()
+    t0 = time.perf_counter()
+    h.envelope_into(mat, spec, F, bn, W, P, T)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    ms, cnt = h.timing_query("outer")
+    h.timing(False)
+    avg_s = ms / max(cnt, 1) / 1e3
+    ach = FLOPS_PER_W * w_samples_outer_kernel(cfg) / avg_s / 1e12
+    err = golden_error(W.cpu().numpy(), T.cpu().numpy(), load_golden("config2_oracle_f64.json"), 1e-3)
+    return {"workload": cfg["name"] + " in FP64", "qps": round(n / t, 2), "ms": round(1e3 * t, 1),
+            "roofline": dict(bound="alu", kernel="k_outer", avg_ms=round(1e3 * avg_s, 2), achieved=round(ach, 3),
+                             unit="TFLOP/s", peak=PEAK["f64"], frac=round(ach / PEAK["f64"], 4),
+                             flops_per_w=FLOPS_PER_W),
+            "error_vs_fp64_oracle": err}
+
+
 def leg_batched(h, r1, WL, torch, np):
     """Config 3: 65,536 points, per point n_t in {257..2049}, 32/64/128 directions, depth 1 or 2."""
     cfg = WL.config3()
@@ -313,15 +406,24 @@ def leg_batched(h, r1, WL, torch, np):
         else:
             wsum += cnt * len(lv[0]["a"]) * (lv[0]["n_t"] - 1) * (len(lv[1]["a"]) * (lv[1]["n_t"] - 1) + 1)
     W = out["W"].cpu().numpy()
+    # the graph replay, timed by the host clock between synchronizations (10 s of
+    # device work against microseconds of host work)
+    ach = FLOPS_PER_W * wsum / t / 1e12
+    plan.close()
     return {"workload": cfg["name"] + " (uneven n_t/n_dir/depth, one persistent graph launch)",
             "qps": round(cfg["n"] / t, 1), "ms": round(1e3 * t, 1), "w_samples": int(wsum),
             "w_samples_per_s": float(wsum / t), "first_call_ms": round(1e3 * t_first, 1),
+            "roofline": dict(bound="alu", kernel="graph (k_bpoint, k_bouter, k_bfinal)", avg_ms=round(1e3 * t, 1),
+                             achieved=round(ach, 2), unit="TFLOP/s", peak=PEAK["f32"], frac=round(ach / PEAK["f32"], 4),
+                             peak_nonpacked=PEAK_NONPACKED["f32"],
+                             frac_nonpacked=round(ach / PEAK_NONPACKED["f32"], 4), flops_per_w=FLOPS_PER_W),
+            "error_vs_fp64_oracle": golden_error(W.astype(np.float64), out["tree"].cpu().numpy(),
+                                                 load_golden("config3_oracle_f32in.json"), 1e-2),
             "all_finite": bool(np.isfinite(W).all())}
 
 
-def leg_3d(h, r1, WL, torch, np, n_check=64):
+def leg_3d(h, r1, WL, torch, np):
     """Config 5: 262,144 3D points, 256 directions (Fibonacci x Fibonacci), 513 points."""
-    from oracle import oracle as O
     cfg = WL.config5()
     mat = r1.material(dim=3)
     spec = r1.LaminationSpec(cfg["levels"])
@@ -332,15 +434,23 @@ def leg_3d(h, r1, WL, torch, np, n_check=64):
     P = torch.empty((9, n), device="cuda")
     lv = cfg["levels"][0]
     lanes = h.autotune(mat, lv["n_t"], r1.R1_F32)              # untimed, as a caller would once
+    h.envelope_into(mat, spec, F, bn, W, P)
+    torch.cuda.synchronize()
+    h.timing(True)
+    h.timing_reset()
     t = timed(lambda: h.envelope_into(mat, spec, F, bn, W, P), 3, torch)
-    om = O.material(dim=3)
-    ospec = O.LaminationSpec([(lv["a"], lv["b"], lv["n_t"], lv["tau"])])
-    sel = np.linspace(0, n - 1, n_check).astype(int)
-    Fin = F.double().cpu().numpy()
-    bin_ = bn.double().cpu().numpy()
-    Wo, _, _ = O.envelope_batch(om, ospec, Fin[:, sel], bin_[sel], want_stress=False)
+    ms, cnt = h.timing_query("depth1")
+    h.timing(False)
+    avg_s = ms / max(cnt, 1) / 1e3
+    ws = w_samples_depth1(n, lv)
+    ach = FLOPS_PER_W * ws / avg_s / 1e12
+    Wo, sel = golden_energies("config5_oracle_f32in.json", cfg)
     return {"workload": cfg["name"], "qps": round(n / t, 1), "ms": round(1e3 * t, 2), "lanes_per_line": lanes,
-            "w_samples_per_s": float(n * len(lv["a"]) * (lv["n_t"] - 1) / t),
+            "w_samples_per_s": float(ws / t),
+            "roofline": dict(bound="alu", kernel="k_depth1", avg_ms=round(1e3 * avg_s, 3), achieved=round(ach, 2),
+                             unit="TFLOP/s", peak=PEAK["f32"], frac=round(ach / PEAK["f32"], 4),
+                             peak_nonpacked=PEAK_NONPACKED["f32"], frac_nonpacked=round(ach / PEAK_NONPACKED["f32"], 4),
+                             w_samples_per_launch=ws, flops_per_w=FLOPS_PER_W),
             "erel_vs_oracle": erel_stats(W.cpu().numpy()[sel], Wo, floor=1e-2)}
 
 
@@ -529,7 +639,8 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
-    ap.add_argument("--leg", choices=["surrogate", "batched", "plain_3d", "surrogate_3d", "stvk", "tangent", "grid"],
+    ap.add_argument("--leg", choices=["surrogate", "batched", "plain_3d", "plain_2d", "headline_f64", "surrogate_3d",
+                                      "stvk", "tangent", "grid"],
                     help="only run this secondary leg and print its result (a profiling aid)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -552,8 +663,9 @@ def main():
         return
 
     if args.leg:
-        legs = dict(surrogate=leg_surrogate, batched=leg_batched, plain_3d=leg_3d,
-                    surrogate_3d=leg_surrogate_3d, stvk=leg_stvk, tangent=leg_tangent, grid=leg_grid)
+        legs = dict(surrogate=leg_surrogate, batched=leg_batched, plain_3d=leg_3d, plain_2d=leg_plain_2d,
+                    headline_f64=leg_headline_f64, surrogate_3d=leg_surrogate_3d, stvk=leg_stvk,
+                    tangent=leg_tangent, grid=leg_grid)
         h = r1.Handle(0)
         res = legs[args.leg](h, r1, WL, torch, np)
         print(json.dumps({"leg": args.leg, **res}))
@@ -625,7 +737,15 @@ def main():
         "roofline": roof,
     }
     log("headline: %.1f QP/s, k_outer %.3f ms (%.1f%% of peak)" % (value, roof["avg_ms"], 100 * roof["frac"]))
+    if args.dtype == "f32":
+        out["error_vs_stored_oracle"] = golden_error(Wn, T.cpu().numpy(), load_golden("config2_oracle_f32in.json"),
+                                                     1e-2)
     if not args.quick:
+        out["headline_f64"] = leg_headline_f64(h, r1, WL, torch, np)
+        log("headline in FP64: %.1f QP/s, k_outer %.3f%% of peak" % (out["headline_f64"]["qps"],
+                                                                     100 * out["headline_f64"]["roofline"]["frac"]))
+        out["plain_2d"] = leg_plain_2d(h, r1, WL, torch, np)
+        log("plain 2d depth-1 leg: %.1f QP/s" % out["plain_2d"]["qps"])
         out["surrogate"] = leg_surrogate(h, r1, WL, torch, np)
         log("surrogate leg: speedup %.3f, fallback %.3f" % (out["surrogate"]["speedup"],
                                                          out["surrogate"]["fallback_frac"]))
@@ -645,7 +765,7 @@ def main():
                                                             out["surrogate_3d"]["fallback_frac"]))
     h.close()
     if not args.no_cpu_baseline:
-        workers = min(16, os.cpu_count() or 1)
+        workers = os.cpu_count() or 1          # every host core: one oracle point per process
         log("cpu baseline: %d oracle processes" % workers)
         base, ref = cpu_baseline(workers)
         out["cpu_baseline"] = base

@@ -13,6 +13,10 @@ Outputs (JSON; floats written with repr, so they read back exactly):
                             (the inputs the FP32 path reads)
   config3_oracle_f32in.json the uneven batch (65,536 points, 24 table entries):
                             the first 2 points of every entry at FP32-rounded inputs
+  config4_infer_oracle_f32in.json  W^1 at the first 2000 of the surrogate's 1M inference
+                            points (16 directions x 201 points, depth 1), FP32-rounded inputs
+  config5_oracle_f32in.json W^1 at 64 evenly spaced points of the 3D workload (262,144
+                            points, 256 directions x 513 points), FP32-rounded inputs
 Each point takes the oracle's full two-level recursion (about 40 s of one core for
 the depth-2 workload), so the script runs a process pool.
 """
@@ -37,6 +41,22 @@ CONFIG2_SEED = 20221128
 CONFIG2_N64 = 64
 CONFIG2_N32 = 32
 CONFIG3_PER_ENTRY = 2
+CONFIG4_N = 2000
+CONFIG5_N = 64
+
+
+def _energy(args):
+    dim, mat_d, levels, F, bn = args
+    mat = O.material(dim=dim, mu=mat_d["mu"], lam=mat_d["lam"], D_inf=mat_d["D_inf"], D0=mat_d["D0"])
+    spec = O.LaminationSpec([(l["a"], l["b"], l["n_t"], l["tau"]) for l in levels])
+    W, _, _ = O.envelope(mat, spec, np.asarray(F, dtype=np.float64).reshape(dim, dim), float(bn))
+    return W
+
+
+def inputs_fingerprint(F, bn):
+    """sha256 (16 hex digits) of the FP32-rounded inputs, to detect a changed generator."""
+    import hashlib
+    return hashlib.sha256(np.float32(F).tobytes() + np.float32(bn).tobytes()).hexdigest()[:16]
 
 
 def _point(args):
@@ -89,7 +109,7 @@ def config3_sample(cfg):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workers", type=int, default=os.cpu_count() or 8)
-    ap.add_argument("--only", choices=["config2", "config3"], default=None)
+    ap.add_argument("--only", choices=["config2", "config3", "config4", "config5"], default=None)
     args = ap.parse_args()
     cmd = "python tests/golden/make_oracle_golden.py"
     cite = ("FP64 oracle (oracle/*.c): successive lamination of eq. 3.3 along the discrete lines of "
@@ -124,6 +144,24 @@ def main():
                        per_entry=CONFIG3_PER_ENTRY)
             _dump(os.path.join(HERE, "config3_oracle_f32in.json"), hdr, pts)
             print("config3: %d points, %.0f s" % (len(pts), time.time() - t0), flush=True)
+        for tag in ("config4", "config5"):
+            if args.only not in (None, tag):
+                continue
+            if tag == "config4":
+                cfg = WL.config4_inference(n=1_000_000)
+                sel = np.arange(CONFIG4_N)
+            else:
+                cfg = WL.config5()
+                sel = np.linspace(0, cfg["n"] - 1, CONFIG5_N).astype(int)
+            dim = cfg["dim"]
+            Fs, bs = cfg["F"][:, sel], cfg["beta_n"][sel]
+            jobs = [(dim, cfg["material"], cfg["levels"], _f32(Fs[:, k]), _f32(bs[k])) for k in range(len(sel))]
+            W = list(ex.map(_energy, jobs, chunksize=16))
+            hdr = dict(workload=cfg["name"], source=cite, command=cmd, inputs="FP32-rounded",
+                       inputs_sha256_16=inputs_fingerprint(Fs, bs))
+            _dump(os.path.join(HERE, "%s_oracle_f32in.json" % ("config4_infer" if tag == "config4" else tag)), hdr,
+                  [dict(p=int(p), W=float(w)) for p, w in zip(sel, W)])
+            print("%s: %d points, %.0f s" % (tag, len(sel), time.time() - t0), flush=True)
 
 
 if __name__ == "__main__":
