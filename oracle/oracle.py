@@ -14,7 +14,16 @@ import subprocess
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB = os.path.join(HERE, "liboracle.so")
+LIB_PLAIN = os.path.join(HERE, "liboracle.so")
+LIB_SAN = os.path.join(HERE, "liboracle_san.so")
+# R1_ORACLE_SANITIZE=1 loads the build under AddressSanitizer and UndefinedBehaviorSanitizer
+# (build(sanitize=True)); the process must have the sanitizer runtime preloaded.
+LIB = LIB_SAN if os.environ.get("R1_ORACLE_SANITIZE") == "1" else LIB_PLAIN
+# sanitized build: the ROCm clang, so that one shared runtime serves it and the library's
+# sanitized build in the same process
+SAN_CC = "/opt/rocm/llvm/bin/clang"
+SAN_FLAGS = ["-fsanitize=address,undefined", "-shared-libsan", "-fno-sanitize-recover=undefined",
+             "-fno-omit-frame-pointer", "-g"]
 SOURCES = ["energy.c", "hull.c", "lamination.c", "mlp.c", "grid.c", "path.c"]
 
 MODEL_NH_DAMAGE = 0
@@ -23,16 +32,18 @@ MODEL_STVK_DAMAGE = 2
 TREE_NODES = 3
 
 
-def build(force=True):
-    """Compile the oracle with plain -O2 (no fast-math) against glibc libm."""
-    if not force and os.path.exists(LIB):
-        return LIB
+def build(force=True, sanitize=False):
+    """Compile the oracle with plain -O2 (no fast-math) against glibc libm; with
+    sanitize=True, liboracle_san.so under AddressSanitizer and UndefinedBehaviorSanitizer."""
+    out = LIB_SAN if sanitize else LIB_PLAIN
+    if not force and os.path.exists(out):
+        return out
     srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
-    cmd = ["gcc", "-O2", "-fno-fast-math", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC",
-           "-o", LIB + ".tmp"] + srcs + ["-lm"]
+    cmd = [SAN_CC if sanitize else "gcc", "-O2", "-fno-fast-math", "-std=c99", "-Wall", "-Wextra", "-shared",
+           "-fPIC", "-o", out + ".tmp"] + (SAN_FLAGS if sanitize else []) + srcs + ["-lm"]
     subprocess.check_call(cmd)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 class Material(ctypes.Structure):
@@ -63,7 +74,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB):
-            build()
+            build(sanitize=LIB == LIB_SAN)
         L = ctypes.CDLL(LIB)
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)

@@ -12,7 +12,10 @@ import os
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libr1.so")
+# R1_LIB_SANITIZE=1 loads the CPU-checking build (host C++ under AddressSanitizer and
+# UndefinedBehaviorSanitizer, same kernels; python -m paper_2211_14318_amd.build --sanitize),
+# which needs the sanitizer runtime preloaded into the process.
+LIB_PATH = os.path.join(_PKG, "libr1_san.so" if os.environ.get("R1_LIB_SANITIZE") == "1" else "libr1.so")
 
 R1_OK = 0
 R1_F32, R1_F64 = 0, 1
@@ -95,7 +98,7 @@ def grid_r11(dim):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError("libr1.so is not built (%s); run __graft_entry__.build() or "
+        raise ImportError("%s is not built; run __graft_entry__.build() or "
                           "python -m paper_2211_14318_amd.build" % LIB_PATH)
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64

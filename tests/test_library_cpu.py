@@ -65,15 +65,24 @@ def test_grid_line_starts_match_brute_force(tmp_path):
     and longest line; stepping from a start
     to a later one (mixed-radix add with carry within a slab, by 1 and by 5) agrees with
     decoding."""
+    check_grid_lines(build_grid_check(tmp_path / "check"))
+
+
+def build_grid_check(exe, extra_flags=()):
+    import subprocess
+    subprocess.check_call(["g++", "-std=c++17", "-O1", "-Wall", "-Wno-unknown-pragmas", "-D__HIP_PLATFORM_AMD__",
+                           "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "paper_2211_14318_amd", "csrc"),
+                           "-I" + os.path.join(ROOT, "include"), *extra_flags,
+                           os.path.join(ROOT, "tests", "grid_lines_check.cpp"), "-o", str(exe)])
+    return exe
+
+
+def check_grid_lines(exe):
+    """Runs the grid_lines_check harness on 36 random meshes and compares with brute force."""
     import subprocess
     import sys
     sys.path.insert(0, ROOT)
     import bench
-    exe = tmp_path / "check"
-    subprocess.check_call(["g++", "-std=c++17", "-O1", "-Wall", "-Wno-unknown-pragmas", "-D__HIP_PLATFORM_AMD__",
-                           "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "paper_2211_14318_amd", "csrc"),
-                           "-I" + os.path.join(ROOT, "include"),
-                           os.path.join(ROOT, "tests", "grid_lines_check.cpp"), "-o", str(exe)])
     rng = np.random.default_rng(5)
     for trial in range(36):
         dim = 2 if trial % 3 else 3
