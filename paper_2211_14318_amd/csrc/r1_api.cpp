@@ -70,6 +70,7 @@ r1_status r1h::check_lamination(const r1_lamination* lam) {
 void r1h::level_meta(const r1_level& lv, int dim, r1d::Level* out) {
   out->a = nullptr;
   out->b = nullptr;
+  out->lay = nullptr;
   out->n_dir = lv.n_dir;
   out->n_t = lv.n_t;
   out->tau = lv.tau;
@@ -93,8 +94,9 @@ namespace {
 uint64_t level_key(const r1_level& lv, int dim) {
   size_t bytes = sizeof(double) * size_t(lv.n_dir) * size_t(dim);
   uint64_t key = 1469598103934665603ull;
-  int32_t hdr[2] = {lv.n_dir, dim};
+  int32_t hdr[3] = {lv.n_dir, dim, lv.n_t};
   key = fnv1a(hdr, sizeof(hdr), key);
+  key = fnv1a(&lv.tau, sizeof(lv.tau), key);
   key = fnv1a(lv.a, bytes, key);
   return fnv1a(lv.b, bytes, key);
 }
@@ -130,13 +132,15 @@ r1_status r1h::device_levels(r1_handle h, const r1_level* const* lv, int count, 
     const size_t bytes = sizeof(double) * size_t(lv[k]->n_dir) * size_t(dim);
     auto it = h->dirs.find(keys[k]);
     if (it == h->dirs.end()) {
+      // a, b, then the lane-layout table of the level's grid
       void* d = nullptr;
-      hipError_t e = hipMalloc(&d, 2 * bytes);
+      hipError_t e = hipMalloc(&d, 2 * bytes + r1d::kLayoutBytes);
       if (e != hipSuccess) return R1_ENOMEM;
-      std::vector<double> host(2 * size_t(lv[k]->n_dir) * size_t(dim));
+      std::vector<double> host(2 * size_t(lv[k]->n_dir) * size_t(dim) + r1d::kLayoutBytes / sizeof(double));
       std::memcpy(host.data(), lv[k]->a, bytes);
       std::memcpy(host.data() + size_t(lv[k]->n_dir) * dim, lv[k]->b, bytes);
-      e = hipMemcpy(d, host.data(), 2 * bytes, hipMemcpyHostToDevice);
+      r1d::layout_table(lv[k]->n_t, lv[k]->tau, host.data() + 2 * size_t(lv[k]->n_dir) * dim);
+      e = hipMemcpy(d, host.data(), 2 * bytes + r1d::kLayoutBytes, hipMemcpyHostToDevice);
       if (e != hipSuccess) {
         (void)hipFree(d);
         return fail(h, e, "hipMemcpy(directions)");
@@ -147,6 +151,7 @@ r1_status r1h::device_levels(r1_handle h, const r1_level* const* lv, int count, 
     const double* base = static_cast<const double*>(it->second);
     out[k].a = base;
     out[k].b = base + size_t(lv[k]->n_dir) * dim;
+    out[k].lay = base + 2 * size_t(lv[k]->n_dir) * dim;
   }
   return R1_OK;
 }

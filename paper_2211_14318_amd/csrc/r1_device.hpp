@@ -24,6 +24,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "r1.h"
+
 namespace r1d {
 
 constexpr int kWave = 64;
@@ -53,7 +55,33 @@ struct Level {           // one lamination level on the device
   int n_dir, n_t;
   double tau;
   double ab2;            // |a|^2 |b|^2 when equal for every direction (to rounding), else NaN
+  const void* lay;       // nullable: the level's lane-layout table (layout_table), else formed in place
 };
+
+// Offsets m = 1 .. kLayoutMax cover the widest lane layout (S K / 2 = 64 x 32 / 2)
+// and every offset of the largest grid.
+constexpr int kLayoutMax = 1024;
+static_assert(kLayoutMax >= (R1_MAX_NT - 1) / 2, "layout table shorter than the largest grid");
+constexpr size_t kLayoutBytes = size_t(kLayoutMax) * (2 * sizeof(double) + 2 * sizeof(float));
+
+// Host side: the lane-layout table of a level with n_t samples on [-tau, tau]:
+// for m = 1 .. kLayoutMax the abscissa t_m = tau 2m / (n_t - 1) (NaN beyond the
+// grid) and 1/m, both in FP64, then both rounded to FP32 -- the same expressions,
+// evaluated in the same order, as make_layout forms in place, so either way the
+// kernels see identical values.
+inline void layout_table(int n_t, double tau, void* out) {
+  double* t64 = static_cast<double*>(out);
+  double* i64 = t64 + kLayoutMax;
+  float* t32 = reinterpret_cast<float*>(i64 + kLayoutMax);
+  float* i32 = t32 + kLayoutMax;
+  const int c = (n_t - 1) / 2;
+  for (int m = 1; m <= kLayoutMax; ++m) {
+    t64[m - 1] = m <= c ? tau * double(2 * m) / double(n_t - 1) : __builtin_nan("");
+    i64[m - 1] = 1.0 / double(m);
+    t32[m - 1] = float(t64[m - 1]);
+    i32[m - 1] = float(i64[m - 1]);
+  }
+}
 
 // Model families, a compile-time parameter M of the sampling code: kFamNH is the
 // neo-Hooke damage model with the double-well test energy (told apart at run
@@ -469,6 +497,27 @@ __device__ __forceinline__ Layout<T, S, K> make_layout(int n_t, double tau) {
     // offsets beyond the grid are padding: a NaN abscissa makes the sample NaN,
     // which every hull comparison treats as absent (no per-sample select)
     lay.t[h] = m <= lay.c ? T(tau * double(2 * m) / double(n_t - 1)) : T(__builtin_nan(""));
+  }
+  return lay;
+}
+
+// Same, from the level's table when it has one (loads instead of two FP64
+// divisions per sample pair).
+template <typename T, int S, int K>
+__device__ __forceinline__ Layout<T, S, K> make_layout(const Level& lv) {
+  static_assert(S * K / 2 <= kLayoutMax, "lane layout wider than the table");
+  if (!lv.lay) return make_layout<T, S, K>(lv.n_t, lv.tau);
+  const T* tab = sizeof(T) == 8 ? static_cast<const T*>(lv.lay)
+                                : reinterpret_cast<const T*>(static_cast<const double*>(lv.lay) + 2 * kLayoutMax);
+  Layout<T, S, K> lay;
+  const int sl = threadIdx.x & (S - 1);
+  lay.c = (lv.n_t - 1) / 2;
+#pragma unroll
+  for (int h = 0; h < K / 2; ++h) {
+    const int m = 1 + sl + S * h;
+    lay.mf[h] = T(m);
+    lay.t[h] = tab[m - 1];
+    lay.inv_m[h] = tab[kLayoutMax + m - 1];
   }
   return lay;
 }
@@ -1057,6 +1106,48 @@ __device__ __forceinline__ void stress0_any(const Material& m, double bn, const 
     stress0<D, kFamSTVK>(m, bn, G, P);
   else
     stress0<D, kFamNH>(m, bn, G, P);
+}
+
+// Laminate endpoint stress in the path's precision.  FP64: stress0.  FP32: the
+// same first Piola-Kirchhoff stress, with cof G, det G and |G|^2 still formed in
+// FP64 but ln J and the damage exponential taken, as for the samples, from the
+// FP32 log2 / exp2 in the point's scaled constants (k psi0 as in w_sample, then
+// e^{-beta/D0} = exp_k(min(k psi0, k beta_n))) and 1/J from the FP32 reciprocal.
+template <typename T, int D, int M>
+__device__ __forceinline__ void stress_at(const Point<T>& q, const Material& m, double bn, const double* G,
+                                          double* P) {
+  if constexpr (sizeof(T) == 8) {
+    stress0<D, M>(m, bn, G, P);
+  } else if constexpr (M == kFamSTVK) {
+    double S[D * D];
+    const double psi = stvk_psi_stress<D>(m, G, S);
+    const float g = float(1.0 - m.D_inf) + float(m.D_inf) * expk(fminf(float(q.kq * psi), q.ub));
+#pragma unroll
+    for (int i = 0; i < D * D; ++i) P[i] = double(g) * S[i];
+  } else {
+    if (m.model != 0) {               // double-well test energy: a polynomial
+      stress0<D, M>(m, bn, G, P);
+      return;
+    }
+    double cof[D * D];
+    cofactor<D>(G, cof);
+    const double J = det_of<D>(G, cof);
+    if (!(J > 0.0)) {
+#pragma unroll
+      for (int i = 0; i < D * D; ++i) P[i] = __builtin_nan("");
+      return;
+    }
+    double n2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < D * D; ++i) n2 += G[i] * G[i];
+    const float lj = lg_t(float(J));                    // log2 J
+    const float u = fmaf(lj, fmaf(q.klk, lj, -q.kmk), float(q.kq * (n2 - double(D))));
+    const float g = float(1.0 - m.D_inf) + float(m.D_inf) * expk(fminf(u, q.ub));
+    const float f = (float(m.lambda) * (lj * 0.693147180559945309f) - float(m.mu)) *
+                    __builtin_amdgcn_rcpf(float(J));
+#pragma unroll
+    for (int i = 0; i < D * D; ++i) P[i] = double(g * fmaf(float(m.mu), float(G[i]), f * float(cof[i])));
+  }
 }
 
 // The per-point factors of the leaf moduli, formed once and shared by its rows.

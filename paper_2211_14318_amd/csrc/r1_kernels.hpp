@@ -50,6 +50,7 @@ __device__ __forceinline__ void line_point(const double* G, const Level& lv, int
 }
 
 __device__ __forceinline__ double t_of(const Level& lv, int m) {   // t at offset m from the centre
+  if (lv.lay && m > 0) return static_cast<const double*>(lv.lay)[m - 1];   // the same value, tabled
   return lv.tau * double(2 * m) / double(lv.n_t - 1);
 }
 
@@ -66,8 +67,8 @@ __device__ Env<T> envelope_with_stress(const KArgs& a, const Level& lv, const La
   double Gm[D * D], Gp[D * D], Pm[D * D], Pp[D * D];
   line_point<D>(G, lv, e.dir, -t_of(lv, e.mp), Gm);
   line_point<D>(G, lv, e.dir, t_of(lv, e.mq), Gp);
-  stress0<D, M>(a.mat, bn, Gm, Pm);
-  stress0<D, M>(a.mat, bn, Gp, Pp);
+  stress_at<T, D, M>(q, a.mat, bn, Gm, Pm);
+  stress_at<T, D, M>(q, a.mat, bn, Gp, Pp);
   double xi = (e.mp + e.mq) ? double(e.mp) / double(e.mp + e.mq) : 1.0;
 #pragma unroll
   for (int k = 0; k < D * D; ++k) P[k] = xi * Pp[k] + (1.0 - xi) * Pm[k];
@@ -93,7 +94,7 @@ template <typename T, int D, int S, int K, int M>
 __device__ __forceinline__ void point_depth1(const KArgs& a, int64_t p, const Level& lv) {
   double G[D * D], bn;
   bool fin = load_point<T, D>(a, p, G, bn);
-  Layout<T, S, K> lay = make_layout<T, S, K>(lv.n_t, lv.tau);
+  Layout<T, S, K> lay = make_layout<T, S, K>(lv);
   Point<T> q = make_point<T, M>(a.mat, bn);
   double cof[D * D];
   cofactor<D>(G, cof);
@@ -110,7 +111,7 @@ __device__ __forceinline__ void point_depth1(const KArgs& a, int64_t p, const Le
     if (lane_id() < 2) {
       double Ge[D * D];
       line_point<D>(G, lv, e.dir, lane_id() == 0 ? -t_of(lv, e.mp) : t_of(lv, e.mq), Ge);
-      stress0<D, M>(a.mat, bn, Ge, Pm);
+      stress_at<T, D, M>(q, a.mat, bn, Ge, Pm);
     }
 #pragma unroll
     for (int k = 0; k < D * D; ++k) Pp[k] = __shfl(Pm[k], 1, kWave);
@@ -297,7 +298,7 @@ __device__ __forceinline__ T outer_line(const KArgs& a, int64_t p, int mo, const
   if (lds_lines)
     for (int i = threadIdx.x; i < kOuterWaves * li.n_dir; i += blockDim.x) warm[i] = T(__builtin_nan(""));
   __syncthreads();
-  Layout<T, S, K> lay = make_layout<T, S, K>(li.n_t, li.tau);
+  Layout<T, S, K> lay = make_layout<T, S, K>(li);
   Point<T> q = make_point<T, M>(a.mat, bn);
   const int wave = threadIdx.x / kWave, nwave = blockDim.x / kWave;
   int capped = 0;
@@ -460,7 +461,7 @@ __device__ __forceinline__ void finalize_point(const KArgs& a, int64_t p, const 
   r1_laminate node[3];
   double Pout[D * D];
   if (a.want_stress || a.tree) {
-    Layout<T, S, K> lay = make_layout<T, S, K>(li.n_t, li.tau);
+    Layout<T, S, K> lay = make_layout<T, S, K>(li);
     double Gm[D * D], Gp[D * D], Pm[D * D], Pp[D * D];
     line_point<D>(F, lo, bd, -t_of(lo, bp), Gm);
     line_point<D>(F, lo, bd, t_of(lo, bq), Gp);
