@@ -1,7 +1,8 @@
-// Kernels of the learned surrogate (gfx950): BF16 MFMA (v_mfma_f32_32x32x16_bf16,
-// FP32 accumulation) for the width x width layers, FP32 for the small first and
-// last layers, fused epilogues, Adam, and the fused inference kernel with the
-// routing gates.
+// Kernels of the learned surrogate (gfx950) outside the training step (which is
+// in r1_train.hip): data packing and statistics, and the fused inference kernel
+// with the routing gates -- BF16 MFMA (v_mfma_f32_32x32x16_bf16, FP32
+// accumulation) for the width x width layers, FP32 for the small first and last
+// layers.
 //
 // MFMA 32x32x16 lane layout (64 lanes): A fragment = row (lane % 32), k =
 // 8*(lane/32) .. +7; B fragment = column (lane % 32), same k; accumulator j of
@@ -26,153 +27,6 @@ namespace r1m {
 // the exactly rounded divide bought nothing and cost 9 instructions per unit.
 __device__ __forceinline__ float sigm(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 __device__ __forceinline__ float silu(float z) { return z * sigm(z); }
-__device__ __forceinline__ float silu_d(float z) {
-  float s = sigm(z);
-  return s * (1.0f + z * (1.0f - s));
-}
-__device__ __forceinline__ float bfr(float x) { return float(__bf16(x)); }   // BF16 rounding
-
-template <typename TB>
-__device__ __forceinline__ __bf16 to_bf(TB v) { return __bf16(v); }
-
-// C(m, n) = sum_k A(m, k) B(n, k) with A(m, k) = A[m*sam + k*sak] (FP32, rounded
-// to BF16 on load) and B(n, k) = B[n*sbn + k*sbk].  Block 4 waves = 64 x 64
-// tile, wave 32 x 32; blockIdx.z splits K in chunks of kchunk.
-// M, N multiples of 32, K and kchunk multiples of 16 (checked by the host).
-template <typename TB, int EPI>
-__global__ __launch_bounds__(256) void k_gemm_nt(int M, int N, int K, const float* A, int64_t sam,
-                                                 int64_t sak, const TB* B, int64_t sbn, int64_t sbk,
-                                                 float* C, int64_t ldc, const float* bias,
-                                                 const float* zaux, float* H, int kchunk) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int m0 = blockIdx.y * 64 + (wave >> 1) * 32;
-  const int n0 = blockIdx.x * 64 + (wave & 1) * 32;
-  if (m0 >= M || n0 >= N) return;
-  const int kb = blockIdx.z * kchunk;
-  const int ke = min(K, kb + kchunk);
-  const int r = lane & 31, kq = 8 * (lane >> 5);
-  f32x16 acc = {};
-  const float* Ar = A + int64_t(m0 + r) * sam;
-  const TB* Br = B + int64_t(n0 + r) * sbn;
-  for (int k0 = kb; k0 < ke; k0 += 16) {
-    bf16x8 a, b;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      a[i] = __bf16(Ar[int64_t(k0 + kq + i) * sak]);
-      b[i] = to_bf(Br[int64_t(k0 + kq + i) * sbk]);
-    }
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
-  }
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const int row = m0 + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
-    const int col = n0 + r;
-    const int64_t o = int64_t(row) * ldc + col;
-    float v = acc[j];
-    if (EPI == kEpiBiasSilu) {
-      v += bias[col];
-      C[o] = v;
-      H[o] = silu(v);
-    } else if (EPI == kEpiDsilu) {
-      C[o] = v * silu_d(zaux[o]);
-    } else {
-      atomicAdd(&C[o], v);
-    }
-  }
-}
-
-// First layer (FP32): Z = X W0^T + b0, H = SiLU(Z).  X: B x d_in, W0: w x d_in.
-__global__ void k_first_fwd(int B, int d_in, int w, const float* X, const float* W, const float* b,
-                            float* Z, float* H) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= int64_t(B) * w) return;
-  const int64_t row = i / w;
-  const int o = int(i % w);
-  float z = b[o];
-  for (int k = 0; k < d_in; ++k) z = fmaf(W[o * d_in + k], X[row * d_in + k], z);
-  Z[i] = z;
-  H[i] = silu(z);
-}
-
-// Output layer (FP32 weights, BF16-rounded activations as at inference), loss and
-// dL/dout.  G is B x 32 (columns >= d_out are zero) for the padded gradient GEMMs.
-// Rows whose standardized gap target is <= z_thr did not laminate: their gap
-// output only has to stay below z_thr - margin (one-sided squared hinge) and
-// their stress outputs are not trained (inference then returns W(F), P0(F)).
-// The energy output's squared error is weighted by ew.
-__global__ void k_out_fwd_loss(int B, int w, int d_out, const float* H, const float* Wo,
-                               const float* bo, const float* Y, float z_thr, float margin,
-                               float ew, float* G, float* loss_acc) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  float e2 = 0.0f;
-  if (i < int64_t(B) * 32) {
-    const int64_t row = i / 32;
-    const int j = int(i % 32);
-    float g = 0.0f;
-    if (j < d_out) {
-      float o = bo[j];
-      for (int k = 0; k < w; ++k) o = fmaf(Wo[j * w + k], bfr(H[row * w + k]), o);
-      const bool convex = Y[row * d_out] <= z_thr;
-      float e;
-      if (!convex) e = o - Y[row * d_out + j];
-      else if (j == 0) e = fmaxf(0.0f, o - (z_thr - margin));
-      else e = 0.0f;
-      const float wj = j == 0 ? ew : 1.0f;
-      e2 = wj * e * e;
-      g = 2.0f * wj * e / float(int64_t(B) * d_out);
-    }
-    G[i] = g;
-  }
-  // block sum of the squared errors
-  __shared__ float red[256];
-  red[threadIdx.x] = e2;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) atomicAdd(loss_acc, red[0] / float(int64_t(B) * d_out));
-}
-
-// Column sums of a B x ncol matrix into out (accumulated with atomics).
-__global__ void k_colsum(int B, int ncol, int ld, const float* A, float* out) {
-  const int col = blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= ncol) return;
-  const int rows_per = (B + gridDim.y - 1) / gridDim.y;
-  const int r0 = blockIdx.y * rows_per, r1 = min(B, r0 + rows_per);
-  float s = 0.0f;
-  for (int r = r0; r < r1; ++r) s += A[int64_t(r) * ld + col];
-  atomicAdd(&out[col], s);
-}
-
-// out[o][i] += sum_b D[b*ldd + o] X[b*ldx + i] for small o, i ranges (first- and
-// output-layer weight gradients); round_x rounds X to BF16 as the forward pass did.
-__global__ void k_outer_small(int B, int no, int ni, const float* D, int ldd, const float* X, int ldx,
-                              int round_x, float* out) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= no * ni) return;
-  const int o = t / ni, i = t % ni;
-  const int rows_per = (B + gridDim.y - 1) / gridDim.y;
-  const int r0 = blockIdx.y * rows_per, r1 = min(B, r0 + rows_per);
-  float s = 0.0f;
-  for (int r = r0; r < r1; ++r) {
-    float x = X[int64_t(r) * ldx + i];
-    s = fmaf(D[int64_t(r) * ldd + o], round_x ? bfr(x) : x, s);
-  }
-  atomicAdd(&out[t], s);
-}
-
-// delta of the last hidden layer: (G Wout) * SiLU'(Z), G: B x 32 (d_out used).
-__global__ void k_out_bwd_dh(int B, int w, int d_out, const float* G, const float* Wo, const float* Z,
-                             float* Dl) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= int64_t(B) * w) return;
-  const int64_t row = i / w;
-  const int k = int(i % w);
-  float s = 0.0f;
-  for (int j = 0; j < d_out; ++j) s = fmaf(G[row * 32 + j], Wo[j * w + k], s);
-  Dl[i] = s * silu_d(Z[i]);
-}
 
 // Packed rows -> SoA F (float) and beta_n.
 __global__ void k_unpack(int dd, int64_t n, const float* X, float* F, float* bn) {
@@ -182,50 +36,9 @@ __global__ void k_unpack(int dd, int64_t n, const float* X, float* F, float* bn)
   bn[p] = X[p * (dd + 1) + dd];
 }
 
-__global__ void k_adam(int64_t n, float* p, const float* g, float* m, float* v, float lr, float b1,
-                       float b2, float eps, float c1, float c2) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  float gi = g[i];
-  float mi = b1 * m[i] + (1.0f - b1) * gi;
-  float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
-  m[i] = mi;
-  v[i] = vi;
-  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
-}
-
-__global__ void k_to_bf16(int64_t n, const float* src, __bf16* dst) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = __bf16(src[i]);
-}
-
 __global__ void k_fill(int64_t n, float* p, float v) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
-}
-
-// Minibatch rows: row i of the batch is training row (a*(s*B + i) + c) mod n_train
-// (a permutation when gcd(a, n_train) = 1), standardized.
-__global__ void k_gather(int B, int64_t n_train, uint64_t a, uint64_t c, int64_t step, int d_in,
-                         int d_out, const float* X, const float* T, const float* xm,
-                         const float* xs, const float* ym, const float* ys, float* Xb, float* Yb) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= B) return;
-  const uint64_t q = (uint64_t(step) * uint64_t(B) + uint64_t(i)) % uint64_t(n_train);
-  const int64_t row = int64_t((a % uint64_t(n_train)) * q % uint64_t(n_train) + c % uint64_t(n_train)) % n_train;
-  for (int k = 0; k < d_in; ++k) Xb[int64_t(i) * d_in + k] = (X[row * d_in + k] - xm[k]) / xs[k];
-  for (int k = 0; k < d_out; ++k) Yb[int64_t(i) * d_out + k] = (T[row * d_out + k] - ym[k]) / ys[k];
-}
-
-// Rows [r0, r1) standardized (validation set).
-__global__ void k_standardize(int64_t r0, int64_t r1, int d_in, int d_out, const float* X,
-                              const float* T, const float* xm, const float* xs, const float* ym,
-                              const float* ys, float* Xb, float* Yb) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (r0 + i >= r1) return;
-  const int64_t row = r0 + i;
-  for (int k = 0; k < d_in; ++k) Xb[i * d_in + k] = (X[row * d_in + k] - xm[k]) / xs[k];
-  for (int k = 0; k < d_out; ++k) Yb[i * d_out + k] = (T[row * d_out + k] - ym[k]) / ys[k];
 }
 
 // Gap-form targets from packed rows: T = (W(F) - W^k, P0(F) - P^k), W and P0 of
@@ -677,97 +490,13 @@ using namespace r1m;
 
 static inline unsigned nblk(int64_t n, int b = 256) { return unsigned((n + b - 1) / b); }
 
-hipError_t r1m_gemm(int epi, bool b_bf16, int M, int N, int K, const float* A, int64_t sam,
-                    int64_t sak, const void* B, int64_t sbn, int64_t sbk, float* C, int64_t ldc,
-                    const float* bias, const float* zaux, float* H, int ksplit, hipStream_t st) {
-  int kchunk = ((K / ksplit + 15) / 16) * 16;
-  if (kchunk < 16) kchunk = 16;
-  dim3 grid(unsigned((N + 63) / 64), unsigned((M + 63) / 64), unsigned((K + kchunk - 1) / kchunk));
-#define R1G(TB, E) hipLaunchKernelGGL((k_gemm_nt<TB, E>), grid, dim3(256), 0, st, M, N, K, A, sam, sak, \
-                                      static_cast<const TB*>(B), sbn, sbk, C, ldc, bias, zaux, H, kchunk)
-  if (b_bf16) {
-    if (epi == kEpiBiasSilu) R1G(__bf16, kEpiBiasSilu);
-    else if (epi == kEpiDsilu) R1G(__bf16, kEpiDsilu);
-    else R1G(__bf16, kEpiAtomic);
-  } else {
-    if (epi == kEpiBiasSilu) R1G(float, kEpiBiasSilu);
-    else if (epi == kEpiDsilu) R1G(float, kEpiDsilu);
-    else R1G(float, kEpiAtomic);
-  }
-#undef R1G
-  return hipGetLastError();
-}
-
-hipError_t r1m_first_fwd(int B, int d_in, int w, const float* X, const float* W, const float* b,
-                         float* Z, float* H, hipStream_t st) {
-  hipLaunchKernelGGL(k_first_fwd, dim3(nblk(int64_t(B) * w)), dim3(256), 0, st, B, d_in, w, X, W, b, Z, H);
-  return hipGetLastError();
-}
-
-hipError_t r1m_out_fwd_loss(int B, int w, int d_out, const float* H, const float* Wo, const float* bo,
-                            const float* Y, float z_thr, float margin, float ew, float* G, float* loss,
-                            hipStream_t st) {
-  hipLaunchKernelGGL(k_out_fwd_loss, dim3(nblk(int64_t(B) * 32)), dim3(256), 0, st, B, w, d_out, H, Wo,
-                     bo, Y, z_thr, margin, ew, G, loss);
-  return hipGetLastError();
-}
-
-// Row chunks of 16 (column sums) and 32 (outer products) rows per thread keep the
-// serial chains short; the chunk sums meet in atomics.
-hipError_t r1m_colsum(int B, int ncol, int ld, const float* A, float* out, hipStream_t st) {
-  dim3 grid(nblk(ncol, 64), unsigned(std::min(65535, (B + 15) / 16)));
-  hipLaunchKernelGGL(k_colsum, grid, dim3(64), 0, st, B, ncol, ld, A, out);
-  return hipGetLastError();
-}
-
-hipError_t r1m_outer_small(int B, int no, int ni, const float* D, int ldd, const float* X, int ldx,
-                           int round_x, float* out, hipStream_t st) {
-  dim3 grid(nblk(int64_t(no) * ni), unsigned(std::min(65535, (B + 31) / 32)));
-  hipLaunchKernelGGL(k_outer_small, grid, dim3(256), 0, st, B, no, ni, D, ldd, X, ldx, round_x, out);
-  return hipGetLastError();
-}
-
-hipError_t r1m_out_bwd_dh(int B, int w, int d_out, const float* G, const float* Wo, const float* Z,
-                          float* Dl, hipStream_t st) {
-  hipLaunchKernelGGL(k_out_bwd_dh, dim3(nblk(int64_t(B) * w)), dim3(256), 0, st, B, w, d_out, G, Wo, Z, Dl);
-  return hipGetLastError();
-}
-
 hipError_t r1m_unpack(int dim, int64_t n, const float* X, float* F, float* bn, hipStream_t st) {
   hipLaunchKernelGGL(k_unpack, dim3(nblk(n)), dim3(256), 0, st, dim * dim, n, X, F, bn);
   return hipGetLastError();
 }
 
-hipError_t r1m_adam(int64_t n, float* p, const float* g, float* m, float* v, float lr, float b1,
-                    float b2, float eps, int64_t t, hipStream_t st) {
-  float c1 = 1.0f - powf(b1, float(t)), c2 = 1.0f - powf(b2, float(t));
-  hipLaunchKernelGGL(k_adam, dim3(nblk(n)), dim3(256), 0, st, n, p, g, m, v, lr, b1, b2, eps, c1, c2);
-  return hipGetLastError();
-}
-
-hipError_t r1m_to_bf16(int64_t n, const float* src, void* dst, hipStream_t st) {
-  hipLaunchKernelGGL(k_to_bf16, dim3(nblk(n)), dim3(256), 0, st, n, src, static_cast<__bf16*>(dst));
-  return hipGetLastError();
-}
-
 hipError_t r1m_fill(int64_t n, float* p, float v, hipStream_t st) {
   hipLaunchKernelGGL(k_fill, dim3(nblk(n)), dim3(256), 0, st, n, p, v);
-  return hipGetLastError();
-}
-
-hipError_t r1m_gather(int B, int64_t n_train, uint64_t a, uint64_t c, int64_t step, int d_in, int d_out,
-                      const float* X, const float* T, const float* norm, float* Xb, float* Yb,
-                      hipStream_t st) {
-  // norm = x_mean (d_in), x_std (d_in), y_mean (d_out), y_std (d_out)
-  hipLaunchKernelGGL(k_gather, dim3(nblk(B)), dim3(256), 0, st, B, n_train, a, c, step, d_in, d_out, X, T,
-                     norm, norm + d_in, norm + 2 * d_in, norm + 2 * d_in + d_out, Xb, Yb);
-  return hipGetLastError();
-}
-
-hipError_t r1m_standardize(int64_t r0, int64_t r1, int d_in, int d_out, const float* X, const float* T,
-                           const float* norm, float* Xb, float* Yb, hipStream_t st) {
-  hipLaunchKernelGGL(k_standardize, dim3(nblk(r1 - r0)), dim3(256), 0, st, r0, r1, d_in, d_out, X, T, norm,
-                     norm + d_in, norm + 2 * d_in, norm + 2 * d_in + d_out, Xb, Yb);
   return hipGetLastError();
 }
 

@@ -7,9 +7,6 @@
 #include "r1.h"
 #include "r1_device.hpp"
 
-constexpr int kEpiBiasSilu = 0;   // C = acc + bias, H = SiLU(C)
-constexpr int kEpiDsilu = 1;      // C = acc * SiLU'(zaux)
-constexpr int kEpiAtomic = 2;     // C += acc (split-K weight gradients)
 constexpr int kMaxCols = 10;      // d_in, d_out <= 10
 constexpr int kMaxHidden = 8;
 constexpr int kBinsR = 16;        // error-gate bins over |F - I|_F
@@ -37,28 +34,57 @@ struct InferParams {
   int32_t* cand_list;               // (the candidates of the a-posteriori check)
 };
 
-hipError_t r1m_gemm(int epi, bool b_bf16, int M, int N, int K, const float* A, int64_t sam,
-                    int64_t sak, const void* B, int64_t sbn, int64_t sbk, float* C, int64_t ldc,
-                    const float* bias, const float* zaux, float* H, int ksplit, hipStream_t st);
-hipError_t r1m_first_fwd(int B, int d_in, int w, const float* X, const float* W, const float* b,
-                         float* Z, float* H, hipStream_t st);
-hipError_t r1m_out_fwd_loss(int B, int w, int d_out, const float* H, const float* Wo, const float* bo,
-                            const float* Y, float z_thr, float margin, float ew, float* G, float* loss,
-                            hipStream_t st);
-hipError_t r1m_out_bwd_dh(int B, int w, int d_out, const float* G, const float* Wo, const float* Z,
-                          float* Dl, hipStream_t st);
-hipError_t r1m_colsum(int B, int ncol, int ld, const float* A, float* out, hipStream_t st);
-hipError_t r1m_outer_small(int B, int no, int ni, const float* D, int ldd, const float* X, int ldx,
-                           int round_x, float* out, hipStream_t st);
-hipError_t r1m_adam(int64_t n, float* p, const float* g, float* m, float* v, float lr, float b1,
-                    float b2, float eps, int64_t t, hipStream_t st);
-hipError_t r1m_to_bf16(int64_t n, const float* src, void* dst, hipStream_t st);
+// One batch of the training step (r1_train.hip).  Rows (mode): 0 = Xn / Yn given,
+// already standardized; 1 = training row (a (step B + b) + c) mod n_train of X / T
+// for batch row b (a permutation when gcd(a, n_train) = 1); 2 = rows r0 .. r0 + B
+// of X / T; modes 1 and 2 standardize with norm = x_mean, x_std (d_in each),
+// y_mean, y_std (d_out each).  B is a multiple of 32.
+struct TrainArgs {
+  int B, d_in, d_out, width, n_hidden;
+  const float* params;                // FP32 master weights (off_w / off_b layout)
+  int64_t off_w[kMaxHidden + 1], off_b[kMaxHidden + 1];
+  const void* wbf;                    // BF16 W_l, l = 1 .. n_hidden - 1 (out x in, width^2 each)
+  const void* wbf_t;                  // BF16 W_l^T (in x out)
+  float* grad;                        // accumulated into (+=)
+  int mode;
+  const float* Xn;
+  const float* Yn;
+  const float* X;
+  const float* T;
+  const float* norm;
+  int64_t n_train, r0, step;
+  uint64_t a, c;
+  float z_thr, margin, ew;            // loss (see k_train_fwd)
+  float* loss;                        // += mean loss of the batch
+  int store;                          // 0: loss only (the workspace below is not touched)
+  float* Xb;                          // B x d_in: standardized inputs
+  float* G;                           // B x d_out: dL/dout
+  float* Z;                           // n_hidden x B x width: pre-activations
+  void* Ht;                           // n_hidden x width x B BF16: activations, transposed
+  void* Dt;                           // n_hidden x width x B BF16: deltas, transposed (layers >= 1)
+  int wgrad_chunk;                    // set by the launcher
+};
+
+// Adam step on n parameters (lr = 0: only the BF16 copies are refreshed), then
+// W_l and W_l^T of the width x width layers rounded to BF16.
+struct AdamArgs {
+  int64_t n;
+  float* p;
+  float* g;                           // cleared after use
+  float* m;
+  float* v;
+  float lr, b1, b2, eps, c1, c2;
+  int n_hidden, width;
+  int64_t off_w[kMaxHidden + 1];
+  void* wbf;
+  void* wbf_t;
+};
+
+hipError_t r1m_train_fwd(const TrainArgs& a, hipStream_t st);        // forward, loss, dL/dout
+hipError_t r1m_train_bwd(const TrainArgs& a, hipStream_t st);        // every gradient (after fwd)
+hipError_t r1m_train_adam(const AdamArgs& a, hipStream_t st);
+
 hipError_t r1m_fill(int64_t n, float* p, float v, hipStream_t st);
-hipError_t r1m_gather(int B, int64_t n_train, uint64_t a, uint64_t c, int64_t step, int d_in, int d_out,
-                      const float* X, const float* T, const float* norm, float* Xb, float* Yb,
-                      hipStream_t st);
-hipError_t r1m_standardize(int64_t r0, int64_t r1, int d_in, int d_out, const float* X, const float* T,
-                           const float* norm, float* Xb, float* Yb, hipStream_t st);
 hipError_t r1m_targets(int dim, int64_t n, const r1d::Material& mat, const float* X, const float* Y,
                        float* T, hipStream_t st);
 hipError_t r1m_colstats(int64_t n, int ncol, int dF, const float* A, double* sum, double* sum2, float* mn,

@@ -24,6 +24,7 @@ struct r1_surrogate_s {
   float* m = nullptr;
   float* v = nullptr;
   void* wbf = nullptr;                      // BF16 copies of the width x width layers
+  void* wbf_t = nullptr;                    // ... and of their transposes (backward pass)
   int64_t t = 0;                            // Adam steps taken
   float norm[4 * kMaxCols] = {};            // x_mean, x_std, y_mean, y_std (packed by d_in/d_out)
   float x_lo[kMaxCols] = {}, x_hi[kMaxCols] = {};
@@ -79,18 +80,37 @@ void* wbf_of(r1_surrogate s, int l) {
   return static_cast<char*>(s->wbf) + size_t(l - 1) * s->width * s->width * 2;
 }
 
-hipError_t refresh_bf16(r1_surrogate s, hipStream_t st) {
-  hipError_t e = hipSuccess;
-  for (int l = 1; l < s->n_hidden && e == hipSuccess; ++l)
-    e = r1m_to_bf16(int64_t(s->width) * s->width, s->params + s->off_w[l], wbf_of(s, l), st);
-  return e;
+// Adam step of lr (lr = 0: none) on the gradient in s->grad, which it clears,
+// then the BF16 copies of the width x width layers from the master weights.
+hipError_t adam_step(r1_surrogate s, float lr, float b1, float b2, float eps, hipStream_t st) {
+  AdamArgs a{};
+  a.n = s->n_params;
+  a.p = s->params;
+  a.g = s->grad;
+  a.m = s->m;
+  a.v = s->v;
+  a.lr = lr;
+  a.b1 = b1;
+  a.b2 = b2;
+  a.eps = eps;
+  a.c1 = 1.0f - powf(b1, float(s->t));
+  a.c2 = 1.0f - powf(b2, float(s->t));
+  a.n_hidden = s->n_hidden;
+  a.width = s->width;
+  for (int l = 0; l <= s->n_hidden; ++l) a.off_w[l] = s->off_w[l];
+  a.wbf = s->wbf;
+  a.wbf_t = s->wbf_t;
+  return r1m_train_adam(a, st);
 }
+
+hipError_t refresh_bf16(r1_surrogate s, hipStream_t st) { return adam_step(s, 0.0f, 0.9f, 0.999f, 1e-8f, st); }
 
 r1_status alloc_state(r1_surrogate s) {
   size_t pb = sizeof(float) * size_t(s->n_params);
   if (hipMalloc(&s->params, pb) != hipSuccess || hipMalloc(&s->grad, pb) != hipSuccess ||
       hipMalloc(&s->m, pb) != hipSuccess || hipMalloc(&s->v, pb) != hipSuccess ||
       hipMalloc(&s->wbf, size_t(std::max(1, s->n_hidden - 1)) * s->width * s->width * 2) != hipSuccess ||
+      hipMalloc(&s->wbf_t, size_t(std::max(1, s->n_hidden - 1)) * s->width * s->width * 2) != hipSuccess ||
       hipMalloc(&s->gate_tau, sizeof(float) * kGateCells) != hipSuccess ||
       hipMalloc(&s->norm_dev, sizeof(float) * 4 * kMaxCols) != hipSuccess)
     return R1_ENOMEM;
@@ -102,7 +122,7 @@ r1_status alloc_state(r1_surrogate s) {
 
 void free_state(r1_surrogate s) {
   for (void* p : {static_cast<void*>(s->params), static_cast<void*>(s->grad), static_cast<void*>(s->m),
-                  static_cast<void*>(s->v), s->wbf, static_cast<void*>(s->gate_tau),
+                  static_cast<void*>(s->v), s->wbf, s->wbf_t, static_cast<void*>(s->gate_tau),
                   static_cast<void*>(s->norm_dev), s->ws})
     if (p) (void)hipFree(p);
 }
@@ -112,76 +132,57 @@ const float* xsd(r1_surrogate s) { return s->norm + s->d_in; }
 const float* ym(r1_surrogate s) { return s->norm + 2 * s->d_in; }
 const float* ysd(r1_surrogate s) { return s->norm + 2 * s->d_in + s->d_out; }
 
-// Training workspace for batches of B rows.
+// Training workspace for batches of B rows (the buffers of TrainArgs).
 struct TrainWs {
-  float *Xb, *Yb, *G, *D1, *D2, *loss;
-  std::vector<float*> Z, H;
+  float *Xb, *G, *Z, *loss;
+  void *Ht, *Dt;
 };
 
 r1_status train_ws(r1_surrogate s, int B, TrainWs* w) {
-  const size_t bw = sizeof(float) * size_t(B) * s->width;
+  const size_t lw = size_t(s->n_hidden) * size_t(B) * s->width;
   size_t bytes = al(sizeof(float) * size_t(B) * s->d_in) + al(sizeof(float) * size_t(B) * s->d_out) +
-                 al(sizeof(float) * size_t(B) * 32) + 2 * al(bw) + al(256) + 2 * size_t(s->n_hidden) * al(bw);
+                 al(sizeof(float) * lw) + 2 * al(2 * lw) + al(256);
   r1_status st = grow(s, bytes);
   if (st) return st;
   char* p = static_cast<char*>(s->ws);
-  auto take = [&](size_t b) { char* q = p; p += al(b); return reinterpret_cast<float*>(q); };
-  w->Xb = take(sizeof(float) * size_t(B) * s->d_in);
-  w->Yb = take(sizeof(float) * size_t(B) * s->d_out);
-  w->G = take(sizeof(float) * size_t(B) * 32);
-  w->D1 = take(bw);
-  w->D2 = take(bw);
-  w->loss = take(256);
-  w->Z.resize(s->n_hidden);
-  w->H.resize(s->n_hidden);
-  for (int l = 0; l < s->n_hidden; ++l) {
-    w->Z[l] = take(bw);
-    w->H[l] = take(bw);
-  }
+  auto take = [&](size_t b) { char* q = p; p += al(b); return q; };
+  w->Xb = reinterpret_cast<float*>(take(sizeof(float) * size_t(B) * s->d_in));
+  w->G = reinterpret_cast<float*>(take(sizeof(float) * size_t(B) * s->d_out));
+  w->Z = reinterpret_cast<float*>(take(sizeof(float) * lw));
+  w->Ht = take(2 * lw);
+  w->Dt = take(2 * lw);
+  w->loss = reinterpret_cast<float*>(take(256));
   return R1_OK;
 }
 
-// Forward pass and loss (accumulated into w.loss) on the B rows in w.Xb / w.Yb.
-hipError_t forward(r1_surrogate s, int B, TrainWs& w, float z_thr, float ew, hipStream_t st) {
-  const int W = s->width;
-  hipError_t e = r1m_first_fwd(B, s->d_in, W, w.Xb, s->params + s->off_w[0], s->params + s->off_b[0],
-                               w.Z[0], w.H[0], st);
-  for (int l = 1; l < s->n_hidden && e == hipSuccess; ++l)
-    e = r1m_gemm(kEpiBiasSilu, true, B, W, W, w.H[l - 1], W, 1, wbf_of(s, l), W, 1, w.Z[l], W,
-                 s->params + s->off_b[l], nullptr, w.H[l], 1, st);
-  if (e == hipSuccess)
-    e = r1m_out_fwd_loss(B, W, s->d_out, w.H[s->n_hidden - 1], s->params + s->off_w[s->n_hidden],
-                         s->params + s->off_b[s->n_hidden], w.Yb, z_thr, kHingeMargin, ew, w.G, w.loss, st);
-  return e;
-}
-
-// Gradient of the loss into s->grad (zeroed here) after forward().
-hipError_t backward(r1_surrogate s, int B, TrainWs& w, hipStream_t st) {
-  const int W = s->width, L = s->n_hidden;
-  const int ks = std::max(1, B / 256);
-  hipError_t e = r1m_fill(s->n_params, s->grad, 0.0f, st);
-  if (e == hipSuccess)
-    e = r1m_outer_small(B, s->d_out, W, w.G, 32, w.H[L - 1], W, 1, s->grad + s->off_w[L], st);
-  if (e == hipSuccess) e = r1m_colsum(B, s->d_out, 32, w.G, s->grad + s->off_b[L], st);
-  float* dcur = w.D1;
-  float* dnext = w.D2;
-  if (e == hipSuccess)
-    e = r1m_out_bwd_dh(B, W, s->d_out, w.G, s->params + s->off_w[L], w.Z[L - 1], dcur, st);
-  for (int l = L - 1; l >= 1 && e == hipSuccess; --l) {
-    // dW_l += delta_l^T H_{l-1}; db_l += colsum(delta_l)
-    e = r1m_gemm(kEpiAtomic, false, W, W, B, dcur, 1, W, w.H[l - 1], 1, W, s->grad + s->off_w[l], W,
-                 nullptr, nullptr, nullptr, ks, st);
-    if (e == hipSuccess) e = r1m_colsum(B, W, W, dcur, s->grad + s->off_b[l], st);
-    // delta_{l-1} = (delta_l W_l) * SiLU'(Z_{l-1})
-    if (e == hipSuccess)
-      e = r1m_gemm(kEpiDsilu, true, B, W, W, dcur, W, 1, wbf_of(s, l), 1, W, dnext, W, nullptr, w.Z[l - 1],
-                   nullptr, 1, st);
-    std::swap(dcur, dnext);
+// Arguments of one batch of B rows with the surrogate's weights and workspace.
+TrainArgs batch_args(r1_surrogate s, int B, const TrainWs& w, float z_thr, float ew) {
+  TrainArgs a{};
+  a.B = B;
+  a.d_in = s->d_in;
+  a.d_out = s->d_out;
+  a.width = s->width;
+  a.n_hidden = s->n_hidden;
+  a.params = s->params;
+  for (int l = 0; l <= s->n_hidden; ++l) {
+    a.off_w[l] = s->off_w[l];
+    a.off_b[l] = s->off_b[l];
   }
-  if (e == hipSuccess)
-    e = r1m_outer_small(B, W, s->d_in, dcur, W, w.Xb, s->d_in, 0, s->grad + s->off_w[0], st);
-  if (e == hipSuccess) e = r1m_colsum(B, W, W, dcur, s->grad + s->off_b[0], st);
-  return e;
+  a.wbf = s->wbf;
+  a.wbf_t = s->wbf_t;
+  a.grad = s->grad;
+  a.norm = s->norm_dev;
+  a.z_thr = z_thr;
+  a.margin = kHingeMargin;
+  a.ew = ew;
+  a.loss = w.loss;
+  a.store = 1;
+  a.Xb = w.Xb;
+  a.G = w.G;
+  a.Z = w.Z;
+  a.Ht = w.Ht;
+  a.Dt = w.Dt;
+  return a;
 }
 
 uint64_t gcd64(uint64_t a, uint64_t b) {
@@ -344,12 +345,14 @@ r1_status r1_surrogate_loss_grad(r1_handle h, r1_surrogate s, const float* Xn, c
   TrainWs w;
   r1_status rs = train_ws(s, int(n), &w);
   if (rs) return rs;
-  hipError_t e = hipMemcpyAsync(w.Xb, Xn, sizeof(float) * size_t(n) * s->d_in, hipMemcpyDeviceToDevice, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(w.Yb, Yn, sizeof(float) * size_t(n) * s->d_out, hipMemcpyDeviceToDevice, st);
+  TrainArgs a = batch_args(s, int(n), w, -INFINITY, 1.0f);   // plain mean squared error
+  a.mode = 0;
+  a.Xn = Xn;
+  a.Yn = Yn;
+  hipError_t e = r1m_fill(s->n_params, s->grad, 0.0f, st);
   if (e == hipSuccess) e = r1m_fill(1, w.loss, 0.0f, st);
-  if (e == hipSuccess) e = forward(s, int(n), w, -INFINITY, 1.0f, st);   // plain mean squared error
-  if (e == hipSuccess) e = backward(s, int(n), w, st);
+  if (e == hipSuccess) e = r1m_train_fwd(a, st);
+  if (e == hipSuccess) e = r1m_train_bwd(a, st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(grad, s->grad, sizeof(float) * size_t(s->n_params), hipMemcpyDeviceToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(loss, w.loss, sizeof(float), hipMemcpyDeviceToHost, st);
@@ -458,6 +461,12 @@ r1_status r1_surrogate_train(r1_handle h, r1_surrogate s, const r1_material* mat
   const float z_thr = (kZeroGap - ym(s)[0]) / ysd(s)[0];
   float last_loss = 0.0f;
   int64_t steps = 0;
+  TrainArgs ta = batch_args(s, B, w, z_thr, cfg->energy_weight);
+  ta.mode = 1;
+  ta.X = X;
+  ta.T = T;
+  ta.n_train = n_train;
+  if (e == hipSuccess) e = r1m_fill(s->n_params, s->grad, 0.0f, st);   // each Adam step clears it again
   for (int ep = 0; ep < cfg->epochs && e == hipSuccess; ++ep) {
     uint64_t a;
     do {
@@ -465,19 +474,19 @@ r1_status r1_surrogate_train(r1_handle h, r1_surrogate s, const r1_material* mat
     } while (gcd64(a, uint64_t(n_train)) != 1);
     uint64_t c = rng.next() % uint64_t(n_train);
     e = r1m_fill(1, w.loss, 0.0f, st);
+    ta.a = a;
+    ta.c = c;
     for (int64_t sidx = 0; sidx < steps_per_epoch && e == hipSuccess; ++sidx) {
-      e = r1m_gather(B, n_train, a, c, sidx, DI, DO, X, T, s->norm_dev, w.Xb, w.Yb, st);
-      if (e == hipSuccess) e = forward(s, B, w, z_thr, cfg->energy_weight, st);
-      if (e == hipSuccess) e = backward(s, B, w, st);
+      ta.step = sidx;
+      e = r1m_train_fwd(ta, st);
+      if (e == hipSuccess) e = r1m_train_bwd(ta, st);
       if (e == hipSuccess) {
         ++s->t;
         // cosine decay of the step size to 2% over this call's steps
         const double frac = double(steps) / double(std::max<int64_t>(total_steps - 1, 1));
         const float lr = float(cfg->lr * (0.02 + 0.98 * 0.5 * (1.0 + std::cos(M_PI * frac))));
-        e = r1m_adam(s->n_params, s->params, s->grad, s->m, s->v, lr, cfg->beta1, cfg->beta2, cfg->eps,
-                     s->t, st);
+        e = adam_step(s, lr, cfg->beta1, cfg->beta2, cfg->eps, st);
       }
-      if (e == hipSuccess) e = refresh_bf16(s, st);
       ++steps;
     }
     if (e == hipSuccess && ep == cfg->epochs - 1) {
@@ -493,9 +502,12 @@ r1_status r1_surrogate_train(r1_handle h, r1_surrogate s, const r1_material* mat
     e = r1m_fill(1, w.loss, 0.0f, st);
     int64_t chunks = 0;
     for (int64_t r0 = n_train; r0 + 32 <= n && e == hipSuccess; r0 += B) {
-      int64_t cnt = std::min<int64_t>(B, n - r0) / 32 * 32;
-      e = r1m_standardize(r0, r0 + cnt, DI, DO, X, T, s->norm_dev, w.Xb, w.Yb, st);
-      if (e == hipSuccess) e = forward(s, int(cnt), w, z_thr, cfg->energy_weight, st);
+      TrainArgs va = ta;
+      va.B = int(std::min<int64_t>(B, n - r0) / 32 * 32);
+      va.mode = 2;
+      va.r0 = r0;
+      va.store = 0;
+      e = r1m_train_fwd(va, st);
       ++chunks;
     }
     if (e == hipSuccess) e = hipMemcpyAsync(&val, w.loss, sizeof(float), hipMemcpyDeviceToHost, st);
