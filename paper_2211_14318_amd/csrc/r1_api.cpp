@@ -192,10 +192,12 @@ int r1h::segment_width(r1_handle h, int n_t, int dtype, int dim, int role) {
   if (it != h->seg_override.end()) return it->second;
   auto jt = h->seg_tuned.find(r1h::tune_key(n_t, dtype, dim, role));
   if (jt != h->seg_tuned.end()) return jt->second;
-  // default: about 16 samples per lane
-  int c = (n_t - 1) / 2;
+  // default: about 16 samples per lane in FP32 and 8 in FP64, whose samples take
+  // twice the registers (16 would cost the depth-2 outer kernel half its occupancy)
+  const int c = (n_t - 1) / 2;
+  const int pairs = dtype == R1_F64 ? 4 : 8;
   int S = 8;
-  while (S < 64 && S * 8 < c) S *= 2;
+  while (S < 64 && S * pairs < c) S *= 2;
   return S;
 }
 

@@ -25,6 +25,7 @@
 #include <stdint.h>
 
 #include "r1.h"
+#include "r1_math.hpp"
 
 namespace r1d {
 
@@ -36,13 +37,13 @@ template <> __device__ __forceinline__ float inf_v<float>() { return __builtin_i
 template <> __device__ __forceinline__ double inf_v<double>() { return __builtin_inf(); }
 
 // Logarithm used by W: FP32 takes the hardware log2 (v_log_f32) and carries
-// ln 2 in the coefficients; FP64 takes the device library's natural log.
+// ln 2 in the coefficients; FP64 takes the natural log of r1_math.hpp.
 __device__ __forceinline__ float lg_t(float x) { return __builtin_amdgcn_logf(x); }
-__device__ __forceinline__ double lg_t(double x) { return log(x); }
+__device__ __forceinline__ double lg_t(double x) { return r1x::log_f64(x); }
 // Exponential of an argument pre-scaled by the per-point constant kexp:
-// FP32 uses the hardware exp2 (kexp carries log2 e), FP64 the device library.
+// FP32 uses the hardware exp2 (kexp carries log2 e), FP64 the exp of r1_math.hpp.
 __device__ __forceinline__ float expk(float x) { return __builtin_amdgcn_exp2f(x); }
-__device__ __forceinline__ double expk(double x) { return exp(x); }
+__device__ __forceinline__ double expk(double x) { return r1x::exp_f64(x); }
 
 struct Material {
   int dim, model;        // model: 0 neo-Hooke damage, 1 double-well test energy, 2 St. Venant-Kirchhoff damage

@@ -68,6 +68,22 @@ def test_grid_line_starts_match_brute_force(tmp_path):
     check_grid_lines(build_grid_check(tmp_path / "check"))
 
 
+def test_fp64_log_exp_accuracy(tmp_path):
+    """The FP64 sampling path's own log and exp (csrc/r1_math.hpp, built with the host
+    compiler without contraction, so the same operations as on the device): at most
+    1.5 units in the last place from the x87 extended-precision logl / expl over the
+    positive range, near 1, over [-745, 0] and near 0, and the C library's special values."""
+    import subprocess
+    exe = tmp_path / "math_check"
+    subprocess.check_call(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-Wall", "-D__HIP_PLATFORM_AMD__",
+                           "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "paper_2211_14318_amd", "csrc"),
+                           os.path.join(ROOT, "tests", "math_f64_check.cpp"), "-o", str(exe)])
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    worst = {l.split()[1]: float(l.split()[2]) for l in out.splitlines() if l.startswith("max_ulp")}
+    assert len(worst) == 7 and out.strip().splitlines()[-1].startswith("ok"), out
+    assert max(worst.values()) <= 1.5, worst
+
+
 def build_grid_check(exe, extra_flags=()):
     import subprocess
     subprocess.check_call(["g++", "-std=c++17", "-O1", "-Wall", "-Wno-unknown-pragmas", "-D__HIP_PLATFORM_AMD__",
