@@ -275,6 +275,21 @@ r1_status r1_autotune(r1_handle handle, const r1_material* material, int32_t n_t
 r1_status r1_autotune_inner(r1_handle handle, const r1_material* material, int32_t n_t, r1_dtype dtype,
                             void* stream, int32_t* lanes);
 
+/* Persisting the tuned segment widths (for a cache kept between runs; the
+ * autotuner's results otherwise live as long as the handle).  A record is five
+ * int32: n_t, dtype (r1_dtype), dim (2, 3), role (R1_TUNE_LEVEL: lines of
+ * one-level envelopes; R1_TUNE_INNER: inner levels of depth-2 laminations) and
+ * lanes (8, 16, 32 or 64).  r1_tuning_export writes up to `capacity` records
+ * (host int32[5 * capacity], nullable when capacity is 0) in ascending key order
+ * and sets *count (host) to the number the handle holds.  r1_tuning_import
+ * checks every record (n_t odd in 3..R1_MAX_NT, known dtype, dim and role, lanes
+ * a supported width whose layout covers the grid) and installs them all, or
+ * none with R1_EINVAL.  Neither touches the device. */
+#define R1_TUNE_LEVEL 0
+#define R1_TUNE_INNER 1
+r1_status r1_tuning_export(r1_handle handle, int32_t* records, int32_t capacity, int32_t* count);
+r1_status r1_tuning_import(r1_handle handle, const int32_t* records, int32_t count);
+
 /* ---- global lamination on a deformation-gradient mesh -------------------------
  *
  * The grid variant of Section 4.1: node values on the mesh of Section 5.2 (one

@@ -269,6 +269,43 @@ r1_status r1_get_segment_width(r1_handle h, int32_t n_t, r1_dtype dtype, int32_t
   return R1_OK;
 }
 
+static_assert(R1_TUNE_LEVEL == r1h::kRoleLevel && R1_TUNE_INNER == r1h::kRoleInner, "tuning roles");
+
+r1_status r1_tuning_export(r1_handle h, int32_t* records, int32_t capacity, int32_t* count) {
+  if (!h || !count || capacity < 0 || (capacity > 0 && !records)) return R1_EINVAL;
+  int32_t k = 0;
+  for (const auto& kv : h->seg_tuned) {
+    if (k < capacity) {
+      int32_t* r = records + 5 * size_t(k);
+      r[0] = int32_t(kv.first >> 8);
+      r[1] = int32_t((kv.first >> 4) & 3);
+      r[2] = int32_t(kv.first & 15);
+      r[3] = int32_t((kv.first >> 6) & 3);
+      r[4] = kv.second;
+    }
+    ++k;
+  }
+  *count = k;
+  return R1_OK;
+}
+
+r1_status r1_tuning_import(r1_handle h, const int32_t* records, int32_t count) {
+  if (!h || count < 0 || (count > 0 && !records)) return R1_EINVAL;
+  for (int32_t k = 0; k < count; ++k) {
+    const int32_t* r = records + 5 * size_t(k);
+    const int n_t = r[0], dtype = r[1], dim = r[2], role = r[3], lanes = r[4];
+    if (n_t < 3 || n_t > R1_MAX_NT || n_t % 2 == 0 || (dtype != R1_F32 && dtype != R1_F64) ||
+        (dim != 2 && dim != 3) || (role != R1_TUNE_LEVEL && role != R1_TUNE_INNER) ||
+        (lanes != 8 && lanes != 16 && lanes != 32 && lanes != 64) || r1h::samples_per_lane(lanes, n_t) == 0)
+      return R1_EINVAL;
+  }
+  for (int32_t k = 0; k < count; ++k) {
+    const int32_t* r = records + 5 * size_t(k);
+    h->seg_tuned[r1h::tune_key(r[0], r[1], r[2], r[3])] = r[4];
+  }
+  return R1_OK;
+}
+
 r1_status r1_get_inner_segment_width(r1_handle h, int32_t n_t, r1_dtype dtype, int32_t dim, int32_t* lanes) {
   if (!h || !lanes || n_t < 3 || n_t > R1_MAX_NT || (n_t % 2) == 0) return R1_EINVAL;
   *lanes = r1h::segment_width(h, n_t, dtype, dim, r1h::kRoleInner);

@@ -133,6 +133,8 @@ def _load():
     L.r1_batched_plan_execute.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.r1_batched_plan_destroy.argtypes = [vp]
     L.r1_set_segment_width.argtypes = [vp, i32, i32]
+    L.r1_tuning_export.argtypes = [vp, ctypes.c_void_p, i32, ctypes.POINTER(i32)]
+    L.r1_tuning_import.argtypes = [vp, ctypes.c_void_p, i32]
     L.r1_get_segment_width.argtypes = [vp, i32, i32, i32, ctypes.POINTER(i32)]
     L.r1_autotune.argtypes = [vp, ctypes.POINTER(Material), i32, i32, vp, ctypes.POINTER(i32)]
     L.r1_autotune_inner.argtypes = [vp, ctypes.POINTER(Material), i32, i32, vp, ctypes.POINTER(i32)]
@@ -251,6 +253,23 @@ class Handle:
 
     def set_segment_width(self, n_t, lanes):
         self._check(_lib.r1_set_segment_width(self.h, int(n_t), int(lanes)), "r1_set_segment_width")
+
+    def tuning(self):
+        """The handle's tuned segment widths as an (k, 5) int32 array of records
+        (n_t, dtype, dim, role, lanes), e.g. to keep them between runs."""
+        cnt = ctypes.c_int32()
+        self._check(_lib.r1_tuning_export(self.h, None, 0, ctypes.byref(cnt)), "r1_tuning_export")
+        rec = np.zeros((cnt.value, 5), dtype=np.int32)
+        if cnt.value:
+            self._check(_lib.r1_tuning_export(self.h, rec.ctypes.data, cnt.value, ctypes.byref(cnt)),
+                        "r1_tuning_export")
+        return rec
+
+    def set_tuning(self, records):
+        """Installs records as returned by tuning() (all checked first)."""
+        rec = np.ascontiguousarray(records, dtype=np.int32).reshape(-1, 5)
+        self._check(_lib.r1_tuning_import(self.h, rec.ctypes.data if len(rec) else None, len(rec)),
+                    "r1_tuning_import")
 
     def segment_width(self, n_t, dtype, dim):
         out = ctypes.c_int32()

@@ -155,6 +155,33 @@ def test_autotuner_returns_admissible_width(lib):
         assert h.segment_width(nt, r1.R1_F32, 2) == lanes
 
 
+def test_tuning_records_round_trip(lib):
+    """The tuned widths leave a handle as records and enter a fresh one unchanged, so
+    a caller can keep the autotuner's results between runs; a bad record (even n_t,
+    unknown role, unsupported width, a width too narrow for the grid) is refused and
+    installs nothing."""
+    r1, h, torch = lib
+    mat = r1.material()
+    h.autotune(mat, 129, r1.R1_F32)
+    h.autotune_inner(mat, 129, r1.R1_F32)
+    rec = h.tuning()
+    assert rec.shape[1] == 5 and len(rec) >= 2
+    assert {(129, r1.R1_F32, 2, 0), (129, r1.R1_F32, 2, 1)} <= {tuple(r[:4]) for r in rec}
+    h2 = r1.Handle(0)
+    try:
+        assert len(h2.tuning()) == 0
+        h2.set_tuning(rec)
+        assert np.array_equal(h2.tuning(), rec)
+        assert h2.segment_width(129, r1.R1_F32, 2) == h.segment_width(129, r1.R1_F32, 2)
+        assert h2.inner_segment_width(129, r1.R1_F32, 2) == h.inner_segment_width(129, r1.R1_F32, 2)
+        for bad in ([128, 0, 2, 0, 16], [129, 0, 2, 2, 16], [129, 0, 2, 0, 12], [2049, 0, 2, 0, 8]):
+            with pytest.raises(r1.R1Error):
+                h2.set_tuning(np.array([[257, 0, 2, 0, 16], bad]))
+            assert np.array_equal(h2.tuning(), rec)
+    finally:
+        h2.close()
+
+
 def _eager(lib, table, Ft, bt, it):
     """One plain launch per table entry on its points (torch tensors)."""
     r1, h, torch = lib
