@@ -107,10 +107,18 @@ constexpr int kFamSTVK = 2;
 // its L coefficients carry ln2 factors); the polynomial part k mu/2 (|G|^2 - d)
 // comes pre-scaled in the line coefficients (line_scale).  St. Venant-Kirchhoff
 // psi0 is a quartic along a rank-one line, pre-scaled by k as a whole.
+//
+// Hull form: lower hulls (and their vertices, bridges and the minimum over
+// directions) are unchanged by a positive scale and a shift, and E1/k < 0, so
+// the lamination works on Ws = (W - B)/sc with sc = -E1/k:
+//   Ws = -u + A2 v + C2 exp_k(v),  A2 = (D_inf - D_n)/(1 - D_n),  C2 = -C/sc,
+// two FMAs after the exponential instead of three; W = sc Ws + B is formed
+// once per envelope.
 template <typename T>
 struct Point {
   T klk, kmk;            // k lambda/2 (ln2^2), k mu (ln2)
   T ub, E1k, Aqk, B, negC;
+  T sc, A2, C2;          // hull form (above)
   double kq;             // scale of the line polynomial, applied in double (line_scale)
   double lam, mu;        // Lame parameters (St. Venant-Kirchhoff line coefficients)
   int model;
@@ -140,6 +148,9 @@ __device__ __forceinline__ Point<T> make_point(const Material& m, double bn) {
   q.Aqk = T((Dn - m.D_inf) / k);
   q.negC = T(-m.D_inf * m.D0);
   q.B = T(m.D_inf * e * (bn + m.D0));
+  q.sc = T(-(1.0 - Dn) / k);
+  q.A2 = T((m.D_inf - Dn) / (1.0 - Dn));
+  q.C2 = T(m.D_inf * m.D0 * k / (1.0 - Dn));
   q.kq = line_scale<T, M>(m);
   q.lam = m.lambda;
   q.mu = m.mu;
@@ -315,27 +326,15 @@ __device__ __forceinline__ Line<T> line_setup(const Point<T>& q, const double* G
   return L;
 }
 
-// One sample of W on a line (the hot loop: 9 VALU + 2 transcendental).  The
-// line's c0, c1, c2 are the scaled polynomial k mu/2 |G(t)|^2 - d (see Point).
+// One sample of W on a line (9 VALU + 2 transcendental; the envelopes sample
+// the hull form below, W itself is for the a-posteriori check).  The line's
+// c0, c1, c2 are the scaled polynomial k mu/2 |G(t)|^2 - d (see Point).
 // det <= 0 gives NaN (J < 0) or NaN/+inf (J = 0): such samples lie outside the
 // admissible interval and every hull comparison below treats NaN as absent.
 template <typename T>
 __device__ __forceinline__ T w_sample(T t, const Line<T>& L, const Point<T>& q) {
   T J = fma(t, L.J1, L.J0);
   T u = fma(t, fma(t, L.c2, L.c1), L.c0);
-  T lj = lg_t(J);
-  u = fma(lj, fma(q.klk, lj, -q.kmk), u);
-  T v = fmin(u, q.ub);
-  return fma(q.negC, expk(v), fma(q.E1k, u, fma(q.Aqk, v, q.B)));
-}
-
-// Same, with the part of the line polynomial that is common to every line
-// through the point given per sample: base = c0 + c2 t^2 (8 VALU + 2
-// transcendental).
-template <typename T>
-__device__ __forceinline__ T w_sample_base(T t, T base, const Line<T>& L, const Point<T>& q) {
-  T J = fma(t, L.J1, L.J0);
-  T u = fma(t, L.c1, base);
   T lj = lg_t(J);
   u = fma(lj, fma(q.klk, lj, -q.kmk), u);
   T v = fmin(u, q.ub);
@@ -351,6 +350,37 @@ __device__ __forceinline__ T w_sample_stvk(T t, const Line<T>& L, const Point<T>
   return fma(q.negC, expk(v), fma(q.E1k, u, fma(q.Aqk, v, q.B)));
 }
 
+// The same samples in the hull form Ws = (W - B)/sc (see Point): 8 VALU + 2
+// transcendental, 7 + 2 when the part of the line polynomial common to every
+// line through the point comes per sample (base = c0 + c2 t^2), 6 + 1 for St.
+// Venant-Kirchhoff.
+template <typename T>
+__device__ __forceinline__ T ws_sample(T t, const Line<T>& L, const Point<T>& q) {
+  T J = fma(t, L.J1, L.J0);
+  T u = fma(t, fma(t, L.c2, L.c1), L.c0);
+  T lj = lg_t(J);
+  u = fma(lj, fma(q.klk, lj, -q.kmk), u);
+  T v = fmin(u, q.ub);
+  return fma(q.C2, expk(v), fma(q.A2, v, -u));
+}
+
+template <typename T>
+__device__ __forceinline__ T ws_sample_base(T t, T base, const Line<T>& L, const Point<T>& q) {
+  T J = fma(t, L.J1, L.J0);
+  T u = fma(t, L.c1, base);
+  T lj = lg_t(J);
+  u = fma(lj, fma(q.klk, lj, -q.kmk), u);
+  T v = fmin(u, q.ub);
+  return fma(q.C2, expk(v), fma(q.A2, v, -u));
+}
+
+template <typename T>
+__device__ __forceinline__ T ws_sample_stvk(T t, const Line<T>& L, const Point<T>& q) {
+  T u = fma(t, fma(t, fma(t, fma(t, L.c4, L.c3), L.c2), L.c1), L.c0);
+  T v = fmin(u, q.ub);
+  return fma(q.C2, expk(v), fma(q.A2, v, -u));
+}
+
 template <typename T>
 __device__ __forceinline__ T w_sample_doublewell(T t, const Line<T>& L) {
   T g = fma(t, L.J1, L.J0);
@@ -358,13 +388,15 @@ __device__ __forceinline__ T w_sample_doublewell(T t, const Line<T>& L) {
   return fma(g2, g2, fma(t, fma(t, L.c2, L.c1), L.c0));
 }
 
-// W at a point (the centre sample of every line through it), in the path's precision.
+// W at a point (the centre sample of every line through it), in the path's precision,
+// through the hull form for the damage energies (the value the envelope returns
+// where the point does not laminate).
 template <typename T, int D, int M = kFamNH>
 __device__ __forceinline__ T w_point(const Point<T>& q, const double* G, const double* cof) {
   double a0[3] = {0, 0, 0};
   Line<T> L = line_setup<T, D, M>(q, G, cof, a0, a0);
-  if constexpr (M == kFamSTVK) return w_sample_stvk<T>(T(0), L, q);
-  return q.model == 0 ? w_sample<T>(T(0), L, q) : w_sample_doublewell<T>(T(0), L);
+  if constexpr (M == kFamSTVK) return fma(ws_sample_stvk<T>(T(0), L, q), q.sc, q.B);
+  return q.model == 0 ? fma(ws_sample<T>(T(0), L, q), q.sc, q.B) : w_sample_doublewell<T>(T(0), L);
 }
 
 // Same, for code whose model is known at run time only.
@@ -857,16 +889,27 @@ __device__ Env<T> envelope_lines(const Point<T>& q, T wc, int n_dir, const Layou
   constexpr int H = K / 2;
   const int lane = threadIdx.x & (kWave - 1);
   const int seg = lane / S;
+  // the damage energies are hulled in the hull form Ws (see Point); every line
+  // through the point has the same J0 and c0, so its centre is any line's t = 0
+  const bool scaled = M == kFamSTVK || q.model == 0;
+  const bool shared = M == kFamNH && q.model == 0 && c2u == c2u;
+  T wcs = wc;
+  T base[H];
+  if (scaled) {
+    const Line<T> L0 = line_fn(0);
+    if constexpr (M == kFamSTVK) {
+      wcs = ws_sample_stvk<T>(T(0), L0, q);
+    } else {
+      wcs = ws_sample<T>(T(0), L0, q);
+      if (shared) {
+#pragma unroll
+        for (int h = 0; h < H; ++h) base[h] = fma(c2u, lay.t[h] * lay.t[h], L0.c0);
+      }
+    }
+  }
   T wci[H];
 #pragma unroll
-  for (int h = 0; h < H; ++h) wci[h] = wc * lay.inv_m[h];
-  const bool shared = M == kFamNH && q.model == 0 && c2u == c2u;
-  T base[H];
-  if (shared) {
-    const T c0 = line_fn(0).c0;
-#pragma unroll
-    for (int h = 0; h < H; ++h) base[h] = fma(c2u, lay.t[h] * lay.t[h], c0);
-  }
+  for (int h = 0; h < H; ++h) wci[h] = wcs * lay.inv_m[h];
   if (order) {
     // stable partition of the directions: warm (bridged last time) first
     int n_warm = 0;
@@ -894,20 +937,20 @@ __device__ Env<T> envelope_lines(const Point<T>& q, T wc, int n_dir, const Layou
     if constexpr (M == kFamSTVK) {
 #pragma unroll
       for (int h = 0; h < H; ++h) {
-        w[h] = w_sample_stvk<T>(-lay.t[h], L, q);
-        w[H + h] = w_sample_stvk<T>(lay.t[h], L, q);
+        w[h] = ws_sample_stvk<T>(-lay.t[h], L, q);
+        w[H + h] = ws_sample_stvk<T>(lay.t[h], L, q);
       }
     } else if (shared) {
 #pragma unroll
       for (int h = 0; h < H; ++h) {
-        w[h] = w_sample_base<T>(-lay.t[h], base[h], L, q);
-        w[H + h] = w_sample_base<T>(lay.t[h], base[h], L, q);
+        w[h] = ws_sample_base<T>(-lay.t[h], base[h], L, q);
+        w[H + h] = ws_sample_base<T>(lay.t[h], base[h], L, q);
       }
     } else if (q.model == 0) {
 #pragma unroll
       for (int h = 0; h < H; ++h) {
-        w[h] = w_sample<T>(-lay.t[h], L, q);
-        w[H + h] = w_sample<T>(lay.t[h], L, q);
+        w[h] = ws_sample<T>(-lay.t[h], L, q);
+        w[H + h] = ws_sample<T>(lay.t[h], L, q);
       }
     } else {
 #pragma unroll
@@ -918,7 +961,7 @@ __device__ Env<T> envelope_lines(const Point<T>& q, T wc, int n_dir, const Layou
     }
     T sg = (warm && act) ? warm[dir] : T(__builtin_nan(""));
     const bool hot = warm && __all(act && sg == sg);
-    LineHull<T> lh = hull_centre<T, S, K>(w, wc, wci, lay, sg, hot);
+    LineHull<T> lh = hull_centre<T, S, K>(w, wcs, wci, lay, sg, hot);
     if (warm && act && (lane & (S - 1)) == 0) warm[dir] = sg;
     if (act) {
       if (lh.h < best.h || (lh.h == best.h && dir < best.dir)) {
@@ -946,6 +989,10 @@ __device__ Env<T> envelope_lines(const Point<T>& q, T wc, int n_dir, const Layou
     best.mp = take ? op : best.mp;
     best.mq = take ? oq : best.mq;
     best.capped |= oc;
+  }
+  if (scaled) {   // back from the hull form; a centre that is a vertex is W there, exactly
+    best.h = (best.mp + best.mq) ? fma(best.h, q.sc, q.B) : wc;
+    best.second = fma(best.second, q.sc, q.B);
   }
   return best;
 }

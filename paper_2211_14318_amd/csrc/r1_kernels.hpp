@@ -333,7 +333,7 @@ __device__ __forceinline__ T outer_line(const KArgs& a, int64_t p, int mo, const
         cofactor<D>(G, cof);
         const double zero[D] = {};
         const Line<T> L0 = line_setup<T, D, M>(q, G, cof, zero, zero);
-        T wc = w_sample_stvk<T>(T(0), L0, q);
+        T wc = fma(ws_sample_stvk<T>(T(0), L0, q), q.sc, q.B);
         v = wc;
         if (wc < inf_v<T>()) {
           const T tt = T(t);
@@ -372,7 +372,7 @@ __device__ __forceinline__ T outer_line(const KArgs& a, int64_t p, int mo, const
               if (i || j) c0 += (G[i * D + j] - (i == j ? 1.0 : 0.0)) * (G[i * D + j] - (i == j ? 1.0 : 0.0));
         }
         Line<T> L0 = {T(J0), T(0), T(c0), T(0), T(0)};
-        T wc = q.model == 0 ? w_sample<T>(T(0), L0, q) : w_sample_doublewell<T>(T(0), L0);
+        T wc = q.model == 0 ? fma(ws_sample<T>(T(0), L0, q), q.sc, q.B) : w_sample_doublewell<T>(T(0), L0);
         v = wc;
         if (wc < inf_v<T>()) {
           const T tt = T(t);
