@@ -128,7 +128,7 @@ struct Point {
 // |G|^2 part, k for the St. Venant-Kirchhoff quartic.
 template <typename T, int M = kFamNH>
 __device__ __forceinline__ double line_scale(const Material& m) {
-  const double k = (sizeof(T) == 4 ? -1.4426950408889634 : -1.0) / m.D0;
+  const double k = (sizeof(T) == 4 ? -1.4426950408889634 : -1.0) * (1.0 / m.D0);   // as in make_point
   if constexpr (M == kFamSTVK) return k;
   return k * 0.5 * m.mu;
 }
@@ -138,19 +138,23 @@ __device__ __forceinline__ Point<T> make_point(const Material& m, double bn) {
   Point<T> q;
   const bool f32 = sizeof(T) == 4;
   const double ln2 = 0.6931471805599453094;
-  const double k = (f32 ? -1.4426950408889634 : -1.0) / m.D0;
-  double e = exp(-bn / m.D0);
+  // two divisions per point: 1/D0 and 1/(1 - D_n); 1/k = -D0 ln2 (FP32) or -D0
+  const double iD0 = 1.0 / m.D0;
+  const double k = (f32 ? -1.4426950408889634 : -1.0) * iD0;
+  const double ik = f32 ? -m.D0 * ln2 : -m.D0;
+  double e = r1x::exp_f64(-bn * iD0);
   double Dn = m.D_inf * (1.0 - e);
+  const double i1D = 1.0 / (1.0 - Dn);
   q.kmk = T(k * (f32 ? m.mu * ln2 : m.mu));
   q.klk = T(k * (f32 ? 0.5 * m.lambda * ln2 * ln2 : 0.5 * m.lambda));
   q.ub = T(k * bn);
-  q.E1k = T((1.0 - Dn) / k);
-  q.Aqk = T((Dn - m.D_inf) / k);
+  q.E1k = T((1.0 - Dn) * ik);
+  q.Aqk = T((Dn - m.D_inf) * ik);
   q.negC = T(-m.D_inf * m.D0);
   q.B = T(m.D_inf * e * (bn + m.D0));
-  q.sc = T(-(1.0 - Dn) / k);
-  q.A2 = T((m.D_inf - Dn) / (1.0 - Dn));
-  q.C2 = T(m.D_inf * m.D0 * k / (1.0 - Dn));
+  q.sc = T(-(1.0 - Dn) * ik);
+  q.A2 = T((m.D_inf - Dn) * i1D);
+  q.C2 = T(m.D_inf * m.D0 * k * i1D);
   q.kq = line_scale<T, M>(m);
   q.lam = m.lambda;
   q.mu = m.mu;
@@ -871,9 +875,12 @@ __device__ __forceinline__ bool near_tie(const Env<T>& e) {
 // One lamination level at a point (wave-uniform): min over the level's n_dir
 // directions of the line hulls at the centre.  wc = W at the point;
 // line_fn(dir) returns the coefficients of W along direction dir.  warm
-// (optional, n_dir entries owned by this wave) carries each direction's bridge
-// slope from one call to the next as the start of the bridge search: NaN for
-// none; callers whose successive points are close pass it.  c2u: when every
+// (optional, 2 n_dir entries owned by this wave) carries each direction's
+// bridge slope at the last call (warm[dir]) and at the call before
+// (warm[n_dir + dir]) to the next, whose bridge search starts from their linear
+// extrapolation (from the last slope alone when the one before is absent): NaN
+// for none; callers whose successive points are close and evenly spaced pass
+// it.  c2u: when every
 // line has the same c2 (and, being lines through one point, the same c0), that
 // c2; the polynomial part c0 + c2 t^2 is then formed once per point (NaN: not
 // uniform).  order (optional with warm, n_dir entries owned by this wave): the
@@ -959,10 +966,19 @@ __device__ Env<T> envelope_lines(const Point<T>& q, T wc, int n_dir, const Layou
         w[H + h] = w_sample_doublewell<T>(lay.t[h], L);
       }
     }
-    T sg = (warm && act) ? warm[dir] : T(__builtin_nan(""));
-    const bool hot = warm && __all(act && sg == sg);
+    T sg = T(__builtin_nan("")), s1 = sg;
+    if (warm && act) {
+      s1 = warm[dir];
+      const T s2 = warm[n_dir + dir];
+      // start from the slope extrapolated linearly from the last two points
+      sg = s2 == s2 ? fma(T(2), s1, -s2) : s1;
+    }
+    const bool hot = warm && __all(act && s1 == s1);
     LineHull<T> lh = hull_centre<T, S, K>(w, wcs, wci, lay, sg, hot);
-    if (warm && act && (lane & (S - 1)) == 0) warm[dir] = sg;
+    if (warm && act && (lane & (S - 1)) == 0) {
+      warm[n_dir + dir] = sg == sg ? s1 : sg;
+      warm[dir] = sg;
+    }
     if (act) {
       if (lh.h < best.h || (lh.h == best.h && dir < best.dir)) {
         best.second = best.h;

@@ -208,12 +208,12 @@ __host__ __device__ constexpr int tab_coefs(int model) { return model == 2 ? 10 
 
 // Bytes of dynamic LDS an outer line needs for samples of elem_bytes bytes:
 // the outer line's samples and, when the inner level is tabulated, its
-// coefficient table, each wave's warm-start bridge slopes and each wave's
-// direction visiting order (int).
+// coefficient table, each wave's warm-start bridge slopes (the last two per
+// direction) and each wave's direction visiting order (int).
 __host__ __device__ inline size_t outer_lds_bytes(size_t elem_bytes, int n_t_outer, int n_dir_inner, int model) {
   const bool tab = n_dir_inner <= kMaxTabDirs;
   return elem_bytes * (size_t(n_t_outer - 1) +
-                       (tab ? size_t(tab_coefs(model) + kOuterWaves) * size_t(n_dir_inner) : 0)) +
+                       (tab ? size_t(tab_coefs(model) + 2 * kOuterWaves) * size_t(n_dir_inner) : 0)) +
          (tab ? sizeof(int) * size_t(kOuterWaves) * size_t(n_dir_inner) : 0);
 }
 
@@ -267,8 +267,8 @@ __device__ __forceinline__ T outer_line(const KArgs& a, int64_t p, int mo, const
   const bool tab = lds_lines;
   constexpr int NC = tab_coefs(M);
   T* coef = reinterpret_cast<T*>(smem_raw);                 // NC * n_dir_i (tab)
-  T* warm = coef + (tab ? NC * li.n_dir : 0);               // kOuterWaves * n_dir_i (lds_lines)
-  T* wl = warm + (lds_lines ? kOuterWaves * li.n_dir : 0);  // outer samples at -m
+  T* warm = coef + (tab ? NC * li.n_dir : 0);                   // 2 kOuterWaves n_dir_i (lds_lines)
+  T* wl = warm + (lds_lines ? 2 * kOuterWaves * li.n_dir : 0);  // outer samples at -m
   T* wr = wl + co;                                          // outer samples at +m
   int* order = reinterpret_cast<int*>(wr + co);             // kOuterWaves * n_dir_i (lds_lines)
   __shared__ int capped_any;
@@ -296,7 +296,7 @@ __device__ __forceinline__ T outer_line(const KArgs& a, int64_t p, int mo, const
     }
   }
   if (lds_lines)
-    for (int i = threadIdx.x; i < kOuterWaves * li.n_dir; i += blockDim.x) warm[i] = T(__builtin_nan(""));
+    for (int i = threadIdx.x; i < 2 * kOuterWaves * li.n_dir; i += blockDim.x) warm[i] = T(__builtin_nan(""));
   __syncthreads();
   Layout<T, S, K> lay = make_layout<T, S, K>(li);
   Point<T> q = make_point<T, M>(a.mat, bn);
@@ -315,9 +315,10 @@ __device__ __forceinline__ T outer_line(const KArgs& a, int64_t p, int mo, const
     if (lane_id() == 0) centre = v;
   }
   // outer samples, interleaved left/right so the waves share both sides; a
-  // wave walks one side outwards in steps of two samples, so the previous
-  // sample's inner bridge slopes (warm, per inner direction) start the next
-  T* warm_w = warm + wave * li.n_dir;          // blocks have kOuterWaves waves
+  // wave walks one side outwards in even steps of two samples, so the inner
+  // bridge slopes of its last two samples (warm, per inner direction),
+  // extrapolated, start the next
+  T* warm_w = warm + 2 * wave * li.n_dir;      // blocks have kOuterWaves waves
   int* order_w = order + wave * li.n_dir;
   for (int s = wave; s < 2 * co; s += nwave) {
     int m = 1 + (s >> 1);
