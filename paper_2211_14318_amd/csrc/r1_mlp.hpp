@@ -9,6 +9,13 @@
 
 constexpr int kMaxCols = 10;      // d_in, d_out <= 10
 constexpr int kMaxHidden = 8;
+
+// Gradients of the small layers per block of 32 batch rows in a training step:
+// W_0 (width x d_in), the biases b_0 .. b_{n_hidden-1} (width each), W_out
+// (d_out x width) and b_out (d_out), in that order.
+__host__ __device__ constexpr int train_n_small(int d_in, int d_out, int width, int n_hidden) {
+  return width * d_in + n_hidden * width + d_out * width + d_out;
+}
 constexpr int kBinsR = 16;        // error-gate bins over |F - I|_F
 constexpr int kBinsB = 8;         // ... and over beta_n
 constexpr int kGateCells = kBinsR * kBinsB;   // each with a threshold on the predicted gap
@@ -62,7 +69,8 @@ struct TrainArgs {
   float* Z;                           // n_hidden x B x width: pre-activations
   void* Ht;                           // n_hidden x width x B BF16: activations, transposed
   void* Dt;                           // n_hidden x width x B BF16: deltas, transposed (layers >= 1)
-  int wgrad_chunk;                    // set by the launcher
+  float* part;                        // (B / 32) x train_n_small: per-block partial gradients of the
+                                      // small layers (k_train_bwd), summed by the weight-gradient launch
 };
 
 // Adam step on n parameters (lr = 0: only the BF16 copies are refreshed), then

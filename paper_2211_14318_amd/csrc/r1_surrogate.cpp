@@ -134,14 +134,15 @@ const float* ysd(r1_surrogate s) { return s->norm + 2 * s->d_in + s->d_out; }
 
 // Training workspace for batches of B rows (the buffers of TrainArgs).
 struct TrainWs {
-  float *Xb, *G, *Z, *loss;
+  float *Xb, *G, *Z, *loss, *part;
   void *Ht, *Dt;
 };
 
 r1_status train_ws(r1_surrogate s, int B, TrainWs* w) {
   const size_t lw = size_t(s->n_hidden) * size_t(B) * s->width;
+  const size_t np = size_t(B / 32) * size_t(train_n_small(s->d_in, s->d_out, s->width, s->n_hidden));
   size_t bytes = al(sizeof(float) * size_t(B) * s->d_in) + al(sizeof(float) * size_t(B) * s->d_out) +
-                 al(sizeof(float) * lw) + 2 * al(2 * lw) + al(256);
+                 al(sizeof(float) * lw) + 2 * al(2 * lw) + al(256) + al(sizeof(float) * np);
   r1_status st = grow(s, bytes);
   if (st) return st;
   char* p = static_cast<char*>(s->ws);
@@ -152,6 +153,7 @@ r1_status train_ws(r1_surrogate s, int B, TrainWs* w) {
   w->Ht = take(2 * lw);
   w->Dt = take(2 * lw);
   w->loss = reinterpret_cast<float*>(take(256));
+  w->part = reinterpret_cast<float*>(take(sizeof(float) * np));
   return R1_OK;
 }
 
@@ -182,6 +184,7 @@ TrainArgs batch_args(r1_surrogate s, int B, const TrainWs& w, float z_thr, float
   a.Z = w.Z;
   a.Ht = w.Ht;
   a.Dt = w.Dt;
+  a.part = w.part;
   return a;
 }
 

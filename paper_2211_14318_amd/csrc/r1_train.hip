@@ -9,11 +9,14 @@
 //                  weight gradients).
 //   k_train_bwd    per block of 32 rows: the delta chain through the width x
 //                  width layers (BF16 MFMA against the transposed weights) with
-//                  SiLU' from Z, the output- and first-layer weight gradients
-//                  and every bias gradient; stores the BF16 deltas transposed.
+//                  SiLU' from Z, and the block's share of the output- and
+//                  first-layer weight gradients and of every bias gradient
+//                  (stored as per-block partials); stores the BF16 deltas
+//                  transposed.
 //   k_train_wgrad  dW_l += Delta_l^T H_{l-1} for every width x width layer in
 //                  one launch (both operands K-contiguous), split over the batch
-//                  in chunks whose partial sums meet in atomics.
+//                  in chunks whose partial sums meet in atomics; and the sum of
+//                  k_train_bwd's partials into the small layers' gradients.
 //   k_train_adam   Adam on every parameter, clearing its gradient for the next
 //                  step and refreshing the BF16 copies of W_l and W_l^T.
 //
@@ -35,11 +38,34 @@ namespace {
 
 constexpr int kR = 32;           // batch rows per block of the fused passes
 
+// Batch rows per partial sum of the weight gradients: the largest of 512 .. 32
+// dividing B (B is a multiple of kR).
+__host__ __device__ inline int wgrad_chunk(int B) {
+  int c = 512;
+  while (B % c != 0) c /= 2;
+  return c;
+}
+
 __device__ __forceinline__ float sigm(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 __device__ __forceinline__ float silu(float z) { return z * sigm(z); }
 __device__ __forceinline__ float silu_d(float z) {
   const float s = sigm(z);
   return s * (1.0f + z * (1.0f - s));
+}
+
+// Index i of the small layers' partial gradients (train_n_small) and the
+// parameter it belongs to.
+__device__ __forceinline__ int small_b(const TrainArgs& a) { return a.width * a.d_in; }
+__device__ __forceinline__ int small_wo(const TrainArgs& a) { return small_b(a) + a.n_hidden * a.width; }
+__device__ __forceinline__ int small_bo(const TrainArgs& a) { return small_wo(a) + a.d_out * a.width; }
+__device__ __forceinline__ int64_t small_param(const TrainArgs& a, int i) {
+  if (i < small_b(a)) return a.off_w[0] + i;
+  if (i < small_wo(a)) {
+    const int j = i - small_b(a);
+    return a.off_b[j / a.width] + j % a.width;
+  }
+  if (i < small_bo(a)) return a.off_w[a.n_hidden] + (i - small_wo(a));
+  return a.off_b[a.n_hidden] + (i - small_bo(a));
 }
 
 // Source row of batch row b (modes 1 and 2; see TrainArgs).
@@ -120,14 +146,21 @@ __global__ __launch_bounds__(256) void k_train_fwd(TrainArgs a) {
   for (int e = tid; e < a.d_out * W; e += blockDim.x) swo[e] = a.params[a.off_w[L] + e];
   load_rows(a, row0, sx, sy, srow);
   __syncthreads();
-  // first layer (FP32): Z0 = X W0^T + b0, H0 = SiLU(Z0)
+  // first layer (FP32): Z0 = X W0^T + b0, H0 = SiLU(Z0).  A thread keeps one
+  // unit c (its weights and bias in registers) over rows r = tid / W, + 256 / W ...
+  static_assert(256 % W == 0, "width divides the block");
   {
+    const int c = tid % W;
     const float* W0 = a.params + a.off_w[0];
-    const float* b0 = a.params + a.off_b[0];
-    for (int e = tid; e < kR * W; e += blockDim.x) {
-      const int r = e / W, c = e % W;
-      float z = b0[c];
-      for (int k = 0; k < a.d_in; ++k) z = fmaf(W0[c * a.d_in + k], sx[r * kMaxCols + k], z);
+    float w0c[kMaxCols];
+#pragma unroll
+    for (int k = 0; k < kMaxCols; ++k) w0c[k] = k < a.d_in ? W0[c * a.d_in + k] : 0.0f;
+    const float b0c = a.params[a.off_b[0] + c];
+    for (int r = tid / W; r < kR; r += 256 / W) {
+      float z = b0c;
+#pragma unroll
+      for (int k = 0; k < kMaxCols; ++k)
+        if (k < a.d_in) z = fmaf(w0c[k], sx[r * kMaxCols + k], z);
       if (a.store) a.Z[(row0 + r) * W + c] = z;
       sh[0][r * LD + c] = __bf16(silu(z));
     }
@@ -141,12 +174,13 @@ __global__ __launch_bounds__(256) void k_train_fwd(TrainArgs a) {
     const __bf16* Wl = static_cast<const __bf16*>(a.wbf) + int64_t(l - 1) * W * W;
     const float* bl = a.params + a.off_b[l];
     for (int t = wave; t < W / 32; t += 4) {
-      const f32x16 acc = tile_mfma<W>(src, LD, Wl, 32 * t);
       const int col = 32 * t + (lane & 31);
+      const float bias = bl[col];
+      const f32x16 acc = tile_mfma<W>(src, LD, Wl, 32 * t);
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         const int row = 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
-        const float z = acc[j] + bl[col];
+        const float z = acc[j] + bias;
         if (a.store) a.Z[(int64_t(l) * B + row0 + row) * W + col] = z;
         dst[row * LD + col] = __bf16(silu(z));
       }
@@ -210,7 +244,7 @@ __global__ __launch_bounds__(256) void k_train_bwd(TrainArgs a) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int64_t B = a.B, row0 = int64_t(blockIdx.x) * kR;
   const int L = a.n_hidden;
-  float* grad = a.grad;
+  float* part = a.part + int64_t(blockIdx.x) * train_n_small(a.d_in, a.d_out, W, L);
   const __bf16* Ht = static_cast<const __bf16*>(a.Ht);
   for (int e = tid; e < kR * a.d_out; e += blockDim.x) {
     const int r = e / a.d_out, j = e % a.d_out;
@@ -231,12 +265,12 @@ __global__ __launch_bounds__(256) void k_train_bwd(TrainArgs a) {
     const int j = e / W, k = e % W;
     float s = 0.0f;
     for (int r = 0; r < kR; ++r) s = fmaf(sg[r * kMaxCols + j], float(sb[r * LD + k]), s);
-    atomicAdd(&grad[a.off_w[L] + e], s);
+    part[small_wo(a) + e] = s;
   }
   if (tid < a.d_out) {
     float s = 0.0f;
     for (int r = 0; r < kR; ++r) s += sg[r * kMaxCols + tid];
-    atomicAdd(&grad[a.off_b[L] + tid], s);
+    part[small_bo(a) + tid] = s;
   }
   // delta of the last hidden layer: (G Wout) * SiLU'(Z)
   for (int e = tid; e < kR * W; e += blockDim.x) {
@@ -251,7 +285,7 @@ __global__ __launch_bounds__(256) void k_train_bwd(TrainArgs a) {
     for (int c = tid; c < W; c += blockDim.x) {
       float s = 0.0f;
       for (int r = 0; r < kR; ++r) s += sd[r * W + c];
-      atomicAdd(&grad[a.off_b[l] + c], s);
+      part[small_b(a) + l * W + c] = s;
     }
     for (int e = tid; e < kR * W; e += blockDim.x) {
       const int r = e / W, c = e % W;
@@ -280,34 +314,60 @@ __global__ __launch_bounds__(256) void k_train_bwd(TrainArgs a) {
   for (int c = tid; c < W; c += blockDim.x) {
     float s = 0.0f;
     for (int r = 0; r < kR; ++r) s += sd[r * W + c];
-    atomicAdd(&grad[a.off_b[0] + c], s);
+    part[small_b(a) + c] = s;
   }
   for (int e = tid; e < W * a.d_in; e += blockDim.x) {
     const int c = e / a.d_in, i = e % a.d_in;
     float s = 0.0f;
     for (int r = 0; r < kR; ++r) s = fmaf(sd[r * W + c], sxb[r * kMaxCols + i], s);
-    atomicAdd(&grad[a.off_w[0] + e], s);
+    part[e] = s;
   }
 }
 
-// One wave per (layer, 32 x 32 tile, batch chunk): dW_l[m][n] += sum_k Dt_l[m][k] Ht_{l-1}[n][k].
+// Two kinds of block of 4 waves.  The first (n_hidden - 1) TILES chunks / 4:
+// one wave per (layer, 32 x 32 tile, batch chunk), dW_l[m][n] += sum over the
+// chunk's rows k of Dt_l[m][k] Ht_{l-1}[n][k], the chunks' partial sums meeting
+// in atomics.  The rest sum k_train_bwd's per-block partials into the small
+// layers' gradients: 64 elements per block, wave w adding the partials of batch
+// blocks w, w + 4, ... (a wave's loads are 64 consecutive elements), the four
+// waves' sums meeting in LDS.
+template <int W>
+__device__ __forceinline__ int wgrad_tasks(const TrainArgs& a) {
+  return (a.n_hidden - 1) * (W / 32) * (W / 32) * (a.B / wgrad_chunk(a.B));
+}
+
 template <int W>
 __global__ __launch_bounds__(256) void k_train_wgrad(TrainArgs a) {
   constexpr int TILES = (W / 32) * (W / 32);
-  const int lane = threadIdx.x & 63, r = lane & 31, kq = 8 * (lane >> 5);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r = lane & 31, kq = 8 * (lane >> 5);
+  const int task_blocks = (wgrad_tasks<W>(a) + 3) / 4;
+  if (int(blockIdx.x) >= task_blocks) {        // block-uniform
+    __shared__ float red[4 * 64];
+    const int ns = train_n_small(a.d_in, a.d_out, W, a.n_hidden), nb = a.B / kR;
+    const int i = (int(blockIdx.x) - task_blocks) * 64 + lane;
+    float s = 0.0f;
+    if (i < ns) {
+#pragma unroll 8
+      for (int b = wave; b < nb; b += 4) s += a.part[int64_t(b) * ns + i];
+    }
+    red[wave * 64 + lane] = s;
+    __syncthreads();
+    if (wave == 0 && i < ns) a.grad[small_param(a, i)] += red[lane] + red[64 + lane] + red[128 + lane] + red[192 + lane];
+    return;
+  }
   const int64_t B = a.B;
-  const int chunks = int(B / a.wgrad_chunk);
-  const int64_t task = int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (task >= int64_t(a.n_hidden - 1) * TILES * chunks) return;       // wave-uniform
-  const int chunk = int(task % chunks);
-  const int tile = int((task / chunks) % TILES);
-  const int l = 1 + int(task / (int64_t(chunks) * TILES));
+  const int chunk_rows = wgrad_chunk(a.B), chunks = int(B / chunk_rows);
+  const int task = int(blockIdx.x) * 4 + wave;
+  if (task >= wgrad_tasks<W>(a)) return;       // wave-uniform
+  const int chunk = task % chunks;
+  const int tile = (task / chunks) % TILES;
+  const int l = 1 + task / (chunks * TILES);
   const int m0 = 32 * (tile / (W / 32)), n0 = 32 * (tile % (W / 32));
   const __bf16* A = static_cast<const __bf16*>(a.Dt) + (int64_t(l) * W + m0 + r) * B;
   const __bf16* Bm = static_cast<const __bf16*>(a.Ht) + (int64_t(l - 1) * W + n0 + r) * B;
   f32x16 acc = {};
-  const int64_t k1 = int64_t(chunk + 1) * a.wgrad_chunk;
-  for (int64_t k0 = int64_t(chunk) * a.wgrad_chunk; k0 < k1; k0 += 16) {
+  const int64_t k1 = int64_t(chunk + 1) * chunk_rows;
+  for (int64_t k0 = int64_t(chunk) * chunk_rows; k0 < k1; k0 += 16) {
     const bf16x8 av = *reinterpret_cast<const bf16x8*>(A + k0 + kq);
     const bf16x8 bv = *reinterpret_cast<const bf16x8*>(Bm + k0 + kq);
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
@@ -355,8 +415,9 @@ hipError_t launch_step(const TrainArgs& a, int pass, hipStream_t st) {
   } else if (pass == 1) {
     hipLaunchKernelGGL(k_train_bwd<W>, dim3(rows), dim3(256), 0, st, a);
   } else {
-    const int64_t tasks = int64_t(a.n_hidden - 1) * (W / 32) * (W / 32) * (a.B / a.wgrad_chunk);
-    hipLaunchKernelGGL(k_train_wgrad<W>, dim3(unsigned((tasks + 3) / 4)), dim3(256), 0, st, a);
+    const int ns = train_n_small(a.d_in, a.d_out, W, a.n_hidden);
+    const int tasks = (a.n_hidden - 1) * (W / 32) * (W / 32) * (a.B / wgrad_chunk(a.B));
+    hipLaunchKernelGGL(k_train_wgrad<W>, dim3(unsigned((tasks + 3) / 4 + (ns + 63) / 64)), dim3(256), 0, st, a);
   }
   return hipGetLastError();
 }
@@ -364,10 +425,7 @@ hipError_t launch_step(const TrainArgs& a, int pass, hipStream_t st) {
 hipError_t launch_pass(const TrainArgs& args, int pass, hipStream_t st) {
   if (args.B < kR || args.B % kR != 0 || args.n_hidden < 2 || args.n_hidden > kMaxHidden)
     return hipErrorInvalidValue;
-  TrainArgs a = args;
-  // batch rows per partial sum of the weight gradients: the largest of 512 .. 32 dividing B
-  a.wgrad_chunk = 512;
-  while (a.B % a.wgrad_chunk != 0) a.wgrad_chunk /= 2;
+  const TrainArgs& a = args;
   switch (a.width) {
     case 32: return launch_step<32>(a, pass, st);
     case 64: return launch_step<64>(a, pass, st);
