@@ -650,10 +650,15 @@ __device__ __forceinline__ void bridge_alternating(const T (&w)[K], const T (&wc
 // Slope iteration for the bridge over the centre (see hull_centre) on the
 // segments with todo set, from slope s: on return those that converged have
 // todo cleared, the pair (mp, mq), the tilted minima (ep, eq) and the slope s
-// of the last pass.  Every lane of the wave must call it.
+// of the last pass.  A pass at any slope bounds the hull value at the centre
+// from below by min(ep, eq, wc) (the line of that slope through the lowest
+// tilted sample lies under every sample); a segment whose bound exceeds thr
+// stops there too, with the pair and tilted minima of that pass, whose chord
+// value at the centre is then an upper bound.  Every lane of the wave must call
+// it.
 template <typename T, int S, int K>
 __device__ __forceinline__ void slope_bridge(const T (&w)[K], const Layout<T, S, K>& lay, bool& todo,
-                                             T& s, int& mp, int& mq, T& ep, T& eq) {
+                                             T& s, int& mp, int& mq, T& ep, T& eq, T wc, T thr) {
   constexpr int H = K / 2;
   const int sl = threadIdx.x & (S - 1);
   for (int pass = 0; pass < kSlopePasses && __any(todo); ++pass) {
@@ -675,6 +680,10 @@ __device__ __forceinline__ void slope_bridge(const T (&w)[K], const Layout<T, S,
     if (todo) {
       if (pass > 0 && mpn == mp && mqn == mq) {
         todo = false;
+        ep = epn; eq = eqn;
+      } else if (fmin(fmin(epn, eqn), wc) > thr) {
+        todo = false;
+        mp = mpn; mq = mqn;
         ep = epn; eq = eqn;
       } else {
         mp = mpn; mq = mqn;
@@ -705,6 +714,10 @@ __device__ __forceinline__ void slope_bridge(const T (&w)[K], const Layout<T, S,
 // start; a warm start (the previous point's slope on a nearby line) usually
 // needs two passes.
 //
+// thr: a line whose hull value at the centre is shown to exceed it may return
+// an upper bound above thr instead (see slope_bridge); +inf: exact for every
+// line.
+//
 // hot (wave-uniform): every line of the wave has a warm start.  The vertex
 // test is then skipped: the centre is a vertex exactly when the bridge of the
 // other samples passes above it.  If any line of the wave ends without a
@@ -712,7 +725,8 @@ __device__ __forceinline__ void slope_bridge(const T (&w)[K], const Layout<T, S,
 // standard path instead.
 template <typename T, int S, int K>
 __device__ __forceinline__ LineHull<T> hull_centre(const T (&w)[K], T wc, const T (&wci)[K / 2],
-                                                   const Layout<T, S, K>& lay, T& sig, bool hot) {
+                                                   const Layout<T, S, K>& lay, T& sig, bool hot,
+                                                   T thr = inf_v<T>()) {
   constexpr int H = K / 2;
   LineHull<T> r;
   r.h = wc; r.mp = 0; r.mq = 0; r.capped = 0;
@@ -722,7 +736,7 @@ __device__ __forceinline__ LineHull<T> hull_centre(const T (&w)[K], T wc, const 
     T s = sig;
     int mp = 0, mq = 0;
     T ep = T(0), eq = T(0);
-    slope_bridge<T, S, K>(w, lay, todo, s, mp, mq, ep, eq);
+    slope_bridge<T, S, K>(w, lay, todo, s, mp, mq, ep, eq, wc, thr);
     if (!__any(todo || !(mp >= 1 && mq >= 1))) {
       const T mpf = T(mp), mqf = T(mq);
       const T hb = (mqf * ep + mpf * eq) / (mqf + mpf);
@@ -761,7 +775,7 @@ __device__ __forceinline__ LineHull<T> hull_centre(const T (&w)[K], T wc, const 
   T s = sig == sig ? fmin(fmax(sig, minR), maxL) : T(0.5) * (maxL + minR);
   int mp = 0, mq = 0;
   T ep = T(0), eq = T(0);
-  slope_bridge<T, S, K>(w, lay, todo, s, mp, mq, ep, eq);
+  slope_bridge<T, S, K>(w, lay, todo, s, mp, mq, ep, eq, wc, thr);
   if (__any(todo)) {
     // slope budget spent (not seen in practice): finish with the alternating search
     T wp = T(0), wq = T(0);
@@ -866,10 +880,12 @@ struct Env {            // W^1 at a point: value, direction, bracketing offsets
 // another direction's value is within the tie margin: 1e-10 (FP64) or 1e-5
 // (FP32) of max(|W|, 1e-3 / 1e-2).
 template <typename T>
+__device__ __forceinline__ T tie_margin() { return sizeof(T) == 4 ? T(1e-5) : T(1e-10); }
+template <typename T>
+__device__ __forceinline__ T tie_floor() { return sizeof(T) == 4 ? T(1e-2) : T(1e-3); }
+template <typename T>
 __device__ __forceinline__ bool near_tie(const Env<T>& e) {
-  const T margin = sizeof(T) == 4 ? T(1e-5) : T(1e-10);
-  const T floor = sizeof(T) == 4 ? T(1e-2) : T(1e-3);
-  return (e.mp + e.mq) > 0 && e.second - e.h <= margin * fmax(fabs(e.h), floor);
+  return (e.mp + e.mq) > 0 && e.second - e.h <= tie_margin<T>() * fmax(fabs(e.h), tie_floor<T>());
 }
 
 // One lamination level at a point (wave-uniform): min over the level's n_dir
@@ -886,12 +902,14 @@ __device__ __forceinline__ bool near_tie(const Env<T>& e) {
 // uniform).  order (optional with warm, n_dir entries owned by this wave): the
 // directions are visited with those that had a bridge last time first, so that
 // lines needing a bridge search share wavefronts; ties in the minimum go to the
-// smaller direction index whatever the visiting order.  Every lane of the wave
-// must call it.
+// smaller direction index whatever the visiting order.  centre (optional): the
+// coefficients of the lines at t = 0 (J0, c0; the rest unused), when the caller
+// has them at hand; else line_fn(0) is taken.  Every lane of the wave must call
+// it.
 template <typename T, int S, int K, int M = kFamNH, typename LineFn>
 __device__ Env<T> envelope_lines(const Point<T>& q, T wc, int n_dir, const Layout<T, S, K>& lay,
                                  LineFn line_fn, T* warm = nullptr, T c2u = T(__builtin_nan("")),
-                                 int* order = nullptr) {
+                                 int* order = nullptr, const Line<T>* centre = nullptr) {
   constexpr int NSEG = kWave / S;
   constexpr int H = K / 2;
   const int lane = threadIdx.x & (kWave - 1);
@@ -903,7 +921,7 @@ __device__ Env<T> envelope_lines(const Point<T>& q, T wc, int n_dir, const Layou
   T wcs = wc;
   T base[H];
   if (scaled) {
-    const Line<T> L0 = line_fn(0);
+    const Line<T> L0 = centre ? *centre : line_fn(0);
     if constexpr (M == kFamSTVK) {
       wcs = ws_sample_stvk<T>(T(0), L0, q);
     } else {
@@ -917,6 +935,7 @@ __device__ Env<T> envelope_lines(const Point<T>& q, T wc, int n_dir, const Layou
   T wci[H];
 #pragma unroll
   for (int h = 0; h < H; ++h) wci[h] = wcs * lay.inv_m[h];
+  const T isc = scaled ? T(1) / q.sc : T(1);
   if (order) {
     // stable partition of the directions: warm (bridged last time) first
     int n_warm = 0;
@@ -966,6 +985,22 @@ __device__ Env<T> envelope_lines(const Point<T>& q, T wc, int n_dir, const Layou
         w[H + h] = w_sample_doublewell<T>(lay.t[h], L);
       }
     }
+    // lines that cannot come within twice the tie margin of the wave's best so
+    // far may stop their bridge search early: the minimum is unchanged and so
+    // is the tie flag (their value only enters the runner-up, beyond the
+    // margin).  Only for cold searches: warm-started lines come first in their
+    // visiting order and rarely meet a lower value already found.
+    T thr = inf_v<T>();
+    if (!warm) {
+      T bw = best.h;
+#pragma unroll
+      for (int off = S; off < kWave; off <<= 1) bw = fmin(bw, __shfl_xor(bw, off, kWave));
+      if (bw < inf_v<T>()) {
+        const T bW = scaled ? fma(bw, q.sc, q.B) : bw;
+        const T mW = T(2) * tie_margin<T>() * fmax(fabs(bW), tie_floor<T>());
+        thr = bw + (scaled ? mW * isc : mW);
+      }
+    }
     T sg = T(__builtin_nan("")), s1 = sg;
     if (warm && act) {
       s1 = warm[dir];
@@ -974,7 +1009,7 @@ __device__ Env<T> envelope_lines(const Point<T>& q, T wc, int n_dir, const Layou
       sg = s2 == s2 ? fma(T(2), s1, -s2) : s1;
     }
     const bool hot = warm && __all(act && s1 == s1);
-    LineHull<T> lh = hull_centre<T, S, K>(w, wcs, wci, lay, sg, hot);
+    LineHull<T> lh = hull_centre<T, S, K>(w, wcs, wci, lay, sg, hot, thr);
     if (warm && act && (lane & (S - 1)) == 0) {
       warm[n_dir + dir] = sg == sg ? s1 : sg;
       warm[dir] = sg;
@@ -1018,12 +1053,18 @@ template <typename T, int D, int S, int K, int M = kFamNH>
 __device__ Env<T> envelope_at(const Point<T>& q, const double* G, T wc, const Level& lv,
                               const Layout<T, S, K>& lay) {
   const auto g = make_geom_m<D, M>(G);
+  // neo-Hooke: every line through G starts at J0 = det G, c0 = kq (|G|^2 - d) (line_of)
+  Line<T> c{};
+  if constexpr (M != kFamSTVK) {
+    c.J0 = T(g.det);
+    c.c0 = T(q.kq * (g.n2 - double(D)));
+  }
   return envelope_lines<T, S, K, M>(q, wc, lv.n_dir, lay, [&](int dd) {
     double a[D], b[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) { a[i] = lv.a[dd * D + i]; b[i] = lv.b[dd * D + i]; }
     return line_of<T, D, M>(q, g, a, b);
-  }, nullptr, T(q.kq * lv.ab2));
+  }, nullptr, T(q.kq * lv.ab2), nullptr, (M != kFamSTVK && q.model == 0) ? &c : nullptr);
 }
 
 // Lines of an inner level along an outer line G(t_o) = F + t_o R_o, R_o rank one.

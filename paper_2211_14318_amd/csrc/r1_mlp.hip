@@ -354,8 +354,11 @@ __global__ __launch_bounds__(512) void k_infer_lds(InferParams ip, const T* F, c
     f32x16 acc[NT];
     for (int l = 1; l < L; ++l) {
       const __bf16* wlay = wl + size_t(l - 1) * WID * LDW;
+      // the accumulators start at the bias (the MFMA sums onto it)
 #pragma unroll
-      for (int t = 0; t < NT; ++t) acc[t] = f32x16{};
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[t][j] = bb[l * WID + t * 32 + 8 * (j >> 2) + 4 * half + (j & 3)];
 #pragma unroll
       for (int s = 0; s < NS; ++s)
 #pragma unroll
@@ -367,7 +370,7 @@ __global__ __launch_bounds__(512) void k_infer_lds(InferParams ip, const T* F, c
       for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int j = 0; j < 16; ++j)
-          acc[t][j] = silu(acc[t][j] + bb[l * WID + t * 32 + 8 * (j >> 2) + 4 * half + (j & 3)]);
+          acc[t][j] = silu(acc[t][j]);
       if (l + 1 < L) {
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
