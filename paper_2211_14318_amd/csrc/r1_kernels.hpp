@@ -88,9 +88,30 @@ __device__ __forceinline__ void write_bad_point(const KArgs& a, int64_t p, bool 
       a.tree[p * R1_TREE_NODES + k] = r1_laminate{0, 0, 0, 1.0f};
 }
 
+// The one-level laminate's stress at point p (eq. 5.2 on the one-level tree of
+// Algorithm 3): P = xi P0(F+) + (1 - xi) P0(F-), F-/+ = G -/+ t a(x)b at offsets
+// mp, mq of direction dir, xi = mp / (mp + mq), written to row k of P.  One
+// thread's work; the one-level kernels and the batched point work share it, so
+// that both give the same bits.
+template <typename T, int D, int M>
+__device__ __forceinline__ void laminate_stress1(const KArgs& a, int64_t p, const Level& lv, const Point<T>& q,
+                                                 const double* G, double bn, int dir, int mp, int mq) {
+  double Gm[D * D], Gp[D * D], Pm[D * D], Pp[D * D];
+  line_point<D>(G, lv, dir, -t_of(lv, mp), Gm);
+  line_point<D>(G, lv, dir, t_of(lv, mq), Gp);
+  stress_at<T, D, M>(q, a.mat, bn, Gm, Pm);
+  stress_at<T, D, M>(q, a.mat, bn, Gp, Pp);
+  const double xi = (mp + mq) ? double(mp) / double(mp + mq) : 1.0;
+#pragma unroll
+  for (int k = 0; k < D * D; ++k)
+    static_cast<T*>(a.P)[int64_t(k) * a.n + p] = T(fma(xi, Pp[k], (1.0 - xi) * Pm[k]));
+}
+
 // One-level envelope of point p on level lv, with stress, tree and flags as
-// requested by a (wave-level: every lane of the wave calls it).
-template <typename T, int D, int S, int K, int M>
+// requested by a (wave-level: every lane of the wave calls it).  kDefer: the
+// stress is left to k_stress1, which finds the point's laminate (direction,
+// m_-, m_+) as integers in the first T slot of rows 0, 1, 2 of P.
+template <typename T, int D, int S, int K, int M, bool kDefer = false>
 __device__ __forceinline__ void point_depth1(const KArgs& a, int64_t p, const Level& lv) {
   double G[D * D], bn;
   bool fin = load_point<T, D>(a, p, G, bn);
@@ -104,27 +125,17 @@ __device__ __forceinline__ void point_depth1(const KArgs& a, int64_t p, const Le
     return;
   }
   Env<T> e = envelope_at<T, D, S, K, M>(q, G, wc, lv, lay);
-  // the laminate's endpoint stresses, P(F-) on lane 0 and P(F+) on lane 1 at once
-  const bool stress = a.want_stress && a.P;
-  double Pm[D * D] = {}, Pp[D * D];
-  if (stress) {
-    if (lane_id() < 2) {
-      double Ge[D * D];
-      line_point<D>(G, lv, e.dir, lane_id() == 0 ? -t_of(lv, e.mp) : t_of(lv, e.mq), Ge);
-      stress_at<T, D, M>(q, a.mat, bn, Ge, Pm);
-    }
-#pragma unroll
-    for (int k = 0; k < D * D; ++k) Pp[k] = __shfl(Pm[k], 1, kWave);
-  }
+  const bool stress = a.want_stress && a.P && !kDefer;
   if (lane_id() == 0) {
     static_cast<T*>(a.W)[p] = e.h;
-    const int c = (lv.n_t - 1) / 2;
-    if (stress) {
-      double xi = (e.mp + e.mq) ? double(e.mp) / double(e.mp + e.mq) : 1.0;
-#pragma unroll
-      for (int k = 0; k < D * D; ++k)
-        static_cast<T*>(a.P)[int64_t(k) * a.n + p] = T(xi * Pp[k] + (1.0 - xi) * Pm[k]);
+    if (kDefer && a.want_stress && a.P) {
+      T* P = static_cast<T*>(a.P);
+      *reinterpret_cast<int32_t*>(P + p) = e.dir;
+      *reinterpret_cast<int32_t*>(P + a.n + p) = e.mp;
+      *reinterpret_cast<int32_t*>(P + 2 * a.n + p) = e.mq;
     }
+    const int c = (lv.n_t - 1) / 2;
+    if (stress) laminate_stress1<T, D, M>(a, p, lv, q, G, bn, e.dir, e.mp, e.mq);
     if (a.tree) {
       float xi = (e.mp + e.mq) ? float(double(e.mp) / double(e.mp + e.mq)) : 1.0f;
       a.tree[p * R1_TREE_NODES] = r1_laminate{e.dir, c - e.mp, c + e.mq, xi};
@@ -138,7 +149,27 @@ template <typename T, int D, int S, int K, int M>
 __global__ __launch_bounds__(256, (sizeof(T) == 4 && K <= 16) ? 3 : 1) void k_depth1(KArgs a) {
   const int64_t p = int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
   if (p >= a.n) return;                       // wave-uniform
-  point_depth1<T, D, S, K, M>(a, p, a.lv0);
+  point_depth1<T, D, S, K, M, true>(a, p, a.lv0);
+}
+
+// Laminate stress of the one-level points (eq. 5.2 on the one-level tree of
+// Algorithm 3: P = xi P0(F+) + (1 - xi) P0(F-)), one thread per point, after
+// k_depth1: it reads the laminate k_depth1 left in P (see point_depth1) and
+// overwrites it with the stress.  Points k_depth1 found bad (W NaN or +inf)
+// already hold NaN stresses.
+template <typename T, int D, int M>
+__global__ __launch_bounds__(256) void k_stress1(KArgs a) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= a.n) return;
+  const T w = static_cast<const T*>(a.W)[p];
+  if (!(w < inf_v<T>())) return;
+  T* P = static_cast<T*>(a.P);
+  const int dir = *reinterpret_cast<const int32_t*>(P + p);
+  const int mp = *reinterpret_cast<const int32_t*>(P + a.n + p);
+  const int mq = *reinterpret_cast<const int32_t*>(P + 2 * a.n + p);
+  double G[D * D], bn;
+  load_point<T, D>(a, p, G, bn);
+  laminate_stress1<T, D, M>(a, p, a.lv0, make_point<T, M>(a.mat, bn), G, bn, dir, mp, mq);
 }
 
 // Outer hull of an LDS-resident line (wave-wide, S = 64): wl[m-1] / wr[m-1] are
@@ -516,6 +547,8 @@ hipError_t launch_T(const KArgs& a, int depth, hipStream_t st, KTimer* tm) {
     dim3 grd(unsigned((a.n + per - 1) / per));
     if (tm) tm->begin("depth1", st);
     hipLaunchKernelGGL((k_depth1<T, D, S, K, M>), grd, blk, 0, st, a);
+    if (a.want_stress && a.P)
+      hipLaunchKernelGGL((k_stress1<T, D, M>), dim3(unsigned((a.n + 255) / 256)), blk, 0, st, a);
     if (tm) tm->end(st);
     return hipGetLastError();
   }
