@@ -23,10 +23,13 @@
 
 namespace {
 
+// A sample in the form the chords are compared in: the damage energies in the
+// hull form (W - B)/sc (sc > 0, so the sign of every chord test is kept when the
+// target takes the same form), the double-well energy as it is.
 template <typename T, int D, int M>
 __device__ __forceinline__ float sample_at(float t, const r1d::Line<float>& L, const r1d::Point<float>& q) {
-  if constexpr (M == r1d::kFamSTVK) return r1d::w_sample_stvk<float>(t, L, q);
-  return q.model == 0 ? r1d::w_sample<float>(t, L, q) : r1d::w_sample_doublewell<float>(t, L);
+  if constexpr (M == r1d::kFamSTVK) return r1d::ws_sample_stvk<float>(t, L, q);
+  return q.model == 0 ? r1d::ws_sample<float>(t, L, q) : r1d::w_sample_doublewell<float>(t, L);
 }
 
 // Point p passes when no subset chord of any direction passes below the target.
@@ -37,17 +40,18 @@ __device__ bool passes(const CheckArgs& a, int64_t p) {
   for (int k = 0; k < D * D; ++k) G[k] = double(static_cast<const T*>(a.F)[int64_t(k) * a.n + p]);
   const double bn = double(static_cast<const T*>(a.beta_n)[p]);
   const float w = float(static_cast<const T*>(a.W)[p]);
-  const float target = w - a.eps * fmaxf(fabsf(w), 0.01f);
   double cof[D * D];
   r1d::cofactor<D>(G, cof);
   const r1d::Point<float> q = r1d::make_point<float, M>(a.mat, bn);
+  float target = w - a.eps * fmaxf(fabsf(w), 0.01f);
+  if (M == r1d::kFamSTVK || q.model == 0) target = (target - q.B) / q.sc;
   const float dt = float(a.lv.tau / double((a.lv.n_t - 1) / 2));
   for (int m = 0; m < a.lv.n_dir; ++m) {
     const r1d::Line<float> L = r1d::line_setup<float, D, M>(q, G, cof, a.lv.a + m * D, a.lv.b + m * D);
     float lo = __builtin_inff(), hi = __builtin_inff();
     for (int k = 0; k < a.n_off; ++k) {
       const float o = float(a.off[k]);
-      const float inv = 1.0f / o;
+      const float inv = a.off_inv[k];
       // NaN samples (det <= 0) are absent: fminf keeps the other operand
       lo = fminf(lo, (sample_at<T, D, M>(-o * dt, L, q) - target) * inv);
       hi = fminf(hi, (sample_at<T, D, M>(o * dt, L, q) - target) * inv);
@@ -101,8 +105,12 @@ int r1_check_offsets(int n_t, int* off) {
   return n;
 }
 
-hipError_t r1_launch_check(int dtype, const CheckArgs& a, hipStream_t st) {
-  if (a.n <= 0) return hipSuccess;
+hipError_t r1_launch_check(int dtype, const CheckArgs& args, hipStream_t st) {
+  if (args.n <= 0) return hipSuccess;
+  // the reciprocals of the offsets, once here instead of a division per sample pair
+  // and direction in the kernel (IEEE float division on both sides: the same bits)
+  CheckArgs a = args;
+  for (int k = 0; k < a.n_off; ++k) a.off_inv[k] = 1.0f / float(a.off[k]);
   if (dtype == R1_F32) return a.mat.dim == 2 ? launch_TD<float, 2>(a, st) : launch_TD<float, 3>(a, st);
   return a.mat.dim == 2 ? launch_TD<double, 2>(a, st) : launch_TD<double, 3>(a, st);
 }
