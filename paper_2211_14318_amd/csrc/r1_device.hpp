@@ -113,11 +113,11 @@ constexpr int kFamSTVK = 2;
 // the lamination works on Ws = (W - B)/sc with sc = -E1/k:
 //   Ws = -u + A2 v + C2 exp_k(v),  A2 = (D_inf - D_n)/(1 - D_n),  C2 = -C/sc,
 // two FMAs after the exponential instead of three; W = sc Ws + B is formed
-// once per envelope.
+// once per envelope.  Every sample is taken in this form.
 template <typename T>
 struct Point {
   T klk, kmk;            // k lambda/2 (ln2^2), k mu (ln2)
-  T ub, E1k, Aqk, B, negC;
+  T ub, B;               // k beta_n; B
   T sc, A2, C2;          // hull form (above)
   double kq;             // scale of the line polynomial, applied in double (line_scale)
   double lam, mu;        // Lame parameters (St. Venant-Kirchhoff line coefficients)
@@ -148,9 +148,6 @@ __device__ __forceinline__ Point<T> make_point(const Material& m, double bn) {
   q.kmk = T(k * (f32 ? m.mu * ln2 : m.mu));
   q.klk = T(k * (f32 ? 0.5 * m.lambda * ln2 * ln2 : 0.5 * m.lambda));
   q.ub = T(k * bn);
-  q.E1k = T((1.0 - Dn) * ik);
-  q.Aqk = T((Dn - m.D_inf) * ik);
-  q.negC = T(-m.D_inf * m.D0);
   q.B = T(m.D_inf * e * (bn + m.D0));
   q.sc = T(-(1.0 - Dn) * ik);
   q.A2 = T((m.D_inf - Dn) * i1D);
@@ -330,34 +327,13 @@ __device__ __forceinline__ Line<T> line_setup(const Point<T>& q, const double* G
   return L;
 }
 
-// One sample of W on a line (9 VALU + 2 transcendental; the envelopes sample
-// the hull form below, W itself is for the a-posteriori check).  The line's
-// c0, c1, c2 are the scaled polynomial k mu/2 |G(t)|^2 - d (see Point).
+// One sample of W on a line in the hull form Ws = (W - B)/sc (see Point): 8
+// VALU + 2 transcendental, 7 + 2 when the part of the line polynomial common to
+// every line through the point comes per sample (base = c0 + c2 t^2), 6 + 1 for
+// St. Venant-Kirchhoff (the quartic k psi0(t), then the damage part).  The
+// line's c0, c1, c2 are the scaled polynomial k mu/2 |G(t)|^2 - d (see Point).
 // det <= 0 gives NaN (J < 0) or NaN/+inf (J = 0): such samples lie outside the
 // admissible interval and every hull comparison below treats NaN as absent.
-template <typename T>
-__device__ __forceinline__ T w_sample(T t, const Line<T>& L, const Point<T>& q) {
-  T J = fma(t, L.J1, L.J0);
-  T u = fma(t, fma(t, L.c2, L.c1), L.c0);
-  T lj = lg_t(J);
-  u = fma(lj, fma(q.klk, lj, -q.kmk), u);
-  T v = fmin(u, q.ub);
-  return fma(q.negC, expk(v), fma(q.E1k, u, fma(q.Aqk, v, q.B)));
-}
-
-// St. Venant-Kirchhoff sample: the quartic k psi0(t), then the damage part of
-// w_sample (7 VALU + 1 transcendental).
-template <typename T>
-__device__ __forceinline__ T w_sample_stvk(T t, const Line<T>& L, const Point<T>& q) {
-  T u = fma(t, fma(t, fma(t, fma(t, L.c4, L.c3), L.c2), L.c1), L.c0);
-  T v = fmin(u, q.ub);
-  return fma(q.negC, expk(v), fma(q.E1k, u, fma(q.Aqk, v, q.B)));
-}
-
-// The same samples in the hull form Ws = (W - B)/sc (see Point): 8 VALU + 2
-// transcendental, 7 + 2 when the part of the line polynomial common to every
-// line through the point comes per sample (base = c0 + c2 t^2), 6 + 1 for St.
-// Venant-Kirchhoff.
 template <typename T>
 __device__ __forceinline__ T ws_sample(T t, const Line<T>& L, const Point<T>& q) {
   T J = fma(t, L.J1, L.J0);
@@ -1216,7 +1192,7 @@ __device__ __forceinline__ void stress0_any(const Material& m, double bn, const 
 // Laminate endpoint stress in the path's precision.  FP64: stress0.  FP32: the
 // same first Piola-Kirchhoff stress, with cof G, det G and |G|^2 still formed in
 // FP64 but ln J and the damage exponential taken, as for the samples, from the
-// FP32 log2 / exp2 in the point's scaled constants (k psi0 as in w_sample, then
+// FP32 log2 / exp2 in the point's scaled constants (k psi0 as in ws_sample, then
 // e^{-beta/D0} = exp_k(min(k psi0, k beta_n))) and 1/J from the FP32 reciprocal.
 template <typename T, int D, int M>
 __device__ __forceinline__ void stress_at(const Point<T>& q, const Material& m, double bn, const double* G,
