@@ -140,7 +140,9 @@ r1_status r1_envelope(r1_handle handle, const r1_material* material,
 
 /* As r1_envelope, plus the laminate-endpoint stress P (d*d x n SoA, eq. 5.2)
  * and, if tree != NULL, the lamination tree: R1_TREE_NODES r1_laminate per
- * point, tree[p*R1_TREE_NODES + node]. */
+ * point, tree[p*R1_TREE_NODES + node].  The outputs (W, P, tree, flags) must
+ * not overlap the inputs or each other: at depth 1 the call keeps each point's
+ * laminate in P's first rows until its stress replaces it. */
 r1_status r1_envelope_stress(r1_handle handle, const r1_material* material,
                              const r1_lamination* lamination, int64_t n, r1_dtype dtype,
                              const void* F, const void* beta_n, void* W, void* P,
