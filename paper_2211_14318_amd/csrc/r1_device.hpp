@@ -1024,11 +1024,11 @@ __device__ Env<T> envelope_lines(const Point<T>& q, T wc, int n_dir, const Layou
   return best;
 }
 
-// One lamination level at point G with the lines set up from G's geometry.
+// One lamination level at a point with the lines set up from its geometry g
+// (make_geom_m).
 template <typename T, int D, int S, int K, int M = kFamNH>
-__device__ Env<T> envelope_at(const Point<T>& q, const double* G, T wc, const Level& lv,
-                              const Layout<T, S, K>& lay) {
-  const auto g = make_geom_m<D, M>(G);
+__device__ Env<T> envelope_geom(const Point<T>& q, const typename GeomOf<D, M>::type& g, T wc, const Level& lv,
+                                const Layout<T, S, K>& lay) {
   // neo-Hooke: every line through G starts at J0 = det G, c0 = kq (|G|^2 - d) (line_of)
   Line<T> c{};
   if constexpr (M != kFamSTVK) {
@@ -1041,6 +1041,13 @@ __device__ Env<T> envelope_at(const Point<T>& q, const double* G, T wc, const Le
     for (int i = 0; i < D; ++i) { a[i] = lv.a[dd * D + i]; b[i] = lv.b[dd * D + i]; }
     return line_of<T, D, M>(q, g, a, b);
   }, nullptr, T(q.kq * lv.ab2), nullptr, (M != kFamSTVK && q.model == 0) ? &c : nullptr);
+}
+
+// The same at point G.
+template <typename T, int D, int S, int K, int M = kFamNH>
+__device__ Env<T> envelope_at(const Point<T>& q, const double* G, T wc, const Level& lv,
+                              const Layout<T, S, K>& lay) {
+  return envelope_geom<T, D, S, K, M>(q, make_geom_m<D, M>(G), wc, lv, lay);
 }
 
 // Lines of an inner level along an outer line G(t_o) = F + t_o R_o, R_o rank one.

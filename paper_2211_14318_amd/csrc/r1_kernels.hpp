@@ -107,24 +107,48 @@ __device__ __forceinline__ void laminate_stress1(const KArgs& a, int64_t p, cons
     static_cast<T*>(a.P)[int64_t(k) * a.n + p] = T(fma(xi, Pp[k], (1.0 - xi) * Pm[k]));
 }
 
-// One-level envelope of point p on level lv, with stress, tree and flags as
-// requested by a (wave-level: every lane of the wave calls it).  kDefer: the
-// stress is left to k_stress1, which finds the point's laminate (direction,
-// m_-, m_+) as integers in the first T slot of rows 0, 1, 2 of P.
-template <typename T, int D, int S, int K, int M, bool kDefer = false>
-__device__ __forceinline__ void point_depth1(const KArgs& a, int64_t p, const Level& lv) {
-  double G[D * D], bn;
-  bool fin = load_point<T, D>(a, p, G, bn);
-  Layout<T, S, K> lay = make_layout<T, S, K>(lv);
-  Point<T> q = make_point<T, M>(a.mat, bn);
+// Per-point constants of a one-level envelope: the geometry (which holds G),
+// the constants of W, W at the point, and the point's state (0: finite and
+// admissible; 1: non-finite input; 2: W(F) = +inf, det F <= 0).
+template <typename T, int D, int M>
+struct PointSetup {
+  typename GeomOf<D, M>::type g;
+  Point<T> q;
+  double bn;
+  T wc;
+  int state;
+};
+
+template <typename T, int D, int M>
+__device__ __forceinline__ PointSetup<T, D, M> point_setup(const KArgs& a, int64_t p) {
+  PointSetup<T, D, M> s;
+  double G[D * D];
+  const bool fin = load_point<T, D>(a, p, G, s.bn);
+  s.q = make_point<T, M>(a.mat, s.bn);
   double cof[D * D];
   cofactor<D>(G, cof);
-  T wc = w_point<T, D, M>(q, G, cof);
-  if (!fin || !(wc < inf_v<T>())) {
-    if (lane_id() == 0) write_bad_point<T, D>(a, p, !fin, a.want_stress);
+  s.wc = w_point<T, D, M>(s.q, G, cof);
+  s.g = make_geom_m<D, M>(G);
+  s.state = !fin ? 1 : (s.wc < inf_v<T>() ? 0 : 2);
+  return s;
+}
+
+// One-level envelope of point p on level lv from its constants s, with stress,
+// tree and flags as requested by a (wave-level: every lane of the wave calls
+// it).  kDefer: the stress is left to k_stress1, which finds the point's
+// laminate (direction, m_-, m_+) as integers in the first T slot of rows 0, 1,
+// 2 of P.
+template <typename T, int D, int S, int K, int M, bool kDefer = false>
+__device__ __forceinline__ void point_depth1_body(const KArgs& a, int64_t p, const Level& lv,
+                                                  const Layout<T, S, K>& lay, const PointSetup<T, D, M>& s) {
+  if (s.state != 0) {
+    if (lane_id() == 0) write_bad_point<T, D>(a, p, s.state == 1, a.want_stress);
     return;
   }
-  Env<T> e = envelope_at<T, D, S, K, M>(q, G, wc, lv, lay);
+  const Point<T>& q = s.q;
+  const double* G = s.g.G;
+  const double bn = s.bn;
+  Env<T> e = envelope_geom<T, D, S, K, M>(q, s.g, s.wc, lv, lay);
   const bool stress = a.want_stress && a.P && !kDefer;
   if (lane_id() == 0) {
     static_cast<T*>(a.W)[p] = e.h;
@@ -145,11 +169,33 @@ __device__ __forceinline__ void point_depth1(const KArgs& a, int64_t p, const Le
   }
 }
 
+// The same with the point's constants formed in place.
+template <typename T, int D, int S, int K, int M, bool kDefer = false>
+__device__ __forceinline__ void point_depth1(const KArgs& a, int64_t p, const Level& lv) {
+  point_depth1_body<T, D, S, K, M, kDefer>(a, p, lv, make_layout<T, S, K>(lv), point_setup<T, D, M>(a, p));
+}
+
+// One-level launch: a block of 4 waves takes kPointsPerWave points per wave.
+// Their constants are formed by one thread per point into LDS first (a point's
+// FP64 set-up then costs a lane, not a wavefront), then each wave laminates its
+// points one after the other.
+constexpr int kPointsPerWave = 8;
+constexpr int kPointsPerBlock = 4 * kPointsPerWave;
+
 template <typename T, int D, int S, int K, int M>
-__global__ __launch_bounds__(256, (sizeof(T) == 4 && K <= 16) ? 3 : 1) void k_depth1(KArgs a) {
-  const int64_t p = int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (p >= a.n) return;                       // wave-uniform
-  point_depth1<T, D, S, K, M, true>(a, p, a.lv0);
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? ((D == 2 && M == kFamNH && K <= 14) ? 4 : K <= 16 ? 3 : 1) : 1) void k_depth1(KArgs a) {
+  __shared__ PointSetup<T, D, M> ps[kPointsPerBlock];
+  const int64_t p0 = int64_t(blockIdx.x) * kPointsPerBlock;
+  if (threadIdx.x < kPointsPerBlock && p0 + threadIdx.x < a.n) ps[threadIdx.x] = point_setup<T, D, M>(a, p0 + threadIdx.x);
+  __syncthreads();
+  const Layout<T, S, K> lay = make_layout<T, S, K>(a.lv0);
+  const int wave = threadIdx.x / kWave;
+  for (int i = 0; i < kPointsPerWave; ++i) {
+    const int slot = i * 4 + wave;
+    const int64_t p = p0 + slot;
+    if (p >= a.n) break;                      // wave-uniform
+    point_depth1_body<T, D, S, K, M, true>(a, p, a.lv0, lay, ps[slot]);
+  }
 }
 
 // Laminate stress of the one-level points (eq. 5.2 on the one-level tree of
@@ -543,10 +589,10 @@ template <typename T, int D, int S, int K, int M>
 hipError_t launch_T(const KArgs& a, int depth, hipStream_t st, KTimer* tm) {
   dim3 blk(256);
   unsigned per = 256 / kWave;
+  const dim3 grd1(unsigned((a.n + kPointsPerBlock - 1) / kPointsPerBlock));
   if (depth == 1) {
-    dim3 grd(unsigned((a.n + per - 1) / per));
     if (tm) tm->begin("depth1", st);
-    hipLaunchKernelGGL((k_depth1<T, D, S, K, M>), grd, blk, 0, st, a);
+    hipLaunchKernelGGL((k_depth1<T, D, S, K, M>), grd1, blk, 0, st, a);
     if (a.want_stress && a.P)
       hipLaunchKernelGGL((k_stress1<T, D, M>), dim3(unsigned((a.n + 255) / 256)), blk, 0, st, a);
     if (tm) tm->end(st);
@@ -562,7 +608,7 @@ hipError_t launch_T(const KArgs& a, int depth, hipStream_t st, KTimer* tm) {
   pre.want_stress = 0;
   dim3 grd(unsigned((a.n + per - 1) / per));
   if (tm) tm->begin("depth2_centre", st);
-  hipLaunchKernelGGL((k_depth1<T, D, S, K, M>), grd, blk, 0, st, pre);
+  hipLaunchKernelGGL((k_depth1<T, D, S, K, M>), grd1, blk, 0, st, pre);
   if (tm) tm->end(st);
   size_t lds = outer_lds_bytes<T>(a.lv0, a.lv1, M);
   dim3 grd_o(unsigned(a.n * a.lv0.n_dir));
