@@ -175,22 +175,30 @@ __device__ __forceinline__ void point_depth1(const KArgs& a, int64_t p, const Le
   point_depth1_body<T, D, S, K, M, kDefer>(a, p, lv, make_layout<T, S, K>(lv), point_setup<T, D, M>(a, p));
 }
 
-// One-level launch: a block of 4 waves takes kPointsPerWave points per wave.
-// Their constants are formed by one thread per point into LDS first (a point's
-// FP64 set-up then costs a lane, not a wavefront), then each wave laminates its
-// points one after the other.
+// One-level launch: a block of 4 waves takes a.pts_per_wave (<= kPointsPerWave)
+// points per wave.  Their constants are formed by one thread per point into LDS
+// first (a point's FP64 set-up then costs a lane, not a wavefront), then each
+// wave laminates its points one after the other.
 constexpr int kPointsPerWave = 8;
 constexpr int kPointsPerBlock = 4 * kPointsPerWave;
+
+// Points per wave for n points: kPointsPerWave, or fewer where that would leave
+// the launch under 2048 blocks (small batches keep the device filled).
+inline int one_level_points_per_wave(int64_t n) {
+  const int64_t q = (n + 4 * 2048 - 1) / (4 * 2048);
+  return int(q < 1 ? 1 : (q > kPointsPerWave ? kPointsPerWave : q));
+}
 
 template <typename T, int D, int S, int K, int M>
 __global__ __launch_bounds__(256, sizeof(T) == 4 ? ((D == 2 && M == kFamNH && K <= 14) ? 4 : K <= 16 ? 3 : 1) : 1) void k_depth1(KArgs a) {
   __shared__ PointSetup<T, D, M> ps[kPointsPerBlock];
-  const int64_t p0 = int64_t(blockIdx.x) * kPointsPerBlock;
-  if (threadIdx.x < kPointsPerBlock && p0 + threadIdx.x < a.n) ps[threadIdx.x] = point_setup<T, D, M>(a, p0 + threadIdx.x);
+  const int per_block = 4 * a.pts_per_wave;
+  const int64_t p0 = int64_t(blockIdx.x) * per_block;
+  if (int(threadIdx.x) < per_block && p0 + threadIdx.x < a.n) ps[threadIdx.x] = point_setup<T, D, M>(a, p0 + threadIdx.x);
   __syncthreads();
   const Layout<T, S, K> lay = make_layout<T, S, K>(a.lv0);
   const int wave = threadIdx.x / kWave;
-  for (int i = 0; i < kPointsPerWave; ++i) {
+  for (int i = 0; i < a.pts_per_wave; ++i) {
     const int slot = i * 4 + wave;
     const int64_t p = p0 + slot;
     if (p >= a.n) break;                      // wave-uniform
@@ -589,10 +597,13 @@ template <typename T, int D, int S, int K, int M>
 hipError_t launch_T(const KArgs& a, int depth, hipStream_t st, KTimer* tm) {
   dim3 blk(256);
   unsigned per = 256 / kWave;
-  const dim3 grd1(unsigned((a.n + kPointsPerBlock - 1) / kPointsPerBlock));
+  const int ppw = one_level_points_per_wave(a.n);
+  const dim3 grd1(unsigned((a.n + 4 * ppw - 1) / (4 * ppw)));
   if (depth == 1) {
+    KArgs a1 = a;
+    a1.pts_per_wave = ppw;
     if (tm) tm->begin("depth1", st);
-    hipLaunchKernelGGL((k_depth1<T, D, S, K, M>), grd1, blk, 0, st, a);
+    hipLaunchKernelGGL((k_depth1<T, D, S, K, M>), grd1, blk, 0, st, a1);
     if (a.want_stress && a.P)
       hipLaunchKernelGGL((k_stress1<T, D, M>), dim3(unsigned((a.n + 255) / 256)), blk, 0, st, a);
     if (tm) tm->end(st);
@@ -606,6 +617,7 @@ hipError_t launch_T(const KArgs& a, int depth, hipStream_t st, KTimer* tm) {
   pre.tree = nullptr;
   pre.flags = nullptr;
   pre.want_stress = 0;
+  pre.pts_per_wave = ppw;
   dim3 grd(unsigned((a.n + per - 1) / per));
   if (tm) tm->begin("depth2_centre", st);
   hipLaunchKernelGGL((k_depth1<T, D, S, K, M>), grd1, blk, 0, st, pre);

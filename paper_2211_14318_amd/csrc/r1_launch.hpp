@@ -24,6 +24,7 @@ struct KArgs {
   int want_stress;
   void* scratch_w1f;      // depth 2: T[n], W^1 at each point
   void* scratch_outer;    // depth 2: per (point, outer direction) hull result
+  int pts_per_wave;       // one-level kernel: points per wave (set by the launcher)
 };
 
 // Per-kernel timing with HIP events recorded on the launch stream (off by default).
