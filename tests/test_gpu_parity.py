@@ -231,3 +231,23 @@ def test_deterministic_across_runs(lib):
     g1 = run_gpu(lib, cfg, "f32")
     g2 = run_gpu(lib, cfg, "f32")
     assert np.array_equal(g1["W"], g2["W"]) and np.array_equal(g1["P"], g2["P"])
+
+
+def test_one_level_result_independent_of_batch(lib):
+    """One-level launches take 1 to 8 points per wave depending on the batch size (more
+    where the launch stays above 2048 blocks) and form each point's constants one thread
+    per point before the waves laminate: a point's W, stress, tree and flags must not
+    depend on the batch it is in.  The first 20,001 points of the 2D inference workload,
+    then slices of 1, 33, 8,193 and 16,385 points at other offsets (1, 1, 2 and 3 points
+    per wave), in FP32 and FP64, compared bit for bit."""
+    cfg = WL.config4_inference(n=20_001)
+    for kind in ("f32", "f64"):
+        full = run_gpu(lib, cfg, kind)
+        for start, m in ((0, 1), (5, 33), (1000, 8193), (3000, 16385)):
+            sub = dict(cfg, n=m, F=cfg["F"][:, start:start + m].copy(),
+                       beta_n=cfg["beta_n"][start:start + m].copy())
+            g = run_gpu(lib, sub, kind)
+            assert np.array_equal(g["W"], full["W"][start:start + m], equal_nan=True), (kind, start, m)
+            assert np.array_equal(g["P"], full["P"][:, start:start + m], equal_nan=True), (kind, start, m)
+            assert np.array_equal(g["tree"], full["tree"][start:start + m]), (kind, start, m)
+            assert np.array_equal(g["flags"], full["flags"][start:start + m]), (kind, start, m)
