@@ -32,61 +32,91 @@ __device__ __forceinline__ float sample_at(float t, const r1d::Line<float>& L, c
   return q.model == 0 ? r1d::ws_sample<float>(t, L, q) : r1d::w_sample_doublewell<float>(t, L);
 }
 
-// Point p passes when no subset chord of any direction passes below the target.
+// One direction's chord test for point p: true when a chord of subset samples
+// passes below the target at the centre.
 template <typename T, int D, int M>
-__device__ bool passes(const CheckArgs& a, int64_t p) {
-  double G[D * D];
-#pragma unroll
-  for (int k = 0; k < D * D; ++k) G[k] = double(static_cast<const T*>(a.F)[int64_t(k) * a.n + p]);
-  const double bn = double(static_cast<const T*>(a.beta_n)[p]);
-  const float w = float(static_cast<const T*>(a.W)[p]);
-  double cof[D * D];
-  r1d::cofactor<D>(G, cof);
-  const r1d::Point<float> q = r1d::make_point<float, M>(a.mat, bn);
-  float target = w - a.eps * fmaxf(fabsf(w), 0.01f);
-  if (M == r1d::kFamSTVK || q.model == 0) target = (target - q.B) / q.sc;
-  const float dt = float(a.lv.tau / double((a.lv.n_t - 1) / 2));
-  for (int m = 0; m < a.lv.n_dir; ++m) {
-    const r1d::Line<float> L = r1d::line_setup<float, D, M>(q, G, cof, a.lv.a + m * D, a.lv.b + m * D);
-    float lo = __builtin_inff(), hi = __builtin_inff();
-    for (int k = 0; k < a.n_off; ++k) {
-      const float o = float(a.off[k]);
-      const float inv = a.off_inv[k];
-      // NaN samples (det <= 0) are absent: fminf keeps the other operand
-      lo = fminf(lo, (sample_at<T, D, M>(-o * dt, L, q) - target) * inv);
-      hi = fminf(hi, (sample_at<T, D, M>(o * dt, L, q) - target) * inv);
-    }
-    if (lo + hi < 0.0f) return false;
+__device__ __forceinline__ bool chord_below(const CheckArgs& a, const r1d::Point<float>& q, const double* G,
+                                            const double* cof, float target, float dt, int m) {
+  const r1d::Line<float> L = r1d::line_setup<float, D, M>(q, G, cof, a.lv.a + m * D, a.lv.b + m * D);
+  float lo = __builtin_inff(), hi = __builtin_inff();
+  for (int k = 0; k < a.n_off; ++k) {
+    const float o = float(a.off[k]);
+    const float inv = a.off_inv[k];
+    // NaN samples (det <= 0) are absent: fminf keeps the other operand
+    lo = fminf(lo, (sample_at<T, D, M>(-o * dt, L, q) - target) * inv);
+    hi = fminf(hi, (sample_at<T, D, M>(o * dt, L, q) - target) * inv);
   }
-  return true;
+  return lo + hi < 0.0f;
 }
 
-// list mode (a.list != nullptr): candidates list[0 .. *count) -> failures appended
-// to fb_list; row mode: rows 0 .. n -> pass[p] = 1 / 0.
-template <typename T, int D, int M>
+// A point passes when no subset chord of any direction passes below the target.
+// NG lanes share a point (NG divides 64, so a group never spans two waves) and
+// take its directions m = g, g + NG, ...: a point's direction loop is the chip's
+// unit of parallel work, since the candidates are only the points the gates
+// serve (a few tens of thousands for 3D workloads of 256 directions).  The loop
+// bound is wave-uniform so that the group votes can use the whole wave; a group
+// stops once one of its lanes has found a chord.
+template <typename T, int D, int M, int NG>
 __global__ __launch_bounds__(256) void k_check(CheckArgs a) {
   const int64_t total = a.list ? int64_t(*a.count) : a.n;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
-       i += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t p = a.list ? int64_t(a.list[i]) : i;
-    const bool ok = passes<T, D, M>(a, p);
-    if (a.list) {
-      if (!ok) a.fb_list[atomicAdd(a.fb_count, 1)] = int32_t(p);
-    } else {
-      a.pass[p] = ok ? 1 : 0;
+  const int lane = int(threadIdx.x) & 63;
+  const int g = lane % NG;
+  const uint64_t gmask = (NG == 64 ? ~uint64_t(0) : ((uint64_t(1) << NG) - 1)) << (lane - g);
+  const int rounds = (a.lv.n_dir + NG - 1) / NG;
+  const float dt = float(a.lv.tau / double((a.lv.n_t - 1) / 2));
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t w0 = int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63u); w0 < total * NG; w0 += stride) {
+    const int64_t i = (w0 + lane) / NG;
+    const bool valid = i < total;
+    const int64_t p = !valid ? 0 : a.list ? int64_t(a.list[i]) : i;
+    double G[D * D], cof[D * D];
+    r1d::Point<float> q{};
+    float target = 0.0f;
+    if (valid) {
+#pragma unroll
+      for (int k = 0; k < D * D; ++k) G[k] = double(static_cast<const T*>(a.F)[int64_t(k) * a.n + p]);
+      const double bn = double(static_cast<const T*>(a.beta_n)[p]);
+      const float w = float(static_cast<const T*>(a.W)[p]);
+      r1d::cofactor<D>(G, cof);
+      q = r1d::make_point<float, M>(a.mat, bn);
+      target = w - a.eps * fmaxf(fabsf(w), 0.01f);
+      if (M == r1d::kFamSTVK || q.model == 0) target = (target - q.B) / q.sc;
+    }
+    bool found = false, done = !valid;
+    for (int r = 0; r < rounds; ++r) {
+      const int m = r * NG + g;
+      if (!done && m < a.lv.n_dir) found = chord_below<T, D, M>(a, q, G, cof, target, dt, m);
+      done = done || (__ballot(found) & gmask) != 0;
+      if (__all(done)) break;
+    }
+    const bool fail = (__ballot(found) & gmask) != 0;
+    if (valid && g == 0) {
+      if (a.list) {
+        if (fail) a.fb_list[atomicAdd(a.fb_count, 1)] = int32_t(p);
+      } else {
+        a.pass[p] = fail ? 0 : 1;
+      }
     }
   }
 }
 
+template <typename T, int D, int NG>
+hipError_t launch_TDG(const CheckArgs& a, hipStream_t st) {
+  // list mode: n bounds the candidate count, which only the device knows
+  const unsigned blocks = unsigned(std::min<int64_t>((a.n * NG + 255) / 256, 8192));
+  if (a.mat.model == R1_STVK_DAMAGE)
+    hipLaunchKernelGGL((k_check<T, D, r1d::kFamSTVK, NG>), dim3(blocks), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_check<T, D, r1d::kFamNH, NG>), dim3(blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// lanes per point: about four directions per lane, at least four lanes
 template <typename T, int D>
 hipError_t launch_TD(const CheckArgs& a, hipStream_t st) {
-  // list mode: n bounds the candidate count, which only the device knows
-  const unsigned blocks = unsigned(std::min<int64_t>((a.n + 255) / 256, 8192));
-  if (a.mat.model == R1_STVK_DAMAGE)
-    hipLaunchKernelGGL((k_check<T, D, r1d::kFamSTVK>), dim3(blocks), dim3(256), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_check<T, D, r1d::kFamNH>), dim3(blocks), dim3(256), 0, st, a);
-  return hipGetLastError();
+  if (a.lv.n_dir >= 256) return launch_TDG<T, D, 64>(a, st);
+  if (a.lv.n_dir >= 64) return launch_TDG<T, D, 16>(a, st);
+  return launch_TDG<T, D, 4>(a, st);
 }
 
 }  // namespace

@@ -415,3 +415,63 @@ def test_check_sends_exactly_the_points_with_a_low_subset_chord(lib, trained):
     print("check: %d kept, %d sent to the fallback, %d within rounding of the criterion" % (n_keep, n_rej, n_skip))
     assert n_keep > 100 and n_rej > 50
     s.close()
+
+
+@pytest.mark.parametrize("n_dir", [32, 64, 256])
+def test_check_3d_sends_exactly_the_points_with_a_low_subset_chord(lib, n_dir):
+    """The a-posteriori check in 3D, where several lanes share a point's directions
+    (4 lanes for 32 directions, as for the 16 of the 2D test above, 16 lanes for
+    64, a whole wave for 256): the same definition as the 2D
+    test above, on served points of a briefly trained, uncalibrated 3D network."""
+    r1, h, torch = lib
+    cfg = WL.config5(n=16384, seed_tag=69)
+    lv = cfg["levels"][0]
+    lv = dict(lv, a=lv["a"][:n_dir], b=lv["b"][:n_dir])
+    mat, spec = r1.material(dim=3), r1.LaminationSpec([lv])
+    Ftr = torch.tensor(cfg["F"], dtype=torch.float32, device="cuda").contiguous()
+    btr = torch.tensor(cfg["beta_n"], dtype=torch.float32, device="cuda").contiguous()
+    otr = h.envelope(mat, spec, Ftr, btr, stress=True)
+    s = r1.Surrogate(h, dim=3, n_hidden=4, width=128, seed=9)
+    X, Y = s.pack(Ftr, btr, otr["W"], otr["P"])
+    s.train(mat, X, Y, epochs=4, batch=1024, lr=1e-3, seed=2)
+    inf = WL.config5(n=4096, seed_tag=70)
+    Ft = torch.tensor(inf["F"], dtype=torch.float32, device="cuda").contiguous()
+    bt = torch.tensor(inf["beta_n"], dtype=torch.float32, device="cuda").contiguous()
+    eps = 5e-4
+    s.set_check(0.0)
+    a = s.infer(mat, spec, Ft, bt)
+    s.set_check(eps)
+    b = s.infer(mat, spec, Ft, bt)
+    s.set_check(0.0)
+    torch.cuda.synchronize()
+    served0 = (a["flags"].cpu().numpy() & r1.PT_FALLBACK) == 0
+    served1 = (b["flags"].cpu().numpy() & r1.PT_FALLBACK) == 0
+    assert not np.any(served1 & ~served0)
+    W0 = a["W"].cpu().numpy().astype(np.float64)
+    c = (lv["n_t"] - 1) // 2
+    offs = r1.check_offsets(lv["n_t"])
+    om = O.material(dim=3)
+    Fn, bn = Ft.double().cpu().numpy(), bt.double().cpu().numpy()
+    R = [np.outer(lv["a"][m], lv["b"][m]) * lv["tau"] / c for m in range(n_dir)]
+    n_rej = n_keep = n_skip = 0
+    for p in np.nonzero(served0)[0][:48]:
+        G = Fn[:, p].reshape(3, 3)
+        T = W0[p] - eps * max(abs(W0[p]), 0.01)
+        crit = np.inf
+        for Rm in R:
+            lo = min((O.energy(om, G - o * Rm, bn[p]) - T) / o for o in offs)
+            hi = min((O.energy(om, G + o * Rm, bn[p]) - T) / o for o in offs)
+            crit = min(crit, lo + hi)
+        if abs(crit) < 1e-5 * max(abs(W0[p]), 0.01):
+            n_skip += 1
+            continue
+        if crit < 0:
+            n_rej += 1
+            assert not served1[p], (p, crit)
+        else:
+            n_keep += 1
+            assert served1[p], (p, crit)
+    print("check, %d directions: %d kept, %d sent to the fallback, %d within rounding of the criterion"
+          % (n_dir, n_keep, n_rej, n_skip))
+    assert n_keep > 0 and n_rej > 0
+    s.close()
