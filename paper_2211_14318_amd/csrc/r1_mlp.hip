@@ -174,7 +174,7 @@ __device__ __forceinline__ int gate_bin(const InferParams& ip, const double* F, 
 // MODE 1 (calibration): box gate only; the gate cell, predicted W and
 // predicted gap go to cal_bin / cal_w / cal_gap, rejected points get cell -1.
 template <typename T, int D, int WID, int MODE, int FAM>
-__global__ __launch_bounds__(256) void k_infer(InferParams ip, const T* F, const T* bn, T* W,
+__global__ __launch_bounds__(256, 2) void k_infer(InferParams ip, const T* F, const T* bn, T* W,
                                                T* P, int32_t* flags, int* fb_count,
                                                int32_t* fb_list, int* cal_bin, float* cal_w,
                                                float* cal_gap) {
@@ -209,19 +209,32 @@ __global__ __launch_bounds__(256) void k_infer(InferParams ip, const T* F, const
     act[r * LD + f] = __bf16(silu(z));
   }
   __syncthreads();
-  // hidden width x width layers on the matrix cores
+  // hidden width x width layers on the matrix cores; a k step's B fragments
+  // (one per 32-column tile) are loaded together, and the next step's while
+  // this step's products run, so their L2 latency overlaps the matrix cores
+  constexpr int NT = WID / 32;
   for (int l = 1; l < ip.n_hidden; ++l) {
-    const __bf16* Wl = static_cast<const __bf16*>(ip.wbf[l]);
-    f32x16 acc[WID / 32];
+    // fragment (k step ks, tile t) of this lane: wf[(ks NT + t) 64] (r1m_wfrag)
+    const bf16x8* wf = static_cast<const bf16x8*>(ip.wfrag) + int64_t(l - 1) * (WID * WID / 8) + lane;
+    f32x16 acc[NT];
+    bf16x8 bw[NT], bn[NT];
 #pragma unroll
-    for (int t = 0; t < WID / 32; ++t) acc[t] = f32x16{};
+    for (int t = 0; t < NT; ++t) {
+      acc[t] = f32x16{};
+      bw[t] = wf[t * 64];
+    }
     for (int k0 = 0; k0 < WID; k0 += 16) {
-      const bf16x8 a = *reinterpret_cast<const bf16x8*>(act + r * LD + k0 + 8 * half);
+      const int kn = k0 + 16 < WID ? k0 / 16 + 1 : k0 / 16;   // the last step reloads its own fragments
 #pragma unroll
-      for (int t = 0; t < WID / 32; ++t) {
-        const bf16x8 bw = *reinterpret_cast<const bf16x8*>(Wl + (t * 32 + r) * WID + k0 + 8 * half);
-        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bw, acc[t], 0, 0, 0);
-      }
+      for (int t = 0; t < NT; ++t) bn[t] = wf[(kn * NT + t) * 64];
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(act + r * LD + k0 + 8 * half);
+      // keep the next step's loads ahead of this step's products (the scheduler
+      // would otherwise sink each load to its use to save registers)
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int t = 0; t < WID / 32; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bw[t], acc[t], 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < WID / 32; ++t) bw[t] = bn[t];
     }
     __syncthreads();
 #pragma unroll
@@ -495,6 +508,26 @@ static inline unsigned nblk(int64_t n, int b = 256) { return unsigned((n + b - 1
 
 hipError_t r1m_unpack(int dim, int64_t n, const float* X, float* F, float* bn, hipStream_t st) {
   hipLaunchKernelGGL(k_unpack, dim3(nblk(n)), dim3(256), 0, st, dim * dim, n, X, F, bn);
+  return hipGetLastError();
+}
+
+// one thread per destination element, in destination order (see r1m_wfrag)
+__global__ void k_wfrag(int64_t total, int width, const __bf16* wbf, __bf16* wfrag) {
+  const int64_t d = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (d >= total) return;
+  const int nt = width / 32, ks_n = width / 16;
+  const int e = int(d % 8), lane = int((d / 8) % 64);
+  const int t = int((d / 512) % nt), ks = int((d / (512 * int64_t(nt))) % ks_n);
+  const int64_t l1 = d / (int64_t(width) * width);
+  const int r = lane & 31, half = lane >> 5;
+  wfrag[d] = wbf[l1 * width * width + int64_t(t * 32 + r) * width + ks * 16 + 8 * half + e];
+}
+
+hipError_t r1m_wfrag(int width, int n_hidden, const void* wbf, void* wfrag, hipStream_t st) {
+  const int64_t total = int64_t(n_hidden - 1) * width * width;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_wfrag, dim3(nblk(total)), dim3(256), 0, st, total, width, static_cast<const __bf16*>(wbf),
+                     static_cast<__bf16*>(wfrag));
   return hipGetLastError();
 }
 

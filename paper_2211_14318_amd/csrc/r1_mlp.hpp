@@ -29,6 +29,7 @@ struct InferParams {
   const float* w0;                  // first layer, width x d_in
   const float* b[kMaxHidden];       // biases of the hidden layers
   const void* wbf[kMaxHidden];      // BF16 width x width weights of hidden layers 1.. (index 0 unused)
+  const void* wfrag;                // the same weights in MFMA fragment order (r1m_wfrag), for k_infer
   const float* wout;                // d_out x width
   const float* bout;
   float x_mean[kMaxCols], x_std[kMaxCols], x_lo[kMaxCols], x_hi[kMaxCols];
@@ -100,6 +101,12 @@ hipError_t r1m_colstats(int64_t n, int ncol, int dF, const float* A, double* sum
 hipError_t r1m_pack(int dtype, int dim, int64_t n, const void* F, const void* bn, const void* W,
                     const void* P, float* X, float* Y, hipStream_t st);
 hipError_t r1m_unpack(int dim, int64_t n, const float* X, float* F, float* bn, hipStream_t st);
+// The BF16 hidden weights wbf (n_hidden - 1 layers of width x width, out x in)
+// rewritten in the order k_infer reads its B fragments: per layer, k step ks
+// (16 inputs), 32-output tile t and lane (r = lane % 32, half = lane / 32), the
+// 8 inputs ks 16 + 8 half .. + 7 of output t 32 + r, so that each fragment load
+// of a wave is 1 KB contiguous.
+hipError_t r1m_wfrag(int width, int n_hidden, const void* wbf, void* wfrag, hipStream_t st);
 size_t r1m_infer_lds(int width);
 hipError_t r1m_infer(int dtype, int dim, const InferParams& ip, int mode, const void* F, const void* bn,
                      void* W, void* P, int32_t* flags, int* fb_count, int32_t* fb_list, int* cal_bin,

@@ -25,6 +25,8 @@ struct r1_surrogate_s {
   float* v = nullptr;
   void* wbf = nullptr;                      // BF16 copies of the width x width layers
   void* wbf_t = nullptr;                    // ... and of their transposes (backward pass)
+  void* wfrag = nullptr;                    // ... in MFMA fragment order (inference without LDS weights)
+  bool wfrag_ok = false;                    // wfrag matches wbf
   int64_t t = 0;                            // Adam steps taken
   float norm[4 * kMaxCols] = {};            // x_mean, x_std, y_mean, y_std (packed by d_in/d_out)
   float x_lo[kMaxCols] = {}, x_hi[kMaxCols] = {};
@@ -100,7 +102,16 @@ hipError_t adam_step(r1_surrogate s, float lr, float b1, float b2, float eps, hi
   for (int l = 0; l <= s->n_hidden; ++l) a.off_w[l] = s->off_w[l];
   a.wbf = s->wbf;
   a.wbf_t = s->wbf_t;
+  s->wfrag_ok = false;
   return r1m_train_adam(a, st);
+}
+
+// The fragment-order copy of the hidden weights, rebuilt after they changed.
+hipError_t ensure_wfrag(r1_surrogate s, hipStream_t st) {
+  if (s->wfrag_ok) return hipSuccess;
+  hipError_t e = r1m_wfrag(s->width, s->n_hidden, s->wbf, s->wfrag, st);
+  if (e == hipSuccess) s->wfrag_ok = true;
+  return e;
 }
 
 hipError_t refresh_bf16(r1_surrogate s, hipStream_t st) { return adam_step(s, 0.0f, 0.9f, 0.999f, 1e-8f, st); }
@@ -111,6 +122,7 @@ r1_status alloc_state(r1_surrogate s) {
       hipMalloc(&s->m, pb) != hipSuccess || hipMalloc(&s->v, pb) != hipSuccess ||
       hipMalloc(&s->wbf, size_t(std::max(1, s->n_hidden - 1)) * s->width * s->width * 2) != hipSuccess ||
       hipMalloc(&s->wbf_t, size_t(std::max(1, s->n_hidden - 1)) * s->width * s->width * 2) != hipSuccess ||
+      hipMalloc(&s->wfrag, size_t(std::max(1, s->n_hidden - 1)) * s->width * s->width * 2) != hipSuccess ||
       hipMalloc(&s->gate_tau, sizeof(float) * kGateCells) != hipSuccess ||
       hipMalloc(&s->norm_dev, sizeof(float) * 4 * kMaxCols) != hipSuccess)
     return R1_ENOMEM;
@@ -122,7 +134,7 @@ r1_status alloc_state(r1_surrogate s) {
 
 void free_state(r1_surrogate s) {
   for (void* p : {static_cast<void*>(s->params), static_cast<void*>(s->grad), static_cast<void*>(s->m),
-                  static_cast<void*>(s->v), s->wbf, s->wbf_t, static_cast<void*>(s->gate_tau),
+                  static_cast<void*>(s->v), s->wbf, s->wbf_t, s->wfrag, static_cast<void*>(s->gate_tau),
                   static_cast<void*>(s->norm_dev), s->ws})
     if (p) (void)hipFree(p);
 }
@@ -219,6 +231,7 @@ InferParams infer_params(r1_surrogate s, const r1_material* mat, int64_t n) {
     ip.b[l] = s->params + s->off_b[l];
     ip.wbf[l] = l == 0 ? nullptr : wbf_of(s, l);
   }
+  ip.wfrag = s->wfrag;
   ip.wout = s->params + s->off_w[s->n_hidden];
   ip.bout = s->params + s->off_b[s->n_hidden];
   for (int k = 0; k < s->d_in; ++k) {
@@ -552,6 +565,7 @@ r1_status r1_surrogate_predict(r1_handle h, r1_surrogate s, const r1_material* m
   float* bs = reinterpret_cast<float*>(p);
   InferParams ip = infer_params(s, mat, n);
   hipError_t e = r1m_unpack(s->dim, n, X, Fs, bs, st);
+  if (e == hipSuccess) e = ensure_wfrag(s, st);
   if (e == hipSuccess) e = r1m_infer(R1_F32, s->dim, ip, 1, Fs, bs, nullptr, nullptr, nullptr, nullptr, nullptr,
                                      cell, W_pred, gap_pred, st);
   return e == hipSuccess ? R1_OK : r1h::fail(h, e, "surrogate predict");
@@ -581,6 +595,7 @@ r1_status r1_surrogate_calibrate(r1_handle h, r1_surrogate s, const r1_material*
   float* cg = reinterpret_cast<float*>(p);
   InferParams ip = infer_params(s, mat, n);
   hipError_t e = r1m_unpack(s->dim, n, X, Fs, bs, st);
+  if (e == hipSuccess) e = ensure_wfrag(s, st);
   if (e == hipSuccess) e = r1m_infer(R1_F32, s->dim, ip, 1, Fs, bs, nullptr, nullptr, nullptr, nullptr, nullptr,
                                      cbin, cw, cg, st);
   std::vector<int> hbin(static_cast<size_t>(n));
@@ -679,6 +694,7 @@ r1_status r1_surrogate_infer(r1_handle h, r1_surrogate s, const r1_material* mat
   }
   hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int), st);
   if (e == hipSuccess && check) e = hipMemsetAsync(ip.cand_count, 0, sizeof(int), st);
+  if (e == hipSuccess) e = ensure_wfrag(s, st);
   if (e == hipSuccess)
     e = r1m_infer(dtype, s->dim, ip, 0, F, beta_n, W, P, flags, cnt, list, nullptr, nullptr, nullptr, st);
   if (e == hipSuccess && check) e = r1_launch_check(dtype, ca, st);
