@@ -170,13 +170,12 @@ __device__ __forceinline__ int gate_bin(const InferParams& ip, const double* F, 
 // width x width layer as 32 x 16-deep MFMA tiles with B fragments read from the
 // BF16 weights in global memory (L2-resident), bias + SiLU, back to LDS; output
 // layer in FP32; exact W(F), P0(F); W = W(F) - max(g, 0), P = P0 - dP.
-// MODE 0: gates on, rejected points appended to the fallback list.
+// MODE 0: gates on, each point's status (fallback / served) to ip.status.
 // MODE 1 (calibration): box gate only; the gate cell, predicted W and
 // predicted gap go to cal_bin / cal_w / cal_gap, rejected points get cell -1.
 template <typename T, int D, int WID, int MODE, int FAM>
 __global__ __launch_bounds__(256, 2) void k_infer(InferParams ip, const T* F, const T* bn, T* W,
-                                               T* P, int32_t* flags, int* fb_count,
-                                               int32_t* fb_list, int* cal_bin, float* cal_w,
+                                               T* P, int32_t* flags, int* cal_bin, float* cal_w,
                                                float* cal_gap) {
   constexpr int DI = D * D + 1, DO = D * D + 1;
   constexpr int LD = WID + 8;                      // padded BF16 row stride (bank spread)
@@ -271,12 +270,9 @@ __global__ __launch_bounds__(256, 2) void k_infer(InferParams ip, const T* F, co
     return;
   }
   if (ip.bins_on) ok = ok && rawf <= ip.gate_tau[bin];
-  if (!ok || !(det > 0.0)) {
-    const int slot = atomicAdd(fb_count, 1);
-    fb_list[slot] = int32_t(pt);
-    return;
-  }
-  if (ip.cand_list) ip.cand_list[atomicAdd(ip.cand_count, 1)] = int32_t(pt);
+  ok = ok && det > 0.0;
+  ip.status[pt] = ok ? 2 : 1;
+  if (!ok) return;
   double P0[D * D];
   r1d::stress0<D, FAM>(ip.mat, b, G, P0);
   W[pt] = T(wpred);
@@ -310,8 +306,7 @@ __host__ __device__ inline size_t infer_lds_bytes(int width, int n_hidden, int d
 // MODE as in k_infer.
 template <typename T, int D, int WID, int MODE, int FAM>
 __global__ __launch_bounds__(512) void k_infer_lds(InferParams ip, const T* F, const T* bn, T* W, T* P,
-                                                   int32_t* flags, int* fb_count, int32_t* fb_list,
-                                                   int* cal_bin, float* cal_w, float* cal_gap) {
+                                                   int32_t* flags, int* cal_bin, float* cal_w, float* cal_gap) {
   constexpr int DI = D * D + 1, DO = D * D + 1;
   constexpr int LDW = WID + 8;
   constexpr int NS = WID / 16, NT = WID / 32;
@@ -445,21 +440,7 @@ __global__ __launch_bounds__(512) void k_infer_lds(InferParams ip, const T* F, c
     }
     if (ip.bins_on) ok = ok && rawf <= ip.gate_tau[bin];
     ok = ok && det > 0.0;
-    // fallback list: one atomic per wave
-    const bool rej = valid && half == 0 && !ok;
-    const unsigned long long m = __ballot(rej);
-    int base = 0;
-    if (lane == 0 && m) base = atomicAdd(fb_count, __popcll(m));
-    base = __shfl(base, 0, kWaveM);
-    if (rej) fb_list[base + __popcll(m & ((1ull << lane) - 1ull))] = int32_t(pt);
-    if (ip.cand_list) {                    // served points: candidates of the check
-      const bool srv = valid && half == 0 && ok;
-      const unsigned long long ms = __ballot(srv);
-      int cb = 0;
-      if (lane == 0 && ms) cb = atomicAdd(ip.cand_count, __popcll(ms));
-      cb = __shfl(cb, 0, kWaveM);
-      if (srv) ip.cand_list[cb + __popcll(ms & ((1ull << lane) - 1ull))] = int32_t(pt);
-    }
+    if (valid && half == 0) ip.status[pt] = ok ? 2 : 1;
     if (!valid || !ok) continue;
     if (half == 0) {
       r1d::Point<double> q = r1d::make_point<double, FAM>(ip.mat, b);
@@ -473,6 +454,53 @@ __global__ __launch_bounds__(512) void k_infer_lds(InferParams ip, const T* F, c
         P[int64_t(k) * ip.n + pt] =
             T(convex ? P0[k] : P0[k] - double(out[1 + k] * ip.y_std[1 + k] + ip.y_mean[1 + k]));
     }
+  }
+}
+
+// The fallback and candidate lists from the inference kernels' per-point status
+// (1 = fallback, 2 = served): each block takes 2048 consecutive points, counts
+// them by wave ballots and reserves its slots with one atomic per list.  Building
+// the lists here rather than in the inference kernels keeps those free of
+// atomics whose returned slot a wave had to wait for on every tile.
+constexpr int kListPer = 8;
+__global__ __launch_bounds__(256) void k_lists(int64_t n, const uint8_t* status, int* fb_count, int32_t* fb_list,
+                                               int* cand_count, int32_t* cand_list) {
+  __shared__ int wsum[2][4], wbase[2][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t b0 = int64_t(blockIdx.x) * 256 * kListPer;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  int v[kListPer];
+  int cf = 0, cc = 0;
+#pragma unroll
+  for (int j = 0; j < kListPer; ++j) {
+    const int64_t p = b0 + j * 256 + threadIdx.x;
+    v[j] = p < n ? status[p] : 0;
+  }
+#pragma unroll
+  for (int j = 0; j < kListPer; ++j) {
+    cf += __popcll(__ballot(v[j] == 1));
+    cc += __popcll(__ballot(v[j] == 2));
+  }
+  if (lane == 0) { wsum[0][wave] = cf; wsum[1][wave] = cc; }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const int li = threadIdx.x;
+    int tot = 0;
+    for (int w = 0; w < 4; ++w) tot += wsum[li][w];
+    int base = 0;
+    if (tot > 0) base = li == 0 ? atomicAdd(fb_count, tot) : (cand_list ? atomicAdd(cand_count, tot) : 0);
+    for (int w = 0; w < 4; ++w) { wbase[li][w] = base; base += wsum[li][w]; }
+  }
+  __syncthreads();
+  int of = wbase[0][wave], oc = wbase[1][wave];
+#pragma unroll
+  for (int j = 0; j < kListPer; ++j) {
+    const int64_t p = b0 + j * 256 + threadIdx.x;
+    const unsigned long long mf = __ballot(v[j] == 1), mc = __ballot(v[j] == 2);
+    if (v[j] == 1) fb_list[of + __popcll(mf & lt)] = int32_t(p);
+    if (v[j] == 2 && cand_list) cand_list[oc + __popcll(mc & lt)] = int32_t(p);
+    of += __popcll(mf);
+    oc += __popcll(mc);
   }
 }
 
@@ -580,7 +608,7 @@ static hipError_t infer_TD(const InferParams& ip, int mode, const void* F, const
       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds2)); \
   hipLaunchKernelGGL((k_infer_lds<T, D, WID, MODE, FAM>), grid, dim3(512), lds2, st, ip, \
       static_cast<const T*>(F), static_cast<const T*>(bn), static_cast<T*>(W), static_cast<T*>(P), flags, \
-      fb_count, fb_list, cal_bin, cal_w, cal_gap)
+      cal_bin, cal_w, cal_gap)
 #define R1V(WID) if (ip.width == WID) { if (mode == 0) { R1L(WID, 0); } else { R1L(WID, 1); } return hipGetLastError(); }
     R1V(32) R1V(64) R1V(128)
 #undef R1V
@@ -593,7 +621,7 @@ static hipError_t infer_TD(const InferParams& ip, int mode, const void* F, const
       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)); \
   hipLaunchKernelGGL((k_infer<T, D, WID, MODE, FAM>), grid, dim3(256), lds, st, ip, \
       static_cast<const T*>(F), static_cast<const T*>(bn), static_cast<T*>(W), static_cast<T*>(P), flags, \
-      fb_count, fb_list, cal_bin, cal_w, cal_gap)
+      cal_bin, cal_w, cal_gap)
 #define R1W(WID) if (ip.width == WID) { if (mode == 0) { R1I(WID, 0); } else { R1I(WID, 1); } return hipGetLastError(); }
   R1W(256)
 #undef R1W
@@ -610,9 +638,14 @@ hipError_t r1m_infer(int dtype, int dim, const InferParams& ip, int mode, const 
                                                        cal_w, cal_gap, st)                                       \
                        : infer_TD<T, D, r1d::kFamNH>(ip, mode, F, bn, W, P, flags, fb_count, fb_list, cal_bin,   \
                                                      cal_w, cal_gap, st))
-  if (dtype == R1_F32) return dim == 2 ? R1F(float, 2) : R1F(float, 3);
-  return dim == 2 ? R1F(double, 2) : R1F(double, 3);
+  hipError_t e = dtype == R1_F32 ? (dim == 2 ? R1F(float, 2) : R1F(float, 3))
+                                 : (dim == 2 ? R1F(double, 2) : R1F(double, 3));
 #undef R1F
+  if (e != hipSuccess || mode != 0) return e;
+  const int64_t blocks = (ip.n + 256 * kListPer - 1) / (256 * kListPer);
+  hipLaunchKernelGGL(k_lists, dim3(unsigned(blocks)), dim3(256), 0, st, ip.n, ip.status, fb_count, fb_list,
+                     ip.cand_count, ip.cand_list);
+  return hipGetLastError();
 }
 
 hipError_t r1m_fb_gather(int dtype, int dim, int64_t n, int nfb, const int32_t* list, const void* F,

@@ -40,6 +40,8 @@ struct InferParams {
   const float* gate_tau;            // kGateCells: accept when the predicted gap is <= the cell's value
   int* cand_count;                  // nullable: points served by the network are also listed here
   int32_t* cand_list;               // (the candidates of the a-posteriori check)
+  uint8_t* status;                  // MODE 0: n bytes, per point 1 = fallback, 2 = served, from which
+                                    // r1m_infer then builds the fallback and candidate lists
 };
 
 // One batch of the training step (r1_train.hip).  Rows (mode): 0 = Xn / Yn given,

@@ -663,10 +663,12 @@ r1_status r1_surrogate_infer(r1_handle h, r1_surrogate s, const r1_material* mat
   const int dd = s->dim * s->dim;
   const size_t ts = dtype == R1_F32 ? 4 : 8;
   // workspace: fallback count and list, then (with the check) the candidates'
-  // count and list, which the fallback's compact arrays reuse after the check
+  // count and list, then the per-point status the lists are built from; the
+  // fallback's compact arrays reuse all but the fallback list after the check
   const bool check = s->check_eps > 0.0f;
   size_t bytes = al(sizeof(int)) + al(sizeof(int32_t) * size_t(n));
   if (check) bytes += al(sizeof(int)) + al(sizeof(int32_t) * size_t(n));
+  bytes += al(size_t(n));                   // per-point status (the lists are built from it)
   rs = grow(s, bytes);
   if (rs) return rs;
   char* p = static_cast<char*>(s->ws);
@@ -691,7 +693,9 @@ r1_status r1_surrogate_infer(r1_handle h, r1_surrogate s, const r1_material* mat
     ca.count = ip.cand_count;
     ca.fb_count = cnt;
     ca.fb_list = list;
+    p += al(sizeof(int32_t) * size_t(n));
   }
+  ip.status = reinterpret_cast<uint8_t*>(p);
   hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int), st);
   if (e == hipSuccess && check) e = hipMemsetAsync(ip.cand_count, 0, sizeof(int), st);
   if (e == hipSuccess) e = ensure_wfrag(s, st);
