@@ -226,14 +226,16 @@ def test_inference_matches_oracle_forward(lib, trained):
     assert uw.max() <= INFER_BF16_UNITS and up.max() <= INFER_BF16_UNITS
 
 
-def test_routing_fallback_and_accuracy(lib, trained):
+@pytest.mark.parametrize("n", [32768, 3001])
+def test_routing_fallback_and_accuracy(lib, trained, n):
     """Inference points from the inference distribution (beta_n up to 1.1, a wider F
     spread), with the a-posteriori check on: out-of-box points fall back and equal
     plain lamination exactly; every served point is within 1e-3 relative energy
-    error (|W| floored at 1e-2) of FP64 plain lamination."""
+    error (|W| floored at 1e-2) of FP64 plain lamination.  3001 points leave ragged
+    last tiles for the inference kernel and for the pass that builds the lists."""
     r1, h, torch = lib
     s, _, _, _, levels = trained
-    cfg = WL.config4_inference(n=32768, seed_tag=63)
+    cfg = WL.config4_inference(n=n, seed_tag=63)
     Ft, bt, plain = laminate(lib, cfg["F"], cfg["beta_n"], levels, torch.float32)
     _, _, p64 = laminate(lib, cfg["F"], cfg["beta_n"], levels, torch.float64)
     s.set_check(5e-4)
@@ -243,6 +245,7 @@ def test_routing_fallback_and_accuracy(lib, trained):
     fl = out["flags"].cpu().numpy()
     fb = (fl & r1.PT_FALLBACK) != 0
     assert out["n_fallback"] == int(fb.sum())
+    assert np.all(fl[~fb] == 0)                     # every point served or laminated
     Wp, Pp = plain["W"].cpu().numpy(), plain["P"].cpu().numpy()
     Wg, Pg = out["W"].cpu().numpy(), out["P"].cpu().numpy()
     assert np.array_equal(Wg[fb], Wp[fb]) and np.array_equal(Pg[:, fb], Pp[:, fb])
