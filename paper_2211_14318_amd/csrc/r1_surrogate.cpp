@@ -107,9 +107,12 @@ hipError_t adam_step(r1_surrogate s, float lr, float b1, float b2, float eps, hi
 }
 
 // The fragment-order copy of the hidden weights, rebuilt after they changed.
+// The rebuild is waited for: the copy is internal state that a later call on
+// another stream reads without any ordering the caller could provide.
 hipError_t ensure_wfrag(r1_surrogate s, hipStream_t st) {
   if (s->wfrag_ok) return hipSuccess;
   hipError_t e = r1m_wfrag(s->width, s->n_hidden, s->wbf, s->wfrag, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e == hipSuccess) s->wfrag_ok = true;
   return e;
 }
