@@ -36,15 +36,15 @@ __device__ __forceinline__ float sample_at(float t, const r1d::Line<float>& L, c
 // passes below the target at the centre.
 template <typename T, int D, int M>
 __device__ __forceinline__ bool chord_below(const CheckArgs& a, const r1d::Point<float>& q, const double* G,
-                                            const double* cof, float target, float dt, int m) {
+                                            const double* cof, float target, int m) {
   const r1d::Line<float> L = r1d::line_setup<float, D, M>(q, G, cof, a.lv.a + m * D, a.lv.b + m * D);
   float lo = __builtin_inff(), hi = __builtin_inff();
   for (int k = 0; k < a.n_off; ++k) {
-    const float o = float(a.off[k]);
+    const float to = a.toff[k];
     const float inv = a.off_inv[k];
     // NaN samples (det <= 0) are absent: fminf keeps the other operand
-    lo = fminf(lo, (sample_at<T, D, M>(-o * dt, L, q) - target) * inv);
-    hi = fminf(hi, (sample_at<T, D, M>(o * dt, L, q) - target) * inv);
+    lo = fminf(lo, (sample_at<T, D, M>(-to, L, q) - target) * inv);
+    hi = fminf(hi, (sample_at<T, D, M>(to, L, q) - target) * inv);
   }
   return lo + hi < 0.0f;
 }
@@ -63,7 +63,6 @@ __global__ __launch_bounds__(256) void k_check(CheckArgs a) {
   const int g = lane % NG;
   const uint64_t gmask = (NG == 64 ? ~uint64_t(0) : ((uint64_t(1) << NG) - 1)) << (lane - g);
   const int rounds = (a.lv.n_dir + NG - 1) / NG;
-  const float dt = float(a.lv.tau / double((a.lv.n_t - 1) / 2));
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t w0 = int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63u); w0 < total * NG; w0 += stride) {
     const int64_t i = (w0 + lane) / NG;
@@ -85,7 +84,7 @@ __global__ __launch_bounds__(256) void k_check(CheckArgs a) {
     bool found = false, done = !valid;
     for (int r = 0; r < rounds; ++r) {
       const int m = r * NG + g;
-      if (!done && m < a.lv.n_dir) found = chord_below<T, D, M>(a, q, G, cof, target, dt, m);
+      if (!done && m < a.lv.n_dir) found = chord_below<T, D, M>(a, q, G, cof, target, m);
       done = done || (__ballot(found) & gmask) != 0;
       if (__all(done)) break;
     }
@@ -137,10 +136,15 @@ int r1_check_offsets(int n_t, int* off) {
 
 hipError_t r1_launch_check(int dtype, const CheckArgs& args, hipStream_t st) {
   if (args.n <= 0) return hipSuccess;
-  // the reciprocals of the offsets, once here instead of a division per sample pair
-  // and direction in the kernel (IEEE float division on both sides: the same bits)
+  // the reciprocals of the offsets and their abscissae off[k] dt, once here
+  // instead of per sample pair and direction in the kernel (IEEE float division
+  // and product on both sides: the same bits)
   CheckArgs a = args;
-  for (int k = 0; k < a.n_off; ++k) a.off_inv[k] = 1.0f / float(a.off[k]);
+  const float dt = float(a.lv.tau / double((a.lv.n_t - 1) / 2));
+  for (int k = 0; k < a.n_off; ++k) {
+    a.off_inv[k] = 1.0f / float(a.off[k]);
+    a.toff[k] = float(a.off[k]) * dt;
+  }
   if (dtype == R1_F32) return a.mat.dim == 2 ? launch_TD<float, 2>(a, st) : launch_TD<float, 3>(a, st);
   return a.mat.dim == 2 ? launch_TD<double, 2>(a, st) : launch_TD<double, 3>(a, st);
 }

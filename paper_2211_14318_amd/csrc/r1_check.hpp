@@ -20,6 +20,7 @@ struct CheckArgs {
   int n_off;
   int off[kCheckMaxOffsets];   // sample offsets from the centre, on the level's grid
   float off_inv[kCheckMaxOffsets];   // 1 / off[k] (set by r1_launch_check)
+  float toff[kCheckMaxOffsets];      // off[k] dt, the offsets' abscissae (set by r1_launch_check)
   const int32_t* list;         // list mode: candidate points list[0 .. *count)
   const int* count;
   int* fb_count;               // list mode: failures appended here
