@@ -478,3 +478,40 @@ def test_check_3d_sends_exactly_the_points_with_a_low_subset_chord(lib, n_dir):
           % (n_dir, n_keep, n_rej, n_skip))
     assert n_keep > 0 and n_rej > 0
     s.close()
+
+
+def test_width256_inference_follows_new_parameters(lib):
+    """The width-256 kernel reads the hidden weights from a copy in MFMA fragment
+    order that the library rebuilds after the weights change: after an inference,
+    new parameters (set_params) give exactly the results of a fresh surrogate
+    loaded with those parameters, and differ from the old results."""
+    r1, h, torch = lib
+    cfg = WL.config5(n=8192, seed_tag=71)
+    lv = cfg["levels"][0]
+    lv = dict(lv, a=lv["a"][:32], b=lv["b"][:32], n_t=65)
+    mat, spec = r1.material(dim=3), r1.LaminationSpec([lv])
+    Ft = torch.tensor(cfg["F"], dtype=torch.float32, device="cuda").contiguous()
+    bt = torch.tensor(cfg["beta_n"], dtype=torch.float32, device="cuda").contiguous()
+    out = h.envelope(mat, spec, Ft, bt, stress=True)
+    s = r1.Surrogate(h, dim=3, n_hidden=4, width=256, seed=11)
+    X, Y = s.pack(Ft, bt, out["W"], out["P"])
+    s.train(mat, X, Y, epochs=2, batch=1024, lr=1e-3, seed=4)
+    inf = WL.config5(n=3000, seed_tag=72)
+    Fi = torch.tensor(inf["F"], dtype=torch.float32, device="cuda").contiguous()
+    bi = torch.tensor(inf["beta_n"], dtype=torch.float32, device="cuda").contiguous()
+    a = s.infer(mat, spec, Fi, bi)
+    p = s.get_params()
+    rng = np.random.default_rng(5)
+    s.set_params(p * (1.0 + 0.05 * rng.standard_normal(p.size)).astype(np.float32))
+    b = s.infer(mat, spec, Fi, bi)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "s.r1s")
+        s.save(path)
+        s2 = r1.Surrogate.load(h, path, dim=3, n_hidden=4, width=256)
+        c = s2.infer(mat, spec, Fi, bi)
+        torch.cuda.synchronize()
+        s2.close()
+    assert torch.equal(b["W"], c["W"]) and torch.equal(b["P"], c["P"]) and torch.equal(b["flags"], c["flags"])
+    served = ((a["flags"] & r1.PT_FALLBACK) == 0) & ((b["flags"] & r1.PT_FALLBACK) == 0)
+    assert int(served.sum()) > 0 and not torch.equal(a["W"][served], b["W"][served])
+    s.close()
