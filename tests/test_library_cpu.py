@@ -48,6 +48,27 @@ def test_argument_checks_need_no_gpu():
     assert L.r1_create(None, 0) == -1
 
 
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libr1.so not built")
+def test_check_offsets_schedule():
+    """The surrogate check's sample offsets (host logic, r1_surrogate_check_offsets)
+    for every odd line length up to R1_MAX_NT: strictly increasing, every offset up
+    to 8 (or to the half-length c), the line's end c last, at most 32 of them, and
+    beyond 8 each step at most about a third of the previous offset (one more than
+    it when that rounds lower); invalid lengths are rejected."""
+    from paper_2211_14318_amd import r1
+    for n_t in range(3, 2050, 2):
+        c = (n_t - 1) // 2
+        offs = [int(o) for o in r1.check_offsets(n_t)]
+        assert offs[0] == 1 and offs[-1] == c and len(offs) <= 32, n_t
+        assert all(b > a for a, b in zip(offs, offs[1:])), n_t
+        assert offs[:min(8, c)] == list(range(1, min(8, c) + 1)), n_t
+        for a, b in zip(offs[7:-1], offs[8:-1]):
+            assert b <= max(a + 1, int(a * 1.3 + 0.5)), (n_t, a, b)
+    for bad in (1, 2, 4, 2051):
+        with pytest.raises(r1.R1Error):
+            r1.check_offsets(bad)
+
+
 def test_grid_reduced_directions_match_oracle():
     """r1_grid_r11 is host code: the library's reduced direction set (eq. 5.1) equals the
     oracle's, in the same order (16 steps in 2D, 169 in 3D)."""
